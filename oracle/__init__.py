@@ -1,0 +1,179 @@
+"""ctypes wrapper of the plain FP64 CPU oracle (``oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, the smoke check and the
+benchmark's CPU-baseline leg.  The library never imports it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+KIND = {"h": 0, "x": 1, "ry": 2, "rz": 3, "p": 4, "u3": 5, "cx": 6, "cp": 7,
+        "swap": 8, "dense": 9, "cdense": 10, "ucry": 11}
+
+
+def build(force: bool = True) -> str:
+    """Compile ``liboracle.so`` with gcc (no FMA contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math",
+               "-fPIC", "-shared", "-Wall", "-Wextra", "-o", _LIB, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+    return _LIB
+
+
+class HHLInfo(ctypes.Structure):
+    _fields_ = [("ns", ctypes.c_int), ("m", ctypes.c_int), ("n", ctypes.c_int),
+                ("j0", ctypes.c_int),
+                ("beta", ctypes.c_double), ("t", ctypes.c_double),
+                ("C", ctypes.c_double), ("lambda_lo", ctypes.c_double),
+                ("lambda_hi", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("p1", ctypes.c_double), ("p10", ctypes.c_double),
+                ("max_imag", ctypes.c_double), ("pad_leak", ctypes.c_double),
+                ("x_norm", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        lp = ctypes.POINTER(ctypes.c_long)
+        L.orc_apply_gate.argtypes = [dp, ctypes.c_int, ctypes.c_int, ip,
+                                     ctypes.c_int, dp, ctypes.c_long]
+        L.orc_apply_circuit.argtypes = [dp, ctypes.c_int, ctypes.c_int, ip,
+                                        ip, ip, lp, dp]
+        L.orc_gate_matrix.argtypes = [ctypes.c_int, dp, dp]
+        L.orc_qft.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                              ctypes.c_int]
+        L.orc_jacobi.argtypes = [dp, ctypes.c_int, dp, dp, ip]
+        L.orc_ge_solve.argtypes = [dp, dp, ctypes.c_int, dp]
+        L.orc_qubit_count.argtypes = [ctypes.c_int, ctypes.c_double,
+                                      ctypes.c_int, ip, ip, ip]
+        L.orc_hhl_solve.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_double, dp, dp, dp,
+                                    ctypes.POINTER(HHLInfo)]
+        L.orc_hhl_params.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_double, ctypes.POINTER(HHLInfo)]
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def _check(rc, what):
+    if rc < 0:
+        raise RuntimeError(f"oracle {what} failed with code {rc}")
+    return rc
+
+
+def apply_circuit(psi: np.ndarray, n: int, gates) -> np.ndarray:
+    """Apply a gate list (``workloads.Gate`` tuples) to a copy of ``psi``."""
+    out = np.array(psi, dtype=np.complex128, copy=True)
+    if out.size != (1 << n):
+        raise ValueError("state size does not match n")
+    L = lib()
+    for g in gates:
+        q = np.asarray(g.qubits, dtype=np.int32)
+        p = np.ascontiguousarray(g.params, dtype=np.float64)
+        pp = _dp(p) if p.size else ctypes.POINTER(ctypes.c_double)()
+        _check(L.orc_apply_gate(_dp(out.view(np.float64)), n, KIND[g.kind],
+                                _ip(q), len(q), pp, p.size), g.kind)
+    return out
+
+
+def zero_state(n: int) -> np.ndarray:
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    psi[0] = 1.0
+    return psi
+
+
+def gate_matrix(kind: str, params=()) -> np.ndarray:
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64).ravel())
+    if p.size == 0:
+        p = np.zeros(1)
+    out = np.zeros(16, dtype=np.complex128)
+    k = _check(lib().orc_gate_matrix(KIND[kind], _dp(p),
+                                     _dp(out.view(np.float64))), kind)
+    d = 1 << k
+    return out[:d * d].reshape(d, d).copy()
+
+
+def qft(psi: np.ndarray, n: int, q0: int, m: int, inverse: bool = False):
+    out = np.array(psi, dtype=np.complex128, copy=True)
+    _check(lib().orc_qft(_dp(out.view(np.float64)), n, q0, m, int(inverse)),
+           "qft")
+    return out
+
+
+def jacobi(A: np.ndarray):
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    N = A.shape[0]
+    V = np.zeros((N, N))
+    lam = np.zeros(N)
+    sw = np.zeros(1, dtype=np.int32)
+    _check(lib().orc_jacobi(_dp(A), N, _dp(V), _dp(lam), _ip(sw)), "jacobi")
+    return lam, V, int(sw[0])
+
+
+def ge_solve(A: np.ndarray, b: np.ndarray) -> np.ndarray:
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.zeros(b.size)
+    _check(lib().orc_ge_solve(_dp(A), _dp(b), b.size, _dp(x)), "ge_solve")
+    return x
+
+
+def qubit_count(dim: int, kappa: float, has_negative: bool):
+    a = np.zeros(3, dtype=np.int32)
+    _check(lib().orc_qubit_count(dim, kappa, int(has_negative), _ip(a[0:]),
+                                 _ip(a[1:]), _ip(a[2:])), "qubit_count")
+    return int(a[0]), int(a[1]), int(a[2])
+
+
+def hhl_params(A, b, m: int, t: float = 0.0) -> dict:
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    info = HHLInfo()
+    _check(lib().orc_hhl_params(_dp(A), _dp(b), b.size, m, t,
+                                ctypes.byref(info)), "hhl_params")
+    return info.as_dict()
+
+
+def hhl_solve(A, b, m: int, t: float = 0.0, want_state: bool = True):
+    """Full HHL solve: returns (psi or None, x_hhl, x_hat, info dict)."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    N = b.size
+    info = HHLInfo()
+    pr = hhl_params(A, b, m, t)
+    n = pr["n"]
+    psi = np.zeros(1 << n, dtype=np.complex128) if want_state else None
+    x_hhl = np.zeros(N)
+    x_hat = np.zeros(N)
+    psi_p = (_dp(psi.view(np.float64)) if want_state
+             else ctypes.POINTER(ctypes.c_double)())
+    _check(lib().orc_hhl_solve(_dp(A), _dp(b), N, m, t, psi_p, _dp(x_hhl),
+                               _dp(x_hat), ctypes.byref(info)), "hhl_solve")
+    return psi, x_hhl, x_hat, info.as_dict()

@@ -1,0 +1,110 @@
+/*
+ * oracle.h -- plain FP64 CPU reference for the HHL state-vector path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Tests, the smoke check and the benchmark's CPU
+ * baseline may call it; the library never does.  It shares no code, header,
+ * table or helper with the device library.  Everything is written for
+ * clarity: one unfused gate at a time over all 2^n amplitudes, in double
+ * precision, compiled without FMA contraction.
+ *
+ * Conventions (the paper fixes none of them; these are the readings used):
+ *   - qubit q is bit q of the amplitude index (little-endian);
+ *   - a state of n qubits is 2^n complex amplitudes stored as interleaved
+ *     (re, im) doubles, caller-owned;
+ *   - a k-qubit matrix acting on the qubit list (q_0..q_{k-1}) is a row-major
+ *     2^k x 2^k complex matrix (interleaved re, im) whose row/column index is
+ *     r = sum_l bit(q_l) * 2^l;
+ *   - HHL registers: system qubits 0..ns-1, clock qubits ns..ns+m-1 (clock
+ *     bit j is qubit ns+j), ancilla qubit ns+m.
+ *
+ * Return codes: 0 on success, negative on error (see ORC_E*).
+ */
+#ifndef HHL_ORACLE_H
+#define HHL_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Gate kinds understood by the oracle. */
+enum {
+    ORC_H = 0,       /* Hadamard                                           */
+    ORC_X = 1,       /* Pauli X                                            */
+    ORC_RY = 2,      /* RY(theta) = [[c, -s], [s, c]], c,s of theta/2     */
+    ORC_RZ = 3,      /* RZ(theta) = diag(e^{-i theta/2}, e^{i theta/2})   */
+    ORC_P = 4,       /* P(phi) = diag(1, e^{i phi})                       */
+    ORC_U3 = 5,      /* U3(theta, phi, lambda), OpenQASM convention       */
+    ORC_CX = 6,      /* qubits (control, target)                          */
+    ORC_CP = 7,      /* controlled phase e^{i phi} on |11>                */
+    ORC_SWAP = 8,
+    ORC_DENSE = 9,   /* params: 2^k x 2^k complex matrix                  */
+    ORC_CDENSE = 10, /* qubits (c, targets...): matrix where bit c is 1   */
+    ORC_UCRY = 11    /* qubits (t, c_0..c_{r-1}); params: 2^r angles      */
+};
+
+enum {
+    ORC_OK = 0,
+    ORC_EINVAL = -1,
+    ORC_ENOMEM = -2,
+    ORC_ENOTSYM = -4,
+    ORC_ENOTPD = -5
+};
+
+/* Apply one gate to psi (2^n complex).  nparams counts doubles. */
+int orc_apply_gate(double *psi, int n, int kind, const int *qubits, int nq,
+                   const double *params, long nparams);
+
+/* Apply a flat gate list: gate g has kind kinds[g], qubits
+ * qubits[qoff[g]..qoff[g+1]) and params params[poff[g]..poff[g+1]). */
+int orc_apply_circuit(double *psi, int n, int ngates, const int *kinds,
+                      const int *qoff, const int *qubits, const long *poff,
+                      const double *params);
+
+/* Matrix (2^k x 2^k complex, interleaved) of a named gate of kind H..SWAP. */
+int orc_gate_matrix(int kind, const double *params, double *out);
+
+/* QFT (inverse = 0) or its inverse (inverse = 1) on qubits q0..q0+m-1,
+ * as the H / controlled-phase / SWAP sequence. */
+int orc_qft(double *psi, int n, int q0, int m, int inverse);
+
+/* Cyclic Jacobi eigen-decomposition of a symmetric N x N matrix A
+ * (row-major): A = V diag(lam) V^T, V row-major with eigenvector k in
+ * column k.  Eigenvalues are returned in ascending order. */
+int orc_jacobi(const double *A, int N, double *V, double *lam, int *sweeps);
+
+/* Gaussian elimination with partial pivoting: solve A x = b (N x N). */
+int orc_ge_solve(const double *A, const double *b, int N, double *x);
+
+/* Qubit-count estimate of the resources section (Sec. III-B), in the
+ * reading that reproduces Table I: n_qpe = max(n_data + 1,
+ * ceil(log2(kappa + 1))) + n_neg, n_total = n_data + n_qpe + 1. */
+int orc_qubit_count(int dim, double kappa, int has_negative, int *n_data,
+                    int *n_qpe, int *n_total);
+
+typedef struct {
+    int ns, m, n, j0;
+    double beta, t, C, lambda_lo, lambda_hi, kappa;
+    double p1;        /* P(ancilla = 1)                                   */
+    double p10;       /* P(ancilla = 1 and clock = 0)                     */
+    double max_imag;  /* max |Im y_s| over the postselected block         */
+    double pad_leak;  /* norm of y over the padded system indices         */
+    double x_norm;    /* ||x|| recovered as sqrt(p10) / C times beta      */
+} orc_hhl_info;
+
+/* Full HHL solve of A x = b (A symmetric positive definite, N x N) with m
+ * clock qubits.  t > 0 fixes the evolution time; t <= 0 selects the
+ * automatic rule.  Outputs (each may be NULL): psi_out (2^n complex final
+ * state), x_hhl (N, the recovered solution), x_hat (N, unit norm). */
+int orc_hhl_solve(const double *A, const double *b, int N, int m, double t,
+                  double *psi_out, double *x_hhl, double *x_hat,
+                  orc_hhl_info *info);
+
+/* Spectral parameters only (no state): fills ns, m, n, j0, beta, t, C,
+ * lambda_lo, lambda_hi, kappa. */
+int orc_hhl_params(const double *A, const double *b, int N, int m, double t,
+                   orc_hhl_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

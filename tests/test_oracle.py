@@ -1,0 +1,247 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle:
+textbook gate identities, tensor-contraction application, the closed form of
+the QFT, unitarity, the HHL identity on exactly representable spectra,
+special cases, library linear algebra and the paper's printed values.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+import workloads as W
+from tests._ref import (apply_tensor, apply_ucry_tensor, cmat, inverse_gates,
+                        max_abs_diff)
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+PX = np.array([[0, 1], [1, 0]], dtype=complex)
+PY = np.array([[0, -1j], [1j, 0]], dtype=complex)
+PZ = np.array([[1, 0], [0, -1]], dtype=complex)
+I2 = np.eye(2)
+
+
+# ---------------------------------------------------------------- gates ---
+@pytest.mark.parametrize("theta", [0.0, 0.3, 1.7, -2.2, 5.9])
+def test_rotation_gates_are_exponentials(theta):
+    assert max_abs_diff(oracle.gate_matrix("ry", [theta]),
+                        scipy.linalg.expm(-0.5j * theta * PY)) < 1e-15
+    assert max_abs_diff(oracle.gate_matrix("rz", [theta]),
+                        scipy.linalg.expm(-0.5j * theta * PZ)) < 1e-15
+    # P(phi) equals RZ(phi) up to the global phase e^{i phi/2}
+    assert max_abs_diff(oracle.gate_matrix("p", [theta]),
+                        np.exp(0.5j * theta) * oracle.gate_matrix("rz", [theta])) < 1e-15
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_u3_is_zyz_product(seed):
+    rng = np.random.default_rng(seed)
+    th, ph, la = rng.uniform(0, 2 * np.pi, 3)
+    zyz = (np.exp(0.5j * (ph + la)) * oracle.gate_matrix("rz", [ph])
+           @ oracle.gate_matrix("ry", [th]) @ oracle.gate_matrix("rz", [la]))
+    assert max_abs_diff(oracle.gate_matrix("u3", [th, ph, la]), zyz) < 1e-14
+
+
+def test_fixed_gates():
+    H = oracle.gate_matrix("h")
+    assert max_abs_diff(H, (PX + PZ) / math.sqrt(2)) < 1e-15
+    assert max_abs_diff(oracle.gate_matrix("x"), PX) == 0.0
+    assert max_abs_diff(oracle.gate_matrix("u3", [np.pi / 2, 0, np.pi]), H) < 1e-15
+    # CX = (I x H) CZ (I x H) with CZ = CP(pi), on qubit list (control, target)
+    n = 2
+    rng = np.random.default_rng(3)
+    psi = rng.standard_normal(4) + 1j * rng.standard_normal(4)
+    via = apply_tensor(psi, n, [1], H)
+    via = apply_tensor(via, n, [0, 1], oracle.gate_matrix("cp", [np.pi]))
+    via = apply_tensor(via, n, [1], H)
+    direct = apply_tensor(psi, n, [0, 1], oracle.gate_matrix("cx"))
+    assert max_abs_diff(via, direct) < 1e-15
+    # SWAP = CX(a,b) CX(b,a) CX(a,b)
+    cx = oracle.gate_matrix("cx")
+    s3 = apply_tensor(apply_tensor(apply_tensor(psi, n, [0, 1], cx), n, [1, 0], cx), n, [0, 1], cx)
+    assert max_abs_diff(s3, apply_tensor(psi, n, [0, 1], oracle.gate_matrix("swap"))) < 1e-15
+    # CP composes additively and is symmetric in its qubits
+    assert max_abs_diff(oracle.gate_matrix("cp", [0.4]) @ oracle.gate_matrix("cp", [0.9]),
+                        oracle.gate_matrix("cp", [1.3])) < 1e-15
+
+
+def test_bell_state_golden():
+    with open(os.path.join(GOLDEN, "bell_state.json")) as f:
+        g = json.load(f)
+    gates = [W.Gate(k, tuple(q), np.array(p, dtype=float)) for k, q, p in g["gates"]]
+    out = oracle.apply_circuit(oracle.zero_state(g["n"]), g["n"], gates)
+    want = np.array(g["amplitudes_re"]) + 1j * np.array(g["amplitudes_im"])
+    assert max_abs_diff(out, want) < 1e-15
+
+
+# ------------------------------------------------------- application ---
+def _reference_apply(psi, n, g):
+    if g.kind in oracle.KIND and g.kind not in ("dense", "cdense", "ucry"):
+        return apply_tensor(psi, n, g.qubits, oracle.gate_matrix(g.kind, g.params))
+    if g.kind == "dense":
+        return apply_tensor(psi, n, g.qubits, cmat(g.params, len(g.qubits)))
+    if g.kind == "cdense":
+        return apply_tensor(psi, n, g.qubits[1:], cmat(g.params, len(g.qubits) - 1),
+                            control=g.qubits[0])
+    if g.kind == "ucry":
+        return apply_ucry_tensor(psi, n, g.qubits[0], g.qubits[1:], g.params)
+    raise ValueError(g.kind)
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (3, 2), (5, 3), (7, 4), (8, 5)])
+def test_apply_matches_tensor_contraction(n, seed):
+    gates = W.random_circuit(n, 40, seed, kmax=min(5, n))
+    psi = W.random_state(n, seed)
+    for g in gates:
+        want = _reference_apply(psi, n, g)
+        got = oracle.apply_circuit(psi, n, [g])
+        assert max_abs_diff(got, want) < 1e-14, g.kind
+        psi = want
+
+
+@pytest.mark.parametrize("n,seed", [(6, 11), (10, 12)])
+def test_norm_preserved_gate_by_gate(n, seed):
+    psi = W.random_state(n, seed)
+    for g in W.random_circuit(n, 60, seed, kmax=4):
+        psi = oracle.apply_circuit(psi, n, [g])
+        assert abs(np.vdot(psi, psi).real - 1.0) < 1e-13
+
+
+@pytest.mark.parametrize("n,seed", [(5, 21), (9, 22)])
+def test_mirror_returns_input(n, seed):
+    gates = W.random_circuit(n, 80, seed, kmax=4)
+    psi0 = W.random_state(n, seed)
+    out = oracle.apply_circuit(oracle.apply_circuit(psi0, n, gates), n,
+                               inverse_gates(gates))
+    assert max_abs_diff(out, psi0) < 1e-13
+
+
+# --------------------------------------------------------------- QFT ---
+@pytest.mark.parametrize("m,q0,extra", [(1, 0, 0), (2, 1, 1), (3, 0, 2), (4, 2, 1), (6, 1, 0), (7, 0, 0)])
+def test_qft_closed_form(m, q0, extra):
+    n = q0 + m + extra
+    M = 1 << m
+    rng = np.random.default_rng(m)
+    for x in sorted(set([0, 1, M - 1] + list(rng.integers(0, M, 3)))):
+        other = (1 << q0) - 1 if q0 else 0     # some spectator bits set
+        idx = (int(x) << q0) | other
+        psi = np.zeros(1 << n, dtype=complex)
+        psi[idx] = 1.0
+        out = oracle.qft(psi, n, q0, m)
+        e = np.zeros(M, dtype=complex)
+        e[x] = 1.0
+        closed = np.fft.ifft(e) * math.sqrt(M)   # 2^{-m/2} sum_y e^{+2 pi i x y / M}
+        want = np.zeros(1 << n, dtype=complex)
+        for y in range(M):
+            want[(y << q0) | other] = closed[y]
+        assert max_abs_diff(out, want) < 1e-14
+    psi = W.random_state(n, m)
+    back = oracle.qft(oracle.qft(psi, n, q0, m), n, q0, m, inverse=True)
+    assert max_abs_diff(back, psi) < 1e-14
+
+
+# ---------------------------------------------------- linear algebra ---
+@pytest.mark.parametrize("N,seed", [(1, 0), (3, 1), (16, 2), (64, 3)])
+def test_jacobi(N, seed):
+    if N == 1:
+        A = np.array([[2.5]])
+    else:
+        A, _ = W.dc_powerflow(N + 1, seed)
+    lam, V, _ = oracle.jacobi(A)
+    nA = np.linalg.norm(A, 2)
+    assert np.linalg.norm(A @ V - V * lam) <= 1e-13 * nA
+    assert np.linalg.norm(V.T @ V - np.eye(N)) <= 1e-14 * max(1, N)
+    assert max_abs_diff(lam, np.linalg.eigvalsh(A)) <= 1e-13 * nA
+    assert np.all(np.diff(lam) >= 0)
+
+
+@pytest.mark.parametrize("N,seed", [(3, 0), (15, 1), (63, 2)])
+def test_ge_solve(N, seed):
+    A, b = W.dc_powerflow(N + 1, seed)
+    x = oracle.ge_solve(A, b)
+    assert np.linalg.norm(A @ x - b) <= 1e-12 * np.linalg.norm(b) * np.linalg.cond(A)
+    assert max_abs_diff(x, np.linalg.solve(A, b)) <= 1e-12 * np.linalg.norm(x) * np.linalg.cond(A)
+
+
+def test_qubit_count_table1():
+    with open(os.path.join(GOLDEN, "table1_qubit_counts.json")) as f:
+        cases = json.load(f)["cases"]
+    for c in cases:
+        rows = 2 * c["rows"] if c["dilated"] else c["rows"]
+        nd, nq, nt = oracle.qubit_count(rows, c["kappa"], True)
+        assert (nd, nq, nt) == (c["n_data"], c["n_qpe"], c["n_total"]), c["name"]
+
+
+# --------------------------------------------------------------- HHL ---
+@pytest.mark.parametrize("ns,m,seed", [(1, 4, 0), (2, 5, 1), (3, 6, 2), (4, 7, 3), (6, 8, 4)])
+def test_hhl_exact_spectrum(ns, m, seed):
+    """With eigenvalues on the clock grid, HHL returns A^{-1} b exactly."""
+    A, b, t, _ = W.exact_spectrum_system(ns, m, seed)
+    psi, x, xh, info = oracle.hhl_solve(A, b, m, t)
+    xs = np.linalg.solve(A, b)
+    assert np.linalg.norm(x - xs) <= 1e-12 * np.linalg.norm(xs)
+    assert abs(info["x_norm"] - np.linalg.norm(xs)) <= 1e-12 * np.linalg.norm(xs)
+    bh = b / np.linalg.norm(b)
+    p_expected = info["C"] ** 2 * np.linalg.norm(np.linalg.solve(A, bh)) ** 2
+    assert abs(info["p1"] - p_expected) < 1e-12
+    assert abs(info["p10"] - p_expected) < 1e-12
+    n = info["n"]
+    anc1 = np.abs(psi[1 << (n - 1):]) ** 2
+    assert anc1.sum() - anc1[: 1 << ns].sum() < 1e-24 + 1e-12
+    # 2m controlled 2^ns-term unitaries built from an eigen-decomposition:
+    # rounding of order 2m * 2^ns * eps bounds the norm drift
+    assert abs(np.vdot(psi, psi).real - 1) < 2 * m * (1 << ns) * 2.3e-16
+    # The printed recovery |lambda_0| sqrt(P) does not give ||A^{-1} b_hat||;
+    # sqrt(P) / lambda_0 does (C equals lambda_0 here).
+    true_norm = np.linalg.norm(np.linalg.solve(A, bh))
+    assert abs(math.sqrt(info["p1"]) / info["lambda_lo"] - true_norm) < 1e-10 * true_norm
+    if abs(info["lambda_lo"] - 1) > 1e-3:
+        assert abs(info["lambda_lo"] * math.sqrt(info["p1"]) - true_norm) > 1e-3 * true_norm
+
+
+@pytest.mark.parametrize("N,lam", [(3, 2.0), (4, 0.5), (5, 7.25)])
+def test_hhl_scaled_identity(N, lam):
+    rng = np.random.default_rng(N)
+    b = rng.standard_normal(N)
+    A = lam * np.eye(N)
+    psi, x, xh, info = oracle.hhl_solve(A, b, 4)
+    assert max_abs_diff(x, b / lam) < 1e-13 * np.linalg.norm(b / lam) + 1e-15
+    assert info["pad_leak"] < 1e-14
+    assert info["max_imag"] < 1e-14
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_hhl_small_powerflow_fidelity(seed):
+    """4-bus DC power flow, 4 clock qubits: fidelity to A^{-1} b (reported)."""
+    A, b = W.dc_powerflow(4, seed)
+    psi, x, xh, info = oracle.hhl_solve(A, b, 4)
+    xs = oracle.ge_solve(A, b)
+    fid = float(np.dot(xh, xs / np.linalg.norm(xs)) ** 2)
+    # When kappa exceeds the clock range (2^m - 1) lambda_lo falls below one
+    # clock step and the discretisation error dominates; still a fair answer.
+    assert fid > (0.99 if info["kappa"] <= (1 << info["m"]) - 1 else 0.5)
+    assert info["pad_leak"] < 1e-12
+    assert abs(np.vdot(psi, psi).real - 1) < 1e-13
+    # the smallest eigenvalue maps onto clock value j0 and the largest stays
+    # in range (no wrap-around)
+    scale = info["t"] * (1 << info["m"]) / (2 * math.pi)
+    top = (1 << info["m"]) - 1
+    if info["kappa"] <= top:
+        assert abs(info["lambda_lo"] * scale - info["j0"]) < 1e-9
+        assert info["lambda_hi"] * scale <= top + 1e-9
+    else:
+        assert abs(info["lambda_hi"] * scale - top) < 1e-9
+
+
+def test_hhl_rejects_bad_inputs():
+    A = np.array([[1.0, 2.0], [0.0, 1.0]])
+    with pytest.raises(RuntimeError):
+        oracle.hhl_solve(A, np.ones(2), 3)
+    A = np.array([[1.0, 0.0], [0.0, -1.0]])
+    with pytest.raises(RuntimeError):
+        oracle.hhl_solve(A, np.ones(2), 3)
+    with pytest.raises(RuntimeError):
+        oracle.hhl_solve(np.eye(2), np.zeros(2), 3)
