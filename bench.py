@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Benchmark: fused-gate HBM throughput on a 33-qubit complex128 state.
+
+Workload: the random layered circuit (40 layers of H, RZ, U3 on every qubit
+then CX on a random matching; seed 2402) on 33 qubits, complex128 (128 GiB in
+HBM, updated in place), fused to k_max-qubit gates.  One step = fuse the
+circuit on the host + apply every fused gate (one HBM sweep each).
+
+value = whole-job algorithmic HBM GB/s = sweeps * 2 * 2^33 * 16 B / step time.
+The roofline object reports the dominant kernel family: algorithmic bytes per
+launch / its mean launch time from HIP events recorded on the state's stream.
+The CPU baseline times the oracle on a bounded sample of the same generator.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--k 4]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fused-gate HBM GB/s (33q SV); HHL solves/s + p99 latency, FP64 vs FP32"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2402_08136_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fused_sweep_33q.txt")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(family):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source (else None)."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    key = f"bytes_per_launch_{family}"
+    return float(vals[key]) if key in vals else None
+
+
+def cpu_baseline(budget_s=15.0, n=26):
+    """Oracle (plain C, one thread) on the same layered-circuit generator at
+    n qubits, unfused, gate by gate until ~budget_s of CPU time."""
+    import numpy as np
+
+    import oracle
+    import workloads as W
+
+    gates = W.layered_circuit(n, 2, 2402)
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    psi[0] = 1.0
+    done = 0
+    t0 = time.perf_counter()
+    L = oracle.lib()
+    import ctypes
+    for g in gates:
+        q = np.asarray(g.qubits, dtype=np.int32)
+        p = np.ascontiguousarray(g.params, dtype=np.float64)
+        pp = p.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if p.size else None
+        rc = L.orc_apply_gate(psi.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              n, oracle.KIND[g.kind],
+                              q.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(q), pp, p.size)
+        if rc < 0:
+            raise RuntimeError("oracle failed")
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    gbs = done * 2 * (1 << n) * 16 / dt / 1e9
+    return {"value": round(gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {done} unfused gates of the layered-circuit generator "
+                      f"(seed 2402) at n={n} (1 GiB state), one thread, {dt:.1f} s; "
+                      f"GB/s = gates * 2 * 2^n * 16 B / time"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--k", type=int, default=4, help="fusion width k_max (1..5)")
+    ap.add_argument("--n", type=int, default=33, help="qubits (the workload is 33)")
+    ap.add_argument("--layers", type=int, default=40)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path "
+              f"(--gpus {args.gpus} requested); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+
+    import paper_2402_08136_amd as hs
+    import workloads as W
+
+    n, k = args.n, args.k
+    log(f"[bench] building {args.layers}-layer circuit on {n} qubits")
+    circ = hs.circuit_from_gates(n, W.layered_circuit(n, args.layers, 2402))
+    log(f"[bench] allocating {16 * 2 ** n / 2 ** 30:.0f} GiB state")
+    state = hs.sv_create(n, "c128")
+    bytes_per_sweep = 2 * (1 << n) * 16
+
+    for w in range(args.warmup):
+        t = time.perf_counter()
+        state.apply(hs.fuse(circ, k))
+        state.synchronize()
+        log(f"[bench] warmup {w}: {time.perf_counter() - t:.2f} s")
+
+    state.synchronize()
+    t0 = time.perf_counter()
+    launch_ms, families = [], []
+    n_sweeps = 0
+    for st in range(args.steps):
+        fused = hs.fuse(circ, k)
+        ms, fam = state.apply_timed(fused)
+        launch_ms.append(ms)
+        families.append(fam)
+        n_sweeps += fused.n_gates
+        log(f"[bench] step {st}: {fused.n_gates} sweeps, {ms.sum() / 1e3:.2f} s device")
+    state.synchronize()
+    elapsed = time.perf_counter() - t0
+    norm = state.norm2()
+
+    ms_all = np.concatenate(launch_ms)
+    fam_all = np.concatenate(families)
+    value = n_sweeps * bytes_per_sweep / elapsed / 1e9
+    per_sweep = bytes_per_sweep / (ms_all * 1e-3) / 1e9
+    by_fam = {}
+    for f in np.unique(fam_all):
+        sel = fam_all == f
+        by_fam[hs.KERNEL_FAMILY[int(f)]] = (float(ms_all[sel].sum()), int(sel.sum()),
+                                            float(ms_all[sel].mean()))
+    dom = max(by_fam, key=lambda f: by_fam[f][0])
+    dom_avg_ms = by_fam[dom][2]
+    achieved = bytes_per_sweep / (dom_avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(dom)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"random layered circuit, {n} qubits, complex128 state "
+                        f"({16 * 2 ** n / 2 ** 30:.0f} GiB in place), {args.layers} layers, "
+                        f"seed 2402, fused to k_max={k}",
+            "n_qubits": n, "layers": args.layers, "k_max": k,
+            "sweeps_per_step": n_sweeps // max(1, args.steps),
+            "bytes_per_sweep": bytes_per_sweep,
+            "per_sweep_GBps": {"min": round(float(per_sweep.min()), 1),
+                               "median": round(float(np.median(per_sweep)), 1),
+                               "max": round(float(per_sweep.max()), 1)},
+            "kernel_families": {f: {"total_ms": round(v[0], 2), "launches": v[1],
+                                    "mean_ms": round(v[2], 3),
+                                    "GBps": round(bytes_per_sweep / (v[2] * 1e-3) / 1e9, 1)}
+                                for f, v in by_fam.items()},
+            "final_norm2": norm,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dom,
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the oracle on the host (bounded sample)")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

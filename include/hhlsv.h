@@ -1,0 +1,243 @@
+/*
+ * hhlsv.h -- C ABI of libhhlsv, an MI355X (gfx950) state-vector simulator
+ * for the HHL quantum linear solver.
+ *
+ * The calls follow the problem statement of Zheng et al., "Early
+ * Exploration of a Flexible Framework for Efficient Quantum Linear Solvers in
+ * Power Systems" (PESGM 2024), Sec. III-A "Practical HHL procedures": given
+ * A and b of A x = b, build the HHL circuit (step 2, Fig. 5), run it on a
+ * state-vector simulator whose dominant cost is the unitary evolution of the
+ * state (Sec. II-C), read the state vector (step 3) and recover x (step 4).
+ * Gate fusion (Sec. II-C, Fig. 4) is exposed as fuse().
+ *
+ * Conventions
+ *   - Qubit q is bit q of the amplitude index (little-endian).
+ *   - An n-qubit state is 2^n complex amplitudes, interleaved (re, im):
+ *     SV_C128 = two doubles per amplitude (16 B), SV_C64 = two floats (8 B).
+ *   - A k-qubit matrix on the qubit list (q_0..q_{k-1}) is row-major
+ *     2^k x 2^k complex (interleaved doubles); its row/column index is
+ *     r = sum_l bit(q_l) 2^l.
+ *   - HHL register layout: system qubits 0..ns-1, clock qubits ns..ns+m-1
+ *     (clock bit j is qubit ns+j), ancilla ns+m; n = ns + m + 1.
+ *
+ * Errors: every call returns an sv_status; on failure sv_last_error() gives
+ * a thread-local message.  No call aborts or throws across the ABI.  Inputs
+ * are validated before any device work.  HIP errors are reported as
+ * SV_ERR_HIP; a kernel fault leaves the HIP context unusable (sticky), so the
+ * caller must treat SV_ERR_HIP as fatal for the process's GPU work.
+ *
+ * Ownership: inputs are copied at the call and stay the caller's.  The
+ * library owns sv_state / sv_circuit / svb / svs objects until their destroy
+ * or stop call; sv_create_from_buffer adopts memory the caller keeps alive.
+ * Outputs go to caller-allocated buffers.
+ *
+ * Streams: device work is ordered on the state's stream (default: a stream
+ * the library creates per state).  sv_apply is asynchronous; calls that
+ * return host data synchronise that stream.  A state is used by one thread
+ * at a time; circuits are read-only after construction and may be shared.
+ */
+#ifndef HHLSV_H
+#define HHLSV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SV_OK = 0,
+    SV_PENDING = 1,
+    SV_ERR_INVALID = -1,
+    SV_ERR_OOM = -2,
+    SV_ERR_HIP = -3,
+    SV_ERR_NOT_SYMMETRIC = -4,
+    SV_ERR_NOT_POSDEF = -5,
+    SV_ERR_SHAPE = -6,
+    SV_ERR_BUSY = -7
+} sv_status;
+
+typedef enum { SV_C128 = 0, SV_C64 = 1 } sv_dtype;
+
+/* Gate kinds for circuit_add_gate (textbook / OpenQASM definitions). */
+typedef enum {
+    SV_GATE_H = 0,      /* qubits (q)                                     */
+    SV_GATE_X = 1,      /* qubits (q)                                     */
+    SV_GATE_RY = 2,     /* qubits (q); params (theta): [[c,-s],[s,c]]     */
+    SV_GATE_RZ = 3,     /* qubits (q); params (theta):
+                           diag(e^{-i theta/2}, e^{i theta/2})            */
+    SV_GATE_P = 4,      /* qubits (q); params (phi): diag(1, e^{i phi})   */
+    SV_GATE_U3 = 5,     /* qubits (q); params (theta, phi, lambda)        */
+    SV_GATE_CX = 6,     /* qubits (control, target)                       */
+    SV_GATE_CP = 7,     /* qubits (a, b); params (phi): e^{i phi} on |11> */
+    SV_GATE_SWAP = 8,   /* qubits (a, b)                                  */
+    SV_GATE_DENSE = 9,  /* qubits (q_0..q_{k-1}), k <= 12; params: the
+                           2^k x 2^k matrix (2 * 4^k doubles)             */
+    SV_GATE_CDENSE = 10,/* qubits (c, q_0..q_{k-1}): DENSE applied where
+                           bit c is 1                                     */
+    SV_GATE_UCRY = 11,  /* qubits (t, c_0..c_{r-1}), r <= 20; params: 2^r
+                           angles; RY(angle[v]) on t where v = sum_l
+                           bit(c_l) 2^l                                   */
+    SV_GATE_DIAG = 12   /* qubits (q_0..q_{k-1}), k <= 12; params: 2^k
+                           complex diagonal entries (2 * 2^k doubles)     */
+} sv_gate_kind;
+
+typedef struct sv_state sv_state;      /* device state vector + stream   */
+typedef struct sv_circuit sv_circuit;  /* host gate list (+ device copy) */
+typedef struct svb svb;                /* batch of small HHL solves      */
+typedef struct svs svs;                /* serving loop                   */
+
+/* Parameters of an HHL circuit (Sec. III-A step 1, Sec. III-B). */
+typedef struct {
+    int n_sys;        /* ns: system qubits, 2^ns >= dim                     */
+    int n_clock;      /* m: clock (phase-estimation) qubits                 */
+    int n_total;      /* ns + m + 1                                         */
+    int n_qpe_est;    /* Sec. III-B estimate for the clock register         */
+    int n_gates;      /* gates in the circuit                               */
+    int dim;          /* N: rows of the caller's A                          */
+    int j0;           /* clock value that stands for lambda_lo              */
+    double t;         /* evolution time of e^{iAt}                          */
+    double C;         /* inversion constant: ancilla |1> amplitude C/lambda  */
+    double lambda_lo, lambda_hi, kappa;  /* over the eigenvectors b reaches */
+    double b_norm;    /* ||b|| (step 1)                                     */
+} sv_hhl_info;
+
+/* Result of postselection (Sec. III-A steps 3-4). */
+typedef struct {
+    double scale;          /* x = scale * x_hat = b_norm * ||Re y|| / C     */
+    double p_anc1;         /* P(ancilla = 1)                                */
+    double p_anc1_clock0;  /* P(ancilla = 1, clock = 0) = ||y||^2           */
+    double max_imag;       /* max |Im y_s|                                  */
+    double pad_leak;       /* ||y_s|| over padded indices s >= N            */
+} sv_solution_info;
+
+/* ---- states ----------------------------------------------------------- */
+
+/* Allocate an n-qubit state (1 <= n <= 34) in device memory, initialised to
+ * |0...0>, with its own stream.  SV_ERR_OOM if HBM is short. */
+sv_status sv_create(int n_qubits, sv_dtype dtype, sv_state **out);
+
+/* Wrap caller-owned device memory (e.g. a torch tensor) of at least
+ * 2^n * amplitude-size bytes; the contents are left as they are.  The
+ * memory must outlive the state. */
+sv_status sv_create_from_buffer(void *dev_ptr, size_t bytes, int n_qubits,
+                                sv_dtype dtype, sv_state **out);
+
+/* Order the state's device work on a caller stream (hipStream_t, e.g.
+ * torch.cuda.current_stream().cuda_stream); NULL restores the state's own. */
+sv_status sv_set_stream(sv_state *s, void *hip_stream);
+
+/* Free the state (and its memory unless adopted). */
+sv_status sv_destroy(sv_state *s);
+
+/* Reset to |0...0> (asynchronous). */
+sv_status sv_reset(sv_state *s);
+
+/* Copy count amplitudes starting at offset to/from host memory, in the
+ * state's dtype (interleaved).  Synchronises the stream. */
+sv_status sv_get_amplitudes(const sv_state *s, size_t offset, size_t count,
+                            void *host_out);
+sv_status sv_set_amplitudes(sv_state *s, size_t offset, size_t count,
+                            const void *host_in);
+
+/* Gather amplitudes at arbitrary indices (each < 2^n) into host_out
+ * (count amplitudes, state dtype).  Synchronises the stream. */
+sv_status sv_get_amplitudes_at(const sv_state *s, const uint64_t *indices,
+                               size_t count, void *host_out);
+
+/* sum |psi_i|^2, accumulated in double with a fixed reduction order.
+ * Synchronises the stream. */
+sv_status sv_norm2(const sv_state *s, double *out);
+
+/* ---- circuits --------------------------------------------------------- */
+
+/* Build the HHL circuit of Fig. 5 for A x = b (Sec. III-A):
+ *   A: dim*dim row-major doubles, symmetric (|A - A^T| <= 1e-12 max|A|),
+ *      positive definite on the span b reaches; b: dim doubles, nonzero.
+ *   clock_bits: m in [1, 16]; t > 0 fixes the evolution time, t <= 0
+ *   selects the rule that puts lambda_lo on clock value
+ *   j0 = floor((2^m - 1) / kappa) (or lambda_hi on 2^m - 1 when kappa >
+ *   2^m - 1).
+ * The circuit: |b> preparation (a tree of uniformly controlled RY), H on the
+ * clock, e^{iAt 2^j} controlled by clock bit j, inverse QFT, controlled-RY
+ * inversion with angle 2 asin(min(1, j0 / c)) for clock value c >= 1, QFT,
+ * the inverse controlled evolutions, H on the clock.
+ * Errors: SV_ERR_NOT_SYMMETRIC, SV_ERR_NOT_POSDEF, SV_ERR_INVALID (b = 0,
+ * dim < 1, m out of range, n > 34). */
+sv_status circuit_build_hhl(const double *A, const double *b, int dim,
+                            int clock_bits, double t, sv_circuit **out);
+
+/* Empty generic circuit on n qubits (1 <= n <= 34). */
+sv_status circuit_create(int n_qubits, sv_circuit **out);
+
+/* Append one gate (see sv_gate_kind for qubits and params).  Qubits must be
+ * distinct and < n; nparams counts doubles. */
+sv_status circuit_add_gate(sv_circuit *c, int kind, const int *qubits, int nq,
+                           const double *params, int nparams);
+
+/* HHL parameters (HHL circuits only; generic circuits fill n_total,
+ * n_gates and zeros). */
+sv_status circuit_info(const sv_circuit *c, sv_hhl_info *out);
+
+/* Number of qubits and gates of any circuit. */
+sv_status circuit_shape(const sv_circuit *c, int *n_qubits, int *n_gates);
+
+/* Serialise the gate list.  With buf == NULL, *len receives the size.
+ * Format (little-endian): int32 n_qubits, int32 n_gates, then per gate:
+ * int32 kind, int32 nq, int32 nparams, nq int32 qubits, nparams float64. */
+sv_status circuit_serialize(const sv_circuit *c, void *buf, size_t *len);
+
+/* Gate fusion (Sec. II-C, Fig. 4): merge gates whose joint qubit set has at
+ * most k_max (1..5) qubits into single DENSE (or DIAG when every member is
+ * diagonal) gates.  Gates wider than k_max (controlled evolutions,
+ * inversion) stay as they are.  The result is a new circuit with the same
+ * unitary; products are formed in double precision. */
+sv_status fuse(const sv_circuit *in, int k_max, sv_circuit **out);
+
+/* Apply every gate of c to s, in order, asynchronously on s's stream.
+ * SV_ERR_SHAPE if the circuit's qubit count differs from the state's. */
+sv_status sv_apply(sv_state *s, const sv_circuit *c);
+
+/* Kernel families reported by sv_apply_timed. */
+typedef enum {
+    SV_KERNEL_DENSE_DIRECT = 0, /* dense k <= 5, all targets >= 6: in registers */
+    SV_KERNEL_DENSE_LDS = 1,    /* dense k <= 5, some target < 6: LDS regroup  */
+    SV_KERNEL_DENSE_SMALL = 2,  /* dense k <= 5 on a state of < 6 + k qubits   */
+    SV_KERNEL_DIAG = 3,         /* diagonal gate                                */
+    SV_KERNEL_WIDE = 4,         /* dense gate on 6..12 targets, optional control */
+    SV_KERNEL_UCRY = 5          /* uniformly controlled RY                      */
+} sv_kernel_family;
+
+/* As sv_apply, and record the device time of each gate's launch with HIP
+ * events on the state's stream: launch_ms[g] for gate g (cap >= n_gates);
+ * kernel_ids (may be NULL) receives each launch's sv_kernel_family.
+ * Synchronises the stream. */
+sv_status sv_apply_timed(sv_state *s, const sv_circuit *c, double *launch_ms,
+                         int *kernel_ids, int cap);
+
+/* Wait for all work queued on the state's stream. */
+sv_status sv_synchronize(sv_state *s);
+
+/* Postselection and recovery (Sec. III-A steps 3-4): y_s = psi[2^{n-1} + s]
+ * (ancilla 1, clock 0); x_hat = Re(y)/||Re y|| over the first dim entries;
+ * info->scale = b_norm * ||Re y|| / C so that x = scale * x_hat.  Sums are
+ * accumulated in double.  dim must equal the circuit's.  Synchronises. */
+sv_status sv_postselect_solution(sv_state *s, const sv_circuit *hhl,
+                                 double *x_hat, int dim,
+                                 sv_solution_info *info);
+
+sv_status circuit_destroy(sv_circuit *c);
+
+const char *sv_last_error(void);
+
+/* Sec. III-B qubit estimate, in the reading that reproduces Table I:
+ * n_data = ceil(log2 dim), n_qpe = max(n_data + 1, ceil(log2(kappa + 1)))
+ * + has_negative, n_total = n_data + n_qpe + 1 (inversion ancilla). */
+sv_status sv_qubit_estimate(int dim, double kappa, int has_negative,
+                            int *n_data, int *n_qpe, int *n_total);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

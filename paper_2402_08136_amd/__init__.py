@@ -1,0 +1,334 @@
+"""Python binding of libhhlsv, the MI355X HHL state-vector simulator.
+
+Argument marshalling only: every step runs in the C++/HIP library
+(``libhhlsv.so``, built in-tree by ``build.py``).  Importing this module
+fails loudly when the library has not been built; there is no fallback.
+
+The functions keep the C-ABI names (``sv_create``, ``circuit_build_hhl``,
+``fuse``, ``sv_apply``, ``sv_postselect_solution`` ...) and raise
+``HHLSVError`` on a non-OK status.  ``State`` and ``Circuit`` are small
+owning wrappers around the handles.  Torch, when used, only supplies device
+memory (``State.from_tensor``) and streams (``State.set_stream``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhhlsv.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+        "or `python paper_2402_08136_amd/build.py` (hipcc for gfx950)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+C128, C64 = 0, 1
+DTYPES = {"c128": C128, "c64": C64, C128: C128, C64: C64}
+KIND = {"h": 0, "x": 1, "ry": 2, "rz": 3, "p": 4, "u3": 5, "cx": 6, "cp": 7,
+        "swap": 8, "dense": 9, "cdense": 10, "ucry": 11, "diag": 12}
+KIND_NAME = {v: k for k, v in KIND.items()}
+KERNEL_FAMILY = {0: "dense_direct", 1: "dense_lds", 2: "dense_small", 3: "diag",
+                 4: "wide", 5: "ucry"}
+STATUS = {0: "SV_OK", 1: "SV_PENDING", -1: "SV_ERR_INVALID", -2: "SV_ERR_OOM",
+          -3: "SV_ERR_HIP", -4: "SV_ERR_NOT_SYMMETRIC", -5: "SV_ERR_NOT_POSDEF",
+          -6: "SV_ERR_SHAPE", -7: "SV_ERR_BUSY"}
+
+
+class HHLSVError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _lib.sv_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {msg}")
+
+
+class HHLInfo(ctypes.Structure):
+    _fields_ = [("n_sys", ctypes.c_int), ("n_clock", ctypes.c_int),
+                ("n_total", ctypes.c_int), ("n_qpe_est", ctypes.c_int),
+                ("n_gates", ctypes.c_int), ("dim", ctypes.c_int),
+                ("j0", ctypes.c_int), ("t", ctypes.c_double),
+                ("C", ctypes.c_double), ("lambda_lo", ctypes.c_double),
+                ("lambda_hi", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("b_norm", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class SolutionInfo(ctypes.Structure):
+    _fields_ = [("scale", ctypes.c_double), ("p_anc1", ctypes.c_double),
+                ("p_anc1_clock0", ctypes.c_double), ("max_imag", ctypes.c_double),
+                ("pad_leak", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+_sz = ctypes.c_size_t
+
+
+def _proto(name, *args):
+    f = getattr(_lib, name)
+    f.argtypes = list(args)
+    f.restype = ctypes.c_int
+    return f
+
+
+_lib.sv_last_error.restype = ctypes.c_char_p
+_proto("sv_create", ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp))
+_proto("sv_create_from_buffer", _vp, _sz, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp))
+_proto("sv_set_stream", _vp, _vp)
+_proto("sv_destroy", _vp)
+_proto("sv_reset", _vp)
+_proto("sv_get_amplitudes", _vp, _sz, _sz, _vp)
+_proto("sv_set_amplitudes", _vp, _sz, _sz, _vp)
+_proto("sv_get_amplitudes_at", _vp, ctypes.POINTER(ctypes.c_uint64), _sz, _vp)
+_proto("sv_norm2", _vp, _dp)
+_proto("circuit_build_hhl", _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.POINTER(_vp))
+_proto("circuit_create", ctypes.c_int, ctypes.POINTER(_vp))
+_proto("circuit_add_gate", _vp, ctypes.c_int, _ip, ctypes.c_int, _dp, ctypes.c_int)
+_proto("circuit_info", _vp, ctypes.POINTER(HHLInfo))
+_proto("circuit_shape", _vp, _ip, _ip)
+_proto("circuit_serialize", _vp, _vp, ctypes.POINTER(_sz))
+_proto("fuse", _vp, ctypes.c_int, ctypes.POINTER(_vp))
+_proto("sv_apply", _vp, _vp)
+_proto("sv_apply_timed", _vp, _vp, _dp, _ip, ctypes.c_int)
+_proto("sv_synchronize", _vp)
+_proto("sv_postselect_solution", _vp, _vp, _dp, ctypes.c_int, ctypes.POINTER(SolutionInfo))
+_proto("circuit_destroy", _vp)
+_proto("sv_qubit_estimate", ctypes.c_int, ctypes.c_double, ctypes.c_int, _ip, _ip, _ip)
+
+
+def _check(rc, where):
+    if rc not in (0, 1):
+        raise HHLSVError(rc, where)
+    return rc
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _amp_dtype(dtype):
+    return np.complex128 if DTYPES[dtype] == C128 else np.complex64
+
+
+# ------------------------------------------------------------------ circuits
+class Circuit:
+    """Owning wrapper of an ``sv_circuit*``."""
+
+    def __init__(self, handle):
+        self.handle = _vp(handle)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            _lib.circuit_destroy(h)
+            self.handle = _vp()
+
+    @property
+    def shape(self):
+        n = ctypes.c_int()
+        g = ctypes.c_int()
+        _check(_lib.circuit_shape(self.handle, ctypes.byref(n), ctypes.byref(g)), "circuit_shape")
+        return n.value, g.value
+
+    @property
+    def n_qubits(self):
+        return self.shape[0]
+
+    @property
+    def n_gates(self):
+        return self.shape[1]
+
+    def info(self):
+        out = HHLInfo()
+        _check(_lib.circuit_info(self.handle, ctypes.byref(out)), "circuit_info")
+        return out.as_dict()
+
+    def serialize(self) -> bytes:
+        ln = _sz()
+        _check(_lib.circuit_serialize(self.handle, None, ctypes.byref(ln)), "circuit_serialize")
+        buf = ctypes.create_string_buffer(ln.value)
+        _check(_lib.circuit_serialize(self.handle, buf, ctypes.byref(ln)), "circuit_serialize")
+        return buf.raw[: ln.value]
+
+    def gates(self):
+        """Decode the serialised gate list: [(kind_name, qubits, params)]."""
+        raw = self.serialize()
+        n, ng = np.frombuffer(raw, dtype="<i4", count=2)
+        off = 8
+        out = []
+        for _ in range(int(ng)):
+            kind, nq, npar = np.frombuffer(raw, dtype="<i4", count=3, offset=off)
+            off += 12
+            qs = np.frombuffer(raw, dtype="<i4", count=int(nq), offset=off).tolist()
+            off += 4 * int(nq)
+            ps = np.frombuffer(raw, dtype="<f8", count=int(npar), offset=off).copy()
+            off += 8 * int(npar)
+            out.append((KIND_NAME[int(kind)], qs, ps))
+        return out
+
+
+def circuit_create(n_qubits: int) -> Circuit:
+    h = _vp()
+    _check(_lib.circuit_create(n_qubits, ctypes.byref(h)), "circuit_create")
+    return Circuit(h.value)
+
+
+def circuit_add_gate(c: Circuit, kind, qubits, params=()):
+    q = np.ascontiguousarray(qubits, dtype=np.int32)
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64).ravel())
+    k = KIND[kind] if isinstance(kind, str) else int(kind)
+    _check(_lib.circuit_add_gate(c.handle, k, q.ctypes.data_as(_ip), q.size,
+                                 _dptr(p) if p.size else None, p.size), "circuit_add_gate")
+
+
+def circuit_from_gates(n_qubits: int, gates) -> Circuit:
+    """Generic circuit from ``workloads.Gate`` tuples (kind, qubits, params)."""
+    c = circuit_create(n_qubits)
+    for g in gates:
+        circuit_add_gate(c, g[0], g[1], g[2])
+    return c
+
+
+def circuit_build_hhl(A, b, clock_bits: int, t: float = 0.0) -> Circuit:
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64).ravel()
+    if A.shape != (b.size, b.size):
+        raise ValueError("A must be dim x dim with dim = len(b)")
+    h = _vp()
+    _check(_lib.circuit_build_hhl(_dptr(A), _dptr(b), b.size, clock_bits, float(t),
+                                  ctypes.byref(h)), "circuit_build_hhl")
+    return Circuit(h.value)
+
+
+def fuse(c: Circuit, k_max: int) -> Circuit:
+    h = _vp()
+    _check(_lib.fuse(c.handle, k_max, ctypes.byref(h)), "fuse")
+    return Circuit(h.value)
+
+
+def sv_qubit_estimate(dim: int, kappa: float, has_negative: bool):
+    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(_lib.sv_qubit_estimate(dim, kappa, int(has_negative), ctypes.byref(a),
+                                  ctypes.byref(b), ctypes.byref(c)), "sv_qubit_estimate")
+    return a.value, b.value, c.value
+
+
+# -------------------------------------------------------------------- states
+class State:
+    """Owning wrapper of an ``sv_state*`` (device state vector + stream)."""
+
+    def __init__(self, handle, n, dtype, keepalive=None):
+        self.handle = _vp(handle)
+        self.n = n
+        self.dtype = DTYPES[dtype]
+        self._keepalive = keepalive
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            _lib.sv_destroy(h)
+            self.handle = _vp()
+
+    def close(self):
+        self.__del__()
+
+    @classmethod
+    def from_tensor(cls, tensor, n_qubits: int, dtype="c128"):
+        """Adopt a torch CUDA tensor's memory (kept alive by the state)."""
+        h = _vp()
+        nbytes = tensor.numel() * tensor.element_size()
+        _check(_lib.sv_create_from_buffer(_vp(tensor.data_ptr()), nbytes, n_qubits,
+                                          DTYPES[dtype], ctypes.byref(h)), "sv_create_from_buffer")
+        return cls(h.value, n_qubits, dtype, keepalive=tensor)
+
+    def set_stream(self, stream=None):
+        """Order work on a torch stream (or a raw hipStream_t integer)."""
+        ptr = getattr(stream, "cuda_stream", stream)
+        _check(_lib.sv_set_stream(self.handle, _vp(ptr) if ptr else None), "sv_set_stream")
+
+    def reset(self):
+        _check(_lib.sv_reset(self.handle), "sv_reset")
+
+    def get(self, offset: int = 0, count: int | None = None) -> np.ndarray:
+        if count is None:
+            count = (1 << self.n) - offset
+        out = np.empty(count, dtype=_amp_dtype(self.dtype))
+        _check(_lib.sv_get_amplitudes(self.handle, offset, count, out.ctypes.data_as(_vp)),
+               "sv_get_amplitudes")
+        return out
+
+    def set(self, values, offset: int = 0):
+        v = np.ascontiguousarray(values, dtype=_amp_dtype(self.dtype))
+        _check(_lib.sv_set_amplitudes(self.handle, offset, v.size, v.ctypes.data_as(_vp)),
+               "sv_set_amplitudes")
+
+    def get_at(self, indices) -> np.ndarray:
+        idx = np.ascontiguousarray(indices, dtype=np.uint64)
+        out = np.empty(idx.size, dtype=_amp_dtype(self.dtype))
+        _check(_lib.sv_get_amplitudes_at(self.handle,
+                                         idx.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                         idx.size, out.ctypes.data_as(_vp)), "sv_get_amplitudes_at")
+        return out
+
+    def norm2(self) -> float:
+        out = ctypes.c_double()
+        _check(_lib.sv_norm2(self.handle, ctypes.byref(out)), "sv_norm2")
+        return out.value
+
+    def apply(self, c: Circuit):
+        _check(_lib.sv_apply(self.handle, c.handle), "sv_apply")
+
+    def apply_timed(self, c: Circuit):
+        """Apply and time every launch: (ms per gate, kernel family per gate)."""
+        ng = c.n_gates
+        ms = np.zeros(max(ng, 1))
+        fam = np.zeros(max(ng, 1), dtype=np.int32)
+        _check(_lib.sv_apply_timed(self.handle, c.handle, _dptr(ms), fam.ctypes.data_as(_ip),
+                                   ms.size), "sv_apply_timed")
+        return ms[:ng], fam[:ng]
+
+    def synchronize(self):
+        _check(_lib.sv_synchronize(self.handle), "sv_synchronize")
+
+    def postselect_solution(self, hhl: Circuit, dim: int):
+        x = np.zeros(dim)
+        info = SolutionInfo()
+        _check(_lib.sv_postselect_solution(self.handle, hhl.handle, _dptr(x), dim,
+                                           ctypes.byref(info)), "sv_postselect_solution")
+        return x, info.as_dict()
+
+
+def sv_create(n_qubits: int, dtype="c128") -> State:
+    h = _vp()
+    _check(_lib.sv_create(n_qubits, DTYPES[dtype], ctypes.byref(h)), "sv_create")
+    return State(h.value, n_qubits, dtype)
+
+
+def sv_apply(s: State, c: Circuit):
+    s.apply(c)
+
+
+def sv_postselect_solution(s: State, hhl: Circuit, dim: int):
+    return s.postselect_solution(hhl, dim)
+
+
+def solve(A, b, clock_bits: int, dtype="c128", k_max: int | None = None, t: float = 0.0):
+    """One HHL solve end to end: build, (fuse), apply, postselect.
+
+    Returns (x, x_hat, solution_info, hhl_info)."""
+    c = circuit_build_hhl(A, b, clock_bits, t)
+    run = fuse(c, k_max) if k_max else c
+    s = sv_create(c.n_qubits, dtype)
+    s.apply(run)
+    x_hat, info = s.postselect_solution(c, len(b))
+    return info["scale"] * x_hat, x_hat, info, c.info()

@@ -1,0 +1,454 @@
+// Circuit IR, its ABI calls, and the gate-fusion pass.
+//
+// Gate fusion follows the idea of Sec. II-C / Fig. 4 (Zheng et al., PESGM
+// 2024): several gates are replaced by one gate, which cuts the number of
+// state-vector sweeps.  The paper's four strategies (1q-1q, 1q into 2q from
+// either side, 2q-2q) are the k_max = 2 case of the greedy pass below, which
+// merges into one dense 2^k x 2^k gate any run of gates whose joint qubit
+// set stays within k_max qubits.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.hpp"
+
+namespace hhlsv {
+
+namespace {
+thread_local std::string g_last_error;
+constexpr double kSqrtHalf = 0.70710678118654752440;
+}  // namespace
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+sv_status fail(sv_status st, const std::string &msg)
+{
+    set_error(msg);
+    return st;
+}
+
+int gate_nparams_named(int kind)
+{
+    switch (kind) {
+    case SV_GATE_H: case SV_GATE_X: case SV_GATE_CX: case SV_GATE_SWAP: return 0;
+    case SV_GATE_RY: case SV_GATE_RZ: case SV_GATE_P: case SV_GATE_CP: return 1;
+    case SV_GATE_U3: return 3;
+    default: return -1;
+    }
+}
+
+bool gate_is_diagonal(int kind)
+{
+    return kind == SV_GATE_RZ || kind == SV_GATE_P || kind == SV_GATE_CP || kind == SV_GATE_DIAG;
+}
+
+static int gate_width(int kind)
+{
+    switch (kind) {
+    case SV_GATE_H: case SV_GATE_X: case SV_GATE_RY: case SV_GATE_RZ:
+    case SV_GATE_P: case SV_GATE_U3: return 1;
+    case SV_GATE_CX: case SV_GATE_CP: case SV_GATE_SWAP: return 2;
+    default: return -1;
+    }
+}
+
+sv_status validate_gate(int n, int kind, const int *qubits, int nq,
+                        const double *params, int nparams)
+{
+    if (kind < SV_GATE_H || kind > SV_GATE_DIAG)
+        return fail(SV_ERR_INVALID, "circuit_add_gate: unknown gate kind");
+    if (nq < 1 || !qubits) return fail(SV_ERR_INVALID, "circuit_add_gate: no qubits");
+    if (nparams < 0 || (nparams > 0 && !params))
+        return fail(SV_ERR_INVALID, "circuit_add_gate: bad params");
+    for (int i = 0; i < nq; ++i) {
+        if (qubits[i] < 0 || qubits[i] >= n) return fail(SV_ERR_INVALID, "circuit_add_gate: qubit out of range");
+        for (int j = 0; j < i; ++j)
+            if (qubits[i] == qubits[j]) return fail(SV_ERR_INVALID, "circuit_add_gate: repeated qubit");
+    }
+    for (int i = 0; i < nparams; ++i)
+        if (!std::isfinite(params[i])) return fail(SV_ERR_INVALID, "circuit_add_gate: non-finite parameter");
+    const int w = gate_width(kind);
+    if (w > 0) {
+        if (nq != w) return fail(SV_ERR_INVALID, "circuit_add_gate: wrong number of qubits for gate kind");
+        if (nparams != gate_nparams_named(kind))
+            return fail(SV_ERR_INVALID, "circuit_add_gate: wrong number of params for gate kind");
+        return SV_OK;
+    }
+    if (kind == SV_GATE_DENSE || kind == SV_GATE_DIAG) {
+        if (nq > kMaxDenseQubits) return fail(SV_ERR_INVALID, "circuit_add_gate: gate wider than 12 qubits");
+        const long need = kind == SV_GATE_DENSE ? 2L << (2 * nq) : 2L << nq;
+        if (nparams != need) return fail(SV_ERR_INVALID, "circuit_add_gate: params must hold the complex matrix");
+        return SV_OK;
+    }
+    if (kind == SV_GATE_CDENSE) {
+        const int k = nq - 1;
+        if (k < 1 || k > kMaxDenseQubits) return fail(SV_ERR_INVALID, "circuit_add_gate: CDENSE needs 1..12 targets");
+        if (nparams != (2L << (2 * k))) return fail(SV_ERR_INVALID, "circuit_add_gate: params must hold the complex matrix");
+        return SV_OK;
+    }
+    // UCRY
+    const int r = nq - 1;
+    if (r > kMaxUcryControls) return fail(SV_ERR_INVALID, "circuit_add_gate: UCRY with more than 20 controls");
+    if (nparams != (1L << r)) return fail(SV_ERR_INVALID, "circuit_add_gate: UCRY needs 2^r angles");
+    return SV_OK;
+}
+
+std::vector<cd> gate_matrix(const Gate &g)
+{
+    const auto &p = g.params;
+    switch (g.kind) {
+    case SV_GATE_H:
+        return {cd(kSqrtHalf, 0), cd(kSqrtHalf, 0), cd(kSqrtHalf, 0), cd(-kSqrtHalf, 0)};
+    case SV_GATE_X:
+        return {0.0, 1.0, 1.0, 0.0};
+    case SV_GATE_RY: {
+        const double c = std::cos(0.5 * p[0]), s = std::sin(0.5 * p[0]);
+        return {c, -s, s, c};
+    }
+    case SV_GATE_U3: {
+        const double c = std::cos(0.5 * p[0]), s = std::sin(0.5 * p[0]);
+        return {cd(c, 0), -std::polar(s, p[2]), std::polar(s, p[1]), std::polar(c, p[1] + p[2])};
+    }
+    case SV_GATE_CX: {  // list (control, target): index r = bit_c + 2 bit_t
+        std::vector<cd> M(16, 0.0);
+        M[0 * 4 + 0] = M[2 * 4 + 2] = 1.0;
+        M[1 * 4 + 3] = M[3 * 4 + 1] = 1.0;
+        return M;
+    }
+    case SV_GATE_SWAP: {
+        std::vector<cd> M(16, 0.0);
+        M[0 * 4 + 0] = M[3 * 4 + 3] = 1.0;
+        M[1 * 4 + 2] = M[2 * 4 + 1] = 1.0;
+        return M;
+    }
+    case SV_GATE_DENSE: {
+        std::vector<cd> M(p.size() / 2);
+        for (size_t i = 0; i < M.size(); ++i) M[i] = cd(p[2 * i], p[2 * i + 1]);
+        return M;
+    }
+    case SV_GATE_CDENSE: {  // block-diag(I, U) over (c, targets): r = bit_c + 2 r_t
+        const int k = (int)g.qubits.size() - 1;
+        const size_t K = (size_t)1 << k, D = 2 * K;
+        std::vector<cd> M(D * D, 0.0);
+        for (size_t r = 0; r < K; ++r) {
+            M[(2 * r) * D + 2 * r] = 1.0;
+            for (size_t c = 0; c < K; ++c)
+                M[(2 * r + 1) * D + (2 * c + 1)] = cd(p[2 * (r * K + c)], p[2 * (r * K + c) + 1]);
+        }
+        return M;
+    }
+    case SV_GATE_UCRY: {  // over (t, c...): r = bit_t + 2 v
+        const int rr = (int)g.qubits.size() - 1;
+        const size_t V = (size_t)1 << rr, D = 2 * V;
+        std::vector<cd> M(D * D, 0.0);
+        for (size_t v = 0; v < V; ++v) {
+            const double c = std::cos(0.5 * p[v]), s = std::sin(0.5 * p[v]);
+            M[(2 * v) * D + 2 * v] = c;
+            M[(2 * v) * D + 2 * v + 1] = -s;
+            M[(2 * v + 1) * D + 2 * v] = s;
+            M[(2 * v + 1) * D + 2 * v + 1] = c;
+        }
+        return M;
+    }
+    default: {  // diagonal kinds
+        std::vector<cd> d = gate_diagonal(g);
+        std::vector<cd> M(d.size() * d.size(), 0.0);
+        for (size_t i = 0; i < d.size(); ++i) M[i * d.size() + i] = d[i];
+        return M;
+    }
+    }
+}
+
+std::vector<cd> gate_diagonal(const Gate &g)
+{
+    const auto &p = g.params;
+    switch (g.kind) {
+    case SV_GATE_RZ: return {std::polar(1.0, -0.5 * p[0]), std::polar(1.0, 0.5 * p[0])};
+    case SV_GATE_P: return {1.0, std::polar(1.0, p[0])};
+    case SV_GATE_CP: return {1.0, 1.0, 1.0, std::polar(1.0, p[0])};
+    case SV_GATE_DIAG: {
+        std::vector<cd> d(p.size() / 2);
+        for (size_t i = 0; i < d.size(); ++i) d[i] = cd(p[2 * i], p[2 * i + 1]);
+        return d;
+    }
+    default: return {};
+    }
+}
+
+namespace {
+
+// ---------------------------------------------------------------- fusion --
+struct Block {
+    std::vector<int> qubits;     // sorted
+    std::vector<cd> M;           // dense: 2^k x 2^k over sorted qubits
+    bool diag = true;
+    bool open = true;            // false: a gate too wide to fuse, kept as is
+    bool alive = true;
+    Gate orig;                   // for closed blocks
+};
+
+// Embed a matrix over qubit list gq (index sum_l bit(gq_l) 2^l) into the
+// sorted qubit set U: identity on U \ gq.
+std::vector<cd> embed(const std::vector<cd> &G, const std::vector<int> &gq,
+                      const std::vector<int> &U)
+{
+    const int u = (int)U.size();
+    const size_t D = (size_t)1 << u;
+    const size_t K = (size_t)1 << gq.size();
+    std::vector<int> pos(gq.size());
+    size_t gmask = 0;
+    for (size_t l = 0; l < gq.size(); ++l) {
+        pos[l] = (int)(std::find(U.begin(), U.end(), gq[l]) - U.begin());
+        gmask |= (size_t)1 << pos[l];
+    }
+    auto sub = [&](size_t R) {
+        size_t r = 0;
+        for (size_t l = 0; l < gq.size(); ++l) r |= ((R >> pos[l]) & 1) << l;
+        return r;
+    };
+    std::vector<cd> E(D * D, 0.0);
+    for (size_t R = 0; R < D; ++R)
+        for (size_t Cc = 0; Cc < D; ++Cc)
+            if ((R & ~gmask) == (Cc & ~gmask)) E[R * D + Cc] = G[sub(R) * K + sub(Cc)];
+    return E;
+}
+
+std::vector<cd> matmul(const std::vector<cd> &A, const std::vector<cd> &B, size_t D)
+{
+    std::vector<cd> C(D * D, 0.0);
+    for (size_t i = 0; i < D; ++i)
+        for (size_t k = 0; k < D; ++k) {
+            const cd a = A[i * D + k];
+            if (a == cd(0.0, 0.0)) continue;
+            for (size_t j = 0; j < D; ++j) C[i * D + j] += a * B[k * D + j];
+        }
+    return C;
+}
+
+std::vector<int> unite(const std::vector<int> &a, const std::vector<int> &b)
+{
+    std::vector<int> u = a;
+    u.insert(u.end(), b.begin(), b.end());
+    std::sort(u.begin(), u.end());
+    u.erase(std::unique(u.begin(), u.end()), u.end());
+    return u;
+}
+
+int fused_width(const Gate &g)
+{
+    return (int)g.qubits.size();
+}
+
+}  // namespace
+
+}  // namespace hhlsv
+
+using namespace hhlsv;
+
+extern "C" const char *sv_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" sv_status circuit_create(int n_qubits, sv_circuit **out)
+{
+    if (!out) return fail(SV_ERR_INVALID, "circuit_create: out is NULL");
+    *out = nullptr;
+    if (n_qubits < 1 || n_qubits > kMaxQubits) return fail(SV_ERR_INVALID, "circuit_create: n must be in [1, 34]");
+    auto *c = new (std::nothrow) sv_circuit;
+    if (!c) return fail(SV_ERR_OOM, "circuit_create: out of host memory");
+    c->c.n = n_qubits;
+    *out = c;
+    return SV_OK;
+}
+
+extern "C" sv_status circuit_add_gate(sv_circuit *c, int kind, const int *qubits, int nq,
+                                      const double *params, int nparams)
+{
+    if (!c) return fail(SV_ERR_INVALID, "circuit_add_gate: circuit is NULL");
+    sv_status st = validate_gate(c->c.n, kind, qubits, nq, params, nparams);
+    if (st != SV_OK) return st;
+    {
+        std::lock_guard<std::mutex> lk(c->c.dev_mu);
+        if (!c->c.dev.empty())
+            return fail(SV_ERR_INVALID, "circuit_add_gate: circuit already applied; it is read-only now");
+    }
+    Gate g;
+    g.kind = kind;
+    g.qubits.assign(qubits, qubits + nq);
+    if (nparams) g.params.assign(params, params + nparams);
+    c->c.gates.push_back(std::move(g));
+    return SV_OK;
+}
+
+extern "C" sv_status circuit_info(const sv_circuit *c, sv_hhl_info *out)
+{
+    if (!c || !out) return fail(SV_ERR_INVALID, "circuit_info: NULL argument");
+    std::memset(out, 0, sizeof(*out));
+    const HHLParams &h = c->c.hhl;
+    out->n_total = c->c.n;
+    out->n_gates = (int)c->c.gates.size();
+    if (h.is_hhl) {
+        out->n_sys = h.ns;
+        out->n_clock = h.m;
+        out->n_qpe_est = h.n_qpe_est;
+        out->dim = h.dim;
+        out->j0 = h.j0;
+        out->t = h.t;
+        out->C = h.C;
+        out->lambda_lo = h.lambda_lo;
+        out->lambda_hi = h.lambda_hi;
+        out->kappa = h.kappa;
+        out->b_norm = h.b_norm;
+    }
+    return SV_OK;
+}
+
+extern "C" sv_status circuit_shape(const sv_circuit *c, int *n_qubits, int *n_gates)
+{
+    if (!c) return fail(SV_ERR_INVALID, "circuit_shape: NULL circuit");
+    if (n_qubits) *n_qubits = c->c.n;
+    if (n_gates) *n_gates = (int)c->c.gates.size();
+    return SV_OK;
+}
+
+extern "C" sv_status circuit_serialize(const sv_circuit *c, void *buf, size_t *len)
+{
+    if (!c || !len) return fail(SV_ERR_INVALID, "circuit_serialize: NULL argument");
+    size_t need = 8;
+    for (const auto &g : c->c.gates) need += 12 + 4 * g.qubits.size() + 8 * g.params.size();
+    if (!buf) {
+        *len = need;
+        return SV_OK;
+    }
+    if (*len < need) {
+        *len = need;
+        return fail(SV_ERR_INVALID, "circuit_serialize: buffer too small");
+    }
+    char *p = static_cast<char *>(buf);
+    auto put32 = [&](int32_t v) { std::memcpy(p, &v, 4); p += 4; };
+    put32(c->c.n);
+    put32((int32_t)c->c.gates.size());
+    for (const auto &g : c->c.gates) {
+        put32(g.kind);
+        put32((int32_t)g.qubits.size());
+        put32((int32_t)g.params.size());
+        for (int q : g.qubits) put32(q);
+        std::memcpy(p, g.params.data(), 8 * g.params.size());
+        p += 8 * g.params.size();
+    }
+    *len = need;
+    return SV_OK;
+}
+
+extern "C" sv_status fuse(const sv_circuit *in, int k_max, sv_circuit **out)
+{
+    if (!in || !out) return fail(SV_ERR_INVALID, "fuse: NULL argument");
+    *out = nullptr;
+    if (k_max < 1 || k_max > 5) return fail(SV_ERR_INVALID, "fuse: k_max must be in [1, 5]");
+    const int n = in->c.n;
+    std::vector<Block> blocks;
+    blocks.reserve(in->c.gates.size());
+    std::vector<int> last(n, -1);
+
+    for (const Gate &g : in->c.gates) {
+        const int w = fused_width(g);
+        if (w > k_max) {
+            Block b;
+            b.qubits = g.qubits;
+            std::sort(b.qubits.begin(), b.qubits.end());
+            b.open = false;
+            b.diag = false;
+            b.orig = g;
+            blocks.push_back(std::move(b));
+            for (int q : g.qubits) last[q] = (int)blocks.size() - 1;
+            continue;
+        }
+        std::vector<int> S = g.qubits;
+        std::sort(S.begin(), S.end());
+        // Candidate blocks: open blocks that are the last block on every one
+        // of their qubits and on at least one qubit of g.  Such a block can
+        // move past everything after it, so it may be merged with g.
+        std::vector<int> cand;
+        for (int q : S) {
+            const int bi = last[q];
+            if (bi < 0 || !blocks[bi].open) continue;
+            if (std::find(cand.begin(), cand.end(), bi) != cand.end()) continue;
+            bool frontier = true;
+            for (int bq : blocks[bi].qubits) frontier = frontier && last[bq] == bi;
+            if (frontier) cand.push_back(bi);
+        }
+        std::vector<int> chosen;
+        {
+            std::vector<int> U = S;
+            for (int bi : cand) U = unite(U, blocks[bi].qubits);
+            if ((int)U.size() <= k_max) {
+                chosen = cand;
+            } else {
+                int best = -1;
+                size_t best_w = 0;
+                for (int bi : cand) {
+                    const auto u = unite(S, blocks[bi].qubits);
+                    if ((int)u.size() <= k_max && u.size() > best_w) {
+                        best = bi;
+                        best_w = u.size();
+                    }
+                }
+                if (best >= 0) chosen.push_back(best);
+            }
+        }
+        Block nb;
+        nb.qubits = S;
+        for (int bi : chosen) nb.qubits = unite(nb.qubits, blocks[bi].qubits);
+        const size_t D = (size_t)1 << nb.qubits.size();
+        std::vector<cd> M(D * D, 0.0);
+        for (size_t i = 0; i < D; ++i) M[i * D + i] = 1.0;
+        nb.diag = gate_is_diagonal(g.kind);
+        for (int bi : chosen) {  // disjoint, so their order does not matter
+            M = matmul(embed(blocks[bi].M, blocks[bi].qubits, nb.qubits), M, D);
+            nb.diag = nb.diag && blocks[bi].diag;
+            blocks[bi].alive = false;
+        }
+        M = matmul(embed(gate_matrix(g), g.qubits, nb.qubits), M, D);
+        nb.M = std::move(M);
+        blocks.push_back(std::move(nb));
+        for (int q : blocks.back().qubits) last[q] = (int)blocks.size() - 1;
+    }
+
+    auto *oc = new (std::nothrow) sv_circuit;
+    if (!oc) return fail(SV_ERR_OOM, "fuse: out of host memory");
+    oc->c.n = n;
+    oc->c.hhl = in->c.hhl;
+    for (auto &b : blocks) {
+        if (!b.alive) continue;
+        if (!b.open) {
+            oc->c.gates.push_back(b.orig);
+            continue;
+        }
+        Gate g;
+        g.qubits = b.qubits;
+        const size_t D = (size_t)1 << b.qubits.size();
+        if (b.diag) {
+            g.kind = SV_GATE_DIAG;
+            g.params.resize(2 * D);
+            for (size_t i = 0; i < D; ++i) {
+                g.params[2 * i] = b.M[i * D + i].real();
+                g.params[2 * i + 1] = b.M[i * D + i].imag();
+            }
+        } else {
+            g.kind = SV_GATE_DENSE;
+            g.params.resize(2 * D * D);
+            for (size_t i = 0; i < D * D; ++i) {
+                g.params[2 * i] = b.M[i].real();
+                g.params[2 * i + 1] = b.M[i].imag();
+            }
+        }
+        oc->c.gates.push_back(std::move(g));
+    }
+    *out = oc;
+    return SV_OK;
+}
+
+extern "C" sv_status circuit_destroy(sv_circuit *c)
+{
+    delete c;
+    return SV_OK;
+}

@@ -1,0 +1,295 @@
+// State-vector runtime: device state objects, circuit application on a HIP
+// stream, and the postselected readout of Sec. III-A steps 3-4 (Zheng et al.,
+// PESGM 2024): the simulator reads the state vector directly and recovers x.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "kernels.hpp"
+
+using namespace hhlsv;
+
+struct sv_state {
+    int n = 0;
+    sv_dtype dtype = SV_C128;
+    int device = 0;
+    void *psi = nullptr;
+    bool owns = true;
+    hipStream_t own_stream = nullptr;
+    hipStream_t stream = nullptr;
+    double *scratch = nullptr;   // kReducePartials partials + 1 result
+};
+
+#define HIPCK(x)                                                                   \
+    do {                                                                           \
+        hipError_t e_ = (x);                                                       \
+        if (e_ != hipSuccess)                                                      \
+            return fail(SV_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+namespace {
+
+sv_status make_state(int n, sv_dtype dtype, void *buf, size_t bytes, sv_state **out)
+{
+    if (!out) return fail(SV_ERR_INVALID, "sv_create: out is NULL");
+    *out = nullptr;
+    if (n < 1 || n > kMaxQubits) return fail(SV_ERR_INVALID, "sv_create: n must be in [1, 34]");
+    if (dtype != SV_C128 && dtype != SV_C64) return fail(SV_ERR_INVALID, "sv_create: bad dtype");
+    const size_t need = amp_bytes(dtype) << n;
+    if (buf && bytes < need) return fail(SV_ERR_INVALID, "sv_create_from_buffer: buffer smaller than 2^n amplitudes");
+    auto *s = new (std::nothrow) sv_state;
+    if (!s) return fail(SV_ERR_OOM, "sv_create: out of host memory");
+    s->n = n;
+    s->dtype = dtype;
+    hipError_t e = hipGetDevice(&s->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->own_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete s;
+        return fail(SV_ERR_HIP, std::string("sv_create: ") + hipGetErrorString(e));
+    }
+    s->stream = s->own_stream;
+    e = hipMalloc(&s->scratch, sizeof(double) * (kReducePartials + 8));
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(s->own_stream);
+        delete s;
+        return fail(SV_ERR_OOM, std::string("sv_create: scratch allocation: ") + hipGetErrorString(e));
+    }
+    if (buf) {
+        s->psi = buf;
+        s->owns = false;
+    } else {
+        e = hipMalloc(&s->psi, need);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipFree(s->scratch);
+            (void)hipStreamDestroy(s->own_stream);
+            delete s;
+            return fail(e == hipErrorOutOfMemory ? SV_ERR_OOM : SV_ERR_HIP,
+                        std::string("sv_create: state allocation of ") + std::to_string(need) +
+                            " bytes: " + hipGetErrorString(e));
+        }
+        sv_status st = launch_init_zero_state(s->psi, n, dtype, s->stream);
+        if (st != SV_OK) {
+            (void)hipFree(s->psi);
+            (void)hipFree(s->scratch);
+            (void)hipStreamDestroy(s->own_stream);
+            delete s;
+            return st;
+        }
+    }
+    *out = s;
+    return SV_OK;
+}
+
+}  // namespace
+
+extern "C" sv_status sv_create(int n_qubits, sv_dtype dtype, sv_state **out)
+{
+    return make_state(n_qubits, dtype, nullptr, 0, out);
+}
+
+extern "C" sv_status sv_create_from_buffer(void *dev_ptr, size_t bytes, int n_qubits,
+                                           sv_dtype dtype, sv_state **out)
+{
+    if (!dev_ptr) return fail(SV_ERR_INVALID, "sv_create_from_buffer: NULL buffer");
+    return make_state(n_qubits, dtype, dev_ptr, bytes, out);
+}
+
+extern "C" sv_status sv_set_stream(sv_state *s, void *hip_stream)
+{
+    if (!s) return fail(SV_ERR_INVALID, "sv_set_stream: NULL state");
+    s->stream = hip_stream ? static_cast<hipStream_t>(hip_stream) : s->own_stream;
+    return SV_OK;
+}
+
+extern "C" sv_status sv_destroy(sv_state *s)
+{
+    if (!s) return SV_OK;
+    (void)hipStreamSynchronize(s->stream);
+    if (s->owns && s->psi) (void)hipFree(s->psi);
+    if (s->scratch) (void)hipFree(s->scratch);
+    if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
+    delete s;
+    return SV_OK;
+}
+
+extern "C" sv_status sv_reset(sv_state *s)
+{
+    if (!s) return fail(SV_ERR_INVALID, "sv_reset: NULL state");
+    return launch_init_zero_state(s->psi, s->n, s->dtype, s->stream);
+}
+
+extern "C" sv_status sv_get_amplitudes(const sv_state *s, size_t offset, size_t count, void *host_out)
+{
+    if (!s || (!host_out && count)) return fail(SV_ERR_INVALID, "sv_get_amplitudes: NULL argument");
+    const size_t namps = size_t(1) << s->n;
+    if (offset > namps || count > namps - offset) return fail(SV_ERR_INVALID, "sv_get_amplitudes: range out of bounds");
+    if (!count) return SV_OK;
+    const size_t ab = amp_bytes(s->dtype);
+    HIPCK(hipMemcpyAsync(host_out, static_cast<char *>(s->psi) + offset * ab, count * ab,
+                         hipMemcpyDeviceToHost, s->stream));
+    HIPCK(hipStreamSynchronize(s->stream));
+    return SV_OK;
+}
+
+extern "C" sv_status sv_set_amplitudes(sv_state *s, size_t offset, size_t count, const void *host_in)
+{
+    if (!s || (!host_in && count)) return fail(SV_ERR_INVALID, "sv_set_amplitudes: NULL argument");
+    const size_t namps = size_t(1) << s->n;
+    if (offset > namps || count > namps - offset) return fail(SV_ERR_INVALID, "sv_set_amplitudes: range out of bounds");
+    if (!count) return SV_OK;
+    const size_t ab = amp_bytes(s->dtype);
+    HIPCK(hipMemcpyAsync(static_cast<char *>(s->psi) + offset * ab, host_in, count * ab,
+                         hipMemcpyHostToDevice, s->stream));
+    HIPCK(hipStreamSynchronize(s->stream));
+    return SV_OK;
+}
+
+extern "C" sv_status sv_get_amplitudes_at(const sv_state *s, const uint64_t *indices, size_t count,
+                                          void *host_out)
+{
+    if (!s || (count && (!indices || !host_out))) return fail(SV_ERR_INVALID, "sv_get_amplitudes_at: NULL argument");
+    if (!count) return SV_OK;
+    const uint64_t namps = uint64_t(1) << s->n;
+    for (size_t i = 0; i < count; ++i)
+        if (indices[i] >= namps) return fail(SV_ERR_INVALID, "sv_get_amplitudes_at: index out of range");
+    const size_t ab = amp_bytes(s->dtype);
+    void *d_idx = nullptr, *d_out = nullptr;
+    HIPCK(hipMalloc(&d_idx, count * sizeof(uint64_t)));
+    hipError_t e = hipMalloc(&d_out, count * ab);
+    if (e != hipSuccess) {
+        (void)hipFree(d_idx);
+        return fail(SV_ERR_HIP, std::string("sv_get_amplitudes_at: ") + hipGetErrorString(e));
+    }
+    sv_status st = SV_OK;
+    e = hipMemcpyAsync(d_idx, indices, count * sizeof(uint64_t), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) {
+        st = launch_gather(s->psi, static_cast<const uint64_t *>(d_idx), count, d_out, s->dtype, s->stream);
+        if (st == SV_OK) e = hipMemcpyAsync(host_out, d_out, count * ab, hipMemcpyDeviceToHost, s->stream);
+        if (st == SV_OK && e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    }
+    (void)hipStreamSynchronize(s->stream);
+    (void)hipFree(d_idx);
+    (void)hipFree(d_out);
+    if (st != SV_OK) return st;
+    if (e != hipSuccess) return fail(SV_ERR_HIP, std::string("sv_get_amplitudes_at: ") + hipGetErrorString(e));
+    return SV_OK;
+}
+
+static sv_status range_norm2(const sv_state *s, uint64_t lo, uint64_t hi, double *out)
+{
+    sv_status st = launch_norm2_range(s->psi, lo, hi, s->dtype, s->scratch, s->scratch + kReducePartials, s->stream);
+    if (st != SV_OK) return st;
+    HIPCK(hipMemcpyAsync(out, s->scratch + kReducePartials, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCK(hipStreamSynchronize(s->stream));
+    return SV_OK;
+}
+
+extern "C" sv_status sv_norm2(const sv_state *s, double *out)
+{
+    if (!s || !out) return fail(SV_ERR_INVALID, "sv_norm2: NULL argument");
+    return range_norm2(s, 0, uint64_t(1) << s->n, out);
+}
+
+static sv_status apply_impl(sv_state *s, const sv_circuit *c, double *launch_ms, int *kernel_ids, int cap)
+{
+    if (!s || !c) return fail(SV_ERR_INVALID, "sv_apply: NULL argument");
+    if (c->c.n != s->n) return fail(SV_ERR_SHAPE, "sv_apply: circuit and state have different qubit counts");
+    if (launch_ms && cap < (int)c->c.gates.size()) return fail(SV_ERR_INVALID, "sv_apply_timed: cap < number of gates");
+    sv_status st = SV_OK;
+    DeviceProgram *prog = get_device_program(c->c, s->dtype, &st);
+    if (!prog) return st;
+    if (!launch_ms) {
+        for (const DevOp &op : prog->ops) {
+            st = launch_op(op, *prog, s->psi, s->n, s->dtype, s->stream);
+            if (st != SV_OK) return st;
+        }
+        return SV_OK;
+    }
+    const size_t ng = prog->ops.size();
+    std::vector<hipEvent_t> ev(ng + 1);
+    for (auto &e : ev) HIPCK(hipEventCreate(&e));
+    HIPCK(hipEventRecord(ev[0], s->stream));
+    for (size_t g = 0; g < ng; ++g) {
+        int fam = -1;
+        st = launch_op(prog->ops[g], *prog, s->psi, s->n, s->dtype, s->stream, &fam);
+        if (st != SV_OK) break;
+        if (kernel_ids) kernel_ids[g] = fam;
+        HIPCK(hipEventRecord(ev[g + 1], s->stream));
+    }
+    if (st == SV_OK) {
+        HIPCK(hipEventSynchronize(ev[ng]));
+        for (size_t g = 0; g < ng; ++g) {
+            float ms = 0.f;
+            HIPCK(hipEventElapsedTime(&ms, ev[g], ev[g + 1]));
+            launch_ms[g] = ms;
+        }
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    return st;
+}
+
+extern "C" sv_status sv_apply(sv_state *s, const sv_circuit *c) { return apply_impl(s, c, nullptr, nullptr, 0); }
+
+extern "C" sv_status sv_apply_timed(sv_state *s, const sv_circuit *c, double *launch_ms, int *kernel_ids,
+                                    int cap)
+{
+    if (!launch_ms) return fail(SV_ERR_INVALID, "sv_apply_timed: launch_ms is NULL");
+    return apply_impl(s, c, launch_ms, kernel_ids, cap);
+}
+
+extern "C" sv_status sv_synchronize(sv_state *s)
+{
+    if (!s) return fail(SV_ERR_INVALID, "sv_synchronize: NULL state");
+    HIPCK(hipStreamSynchronize(s->stream));
+    return SV_OK;
+}
+
+extern "C" sv_status sv_postselect_solution(sv_state *s, const sv_circuit *hhl, double *x_hat, int dim,
+                                            sv_solution_info *info)
+{
+    if (!s || !hhl || !x_hat) return fail(SV_ERR_INVALID, "sv_postselect_solution: NULL argument");
+    const HHLParams &h = hhl->c.hhl;
+    if (!h.is_hhl) return fail(SV_ERR_INVALID, "sv_postselect_solution: not an HHL circuit");
+    if (hhl->c.n != s->n) return fail(SV_ERR_SHAPE, "sv_postselect_solution: circuit and state differ in size");
+    if (dim != h.dim) return fail(SV_ERR_SHAPE, "sv_postselect_solution: dim differs from the circuit's");
+    const int n = s->n;
+    const uint64_t base = uint64_t(1) << (n - 1);
+    const size_t D = size_t(1) << h.ns;
+    // P(ancilla = 1): device reduction in double.
+    double p1 = 0.0;
+    sv_status st = range_norm2(s, base, uint64_t(1) << n, &p1);
+    if (st != SV_OK) return st;
+    // y_s = psi[2^{n-1} + s]: the ancilla-1, clock-0 block.
+    std::vector<double> y(2 * D);
+    if (s->dtype == SV_C128) {
+        st = sv_get_amplitudes(s, base, D, y.data());
+    } else {
+        std::vector<float> yf(2 * D);
+        st = sv_get_amplitudes(s, base, D, yf.data());
+        for (size_t i = 0; i < 2 * D; ++i) y[i] = yf[i];
+    }
+    if (st != SV_OK) return st;
+    double p10 = 0.0, max_imag = 0.0, leak = 0.0, re2 = 0.0;
+    for (size_t i = 0; i < D; ++i) {
+        const double re = y[2 * i], im = y[2 * i + 1];
+        p10 += re * re + im * im;
+        max_imag = std::max(max_imag, std::fabs(im));
+        if ((int)i >= dim)
+            leak += re * re + im * im;
+        else
+            re2 += re * re;
+    }
+    const double rn = std::sqrt(re2);
+    for (int i = 0; i < dim; ++i) x_hat[i] = rn > 0.0 ? y[2 * i] / rn : 0.0;
+    if (info) {
+        // Step 4: the |1> amplitude of eigen-component i is C b_i / lambda_i,
+        // so x = ||b|| Re(y) / C.
+        info->scale = h.b_norm * rn / h.C;
+        info->p_anc1 = p1;
+        info->p_anc1_clock0 = p10;
+        info->max_imag = max_imag;
+        info->pad_leak = std::sqrt(leak);
+    }
+    return SV_OK;
+}

@@ -1,0 +1,222 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle, on the
+same seeded inputs, element by element over the full state.
+
+Bars: complex128 max |delta amplitude| <= 1e-12, complex64 <= 2e-5.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-12, "c64": 2e-5}
+
+
+def _hs():
+    import paper_2402_08136_amd as hs
+    return hs
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(n, gates, psi0, dtype, k=None):
+    hs = _hs()
+    c = hs.circuit_from_gates(n, gates)
+    run = hs.fuse(c, k) if k else c
+    s = hs.sv_create(n, dtype)
+    s.set(psi0)
+    s.apply(run)
+    out = s.get()
+    s.close()
+    return out
+
+
+# ------------------------------------------------------ random circuits ---
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,seed", [(1, 0), (3, 1), (5, 2), (7, 3), (11, 4), (13, 5)])
+@pytest.mark.parametrize("k", [None, 1, 2, 3, 4, 5])
+def test_random_circuit_parity(n, seed, k, dtype):
+    _say(f"random circuit n={n} seed={seed} k={k} dtype={dtype}")
+    gates = W.random_circuit(n, 40, seed, kmax=min(5, n))
+    psi0 = W.random_state(n, seed)
+    want = oracle.apply_circuit(psi0, n, gates)
+    got = run_gpu(n, gates, psi0, dtype, k if k is None or k <= n else n)
+    assert np.max(np.abs(got - want)) <= TOL[dtype]
+
+
+# ----------------------------------------- tiled kernel target patterns ---
+def _targets(pattern, k, n, rng):
+    if pattern == "low":
+        return sorted(rng.choice(6, size=k, replace=False).tolist())
+    if pattern == "high":
+        return sorted(rng.choice(np.arange(6, n), size=k, replace=False).tolist())
+    if pattern == "adjacent":
+        q0 = int(rng.integers(0, n - k + 1))
+        return list(range(q0, q0 + k))
+    if pattern == "spread":
+        return sorted(set(np.linspace(0, n - 1, k).astype(int).tolist()))
+    # mixed: at least one low and one high
+    lo = rng.choice(6, size=max(1, k // 2), replace=False).tolist()
+    hi = rng.choice(np.arange(6, n), size=k - len(lo), replace=False).tolist()
+    return sorted(lo + hi)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("pattern", ["low", "high", "mixed", "adjacent", "spread"])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("n", [12, 15])
+def test_dense_gate_target_patterns(n, k, pattern, dtype):
+    rng = np.random.default_rng(1000 * n + 10 * k + len(pattern))
+    qs = _targets(pattern, k, n, rng)
+    if pattern == "mixed" and k == 1:
+        qs = [int(rng.integers(0, n))]
+    kk = len(qs)
+    U = W.random_unitary(1 << kk, rng)
+    # shuffle the qubit list so the matrix index order is not the sorted order
+    perm = rng.permutation(kk)
+    qs_list = [qs[i] for i in perm]
+    g = W.Gate("dense", tuple(qs_list), np.ascontiguousarray(U).view(np.float64).ravel())
+    _say(f"dense n={n} targets={qs_list} dtype={dtype}")
+    psi0 = W.random_state(n, int(rng.integers(1 << 30)))
+    want = oracle.apply_circuit(psi0, n, [g])
+    got = run_gpu(n, [g], psi0, dtype)
+    assert np.max(np.abs(got - want)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("k", [1, 3, 7, 12])
+def test_diagonal_gate(k, dtype):
+    n = 14
+    rng = np.random.default_rng(k)
+    qs = rng.choice(n, size=k, replace=False).tolist()
+    d = np.exp(1j * rng.uniform(0, 2 * np.pi, 1 << k))
+    g = W.Gate("dense", tuple(qs), np.ascontiguousarray(np.diag(d)).view(np.float64).ravel()) \
+        if k <= 5 else None
+    gd = W.Gate("diag", tuple(qs), np.ascontiguousarray(d).view(np.float64).ravel())
+    psi0 = W.random_state(n, k)
+    hs = _hs()
+    c = hs.circuit_create(n)
+    hs.circuit_add_gate(c, "diag", qs, gd.params)
+    s = hs.sv_create(n, dtype)
+    s.set(psi0)
+    s.apply(c)
+    got = s.get()
+    ref = psi0.copy()
+    idx = np.arange(1 << n)
+    v = np.zeros(1 << n, dtype=np.int64)
+    for j, q in enumerate(qs):
+        v |= ((idx >> q) & 1) << j
+    ref = ref * d[v]
+    assert np.max(np.abs(got - ref)) <= TOL[dtype]
+    if g is not None:
+        want = oracle.apply_circuit(psi0, n, [g])
+        assert np.max(np.abs(want - ref)) < 1e-14
+
+
+# --------------------------------------------- HHL-shaped wide gates ---
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("ns,m,seed", [(1, 3, 0), (2, 4, 1), (4, 5, 2), (5, 6, 3), (6, 6, 4), (8, 4, 5)])
+def test_wide_gate_circuit(ns, m, seed, dtype):
+    n = ns + m + 1
+    _say(f"wide-gate circuit ns={ns} m={m} dtype={dtype}")
+    gates = W.wide_gate_circuit(ns, m, seed)
+    psi0 = W.random_state(n, seed)
+    want = oracle.apply_circuit(psi0, n, gates)
+    for k in (None, 2, 5):
+        got = run_gpu(n, gates, psi0, dtype, k)
+        assert np.max(np.abs(got - want)) <= TOL[dtype], k
+
+
+# -------------------------------------------------------- HHL solves ---
+@pytest.mark.parametrize("seed", range(100))
+def test_hhl_4bus_unfused_c128(seed):
+    """4-bus DC power flow, 2 system + 4 clock + 1 ancilla qubits, unfused."""
+    hs = _hs()
+    A, b = W.dc_powerflow(4, seed)
+    psi_ref, x_ref, xh_ref, info_ref = oracle.hhl_solve(A, b, 4)
+    c = hs.circuit_build_hhl(A, b, 4)
+    s = hs.sv_create(c.n_qubits, "c128")
+    s.apply(c)
+    psi = s.get()
+    x_hat, info = s.postselect_solution(c, 3)
+    assert np.max(np.abs(psi - psi_ref)) <= 1e-12
+    assert np.max(np.abs(x_hat - xh_ref)) <= 1e-12
+    assert abs(info["p_anc1"] - info_ref["p1"]) <= 1e-12
+    assert abs(info["p_anc1_clock0"] - info_ref["p10"]) <= 1e-12
+    xs = oracle.ge_solve(A, b)
+    fid = float(np.dot(x_hat, xs / np.linalg.norm(xs)) ** 2)
+    _say(f"seed={seed} kappa={info_ref['kappa']:.2f} fidelity={fid:.6f}")
+    assert fid > 0.5
+
+
+# Level-B tolerance for the 64-bus, 10-clock-qubit case: the two sides build
+# e^{iAt 2^j} from different eigen-solvers, and a phase error
+# t 2^j |dlambda| ~ 2 pi 2^9 (few eps) propagates into every amplitude.
+HHL64_TOL = {"c128": 1e-10, "c64": 2e-5}
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("k", [None, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_hhl_64bus(seed, k, dtype):
+    hs = _hs()
+    A, b = W.dc_powerflow(64, seed)
+    psi_ref, x_ref, xh_ref, info_ref = oracle.hhl_solve(A, b, 10)
+    c = hs.circuit_build_hhl(A, b, 10)
+    run = hs.fuse(c, k) if k else c
+    s = hs.sv_create(c.n_qubits, dtype)
+    s.apply(run)
+    psi = s.get()
+    x_hat, info = s.postselect_solution(c, 63)
+    err = float(np.max(np.abs(psi - psi_ref)))
+    fid = float(np.dot(x_hat, xh_ref) ** 2)
+    _say(f"64-bus seed={seed} k={k} {dtype}: max|d amp|={err:.3e} fid_vs_oracle={fid:.12f} "
+         f"gates={run.n_gates}")
+    assert err <= HHL64_TOL[dtype]
+    assert fid >= 0.999
+
+
+def test_exact_spectrum_gpu():
+    hs = _hs()
+    A, b, t, _ = W.exact_spectrum_system(3, 6, 11)
+    c = hs.circuit_build_hhl(A, b, 6, t)
+    s = hs.sv_create(c.n_qubits, "c128")
+    s.apply(hs.fuse(c, 4))
+    x_hat, info = s.postselect_solution(c, b.size)
+    xs = np.linalg.solve(A, b)
+    assert np.linalg.norm(info["scale"] * x_hat - xs) <= 1e-11 * np.linalg.norm(xs)
+
+
+# ---------------------------------------------------- state utilities ---
+def test_norm_gather_reset():
+    hs = _hs()
+    n = 16
+    psi0 = W.random_state(n, 3)
+    s = hs.sv_create(n, "c128")
+    assert abs(s.norm2() - 1.0) < 1e-15 and s.get_at([0])[0] == 1
+    s.set(psi0)
+    assert abs(s.norm2() - 1.0) < 1e-13
+    idx = np.array([0, 5, (1 << n) - 1, 12345])
+    assert np.max(np.abs(s.get_at(idx) - psi0[idx])) == 0
+    s.reset()
+    out = s.get()
+    assert out[0] == 1 and np.count_nonzero(out) == 1
+
+
+def test_errors_on_gpu_calls():
+    hs = _hs()
+    s = hs.sv_create(5, "c128")
+    c = hs.circuit_create(6)
+    with pytest.raises(hs.HHLSVError, match="SHAPE"):
+        s.apply(c)
+    with pytest.raises(hs.HHLSVError, match="INVALID"):
+        s.get_at([1 << 5])
+    with pytest.raises(hs.HHLSVError, match="INVALID"):
+        s.get(30, 10)

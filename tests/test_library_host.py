@@ -1,0 +1,257 @@
+"""CPU tests of libhhlsv's host side: exported symbols, the HHL circuit
+builder, the fusion pass and input validation.  No GPU call is made; circuits
+are evaluated with the numpy tensor helpers of tests/_ref.py.
+"""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+import paper_2402_08136_amd as hs
+import workloads as W
+from tests._ref import apply_tensor, apply_ucry_tensor, cmat, max_abs_diff
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names += re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", txt, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _header_functions()
+    assert "sv_create" in names and "fuse" in names
+    for nm in names:
+        assert hasattr(hs._lib, nm), f"{nm} declared in include/ but not exported"
+
+
+# ------------------------------------------------------- numpy evaluation ---
+def _np_apply_gate(psi, n, kind, qs, ps):
+    if kind in ("dense",):
+        return apply_tensor(psi, n, qs, cmat(ps, len(qs)))
+    if kind == "diag":
+        return apply_tensor(psi, n, qs, np.diag(np.asarray(ps).view(np.complex128)))
+    if kind == "cdense":
+        return apply_tensor(psi, n, qs[1:], cmat(ps, len(qs) - 1), control=qs[0])
+    if kind == "ucry":
+        return apply_ucry_tensor(psi, n, qs[0], qs[1:], ps)
+    return apply_tensor(psi, n, qs, oracle.gate_matrix(kind, ps))
+
+
+def np_run(circ: hs.Circuit, psi):
+    n = circ.n_qubits
+    for kind, qs, ps in circ.gates():
+        psi = _np_apply_gate(psi, n, kind, qs, ps)
+    return psi
+
+
+# ------------------------------------------------------------ HHL builder ---
+@pytest.mark.parametrize("ns,m", [(2, 4), (6, 10), (3, 7)])
+def test_hhl_gate_count(ns, m):
+    A, b = W.dc_powerflow(1 << ns, 5)
+    c = hs.circuit_build_hhl(A, b, m)
+    assert c.n_qubits == ns + m + 1
+    assert c.n_gates == ns + 6 * m + m * (m - 1) + 2 * (m // 2) + 1
+
+
+@pytest.mark.parametrize("nbus,m,seed", [(4, 4, 0), (16, 7, 1), (64, 10, 2), (4, 4, 14)])
+def test_hhl_parameters_match_oracle(nbus, m, seed):
+    A, b = W.dc_powerflow(nbus, seed)
+    info = hs.circuit_build_hhl(A, b, m).info()
+    ref = oracle.hhl_params(A, b, m)
+    assert info["n_sys"] == ref["ns"] and info["j0"] == ref["j0"]
+    for key_l, key_o in [("t", "t"), ("C", "C"), ("lambda_lo", "lambda_lo"),
+                         ("lambda_hi", "lambda_hi"), ("kappa", "kappa"), ("b_norm", "beta")]:
+        assert abs(info[key_l] - ref[key_o]) <= 1e-12 * abs(ref[key_o]), key_l
+
+
+@pytest.mark.parametrize("nbus,m,seed", [(4, 4, 3), (32, 8, 4), (64, 10, 5)])
+def test_hhl_evolutions_are_matrix_exponentials(nbus, m, seed):
+    A, b = W.dc_powerflow(nbus, seed)
+    c = hs.circuit_build_hhl(A, b, m)
+    info = c.info()
+    ns = info["n_sys"]
+    D = 1 << ns
+    Ap = np.eye(D)
+    Ap[: A.shape[0], : A.shape[0]] = A
+    cd = [g for g in c.gates() if g[0] == "cdense"]
+    assert len(cd) == 2 * m
+    for j in range(m):
+        want = scipy.linalg.expm(1j * Ap * info["t"] * 2 ** j)
+        kind, qs, ps = cd[j]
+        assert qs == [ns + j] + list(range(ns))
+        U = cmat(ps, ns)
+        # phase error grows with t 2^j ||A||; bound from the exponent's size
+        tol = 1e-13 * max(1.0, info["t"] * 2 ** j * np.linalg.norm(Ap, 2)) * D
+        assert max_abs_diff(U, want) < tol
+        assert max_abs_diff(cmat(cd[2 * m - 1 - j][2], ns), want.conj().T) < tol
+
+
+@pytest.mark.parametrize("ns,seed", [(1, 0), (2, 1), (3, 2), (6, 3)])
+def test_state_prep_tree_loads_b(ns, seed):
+    """The |b> preparation gates map |0> exactly to b / ||b||."""
+    rng = np.random.default_rng(seed)
+    N = (1 << ns) - (1 if ns > 1 else 0)
+    b = rng.standard_normal(N)
+    b[0] = -abs(b[0])                      # signs must survive
+    A = np.eye(N) * 2.0
+    c = hs.circuit_build_hhl(A, b, 2)
+    n = c.n_qubits
+    psi = np.zeros(1 << n, dtype=complex)
+    psi[0] = 1
+    for kind, qs, ps in c.gates()[:ns]:
+        assert kind == "ucry"
+        psi = _np_apply_gate(psi, n, kind, qs, ps)
+    want = np.zeros(1 << n, dtype=complex)
+    want[:N] = b / np.linalg.norm(b)
+    assert max_abs_diff(psi, want) < 1e-14
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 5])
+def test_inverse_qft_gates_closed_form(m):
+    ns = 1
+    A = np.array([[2.0, 0.5], [0.5, 3.0]])
+    c = hs.circuit_build_hhl(A, np.array([1.0, 0.2]), m)
+    g = c.gates()
+    start = ns + 2 * m
+    qft_inv = g[start: start + m + m * (m - 1) // 2 + m // 2]
+    n = c.n_qubits
+    M = 1 << m
+    for x in range(M):
+        psi = np.zeros(1 << n, dtype=complex)
+        psi[x << ns] = 1
+        for kind, qs, ps in qft_inv:
+            psi = _np_apply_gate(psi, n, kind, qs, ps)
+        e = np.zeros(M, dtype=complex)
+        e[x] = 1
+        closed = np.fft.fft(e) / math.sqrt(M)    # inverse QFT: e^{-2 pi i x y / M}
+        want = np.zeros(1 << n, dtype=complex)
+        for y in range(M):
+            want[y << ns] = closed[y]
+        assert max_abs_diff(psi, want) < 1e-14
+
+
+def test_hhl_numpy_evaluation_matches_oracle():
+    """Library gate list evaluated by numpy equals the oracle's own HHL."""
+    A, b = W.dc_powerflow(4, 7)
+    c = hs.circuit_build_hhl(A, b, 4)
+    n = c.n_qubits
+    psi = np.zeros(1 << n, dtype=complex)
+    psi[0] = 1
+    psi = np_run(c, psi)
+    ref, _, _, _ = oracle.hhl_solve(A, b, 4)
+    assert max_abs_diff(psi, ref) < 1e-13
+
+
+# ----------------------------------------------------------------- fusion ---
+@pytest.mark.parametrize("n,seed,k", [(4, 0, 1), (5, 1, 2), (6, 2, 3), (7, 3, 4), (8, 4, 5), (8, 5, 2)])
+def test_fusion_preserves_unitary(n, seed, k):
+    gates = W.random_circuit(n, 60, seed, kmax=3)
+    c = hs.circuit_from_gates(n, gates)
+    f = hs.fuse(c, k)
+    assert f.n_gates <= c.n_gates
+    wide_in = sum(len(g.qubits) > k for g in gates)
+    wide_out = 0
+    for kind, qs, ps in f.gates():
+        if len(qs) <= k:
+            assert kind in ("dense", "diag") and qs == sorted(qs)
+        else:
+            wide_out += 1          # too wide to fuse: passed through unchanged
+    assert wide_out == wide_in
+    psi = W.random_state(n, seed)
+    assert max_abs_diff(np_run(f, psi), np_run(c, psi)) < 1e-13
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
+def test_fusion_of_hhl_circuit(k):
+    A, b = W.dc_powerflow(4, 2)
+    c = hs.circuit_build_hhl(A, b, 4)
+    f = hs.fuse(c, k)
+    psi = np.zeros(1 << c.n_qubits, dtype=complex)
+    psi[0] = 1
+    assert max_abs_diff(np_run(f, psi), np_run(c, psi)) < 1e-13
+    assert f.info()["C"] == c.info()["C"]
+
+
+def test_fusion_counts_layered_33q():
+    gates = W.layered_circuit(33, 40, 2402)
+    assert len(gates) == 40 * (3 * 33 + 16) == 4600
+    c = hs.circuit_from_gates(33, gates)
+    counts = {k: hs.fuse(c, k).n_gates for k in (1, 2, 3, 4, 5)}
+    # k = 1 merges each qubit's 1q run; the idle qubit of a layer also merges
+    # into the next layer's run (39 times)
+    assert counts[1] == 40 * (33 + 16) - 39
+    assert counts[1] > counts[2] > counts[3] >= counts[4] >= counts[5]
+
+
+def test_fusion_k2_is_the_papers_four_strategies():
+    """1q-1q, 1q before/after a 2q gate, and 2q-2q on the same pair all
+    collapse into one gate at k_max = 2."""
+    n = 3
+    gates = [W.Gate("h", (0,), np.array([])), W.Gate("rz", (0,), np.array([0.3])),
+             W.Gate("ry", (1,), np.array([0.2])), W.Gate("cx", (0, 1), np.array([])),
+             W.Gate("u3", (1,), np.array([0.1, 0.2, 0.3])), W.Gate("cp", (1, 0), np.array([0.7])),
+             W.Gate("h", (2,), np.array([]))]
+    f = hs.fuse(hs.circuit_from_gates(n, gates), 2)
+    assert f.n_gates == 2
+    assert sorted(len(qs) for _, qs, _ in f.gates()) == [1, 2]
+
+
+def test_diagonal_runs_stay_diagonal():
+    gates = [W.Gate("rz", (0,), np.array([0.3])), W.Gate("cp", (0, 1), np.array([0.5])),
+             W.Gate("p", (1,), np.array([0.9]))]
+    f = hs.fuse(hs.circuit_from_gates(2, gates), 2)
+    assert [g[0] for g in f.gates()] == ["diag"]
+
+
+# ------------------------------------------------------------- validation ---
+def test_validation_errors():
+    with pytest.raises(hs.HHLSVError, match="NOT_SYMMETRIC"):
+        hs.circuit_build_hhl(np.array([[1.0, 2.0], [0.0, 1.0]]), np.ones(2), 3)
+    with pytest.raises(hs.HHLSVError, match="NOT_POSDEF"):
+        hs.circuit_build_hhl(np.array([[1.0, 0.0], [0.0, -1.0]]), np.ones(2), 3)
+    with pytest.raises(hs.HHLSVError, match="INVALID"):
+        hs.circuit_build_hhl(np.eye(2), np.zeros(2), 3)
+    with pytest.raises(hs.HHLSVError, match="INVALID"):
+        hs.circuit_build_hhl(np.eye(2), np.ones(2), 0)
+    with pytest.raises(hs.HHLSVError, match="INVALID"):
+        hs.circuit_build_hhl(np.eye(4), np.ones(4), 33)
+    c = hs.circuit_create(3)
+    with pytest.raises(hs.HHLSVError, match="INVALID"):
+        hs.circuit_add_gate(c, "cx", [0, 0])
+    with pytest.raises(hs.HHLSVError, match="INVALID"):
+        hs.circuit_add_gate(c, "h", [3])
+    with pytest.raises(hs.HHLSVError, match="INVALID"):
+        hs.circuit_add_gate(c, "ry", [0], [])
+    with pytest.raises(hs.HHLSVError, match="INVALID"):
+        hs.circuit_add_gate(c, "dense", [0, 1], np.zeros(8))
+    with pytest.raises(hs.HHLSVError, match="INVALID"):
+        hs.fuse(c, 6)
+    with pytest.raises(hs.HHLSVError, match="INVALID"):
+        hs.circuit_create(35)
+
+
+def test_qubit_estimate_matches_table1():
+    assert hs.sv_qubit_estimate(16, 119.2, True) == (4, 8, 13)
+    assert hs.sv_qubit_estimate(32, 492.5, True) == (5, 10, 16)
+    assert hs.sv_qubit_estimate(64, 109.3, True) == (6, 8, 15)
+
+
+def test_sym_eig_against_numpy():
+    """The library's eigen-solve (through the circuit parameters) agrees with
+    LAPACK's on an ill-conditioned 64-bus system."""
+    A, b = W.dc_powerflow(64, 9)
+    info = hs.circuit_build_hhl(A, b, 10).info()
+    w = np.linalg.eigvalsh(A)
+    assert abs(info["lambda_lo"] - w[0]) < 1e-12 * w[-1]
+    assert abs(info["lambda_hi"] - w[-1]) < 1e-12 * w[-1]
