@@ -38,7 +38,7 @@ def kernel_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(family):
+def measured_traffic(label):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel source (else None)."""
     if not os.path.exists(TRAFFIC_FILE):
@@ -51,8 +51,16 @@ def measured_traffic(family):
                 vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    key = f"bytes_per_launch_{family}"
+    key = "bytes_per_launch " + label
     return float(vals[key]) if key in vals else None
+
+
+def kernel_label(family, k, real="double"):
+    """Name of the kernel template instance a launch used (as rocprofv3 shows it)."""
+    name = {"dense_direct": "k_dense_direct", "dense_lds": "k_dense_lds",
+            "dense_small": "k_dense_generic", "diag": "k_diag", "wide": "k_wide",
+            "ucry": "k_ucry"}[family]
+    return f"{name}<{real}, {k}>" if family.startswith("dense") else f"{name}<{real}>"
 
 
 def cpu_baseline(budget_s=15.0, n=26):
@@ -140,13 +148,14 @@ def main():
 
     ms_all = np.concatenate(launch_ms)
     fam_all = np.concatenate(families)
+    width = np.array([len(g[1]) for g in fused.gates()] * args.steps)
     value = n_sweeps * bytes_per_sweep / elapsed / 1e9
     per_sweep = bytes_per_sweep / (ms_all * 1e-3) / 1e9
     by_fam = {}
-    for f in np.unique(fam_all):
-        sel = fam_all == f
-        by_fam[hs.KERNEL_FAMILY[int(f)]] = (float(ms_all[sel].sum()), int(sel.sum()),
-                                            float(ms_all[sel].mean()))
+    labels = np.array([kernel_label(hs.KERNEL_FAMILY[int(f)], int(w)) for f, w in zip(fam_all, width)])
+    for lab in np.unique(labels):
+        sel = labels == lab
+        by_fam[str(lab)] = (float(ms_all[sel].sum()), int(sel.sum()), float(ms_all[sel].mean()))
     dom = max(by_fam, key=lambda f: by_fam[f][0])
     dom_avg_ms = by_fam[dom][2]
     achieved = bytes_per_sweep / (dom_avg_ms * 1e-3) / 1e9

@@ -43,14 +43,16 @@ __device__ __forceinline__ void cmac(C &acc, const C m, const C v)
     acc.y = __builtin_fma(m.y, v.x, acc.y);
 }
 
-// Hide a uniform pointer's value from the optimiser at this point, so loads
-// through it are not hoisted out of the surrounding loop (which would pin the
-// whole gate matrix in registers); the loads stay scalar (s_load).
+// Offset the (uniform) matrix pointer by a zero the optimiser cannot see
+// through, so loads of the matrix are not hoisted out of the tile loop (which
+// would pin the whole gate matrix in registers).  The pointer keeps its
+// global address space and stays uniform, so the loads remain scalar.
 template <typename T>
 __device__ __forceinline__ const T *opaque(const T *p)
 {
-    asm volatile("" : "+s"(p));
-    return p;
+    int z = 0;
+    asm volatile("" : "+s"(z));
+    return p + z;
 }
 
 __device__ __forceinline__ uint64_t insert_zero(uint64_t x, int p)
@@ -109,7 +111,10 @@ __global__ __launch_bounds__(256) void k_dense_direct(typename V2<R>::type *__re
         for (int r = 0; r < NR; ++r) {
             C acc = {0, 0};
 #pragma unroll
-            for (int c = 0; c < NR; ++c) cmac(acc, m[r * NR + c], v[c]);
+            for (int c = 0; c < NR; ++c) {
+                cmac(acc, m[r * NR + c], v[c]);
+                if (NR > 16 && (c & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+            }
             st_nt(acc, psi + base + a.reg_off[r]);
         }
     }
@@ -142,7 +147,10 @@ __global__ __launch_bounds__(64) void k_dense_lds(typename V2<R>::type *__restri
         for (int r = 0; r < NR; ++r) {
             C acc = {0, 0};
 #pragma unroll
-            for (int c = 0; c < NR; ++c) cmac(acc, m[r * NR + c], v[c]);
+            for (int c = 0; c < NR; ++c) {
+                cmac(acc, m[r * NR + c], v[c]);
+                if (NR > 16 && (c & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+            }
             tile[lds_phys(a.slot_r[r] + sg)] = acc;
         }
         __syncthreads();
