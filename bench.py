@@ -11,6 +11,13 @@ The roofline object reports the dominant kernel family: algorithmic bytes per
 launch / its mean launch time from HIP events recorded on the state's stream.
 The CPU baseline times the oracle on a bounded sample of the same generator.
 
+The HHL half of the metric is reported in the "hhl" object (skip with
+--no-hhl): solves/s of the plain one-circuit-at-a-time path (64-bus system,
+10 clock qubits, complex128 and complex64), of the batched persistent path
+(8192 instances, 2-6 system and 4-10 clock qubits) and of the serving loop
+(Poisson arrivals at 2000 req/s, 8-256 buses, 6-12 clock qubits) with p50 /
+p99 latency, each for complex128 and complex64.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--k 4]
 """
 import argparse
@@ -98,6 +105,111 @@ def cpu_baseline(budget_s=15.0, n=26):
                       f"GB/s = gates * 2 * 2^n * 16 B / time"}
 
 
+def hhl_single(hs, W, reps=40):
+    """Plain one-circuit-at-a-time path on the 64-bus, 10-clock-qubit system:
+    reset + apply (cached hipGraph) + postselect per solve."""
+    A, b = W.dc_powerflow(64, 0)
+    c = hs.circuit_build_hhl(A, b, 10)
+    out = {}
+    for dtype in ("c128", "c64"):
+        best = None
+        for k in (2, 3, 4):
+            run = hs.fuse(c, k)
+            s = hs.sv_create(c.n_qubits, dtype)
+            s.apply(run)
+            s.postselect_solution(c, 63)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                s.reset()
+                s.apply(run)
+                s.postselect_solution(c, 63)
+            dt = (time.perf_counter() - t0) / reps
+            s.close()
+            if best is None or dt < best[1]:
+                best = (k, dt)
+        out[dtype] = {"solves_per_s": round(1.0 / best[1], 1), "ms_per_solve": round(best[1] * 1e3, 4),
+                      "k_max": best[0]}
+    return out
+
+
+def hhl_batch(hs, W, count=8192):
+    """Batched persistent path on the 8192-instance mix (seed 8136); one
+    autotuned k_max per (ns, m) shape; device time of the replayed graph."""
+    specs = W.batch_specs(count, 8136)
+    t0 = time.perf_counter()
+    circs = []
+    for ns, m, gseed in specs:
+        A, b = W.dc_powerflow(1 << ns, gseed)
+        circs.append(hs.circuit_build_hhl(A, b, m, device_evolutions=True))
+    build_s = time.perf_counter() - t0
+    out = {"instances": count, "host_build_s": round(build_s, 2)}
+    for dtype in ("c128", "c64"):
+        shapes = {}
+        for (ns, m, _), c in zip(specs, circs):
+            shapes.setdefault((ns, m), c)
+        t0 = time.perf_counter()
+        tuned = {}
+        for (ns, m), c in sorted(shapes.items()):
+            tuned[f"{ns},{m}"] = hs.svb_autotune(dtype, c, 16)[0]
+        tune_s = time.perf_counter() - t0
+        bt = hs.Batch(dtype, 0)
+        for c in circs:
+            bt.add(c)
+        t0 = time.perf_counter()
+        first_ms = bt.run()      # upload, device evolution tables, capture, run
+        setup_s = time.perf_counter() - t0
+        runs = [bt.run() for _ in range(5)]
+        ms = float(np.median(runs))
+        out[dtype] = {"solves_per_s": round(count / (ms * 1e-3), 1), "device_ms": round(ms, 3),
+                      "first_run_s": round(setup_s, 3), "autotune_s": round(tune_s, 2),
+                      "k_by_shape": tuned}
+        bt.close()
+    return out
+
+
+def hhl_serve(hs, W, seconds, rate=2000.0, pool_per_size=48):
+    """Serving loop under open-loop Poisson arrivals (seed 2000 for arrivals,
+    2001 for sizes); request systems come from a pool of seeded systems per
+    size.  Latency = submit to finish inside the server."""
+    sched = W.serve_specs(rate, seconds, 2000, 2001)
+    pool = {}
+    for ns in range(3, 9):
+        pool[ns] = [W.dc_powerflow(1 << ns, 50000 + 100 * ns + i) for i in range(pool_per_size)]
+    out = {"offered_rate_per_s": rate, "duration_s": seconds, "requests": len(sched)}
+    for dtype in ("c128", "c64"):
+        srv = hs.Server(dtype, k_max=3)
+        t_start = time.perf_counter()
+        rejected = 0
+        for i, (ta, ns, m, _) in enumerate(sched):
+            delay = t_start + ta - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            A, b = pool[ns][i % pool_per_size]
+            try:
+                srv.submit(A, b, m)
+            except hs.HHLSVError:
+                rejected += 1
+        srv.drain()
+        st = srv.stats()
+        srv.stop()
+        out[dtype] = {"p50_ms": round(st["p50_s"] * 1e3, 3), "p99_ms": round(st["p99_s"] * 1e3, 3),
+                      "solves_per_s": round(st["solves_per_s"], 1), "done": st["done"],
+                      "failed": st["failed"], "rejected": st["rejected"] + rejected}
+        log(f"[bench] serve {dtype}: {out[dtype]}")
+    # the plain one-circuit-at-a-time FP64 path on a sample of the same requests
+    sample = sched[:: max(1, len(sched) // 200)]
+    t0 = time.perf_counter()
+    for i, (ta, ns, m, _) in enumerate(sample):
+        A, b = pool[ns][i % pool_per_size]
+        c = hs.circuit_build_hhl(A, b, m, device_evolutions=True)
+        st = hs.sv_create(c.n_qubits, "c128")
+        st.apply(hs.fuse(c, 3))
+        st.postselect_solution(c, A.shape[0])
+        st.close()
+    out["plain_fp64_path_solves_per_s"] = round(len(sample) / (time.perf_counter() - t0), 1)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +219,9 @@ def main():
     ap.add_argument("--n", type=int, default=33, help="qubits (the workload is 33)")
     ap.add_argument("--layers", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-hhl", action="store_true", help="skip the HHL solves/s part")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of the Poisson arrival window (the full schedule is 60 s)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path "
@@ -200,6 +315,15 @@ def main():
             "traffic": traffic,
         },
     }
+    state.close()
+    if not args.no_hhl:
+        log("[bench] HHL: one-circuit-at-a-time path")
+        hhl = {"single_64bus_m10": hhl_single(hs, W)}
+        log("[bench] HHL: batched 8192 instances")
+        hhl["batch_8192"] = hhl_batch(hs, W)
+        log(f"[bench] HHL: serving, {args.serve_seconds:.0f} s of arrivals at 2000/s")
+        hhl["serve"] = hhl_serve(hs, W, args.serve_seconds)
+        out["hhl"] = hhl
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host (bounded sample)")
         out["cpu_baseline"] = cpu_baseline()

@@ -168,6 +168,21 @@ sv_status sv_norm2(const sv_state *s, double *out);
 sv_status circuit_build_hhl(const double *A, const double *b, int dim,
                             int clock_bits, double t, sv_circuit **out);
 
+/* Flags for circuit_build_hhl_ex. */
+enum {
+    /* Keep the eigen-decomposition in the circuit and build the controlled
+     * e^{iAt 2^j} matrices on the device (FP64) when the circuit is first
+     * applied or added to a batch, instead of on the host at build time.
+     * Host consumers that need them (circuit_serialize, fuse when the gate
+     * fits in k_max) build them on demand. */
+    SV_HHL_DEVICE_EVOLUTIONS = 1
+};
+
+/* circuit_build_hhl with flags (0 = circuit_build_hhl). */
+sv_status circuit_build_hhl_ex(const double *A, const double *b, int dim,
+                               int clock_bits, double t, int flags,
+                               sv_circuit **out);
+
 /* Empty generic circuit on n qubits (1 <= n <= 34). */
 sv_status circuit_create(int n_qubits, sv_circuit **out);
 
@@ -228,6 +243,92 @@ sv_status sv_postselect_solution(sv_state *s, const sv_circuit *hhl,
                                  sv_solution_info *info);
 
 sv_status circuit_destroy(sv_circuit *c);
+
+/* ---- batched solves --------------------------------------------------- */
+/* Many small HHL solves in persistent launches: each workgroup runs a whole
+ * circuit on one state held in LDS (n <= 13 at complex128, n <= 14 at
+ * complex64) or in HBM, one launch per size class on its own stream, the
+ * whole run captured once in a hipGraph and replayed by later svb_run calls.
+ * Every instance's arithmetic is independent of the rest of the batch.
+ *
+ * svb_create: k_max in 1..5 fuses every instance with that width; 0 uses the
+ * width svb_autotune chose for the instance's (ns, m), else 3.  hip_stream may
+ * be NULL (own stream).
+ * svb_add: copies and fuses an HHL circuit (<= 24 qubits); *index_out gets
+ * its index.  Adding invalidates the device copy (re-uploaded by svb_run).
+ * svb_run: runs every instance; synchronises.  SV_ERR_OOM if HBM is short.
+ * svb_solution: the instance's x_hat (unit norm, dim entries) and info as in
+ * sv_postselect_solution.  svb_last_run_ms: device time of the last run
+ * (HIP events around the graph launch). */
+sv_status svb_create(sv_dtype dtype, int k_max, void *hip_stream, svb **out);
+sv_status svb_add(svb *bt, const sv_circuit *hhl, int *index_out);
+sv_status svb_run(svb *bt);
+sv_status svb_solution(svb *bt, int index, double *x_hat, int dim,
+                       sv_solution_info *info);
+sv_status svb_last_run_ms(const svb *bt, double *ms);
+sv_status svb_size(const svb *bt, int *count);
+sv_status svb_destroy(svb *bt);
+
+/* ---- serving ----------------------------------------------------------- */
+/* Continuous-batching server for HHL solves on one GPU.  svs_submit copies
+ * the inputs and queues the request; prep threads build each circuit (the
+ * controlled evolutions are built on the device), fuse it, wait until its
+ * device footprint fits in the HBM budget and a slot is free (admission),
+ * and upload it.  A scheduler keeps several micro-batches in flight on
+ * separate streams: requests whose state fits in LDS run together in the
+ * batched persistent kernel, larger ones alone through the sweep kernels.
+ * Requests that arrive while others are on the GPU are admitted as memory
+ * and slots free up.  A request's result does not depend on what else is
+ * in flight.  All svs_* calls are thread-safe.
+ *
+ * svs_start: hbm_budget_bytes = 0 uses half of the free HBM; max_slots
+ *   bounds the requests resident at once.
+ * svs_configure: before the first submit (SV_ERR_BUSY after).
+ * svs_submit: dim in [1, 4096], clock_bits in [1, 16]; SV_ERR_BUSY when the
+ *   queue limit is reached (counted as rejected).  *ticket identifies it.
+ * svs_poll: SV_PENDING until done; then SV_OK with x_hat (dim entries,
+ *   unit norm) and info as in sv_postselect_solution, or the request's
+ *   error (SV_ERR_OOM when it can never fit the budget or its allocation
+ *   failed, SV_ERR_NOT_SYMMETRIC / SV_ERR_NOT_POSDEF / SV_ERR_INVALID from
+ *   the build, SV_ERR_INVALID if cancelled).  A finished ticket is consumed
+ *   by the poll that returns it.
+ * svs_cancel: cancels a request that has not been admitted yet.
+ * svs_drain: waits until every submitted request has finished (timeout_s
+ *   <= 0: no limit; SV_ERR_BUSY on timeout).
+ * svs_stats: latency = finish - submit (host monotonic clock); p50 / p99 by
+ *   nearest rank over the exact sorted sample of successful requests;
+ *   solves/s = successful requests / (last finish - first submit).
+ * svs_stop: drains, joins the threads and frees the server. */
+enum {
+    SVS_OPT_PREP_THREADS = 1,  /* host build threads (default min(12, cores-1)) */
+    SVS_OPT_K_MAX = 2,         /* fusion width (0: autotuned per shape, else 3) */
+    SVS_OPT_MAX_BATCH = 3,     /* requests per batched launch (default 256)      */
+    SVS_OPT_STREAMS = 4,       /* micro-batches in flight (default 4)            */
+    SVS_OPT_QUEUE_LIMIT = 5,   /* queued, not yet admitted requests              */
+    SVS_OPT_FAIL_ALLOC_AT = 6  /* failure injection: the n-th request device
+                                  allocation fails as out of memory (0 = off)  */
+};
+sv_status svs_start(size_t hbm_budget_bytes, int max_slots, sv_dtype dtype,
+                    svs **out);
+sv_status svs_configure(svs *srv, int option, double value);
+sv_status svs_submit(svs *srv, const double *A, const double *b, int dim,
+                     int clock_bits, double t, uint64_t *ticket);
+sv_status svs_poll(svs *srv, uint64_t ticket, double *x_hat, int dim,
+                   sv_solution_info *info);
+sv_status svs_cancel(svs *srv, uint64_t ticket);
+sv_status svs_drain(svs *srv, double timeout_s);
+sv_status svs_stats(svs *srv, double *p50_s, double *p99_s,
+                    double *solves_per_s, uint64_t *n_rejected);
+sv_status svs_counts(svs *srv, uint64_t *done, uint64_t *failed,
+                     uint64_t *pending);
+sv_status svs_stop(svs *srv);
+
+/* Autotuner: time a batch of `copies` copies of `sample` at k_max = 1..5,
+ * record the fastest width for the sample's (dtype, ns, m) (used by batches
+ * created with k_max = 0), and return it.  ms_per_k (5 entries, may be NULL)
+ * receives the measured device times. */
+sv_status svb_autotune(sv_dtype dtype, const sv_circuit *sample, int copies,
+                       int *best_k, double *ms_per_k);
 
 const char *sv_last_error(void);
 

@@ -92,6 +92,8 @@ _proto("sv_set_amplitudes", _vp, _sz, _sz, _vp)
 _proto("sv_get_amplitudes_at", _vp, ctypes.POINTER(ctypes.c_uint64), _sz, _vp)
 _proto("sv_norm2", _vp, _dp)
 _proto("circuit_build_hhl", _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.POINTER(_vp))
+_proto("circuit_build_hhl_ex", _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+       ctypes.POINTER(_vp))
 _proto("circuit_create", ctypes.c_int, ctypes.POINTER(_vp))
 _proto("circuit_add_gate", _vp, ctypes.c_int, _ip, ctypes.c_int, _dp, ctypes.c_int)
 _proto("circuit_info", _vp, ctypes.POINTER(HHLInfo))
@@ -104,6 +106,24 @@ _proto("sv_synchronize", _vp)
 _proto("sv_postselect_solution", _vp, _vp, _dp, ctypes.c_int, ctypes.POINTER(SolutionInfo))
 _proto("circuit_destroy", _vp)
 _proto("sv_qubit_estimate", ctypes.c_int, ctypes.c_double, ctypes.c_int, _ip, _ip, _ip)
+_proto("svb_create", ctypes.c_int, ctypes.c_int, _vp, ctypes.POINTER(_vp))
+_proto("svb_add", _vp, _vp, _ip)
+_proto("svb_run", _vp)
+_proto("svb_solution", _vp, ctypes.c_int, _dp, ctypes.c_int, ctypes.POINTER(SolutionInfo))
+_proto("svb_last_run_ms", _vp, _dp)
+_proto("svb_size", _vp, _ip)
+_proto("svb_destroy", _vp)
+_proto("svb_autotune", ctypes.c_int, _vp, ctypes.c_int, _ip, _dp)
+_u64 = ctypes.c_uint64
+_proto("svs_start", _sz, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp))
+_proto("svs_configure", _vp, ctypes.c_int, ctypes.c_double)
+_proto("svs_submit", _vp, _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.POINTER(_u64))
+_proto("svs_poll", _vp, _u64, _dp, ctypes.c_int, ctypes.POINTER(SolutionInfo))
+_proto("svs_cancel", _vp, _u64)
+_proto("svs_drain", _vp, ctypes.c_double)
+_proto("svs_stats", _vp, _dp, _dp, _dp, ctypes.POINTER(_u64))
+_proto("svs_counts", _vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64), ctypes.POINTER(_u64))
+_proto("svs_stop", _vp)
 
 
 def _check(rc, where):
@@ -199,14 +219,21 @@ def circuit_from_gates(n_qubits: int, gates) -> Circuit:
     return c
 
 
-def circuit_build_hhl(A, b, clock_bits: int, t: float = 0.0) -> Circuit:
+SV_HHL_DEVICE_EVOLUTIONS = 1
+
+
+def circuit_build_hhl(A, b, clock_bits: int, t: float = 0.0,
+                      device_evolutions: bool = False) -> Circuit:
+    """HHL circuit for A x = b.  device_evolutions=True keeps the
+    eigen-decomposition and builds the controlled e^{iAt 2^j} on the GPU."""
     A = np.ascontiguousarray(A, dtype=np.float64)
     b = np.ascontiguousarray(b, dtype=np.float64).ravel()
     if A.shape != (b.size, b.size):
         raise ValueError("A must be dim x dim with dim = len(b)")
     h = _vp()
-    _check(_lib.circuit_build_hhl(_dptr(A), _dptr(b), b.size, clock_bits, float(t),
-                                  ctypes.byref(h)), "circuit_build_hhl")
+    flags = SV_HHL_DEVICE_EVOLUTIONS if device_evolutions else 0
+    _check(_lib.circuit_build_hhl_ex(_dptr(A), _dptr(b), b.size, clock_bits, float(t), flags,
+                                     ctypes.byref(h)), "circuit_build_hhl")
     return Circuit(h.value)
 
 
@@ -332,3 +359,123 @@ def solve(A, b, clock_bits: int, dtype="c128", k_max: int | None = None, t: floa
     s.apply(run)
     x_hat, info = s.postselect_solution(c, len(b))
     return info["scale"] * x_hat, x_hat, info, c.info()
+
+
+# ------------------------------------------------------------------- batches
+class Batch:
+    """Owning wrapper of an ``svb*``: many small HHL solves per launch."""
+
+    def __init__(self, dtype="c128", k_max: int = 0, stream=None):
+        h = _vp()
+        ptr = getattr(stream, "cuda_stream", stream)
+        _check(_lib.svb_create(DTYPES[dtype], k_max, _vp(ptr) if ptr else None, ctypes.byref(h)),
+               "svb_create")
+        self.handle = h
+        self.dims = []
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            _lib.svb_destroy(h)
+            self.handle = _vp()
+
+    def close(self):
+        self.__del__()
+
+    def add(self, hhl: Circuit) -> int:
+        idx = ctypes.c_int()
+        _check(_lib.svb_add(self.handle, hhl.handle, ctypes.byref(idx)), "svb_add")
+        self.dims.append(hhl.info()["dim"])
+        return idx.value
+
+    def __len__(self):
+        return len(self.dims)
+
+    def run(self) -> float:
+        """Run every instance; returns the device time in ms."""
+        _check(_lib.svb_run(self.handle), "svb_run")
+        ms = ctypes.c_double()
+        _check(_lib.svb_last_run_ms(self.handle, ctypes.byref(ms)), "svb_last_run_ms")
+        return ms.value
+
+    def solution(self, index: int):
+        dim = self.dims[index]
+        x = np.zeros(dim)
+        info = SolutionInfo()
+        _check(_lib.svb_solution(self.handle, index, _dptr(x), dim, ctypes.byref(info)),
+               "svb_solution")
+        return x, info.as_dict()
+
+
+def svb_autotune(dtype, sample: Circuit, copies: int = 64):
+    """Time k_max = 1..5 on copies of ``sample``; record and return the best."""
+    best = ctypes.c_int()
+    ms = np.zeros(5)
+    _check(_lib.svb_autotune(DTYPES[dtype], sample.handle, copies, ctypes.byref(best), _dptr(ms)),
+           "svb_autotune")
+    return best.value, ms
+
+
+# ------------------------------------------------------------------- serving
+SVS_OPT = {"prep_threads": 1, "k_max": 2, "max_batch": 3, "streams": 4, "queue_limit": 5,
+           "fail_alloc_at": 6}
+
+
+class Server:
+    """Owning wrapper of an ``svs*`` continuous-batching server."""
+
+    def __init__(self, dtype="c128", hbm_budget_bytes: int = 0, max_slots: int = 4096, **options):
+        h = _vp()
+        _check(_lib.svs_start(hbm_budget_bytes, max_slots, DTYPES[dtype], ctypes.byref(h)), "svs_start")
+        self.handle = h
+        self.dims = {}
+        for k, v in options.items():
+            _check(_lib.svs_configure(self.handle, SVS_OPT[k], float(v)), "svs_configure")
+
+    def submit(self, A, b, clock_bits: int, t: float = 0.0) -> int:
+        A = np.ascontiguousarray(A, dtype=np.float64)
+        b = np.ascontiguousarray(b, dtype=np.float64).ravel()
+        tk = _u64()
+        _check(_lib.svs_submit(self.handle, _dptr(A), _dptr(b), b.size, clock_bits, float(t),
+                               ctypes.byref(tk)), "svs_submit")
+        self.dims[tk.value] = b.size
+        return tk.value
+
+    def poll(self, ticket: int):
+        """None while pending; (x_hat, info) when done; raises on failure."""
+        dim = self.dims[ticket]
+        x = np.zeros(dim)
+        info = SolutionInfo()
+        rc = _lib.svs_poll(self.handle, ticket, _dptr(x), dim, ctypes.byref(info))
+        if rc == 1:
+            return None
+        self.dims.pop(ticket, None)
+        _check(rc, "svs_poll")
+        return x, info.as_dict()
+
+    def cancel(self, ticket: int):
+        _check(_lib.svs_cancel(self.handle, ticket), "svs_cancel")
+
+    def drain(self, timeout_s: float = 0.0):
+        _check(_lib.svs_drain(self.handle, timeout_s), "svs_drain")
+
+    def stats(self):
+        p50, p99, sps = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        rej = _u64()
+        _check(_lib.svs_stats(self.handle, ctypes.byref(p50), ctypes.byref(p99), ctypes.byref(sps),
+                              ctypes.byref(rej)), "svs_stats")
+        done, failed, pending = _u64(), _u64(), _u64()
+        _check(_lib.svs_counts(self.handle, ctypes.byref(done), ctypes.byref(failed),
+                               ctypes.byref(pending)), "svs_counts")
+        return {"p50_s": p50.value, "p99_s": p99.value, "solves_per_s": sps.value,
+                "rejected": rej.value, "done": done.value, "failed": failed.value,
+                "pending": pending.value}
+
+    def stop(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            _lib.svs_stop(h)
+            self.handle = _vp()
+
+    def __del__(self):
+        self.stop()

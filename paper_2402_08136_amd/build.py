@@ -16,11 +16,11 @@ LIB = os.path.join(HERE, "libhhlsv.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CXX_SOURCES = ["circuit.cpp", "hhl_build.cpp"]
-HIP_SOURCES = ["kernels.hip", "state.hip"]
+HIP_SOURCES = ["kernels.hip", "state.hip", "batch.hip", "serve.hip"]
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", "-Wno-unused-result", "-I", INCLUDE, "-I", CSRC]
-CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra",
+CXX_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wextra",
              "-I", INCLUDE, "-I", CSRC, "-I", "/opt/rocm/include",
              "-D__HIP_PLATFORM_AMD__"]
 

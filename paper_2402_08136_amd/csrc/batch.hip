@@ -1,0 +1,758 @@
+// Batched execution of many small HHL solves in persistent launches.
+//
+// Each workgroup runs one whole circuit at a time on one state: the state
+// lives in LDS when it fits (2^n amplitudes of up to 128 KiB, i.e. n <= 13 at
+// complex128 and n <= 14 at complex64) and in HBM otherwise; the gate program
+// (fused ops with FP64-built tables) is read from device memory; the
+// postselected block y and P(ancilla = 1) (Sec. III-A steps 3-4 of Zheng et
+// al., PESGM 2024) are written out at the end.  Instances are grouped by size
+// class, one persistent launch per class on its own stream, and the whole run
+// is captured once into a hipGraph and replayed.  Per-instance arithmetic
+// does not depend on the batch composition (one workgroup per instance, fixed
+// op and reduction order), so a solve gives the same bits alone or in a mix.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+
+#include "device_common.hpp"
+#include "hhlsv_batch.hpp"
+#include "kernels.hpp"
+
+namespace hhlsv {
+
+#define HIPCK(x)                                                                   \
+    do {                                                                           \
+        hipError_t e_ = (x);                                                       \
+        if (e_ != hipSuccess)                                                      \
+            return fail(SV_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+namespace {
+
+constexpr int kThreads = kBatchThreads;
+constexpr int kRedBytes = kThreads * 8;
+constexpr int kMaxBatchQubits = 24;
+
+
+// ------------------------------------------------------------- device ops --
+template <typename C, int K>
+__device__ void b_dense(C *psi, int n, const BOp &op, const C *mat)
+{
+    constexpr int NR = 1 << K;
+    const uint32_t ngroups = 1u << (n - K);
+    for (uint32_t g = threadIdx.x; g < ngroups; g += blockDim.x) {
+        uint32_t base = g;
+#pragma unroll
+        for (int j = 0; j < K; ++j) base = insert_zero32(base, op.q[j]);
+        uint32_t off[NR];
+        C v[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            uint32_t o = 0;
+#pragma unroll
+            for (int j = 0; j < K; ++j) o |= ((r >> j) & 1u) << op.q[j];
+            off[r] = base | o;
+            v[r] = psi[off[r]];
+        }
+        const C *m = opaque(mat);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            C acc = {0, 0};
+#pragma unroll
+            for (int c = 0; c < NR; ++c) {
+                cmac(acc, m[r * NR + c], v[c]);
+                if (NR > 16 && (c & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+            }
+            psi[off[r]] = acc;
+        }
+    }
+}
+
+template <typename C>
+__device__ void b_diag(C *psi, int n, const BOp &op, const C *d)
+{
+    const uint32_t N = 1u << n;
+    for (uint32_t i = threadIdx.x; i < N; i += blockDim.x) {
+        uint32_t v = 0;
+        if (op.contiguous)
+            v = (i >> op.q[0]) & ((1u << op.k) - 1);
+        else
+            for (int j = 0; j < op.k; ++j) v |= ((i >> op.q[j]) & 1u) << j;
+        psi[i] = cmul(d[v], psi[i]);
+    }
+}
+
+// Wide dense gate (e.g. e^{iAt 2^j} on the system register controlled by a
+// clock qubit).  The table holds U^T so that a wave reads row c of U^T
+// (column c of U) coalesced.  Thread (i, s) produces output i of R groups
+// per pass, with the group amplitudes read from the state by broadcast.
+template <typename C>
+__device__ void b_wide(C *psi, int n, const BOp &op, const C *UT)
+{
+    constexpr int R = 4;
+    const int k = op.k;
+    const uint32_t D = 1u << k;
+    const uint32_t ngroups = 1u << (n - k - (op.control >= 0 ? 1 : 0));
+    const uint32_t slots = blockDim.x >= D ? blockDim.x / D : 1;
+    auto off = [&](uint32_t c) -> uint32_t {
+        if (op.contiguous) return c << op.q[0];
+        uint32_t o = 0;
+        for (int j = 0; j < k; ++j) o |= ((c >> j) & 1u) << op.q[j];
+        return o;
+    };
+    auto gbase = [&](uint32_t g) -> uint32_t {
+        uint32_t b = g;
+        bool placed = op.control < 0;
+        for (int j = 0; j < k; ++j) {
+            if (!placed && op.control < op.q[j]) {
+                b = insert_zero32(b, op.control) | (1u << op.control);
+                placed = true;
+            }
+            b = insert_zero32(b, op.q[j]);
+        }
+        if (!placed) b = insert_zero32(b, op.control) | (1u << op.control);
+        return b;
+    };
+    // outputs handled by this thread: i = tid % D (+ multiples of blockDim
+    // when D > blockDim), group slot s = tid / D
+    const uint32_t s = D <= blockDim.x ? threadIdx.x / D : 0;
+    for (uint32_t chunk = 0; chunk < ngroups; chunk += slots * R) {
+        for (uint32_t i = (D <= blockDim.x ? threadIdx.x % D : threadIdx.x); i < D; i += blockDim.x) {
+            C acc[R];
+            uint32_t gb[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                acc[r] = C{0, 0};
+                const uint32_t g = chunk + s + slots * r;
+                gb[r] = g < ngroups ? gbase(g) : 0xffffffffu;
+            }
+            if (threadIdx.x < slots * D || D > blockDim.x) {
+                for (uint32_t c = 0; c < D; ++c) {
+                    const C u = UT[(size_t)c * D + i];
+                    const uint32_t oc = off(c);
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        if (gb[r] != 0xffffffffu) cmac(acc[r], u, psi[gb[r] | oc]);
+                }
+            }
+            __syncthreads();
+            if (threadIdx.x < slots * D || D > blockDim.x) {
+                const uint32_t oi = off(i);
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (gb[r] != 0xffffffffu) psi[gb[r] | oi] = acc[r];
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <typename C>
+__device__ void b_ucry(C *psi, int n, const BOp &op, const C *cs)
+{
+    const uint32_t npairs = 1u << (n - 1);
+    const uint32_t tbit = 1u << op.target;
+    for (uint32_t p = threadIdx.x; p < npairs; p += blockDim.x) {
+        const uint32_t i0 = insert_zero32(p, op.target);
+        uint32_t v = 0;
+        if (op.contiguous)
+            v = op.k ? (i0 >> op.q[0]) & ((1u << op.k) - 1) : 0;
+        else
+            for (int l = 0; l < op.k; ++l) v |= ((i0 >> op.q[l]) & 1u) << l;
+        const C t = cs[v];
+        const C x0 = psi[i0], x1 = psi[i0 | tbit];
+        C y0, y1;
+        y0.x = t.x * x0.x - t.y * x1.x;
+        y0.y = t.x * x0.y - t.y * x1.y;
+        y1.x = t.y * x0.x + t.x * x1.x;
+        y1.y = t.y * x0.y + t.x * x1.y;
+        psi[i0] = y0;
+        psi[i0 | tbit] = y1;
+    }
+}
+
+template <typename R, bool RESIDENT>
+__global__ __launch_bounds__(kThreads) void k_batch(const BInst *__restrict__ insts,
+                                                    const int *__restrict__ order, int count)
+{
+    typedef typename V2<R>::type C;
+    extern __shared__ unsigned char smem[];
+    double *red = reinterpret_cast<double *>(smem);
+    C *lstate = reinterpret_cast<C *>(smem + kRedBytes);
+    for (int w = blockIdx.x; w < count; w += gridDim.x) {
+        const BInst in = insts[order[w]];
+        C *psi = RESIDENT ? lstate : reinterpret_cast<C *>(in.state);
+        const uint32_t N = 1u << in.n;
+        for (uint32_t i = threadIdx.x; i < N; i += blockDim.x) psi[i] = C{(R)(i == 0), (R)0};
+        __syncthreads();
+        for (int o = 0; o < in.op_count; ++o) {
+            const BOp &op = in.ops[o];
+            const C *tab = reinterpret_cast<const C *>(in.tables + op.off);
+            switch (op.type) {
+            case OP_DENSE:
+                switch (op.k) {
+                case 1: b_dense<C, 1>(psi, in.n, op, tab); break;
+                case 2: b_dense<C, 2>(psi, in.n, op, tab); break;
+                case 3: b_dense<C, 3>(psi, in.n, op, tab); break;
+                case 4: b_dense<C, 4>(psi, in.n, op, tab); break;
+                default: b_dense<C, 5>(psi, in.n, op, tab); break;
+                }
+                break;
+            case OP_DIAG: b_diag(psi, in.n, op, tab); break;
+            case OP_WIDE: b_wide(psi, in.n, op, tab); break;
+            default: b_ucry(psi, in.n, op, tab); break;
+            }
+            __syncthreads();
+        }
+        // Postselection: y_s = psi[2^{n-1} + s] and P(ancilla = 1), in FP64.
+        const uint32_t half = N >> 1;
+        double s2 = 0.0;
+        for (uint32_t i = half + threadIdx.x; i < N; i += blockDim.x) {
+            const C x = psi[i];
+            s2 += (double)x.x * (double)x.x + (double)x.y * (double)x.y;
+        }
+        red[threadIdx.x] = s2;
+        double *out = in.out;
+        const uint32_t D = 1u << in.ns;
+        for (uint32_t i = threadIdx.x; i < D; i += blockDim.x) {
+            const C y = psi[half + i];
+            out[2 + 2 * i] = (double)y.x;
+            out[3 + 2 * i] = (double)y.y;
+        }
+        __syncthreads();
+        for (int wdt = kThreads / 2; wdt > 0; wdt >>= 1) {
+            if ((int)threadIdx.x < wdt) red[threadIdx.x] += red[threadIdx.x + wdt];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            out[0] = red[0];
+            out[1] = 0.0;
+        }
+        __syncthreads();
+    }
+}
+
+
+}  // namespace
+
+void lower_for_batch(const Circuit &f, sv_dtype dtype, std::vector<BOp> &ops, std::vector<unsigned char> &tables,
+                     std::vector<EvoJob> &evo)
+{
+    const size_t as = dtype == SV_C128 ? 16 : 8;
+    for (const Gate &g : f.gates) {
+        LoweredOp L = lower_gate_op(g, f.hhl);
+        BOp op;
+        std::memset(&op, 0, sizeof(op));
+        op.type = L.op.type;
+        op.k = L.op.k;
+        op.target = L.op.target;
+        op.control = L.op.control;
+        for (int j = 0; j < L.op.k; ++j) op.q[j] = L.op.q[j];
+        op.contiguous = 1;
+        for (int j = 1; j < L.op.k; ++j)
+            if (op.q[j] != op.q[0] + j) op.contiguous = 0;
+        const size_t entries = L.deferred ? ((size_t)1 << (2 * L.op.k)) : L.table.size();
+        const size_t off = (tables.size() + 255) & ~size_t(255);
+        tables.resize(off + entries * as);
+        unsigned char *dst = tables.data() + off;
+        if (L.deferred) {
+            EvoJob jb;
+            std::memset(&jb, 0, sizeof(jb));
+            jb.out_off = off;
+            jb.D = 1 << L.op.k;
+            jb.j = L.evo_j;
+            jb.inv = L.evo_inv ? 1 : 0;
+            jb.t = f.hhl.spec->t;
+            evo.push_back(jb);
+        } else {
+            const std::vector<cd> &tab = L.table;   // OP_WIDE tables hold U^T
+            for (size_t i = 0; i < tab.size(); ++i) {
+                if (dtype == SV_C128) {
+                    const double v[2] = {tab[i].real(), tab[i].imag()};
+                    std::memcpy(dst + 16 * i, v, 16);
+                } else {
+                    const float v[2] = {(float)tab[i].real(), (float)tab[i].imag()};
+                    std::memcpy(dst + 8 * i, v, 8);
+                }
+            }
+        }
+        op.off = off;
+        ops.push_back(op);
+    }
+}
+
+namespace {
+template <typename R>
+sv_status set_lds_attr()
+{
+    static std::once_flag once;
+    static hipError_t err = hipSuccess;
+    std::call_once(once, [] {
+        err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch<R, true>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, kBatchLdsLimit);
+    });
+    if (err != hipSuccess) return fail(SV_ERR_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(err));
+    return SV_OK;
+}
+}  // namespace
+
+sv_status launch_batch_class(const BInst *d_insts, const int *d_order, int count, int n, sv_dtype dtype,
+                             hipStream_t st)
+{
+    bool resident = false;
+    const size_t lds = batch_lds_bytes(n, dtype, &resident);
+    const int per_cu = std::max(1, std::min(8, (int)(kBatchLdsLimit / lds)));
+    const int grid = std::max(1, std::min(count, 256 * (resident ? per_cu : 2)));
+    sv_status s = dtype == SV_C128 ? set_lds_attr<double>() : set_lds_attr<float>();
+    if (s != SV_OK) return s;
+    if (dtype == SV_C128) {
+        if (resident)
+            hipLaunchKernelGGL((k_batch<double, true>), dim3(grid), dim3(kThreads), lds, st, d_insts, d_order, count);
+        else
+            hipLaunchKernelGGL((k_batch<double, false>), dim3(grid), dim3(kThreads), lds, st, d_insts, d_order, count);
+    } else {
+        if (resident)
+            hipLaunchKernelGGL((k_batch<float, true>), dim3(grid), dim3(kThreads), lds, st, d_insts, d_order, count);
+        else
+            hipLaunchKernelGGL((k_batch<float, false>), dim3(grid), dim3(kThreads), lds, st, d_insts, d_order, count);
+    }
+    HIPCK(hipGetLastError());
+    return SV_OK;
+}
+
+namespace {
+size_t amp_size(sv_dtype d) { return d == SV_C128 ? 16 : 8; }
+
+// Process-wide autotune table: best k_max per (device arch, dtype, ns, m).
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, int> g_tune;
+
+}  // namespace
+
+struct BatchClass {
+    int n = 0;
+    int first = 0, count = 0;   // range in the order array
+};
+
+}  // namespace hhlsv
+
+using namespace hhlsv;
+
+struct svb {
+    sv_dtype dtype = SV_C128;
+    int k_max = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t own_stream = nullptr;
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> ev;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    // host staging
+    std::vector<BOp> ops;
+    std::vector<unsigned char> tables;
+    struct Meta {
+        int n, ns, op_begin, op_count;
+        size_t state_off, out_off;
+    };
+    std::vector<Meta> insts;
+    std::vector<HHLParams> params;
+    // evolution tables built on the device at upload: (spec owner, job)
+    std::vector<std::pair<std::shared_ptr<const Spectral>, EvoJob>> evo_jobs;
+    size_t out_doubles = 0;
+    size_t state_bytes = 0;
+    // device
+    bool uploaded = false;
+    BOp *d_ops = nullptr;
+    unsigned char *d_tables = nullptr;
+    BInst *d_insts = nullptr;
+    int *d_order = nullptr;
+    unsigned char *d_states = nullptr;
+    double *d_out = nullptr;
+    double *h_out = nullptr;   // pinned
+    std::vector<BatchClass> classes;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool have_result = false;
+    double last_ms = 0.0;
+};
+
+namespace {
+
+void release_device(svb *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    (void)hipFree(b->d_ops);
+    (void)hipFree(b->d_tables);
+    (void)hipFree(b->d_insts);
+    (void)hipFree(b->d_order);
+    (void)hipFree(b->d_states);
+    (void)hipFree(b->d_out);
+    if (b->h_out) (void)hipHostFree(b->h_out);
+    b->d_ops = nullptr;
+    b->d_tables = nullptr;
+    b->d_insts = nullptr;
+    b->d_order = nullptr;
+    b->d_states = nullptr;
+    b->d_out = nullptr;
+    b->h_out = nullptr;
+    b->uploaded = false;
+}
+
+sv_status upload(svb *b)
+{
+    // state arena offsets for instances that do not fit in LDS
+    size_t arena = 0;
+    std::map<int, std::vector<int>> by_n;
+    for (size_t i = 0; i < b->insts.size(); ++i) {
+        svb::Meta &in = b->insts[i];
+        bool resident = false;
+        batch_lds_bytes(in.n, b->dtype, &resident);
+        in.state_off = 0;
+        if (!resident) {
+            in.state_off = arena;
+            arena += ((amp_size(b->dtype) << in.n) + 255) & ~size_t(255);
+        }
+        by_n[in.n].push_back((int)i);
+    }
+    b->state_bytes = arena;
+    std::vector<int> order;
+    b->classes.clear();
+    for (auto &kv : by_n) {
+        auto &v = kv.second;
+        // longest programs first so the tail of each launch is short
+        std::stable_sort(v.begin(), v.end(), [&](int x, int y) { return b->insts[x].op_count > b->insts[y].op_count; });
+        BatchClass cl;
+        cl.n = kv.first;
+        cl.first = (int)order.size();
+        cl.count = (int)v.size();
+        order.insert(order.end(), v.begin(), v.end());
+        b->classes.push_back(cl);
+    }
+    auto alloc = [&](void **p, size_t bytes) -> sv_status {
+        hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 256));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(e == hipErrorOutOfMemory ? SV_ERR_OOM : SV_ERR_HIP,
+                        std::string("svb_run: device allocation: ") + hipGetErrorString(e));
+        }
+        return SV_OK;
+    };
+    sv_status st;
+    if ((st = alloc((void **)&b->d_ops, b->ops.size() * sizeof(BOp))) != SV_OK) return st;
+    if ((st = alloc((void **)&b->d_tables, b->tables.size())) != SV_OK) return st;
+    if ((st = alloc((void **)&b->d_insts, b->insts.size() * sizeof(BInst))) != SV_OK) return st;
+    if ((st = alloc((void **)&b->d_order, order.size() * sizeof(int))) != SV_OK) return st;
+    if ((st = alloc((void **)&b->d_states, arena)) != SV_OK) return st;
+    if ((st = alloc((void **)&b->d_out, b->out_doubles * sizeof(double))) != SV_OK) return st;
+    HIPCK(hipHostMalloc((void **)&b->h_out, std::max<size_t>(b->out_doubles, 1) * sizeof(double)));
+    std::vector<BInst> dev(b->insts.size());
+    for (size_t i = 0; i < b->insts.size(); ++i) {
+        const svb::Meta &m = b->insts[i];
+        BInst &d = dev[i];
+        std::memset(&d, 0, sizeof(d));
+        d.n = m.n;
+        d.ns = m.ns;
+        d.op_count = m.op_count;
+        d.ops = b->d_ops + m.op_begin;
+        d.tables = b->d_tables;
+        d.state = b->d_states + m.state_off;
+        d.out = b->d_out + m.out_off;
+    }
+    HIPCK(hipMemcpy(b->d_ops, b->ops.data(), b->ops.size() * sizeof(BOp), hipMemcpyHostToDevice));
+    HIPCK(hipMemcpy(b->d_tables, b->tables.data(), b->tables.size(), hipMemcpyHostToDevice));
+    HIPCK(hipMemcpy(b->d_insts, dev.data(), dev.size() * sizeof(BInst), hipMemcpyHostToDevice));
+    HIPCK(hipMemcpy(b->d_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (!b->evo_jobs.empty()) {
+        // Spectral arena: each distinct eigen-decomposition once (Vt, then w).
+        std::map<const Spectral *, std::pair<size_t, size_t>> where;
+        std::vector<double> arena;
+        std::vector<EvoJob> jobs;
+        int max_D = 0;
+        for (auto &pj : b->evo_jobs) {
+            const Spectral *sp = pj.first.get();
+            auto it = where.find(sp);
+            if (it == where.end()) {
+                const size_t vt = arena.size();
+                arena.insert(arena.end(), sp->Vt.begin(), sp->Vt.end());
+                const size_t wo = arena.size();
+                arena.insert(arena.end(), sp->w.begin(), sp->w.end());
+                it = where.emplace(sp, std::make_pair(vt, wo)).first;
+            }
+            EvoJob jb = pj.second;
+            jb.vt_off = it->second.first;
+            jb.w_off = it->second.second;
+            jobs.push_back(jb);
+            max_D = std::max(max_D, jb.D);
+        }
+        void *d_arena = nullptr, *d_jobs = nullptr;
+        hipError_t e = hipMalloc(&d_arena, arena.size() * sizeof(double));
+        if (e == hipSuccess) e = hipMalloc(&d_jobs, jobs.size() * sizeof(EvoJob));
+        if (e == hipSuccess)
+            e = hipMemcpy(d_arena, arena.data(), arena.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(d_jobs, jobs.data(), jobs.size() * sizeof(EvoJob), hipMemcpyHostToDevice);
+        sv_status bst = SV_OK;
+        // one launch per 65535 jobs (grid.y limit)
+        for (size_t j0 = 0; e == hipSuccess && bst == SV_OK && j0 < jobs.size(); j0 += 65535) {
+            const int nj = (int)std::min<size_t>(65535, jobs.size() - j0);
+            bst = launch_build_evolutions(static_cast<const EvoJob *>(d_jobs) + j0, nj, max_D,
+                                          static_cast<const double *>(d_arena), b->d_tables, b->dtype, b->stream);
+        }
+        if (e == hipSuccess && bst == SV_OK) e = hipStreamSynchronize(b->stream);
+        if (d_arena) (void)hipFree(d_arena);
+        if (d_jobs) (void)hipFree(d_jobs);
+        if (bst != SV_OK) return bst;
+        if (e != hipSuccess) return fail(SV_ERR_HIP, std::string("svb_run: evolution tables: ") + hipGetErrorString(e));
+    }
+    b->uploaded = true;
+    return SV_OK;
+}
+
+sv_status capture(svb *b)
+{
+    const int nside = (int)b->side.size();
+    HIPCK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipEventRecord(b->ev[0], b->stream);
+    for (int i = 0; i < nside && e == hipSuccess; ++i) e = hipStreamWaitEvent(b->side[i], b->ev[0], 0);
+    for (size_t c = 0; c < b->classes.size() && e == hipSuccess; ++c) {
+        const BatchClass &cl = b->classes[c];
+        if (launch_batch_class(b->d_insts, b->d_order + cl.first, cl.count, cl.n, b->dtype,
+                               b->side[c % nside]) != SV_OK)
+            e = hipErrorLaunchFailure;
+    }
+    for (int i = 0; i < nside && e == hipSuccess; ++i) {
+        e = hipEventRecord(b->ev[1 + i], b->side[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev[1 + i], 0);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->h_out, b->d_out, b->out_doubles * sizeof(double), hipMemcpyDeviceToHost, b->stream);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(SV_ERR_HIP, std::string("svb_run: graph capture: ") +
+                                    hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    b->graph = g;
+    HIPCK(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+    return SV_OK;
+}
+
+}  // namespace
+
+extern "C" sv_status svb_create(sv_dtype dtype, int k_max, void *hip_stream, svb **out)
+{
+    if (!out) return fail(SV_ERR_INVALID, "svb_create: out is NULL");
+    *out = nullptr;
+    if (dtype != SV_C128 && dtype != SV_C64) return fail(SV_ERR_INVALID, "svb_create: bad dtype");
+    if (k_max < 0 || k_max > 5) return fail(SV_ERR_INVALID, "svb_create: k_max must be 0 (autotuned) or 1..5");
+    auto *b = new (std::nothrow) svb;
+    if (!b) return fail(SV_ERR_OOM, "svb_create: out of host memory");
+    b->dtype = dtype;
+    b->k_max = k_max;
+    hipError_t e = hipGetDevice(&b->device);
+    if (e == hipSuccess && !hip_stream) e = hipStreamCreateWithFlags(&b->own_stream, hipStreamNonBlocking);
+    b->stream = hip_stream ? static_cast<hipStream_t>(hip_stream) : b->own_stream;
+    b->side.resize(4, nullptr);
+    b->ev.resize(1 + b->side.size(), nullptr);
+    for (auto &s : b->side)
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    for (auto &v : b->ev)
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&v, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreate(&b->t0);
+    if (e == hipSuccess) e = hipEventCreate(&b->t1);
+    if (e != hipSuccess) {
+        svb_destroy(b);
+        return fail(SV_ERR_HIP, std::string("svb_create: ") + hipGetErrorString(e));
+    }
+    *out = b;
+    return SV_OK;
+}
+
+int hhlsv::batch_tuned_k(sv_dtype dtype, int ns, int m)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find({(int)dtype, ns, m});
+    return it == g_tune.end() ? 0 : it->second;
+}
+
+void hhlsv::batch_set_tuned_k(sv_dtype dtype, int ns, int m, int k)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[{(int)dtype, ns, m}] = k;
+}
+
+extern "C" sv_status svb_add(svb *b, const sv_circuit *hhl, int *index_out)
+{
+    if (!b || !hhl) return fail(SV_ERR_INVALID, "svb_add: NULL argument");
+    const HHLParams &h = hhl->c.hhl;
+    if (!h.is_hhl) return fail(SV_ERR_INVALID, "svb_add: not an HHL circuit");
+    if (hhl->c.n > kMaxBatchQubits) return fail(SV_ERR_INVALID, "svb_add: batch instances are limited to 24 qubits");
+    int k = b->k_max;
+    if (k == 0) k = batch_tuned_k(b->dtype, h.ns, h.m);
+    if (k == 0) k = kDefaultBatchK;
+    sv_circuit *f = nullptr;
+    sv_status st = fuse(hhl, k, &f);
+    if (st != SV_OK) return st;
+    svb::Meta in;
+    std::memset(&in, 0, sizeof(in));
+    in.n = hhl->c.n;
+    in.ns = h.ns;
+    in.op_begin = (int)b->ops.size();
+    {
+        std::vector<BOp> ops;
+        std::vector<unsigned char> tab;
+        std::vector<EvoJob> evo;
+        lower_for_batch(f->c, b->dtype, ops, tab, evo);
+        const size_t base = (b->tables.size() + 255) & ~size_t(255);
+        b->tables.resize(base + tab.size());
+        std::memcpy(b->tables.data() + base, tab.data(), tab.size());
+        for (BOp &op : ops) {
+            op.off += base;
+            b->ops.push_back(op);
+        }
+        for (EvoJob &jb : evo) {
+            jb.out_off += base;
+            b->evo_jobs.emplace_back(f->c.hhl.spec, jb);
+        }
+    }
+    in.op_count = (int)b->ops.size() - in.op_begin;
+    in.out_off = b->out_doubles;
+    b->out_doubles += 2 + 2 * ((size_t)1 << h.ns);
+    circuit_destroy(f);
+    b->insts.push_back(in);
+    b->params.push_back(h);
+    // the device copy and the captured graph no longer match
+    release_device(b);
+    b->have_result = false;
+    if (index_out) *index_out = (int)b->insts.size() - 1;
+    return SV_OK;
+}
+
+extern "C" sv_status svb_run(svb *b)
+{
+    if (!b) return fail(SV_ERR_INVALID, "svb_run: NULL batch");
+    if (b->insts.empty()) return fail(SV_ERR_INVALID, "svb_run: empty batch");
+    sv_status st;
+    if (!b->uploaded) {
+        if ((st = upload(b)) != SV_OK) {
+            release_device(b);
+            return st;
+        }
+        if ((st = capture(b)) != SV_OK) {
+            release_device(b);
+            return st;
+        }
+    }
+    HIPCK(hipEventRecord(b->t0, b->stream));
+    HIPCK(hipGraphLaunch(b->exec, b->stream));
+    HIPCK(hipEventRecord(b->t1, b->stream));
+    HIPCK(hipStreamSynchronize(b->stream));
+    float ms = 0.f;
+    HIPCK(hipEventElapsedTime(&ms, b->t0, b->t1));
+    b->last_ms = ms;
+    b->have_result = true;
+    return SV_OK;
+}
+
+extern "C" sv_status svb_last_run_ms(const svb *b, double *ms)
+{
+    if (!b || !ms) return fail(SV_ERR_INVALID, "svb_last_run_ms: NULL argument");
+    if (!b->have_result) return fail(SV_ERR_INVALID, "svb_last_run_ms: batch has not run");
+    *ms = b->last_ms;
+    return SV_OK;
+}
+
+extern "C" sv_status svb_size(const svb *b, int *count)
+{
+    if (!b || !count) return fail(SV_ERR_INVALID, "svb_size: NULL argument");
+    *count = (int)b->insts.size();
+    return SV_OK;
+}
+
+sv_status hhlsv::recover_solution(const HHLParams &h, const double *p1_y, double *x_hat, int dim,
+                                  sv_solution_info *info)
+{
+    const size_t D = (size_t)1 << h.ns;
+    const double *y = p1_y + 2;
+    double p10 = 0.0, max_imag = 0.0, leak = 0.0, re2 = 0.0;
+    for (size_t i = 0; i < D; ++i) {
+        const double re = y[2 * i], im = y[2 * i + 1];
+        p10 += re * re + im * im;
+        max_imag = std::max(max_imag, std::fabs(im));
+        if ((int)i >= dim)
+            leak += re * re + im * im;
+        else
+            re2 += re * re;
+    }
+    const double rn = std::sqrt(re2);
+    for (int i = 0; i < dim; ++i) x_hat[i] = rn > 0.0 ? y[2 * i] / rn : 0.0;
+    if (info) {
+        info->scale = h.b_norm * rn / h.C;
+        info->p_anc1 = p1_y[0];
+        info->p_anc1_clock0 = p10;
+        info->max_imag = max_imag;
+        info->pad_leak = std::sqrt(leak);
+    }
+    return SV_OK;
+}
+
+extern "C" sv_status svb_solution(svb *b, int index, double *x_hat, int dim, sv_solution_info *info)
+{
+    if (!b || !x_hat) return fail(SV_ERR_INVALID, "svb_solution: NULL argument");
+    if (index < 0 || index >= (int)b->insts.size()) return fail(SV_ERR_INVALID, "svb_solution: index out of range");
+    if (!b->have_result) return fail(SV_ERR_INVALID, "svb_solution: batch has not run");
+    const HHLParams &h = b->params[index];
+    if (dim != h.dim) return fail(SV_ERR_SHAPE, "svb_solution: dim differs from the instance's");
+    return recover_solution(h, b->h_out + b->insts[index].out_off, x_hat, dim, info);
+}
+
+extern "C" sv_status svb_destroy(svb *b)
+{
+    if (!b) return SV_OK;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    release_device(b);
+    for (auto &s : b->side)
+        if (s) (void)hipStreamDestroy(s);
+    for (auto &v : b->ev)
+        if (v) (void)hipEventDestroy(v);
+    if (b->t0) (void)hipEventDestroy(b->t0);
+    if (b->t1) (void)hipEventDestroy(b->t1);
+    if (b->own_stream) (void)hipStreamDestroy(b->own_stream);
+    delete b;
+    return SV_OK;
+}
+
+extern "C" sv_status svb_autotune(sv_dtype dtype, const sv_circuit *sample, int copies, int *best_k,
+                                  double *ms_per_k)
+{
+    if (!sample || copies < 1) return fail(SV_ERR_INVALID, "svb_autotune: need a sample circuit and copies >= 1");
+    const HHLParams &h = sample->c.hhl;
+    if (!h.is_hhl) return fail(SV_ERR_INVALID, "svb_autotune: not an HHL circuit");
+    double best = 0.0;
+    int bk = 0;
+    for (int k = 1; k <= 5; ++k) {
+        svb *b = nullptr;
+        sv_status st = svb_create(dtype, k, nullptr, &b);
+        for (int i = 0; i < copies && st == SV_OK; ++i) st = svb_add(b, sample, nullptr);
+        if (st == SV_OK) st = svb_run(b);   // upload + capture + first run
+        double ms = 0.0;
+        if (st == SV_OK) st = svb_run(b);
+        if (st == SV_OK) st = svb_last_run_ms(b, &ms);
+        svb_destroy(b);
+        if (st != SV_OK) return st;
+        if (ms_per_k) ms_per_k[k - 1] = ms;
+        if (bk == 0 || ms < best) {
+            best = ms;
+            bk = k;
+        }
+    }
+    batch_set_tuned_k(dtype, h.ns, h.m, bk);
+    if (best_k) *best_k = bk;
+    return SV_OK;
+}

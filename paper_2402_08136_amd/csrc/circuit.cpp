@@ -314,7 +314,11 @@ extern "C" sv_status circuit_serialize(const sv_circuit *c, void *buf, size_t *l
 {
     if (!c || !len) return fail(SV_ERR_INVALID, "circuit_serialize: NULL argument");
     size_t need = 8;
-    for (const auto &g : c->c.gates) need += 12 + 4 * g.qubits.size() + 8 * g.params.size();
+    for (const auto &g : c->c.gates) {
+        size_t np = g.params.size();
+        if (gate_deferred(g)) np = (size_t)2 << (2 * (g.qubits.size() - 1));
+        need += 12 + 4 * g.qubits.size() + 8 * np;
+    }
     if (!buf) {
         *len = need;
         return SV_OK;
@@ -327,7 +331,13 @@ extern "C" sv_status circuit_serialize(const sv_circuit *c, void *buf, size_t *l
     auto put32 = [&](int32_t v) { std::memcpy(p, &v, 4); p += 4; };
     put32(c->c.n);
     put32((int32_t)c->c.gates.size());
-    for (const auto &g : c->c.gates) {
+    for (const auto &g0 : c->c.gates) {
+        Gate tmp;
+        if (gate_deferred(g0)) {
+            tmp = g0;
+            materialize(tmp, c->c.hhl);
+        }
+        const Gate &g = gate_deferred(g0) ? tmp : g0;
         put32(g.kind);
         put32((int32_t)g.qubits.size());
         put32((int32_t)g.params.size());
@@ -349,8 +359,14 @@ extern "C" sv_status fuse(const sv_circuit *in, int k_max, sv_circuit **out)
     blocks.reserve(in->c.gates.size());
     std::vector<int> last(n, -1);
 
-    for (const Gate &g : in->c.gates) {
-        const int w = fused_width(g);
+    for (const Gate &g0 : in->c.gates) {
+        const int w = fused_width(g0);
+        Gate tmp;
+        if (w <= k_max && gate_deferred(g0)) {  // merged on the host: build its matrix here
+            tmp = g0;
+            materialize(tmp, in->c.hhl);
+        }
+        const Gate &g = (w <= k_max && gate_deferred(g0)) ? tmp : g0;
         if (w > k_max) {
             Block b;
             b.qubits = g.qubits;

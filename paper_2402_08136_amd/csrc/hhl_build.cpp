@@ -14,106 +14,136 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 
-inline double &at(std::vector<double> &M, int N, int i, int j) { return M[(size_t)i * N + j]; }
-
-// Householder reduction of a symmetric matrix to tridiagonal form T with
-// A = Z T Z^T (Golub & Van Loan, Sec. 8.3.1).  T and Z are dense N x N.
-void tridiagonalise(std::vector<double> &T, std::vector<double> &Z, int N)
+// Householder reduction of a symmetric matrix (dense, row-major, destroyed)
+// to tridiagonal form: A = Q T Q^T with T = tridiag(e, d, e).  Returns
+// Qt = Q^T (row-major).  Golub & Van Loan, Sec. 8.3.1: for each column a
+// reflector I - 2 v v^T, with p = A v, w = p - (v.p) v, A -= 2 (v w^T + w v^T)
+// on the trailing block.
+void tridiagonalise(std::vector<double> &A, int N, std::vector<double> &d, std::vector<double> &e,
+                    std::vector<double> &Qt)
 {
-    Z.assign((size_t)N * N, 0.0);
-    for (int i = 0; i < N; ++i) at(Z, N, i, i) = 1.0;
-    std::vector<double> v(N);
+    d.assign(N, 0.0);
+    e.assign(N > 1 ? N - 1 : 0, 0.0);
+    std::vector<double> vs((size_t)N * N, 0.0);   // reflector k in row k (offset k+1)
+    std::vector<char> used(N, 0);
+    std::vector<double> p(N), w(N);
     for (int k = 0; k + 2 < N; ++k) {
-        const int L = N - k - 1;  // reflector acts on indices k+1..N-1
+        const int L = N - k - 1;
+        double *v = &vs[(size_t)k * N];            // v[0..L)
+        const double *col = &A[(size_t)k * N + k + 1];  // row k = column k (symmetric)
         double xn = 0.0;
-        for (int j = 0; j < L; ++j) xn += at(T, N, k + 1 + j, k) * at(T, N, k + 1 + j, k);
+        for (int j = 0; j < L; ++j) xn += col[j] * col[j];
         xn = std::sqrt(xn);
-        if (xn == 0.0) continue;
-        const double x0 = at(T, N, k + 1, k);
-        const double alpha = x0 >= 0.0 ? -xn : xn;
-        for (int j = 0; j < L; ++j) v[j] = at(T, N, k + 1 + j, k);
+        if (xn == 0.0) {
+            e[k] = 0.0;
+            continue;
+        }
+        const double alpha = col[0] >= 0.0 ? -xn : xn;
+        for (int j = 0; j < L; ++j) v[j] = col[j];
         v[0] -= alpha;
         double vn = 0.0;
         for (int j = 0; j < L; ++j) vn += v[j] * v[j];
         vn = std::sqrt(vn);
-        if (vn == 0.0) continue;
+        if (vn == 0.0) {
+            e[k] = alpha;
+            continue;
+        }
         for (int j = 0; j < L; ++j) v[j] /= vn;
-        // T <- H T H with H = I - 2 v v^T on the trailing indices.
-        for (int i = 0; i < N; ++i) {      // columns
-            double s = 0.0;
-            for (int j = 0; j < L; ++j) s += at(T, N, i, k + 1 + j) * v[j];
-            for (int j = 0; j < L; ++j) at(T, N, i, k + 1 + j) -= 2.0 * s * v[j];
+        used[k] = 1;
+        // p = A_sub v (rows of the trailing block are contiguous)
+        double kv = 0.0;
+        for (int i = 0; i < L; ++i) {
+            const double *row = &A[(size_t)(k + 1 + i) * N + k + 1];
+            double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+            int j = 0;
+            for (; j + 3 < L; j += 4) {
+                s0 += row[j] * v[j];
+                s1 += row[j + 1] * v[j + 1];
+                s2 += row[j + 2] * v[j + 2];
+                s3 += row[j + 3] * v[j + 3];
+            }
+            for (; j < L; ++j) s0 += row[j] * v[j];
+            p[i] = (s0 + s1) + (s2 + s3);
+            kv += v[i] * p[i];
         }
-        for (int i = 0; i < N; ++i) {      // rows
-            double s = 0.0;
-            for (int j = 0; j < L; ++j) s += v[j] * at(T, N, k + 1 + j, i);
-            for (int j = 0; j < L; ++j) at(T, N, k + 1 + j, i) -= 2.0 * s * v[j];
+        for (int i = 0; i < L; ++i) w[i] = p[i] - kv * v[i];
+        for (int i = 0; i < L; ++i) {
+            double *row = &A[(size_t)(k + 1 + i) * N + k + 1];
+            const double vi = 2.0 * v[i], wi = 2.0 * w[i];
+            for (int j = 0; j < L; ++j) row[j] -= vi * w[j] + wi * v[j];
         }
-        for (int i = 0; i < N; ++i) {      // Z <- Z H
-            double s = 0.0;
-            for (int j = 0; j < L; ++j) s += at(Z, N, i, k + 1 + j) * v[j];
-            for (int j = 0; j < L; ++j) at(Z, N, i, k + 1 + j) -= 2.0 * s * v[j];
+        e[k] = alpha;
+    }
+    for (int k = 0; k < N; ++k) d[k] = A[(size_t)k * N + k];
+    if (N >= 2) e[N - 2] = A[(size_t)(N - 2) * N + N - 1];
+    // Q^T = H_{N-3} ... H_0: apply the reflectors from the left, last first is
+    // not needed since each acts on a trailing block: M <- H_k M for k = 0, 1, ...
+    Qt.assign((size_t)N * N, 0.0);
+    for (int i = 0; i < N; ++i) Qt[(size_t)i * N + i] = 1.0;
+    std::vector<double> sv(N);
+    for (int k = 0; k + 2 < N; ++k) {
+        if (!used[k]) continue;
+        const int L = N - k - 1;
+        const double *v = &vs[(size_t)k * N];
+        std::fill(sv.begin(), sv.end(), 0.0);
+        for (int i = 0; i < L; ++i) {
+            const double *row = &Qt[(size_t)(k + 1 + i) * N];
+            const double vi = v[i];
+            for (int j = 0; j < N; ++j) sv[j] += vi * row[j];
         }
-        for (int j = 1; j < L; ++j) at(T, N, k + 1 + j, k) = at(T, N, k, k + 1 + j) = 0.0;
-        at(T, N, k + 1, k) = at(T, N, k, k + 1) = alpha;
+        for (int i = 0; i < L; ++i) {
+            double *row = &Qt[(size_t)(k + 1 + i) * N];
+            const double vi = 2.0 * v[i];
+            for (int j = 0; j < N; ++j) row[j] -= vi * sv[j];
+        }
     }
 }
 
-// Rotate rows and columns p, p+1 of T (T <- G T G^T) and columns of Z.
-void rotate(std::vector<double> &T, std::vector<double> &Z, int N, int p,
-            double c, double s)
-{
-    for (int i = 0; i < N; ++i) {
-        const double a = at(T, N, p, i), b = at(T, N, p + 1, i);
-        at(T, N, p, i) = c * a + s * b;
-        at(T, N, p + 1, i) = -s * a + c * b;
-    }
-    for (int i = 0; i < N; ++i) {
-        const double a = at(T, N, i, p), b = at(T, N, i, p + 1);
-        at(T, N, i, p) = c * a + s * b;
-        at(T, N, i, p + 1) = -s * a + c * b;
-    }
-    for (int i = 0; i < N; ++i) {
-        const double a = at(Z, N, i, p), b = at(Z, N, i, p + 1);
-        at(Z, N, i, p) = c * a + s * b;
-        at(Z, N, i, p + 1) = -s * a + c * b;
-    }
-}
-
-// Implicit symmetric QR with Wilkinson shifts on a tridiagonal T, chasing the
-// bulge with Givens rotations (Golub & Van Loan, Alg. 8.3.2/8.3.3).
-bool tridiagonal_qr(std::vector<double> &T, std::vector<double> &Z, int N)
+// Implicit symmetric QR with Wilkinson shifts on T = tridiag(e, d, e)
+// (Golub & Van Loan, Alg. 8.3.2): each step chases a bulge down the active
+// block with Givens rotations G(p, p+1) = [[c, s], [-s, c]], T <- G T G^T,
+// applied to d / e in O(1) and to the rows p, p+1 of Z^T in O(N).
+bool tridiagonal_qr(std::vector<double> &d, std::vector<double> &e, std::vector<double> &Zt, int N)
 {
     const double eps = 2.220446049250313e-16;
     int hi = N - 1, iters = 0;
     while (hi > 0) {
-        if (std::fabs(at(T, N, hi, hi - 1)) <=
-            eps * (std::fabs(at(T, N, hi, hi)) + std::fabs(at(T, N, hi - 1, hi - 1)))) {
-            at(T, N, hi, hi - 1) = at(T, N, hi - 1, hi) = 0.0;
+        if (std::fabs(e[hi - 1]) <= eps * (std::fabs(d[hi]) + std::fabs(d[hi - 1]))) {
+            e[hi - 1] = 0.0;
             --hi;
             continue;
         }
         if (++iters > 60 * N) return false;
         int lo = hi - 1;
-        while (lo > 0 && std::fabs(at(T, N, lo, lo - 1)) >
-                             eps * (std::fabs(at(T, N, lo, lo)) + std::fabs(at(T, N, lo - 1, lo - 1))))
-            --lo;
-        if (lo > 0) at(T, N, lo, lo - 1) = at(T, N, lo - 1, lo) = 0.0;
-        // Wilkinson shift from the trailing 2x2 block.
-        const double a = at(T, N, hi - 1, hi - 1), b = at(T, N, hi, hi - 1), c = at(T, N, hi, hi);
-        const double d = 0.5 * (a - c);
-        const double mu = c - b * b / (d + (d >= 0 ? 1.0 : -1.0) * std::hypot(d, b));
-        double x = at(T, N, lo, lo) - mu, z = at(T, N, lo + 1, lo);
+        while (lo > 0 && std::fabs(e[lo - 1]) > eps * (std::fabs(d[lo]) + std::fabs(d[lo - 1]))) --lo;
+        if (lo > 0) e[lo - 1] = 0.0;
+        const double a = d[hi - 1], b = e[hi - 1], c = d[hi];
+        const double dd = 0.5 * (a - c);
+        const double mu = c - b * b / (dd + (dd >= 0 ? 1.0 : -1.0) * std::hypot(dd, b));
+        double x = d[lo] - mu, z = e[lo], bulge = 0.0;
         for (int p = lo; p < hi; ++p) {
             if (p > lo) {
-                x = at(T, N, p, p - 1);
-                z = at(T, N, p + 1, p - 1);
+                x = e[p - 1];
+                z = bulge;
             }
             const double r = std::hypot(x, z);
             const double cs = r == 0.0 ? 1.0 : x / r;
             const double sn = r == 0.0 ? 0.0 : z / r;
-            rotate(T, Z, N, p, cs, sn);
-            if (p > lo) at(T, N, p + 1, p - 1) = at(T, N, p - 1, p + 1) = 0.0;
+            if (p > lo) e[p - 1] = r;
+            const double a0 = d[p], b0 = e[p], d1 = d[p + 1];
+            d[p] = cs * cs * a0 + 2.0 * cs * sn * b0 + sn * sn * d1;
+            d[p + 1] = sn * sn * a0 - 2.0 * cs * sn * b0 + cs * cs * d1;
+            e[p] = cs * sn * (d1 - a0) + (cs * cs - sn * sn) * b0;
+            if (p + 1 < hi) {
+                bulge = sn * e[p + 1];
+                e[p + 1] = cs * e[p + 1];
+            }
+            double *zp = &Zt[(size_t)p * N], *zq = &Zt[(size_t)(p + 1) * N];
+            for (int i = 0; i < N; ++i) {
+                const double u = zp[i], v = zq[i];
+                zp[i] = cs * u + sn * v;
+                zq[i] = -sn * u + cs * v;
+            }
         }
     }
     return true;
@@ -131,18 +161,18 @@ int ceil_log2(int v)
 bool sym_eig(const std::vector<double> &A, int N, std::vector<double> &w,
              std::vector<double> &V)
 {
-    std::vector<double> T = A, Z;
-    tridiagonalise(T, Z, N);
-    if (!tridiagonal_qr(T, Z, N)) return false;
+    std::vector<double> T = A, d, e, Zt;
+    tridiagonalise(T, N, d, e, Zt);
+    if (!tridiagonal_qr(d, e, Zt, N)) return false;
     std::vector<int> order(N);
     for (int i = 0; i < N; ++i) order[i] = i;
-    std::sort(order.begin(), order.end(),
-              [&](int p, int q) { return at(T, N, p, p) < at(T, N, q, q); });
+    std::sort(order.begin(), order.end(), [&](int p, int q) { return d[p] < d[q]; });
     w.resize(N);
     V.assign((size_t)N * N, 0.0);
     for (int k = 0; k < N; ++k) {
-        w[k] = at(T, N, order[k], order[k]);
-        for (int i = 0; i < N; ++i) V[(size_t)i * N + k] = at(Z, N, i, order[k]);
+        w[k] = d[order[k]];
+        const double *z = &Zt[(size_t)order[k] * N];
+        for (int i = 0; i < N; ++i) V[(size_t)i * N + k] = z[i];
     }
     return true;
 }
@@ -210,33 +240,49 @@ void add_qft(Circuit &c, int q0, int m, bool inverse)
     for (auto &g : seq) c.gates.push_back(std::move(g));
 }
 
-// e^{+i A t 2^j} (or its inverse) from A = V diag(w) V^T, each power taken
-// directly from the eigenvalues (phase reduced mod 2 pi in double).
-std::vector<double> evolution(const std::vector<double> &w, const std::vector<double> &V,
-                              int D, double tj, bool inverse)
+}  // namespace
+
+// e^{+iAt 2^j} (or its inverse) from A' = V diag(w) V^T, each power taken
+// directly from the eigenvalues with the phase reduced mod 2 pi in double:
+// U[a][b] = sum_k V[a][k] V[b][k] e^{+-i phi_k}.  U is symmetric, so only
+// b >= a is accumulated (rows of Vt are contiguous: AXPY over b) and mirrored.
+std::vector<double> evolution_params(const Spectral &sp, int j, bool inverse)
 {
+    const int D = sp.D;
+    const double tj = sp.t * std::ldexp(1.0, j);
     std::vector<double> cs(D), sn(D);
     for (int k = 0; k < D; ++k) {
-        const double ph = std::fmod(w[k] * tj, 2.0 * kPi);
+        const double ph = std::fmod(sp.w[k] * tj, 2.0 * kPi);
         cs[k] = std::cos(ph);
         sn[k] = inverse ? -std::sin(ph) : std::sin(ph);
+    }
+    std::vector<double> re((size_t)D * D, 0.0), im((size_t)D * D, 0.0);
+    for (int a = 0; a < D; ++a) {
+        double *ra = &re[(size_t)a * D], *ia = &im[(size_t)a * D];
+        for (int k = 0; k < D; ++k) {
+            const double *vk = &sp.Vt[(size_t)k * D];
+            const double fc = vk[a] * cs[k], fs = vk[a] * sn[k];
+            for (int b = a; b < D; ++b) {
+                ra[b] += fc * vk[b];
+                ia[b] += fs * vk[b];
+            }
+        }
     }
     std::vector<double> U((size_t)2 * D * D);
     for (int a = 0; a < D; ++a)
         for (int b = 0; b < D; ++b) {
-            double re = 0.0, im = 0.0;
-            for (int k = 0; k < D; ++k) {
-                const double vv = V[(size_t)a * D + k] * V[(size_t)b * D + k];
-                re += vv * cs[k];
-                im += vv * sn[k];
-            }
-            U[2 * ((size_t)a * D + b)] = re;
-            U[2 * ((size_t)a * D + b) + 1] = im;
+            const size_t src = a <= b ? (size_t)a * D + b : (size_t)b * D + a;
+            U[2 * ((size_t)a * D + b)] = re[src];
+            U[2 * ((size_t)a * D + b) + 1] = im[src];
         }
     return U;
 }
 
-}  // namespace
+void materialize(Gate &g, const HHLParams &h)
+{
+    if (!gate_deferred(g) || !h.spec) return;
+    g.params = evolution_params(*h.spec, g.evo_j, g.evo_inv);
+}
 
 }  // namespace hhlsv
 
@@ -259,6 +305,12 @@ extern "C" sv_status sv_qubit_estimate(int dim, double kappa, int has_negative,
 extern "C" sv_status circuit_build_hhl(const double *A, const double *b, int dim,
                                        int clock_bits, double t, sv_circuit **out)
 {
+    return circuit_build_hhl_ex(A, b, dim, clock_bits, t, 0, out);
+}
+
+extern "C" sv_status circuit_build_hhl_ex(const double *A, const double *b, int dim,
+                                          int clock_bits, double t, int flags, sv_circuit **out)
+{
     if (!out) return fail(SV_ERR_INVALID, "circuit_build_hhl: out is NULL");
     *out = nullptr;
     if (!A || !b) return fail(SV_ERR_INVALID, "circuit_build_hhl: A or b is NULL");
@@ -270,6 +322,7 @@ extern "C" sv_status circuit_build_hhl(const double *A, const double *b, int dim
     if (n > kMaxQubits) return fail(SV_ERR_INVALID, "circuit_build_hhl: more than 34 qubits");
     if (ns > kMaxDenseQubits) return fail(SV_ERR_INVALID, "circuit_build_hhl: system register wider than 12 qubits");
     if (!std::isfinite(t)) return fail(SV_ERR_INVALID, "circuit_build_hhl: t is not finite");
+    if (flags & ~SV_HHL_DEVICE_EVOLUTIONS) return fail(SV_ERR_INVALID, "circuit_build_hhl_ex: unknown flags");
 
     // Step 1: symmetry (the Hermitian case), ||b||, pad to 2^ns with a unit
     // diagonal and zero entries of b.
@@ -341,20 +394,33 @@ extern "C" sv_status circuit_build_hhl(const double *A, const double *b, int dim
         sv_qubit_estimate(D, std::max(1.0, kappa), 0, &nd, &nq, &nt);
         h.n_qpe_est = nq;
     }
-
-    std::vector<int> sys(ns);
-    for (int s = 0; s < ns; ++s) sys[s] = s;
-    auto ctrl_sys = [&](int ctl) {
-        std::vector<int> q{ctl};
-        q.insert(q.end(), sys.begin(), sys.end());
-        return q;
+    {
+        auto sp = std::make_shared<Spectral>();
+        sp->D = D;
+        sp->w = w;
+        sp->t = tt;
+        sp->Vt.resize((size_t)D * D);
+        for (int k = 0; k < D; ++k)
+            for (int i = 0; i < D; ++i) sp->Vt[(size_t)k * D + i] = V[(size_t)i * D + k];
+        h.spec = sp;
+    }
+    const bool defer = (flags & SV_HHL_DEVICE_EVOLUTIONS) != 0;
+    auto evo = [&](int ctl, int j, bool inverse) {
+        Gate g;
+        g.kind = SV_GATE_CDENSE;
+        g.qubits = {ctl};
+        for (int q = 0; q < ns; ++q) g.qubits.push_back(q);
+        g.evo_j = j;
+        g.evo_inv = inverse;
+        if (!defer) g.params = evolution_params(*h.spec, j, inverse);
+        c.gates.push_back(std::move(g));
     };
+
     // |b> on the system register.
     add_state_prep(c, bh, ns);
     // Phase estimation with controlled e^{iAt 2^j}.
     for (int j = 0; j < m; ++j) add(c, SV_GATE_H, {ns + j});
-    for (int j = 0; j < m; ++j)
-        add(c, SV_GATE_CDENSE, ctrl_sys(ns + j), evolution(w, V, D, tt * std::ldexp(1.0, j), false));
+    for (int j = 0; j < m; ++j) evo(ns + j, j, false);
     add_qft(c, ns, m, true);
     // Eigenvalue inversion: clock value c stands for lambda = C c / j0, and
     // the ancilla's |1> amplitude becomes C / lambda = j0 / c (clamped).
@@ -369,8 +435,7 @@ extern "C" sv_status circuit_build_hhl(const double *A, const double *b, int dim
     }
     // Uncompute.
     add_qft(c, ns, m, false);
-    for (int j = m - 1; j >= 0; --j)
-        add(c, SV_GATE_CDENSE, ctrl_sys(ns + j), evolution(w, V, D, tt * std::ldexp(1.0, j), true));
+    for (int j = m - 1; j >= 0; --j) evo(ns + j, j, true);
     for (int j = 0; j < m; ++j) add(c, SV_GATE_H, {ns + j});
     *out = sc;
     return SV_OK;

@@ -1,0 +1,67 @@
+// Internal helpers shared by the batch and serving runtimes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+
+namespace hhlsv {
+
+// One lowered op of a batch instance (device layout).
+struct BOp {
+    int type;        // OP_DENSE / OP_DIAG / OP_WIDE / OP_UCRY
+    int k;           // targets (UCRY: controls)
+    int target;      // UCRY target
+    int control;     // OP_WIDE control, -1 = none
+    int contiguous;  // targets (UCRY: controls) are q[0], q[0]+1, ...
+    int q[kMaxUcryControls];
+    int pad;
+    unsigned long long off;   // byte offset of the op's table in the instance's tables
+};
+
+// One instance of a batch launch: its program and buffers in device memory.
+struct BInst {
+    int n, ns, op_count, pad;
+    const BOp *ops;
+    const unsigned char *tables;
+    unsigned char *state;   // HBM state (2^n amplitudes) when it does not fit in LDS
+    double *out;            // [P(ancilla=1), 0, y_0.re, y_0.im, ...], 2 + 2^(ns+1) doubles
+};
+
+// LDS budget of one batch workgroup and whether an n-qubit state fits in it.
+constexpr int kBatchThreads = 256;
+constexpr int kBatchLdsLimit = 160 * 1024;
+inline size_t batch_lds_bytes(int n, sv_dtype d, bool *resident)
+{
+    const size_t red = kBatchThreads * 8;
+    const size_t sb = (d == SV_C128 ? size_t(16) : size_t(8)) << n;
+    *resident = sb + red <= (size_t)kBatchLdsLimit;
+    return red + (*resident ? sb : 0);
+}
+
+// Launch the batch kernel over count instances (insts[order[i]]) that all
+// have n qubits; grid chosen from the LDS footprint.
+sv_status launch_batch_class(const BInst *d_insts, const int *d_order, int count, int n, sv_dtype dtype,
+                             hipStream_t st);
+
+// Lower a (fused) HHL circuit into batch ops and a table image.  Deferred
+// evolutions get a reserved table region and an entry in evo (out_off set,
+// vt_off / w_off left for the caller).
+struct EvoJob;
+void lower_for_batch(const Circuit &f, sv_dtype dtype, std::vector<BOp> &ops, std::vector<unsigned char> &tables,
+                     std::vector<EvoJob> &evo);
+
+// k_max used for batch instances when the batch was created with k_max = 0
+// and the autotuner has no entry for the instance's shape.
+constexpr int kDefaultBatchK = 3;
+
+// Autotuned k_max per (dtype, ns, m); 0 when unknown.
+int batch_tuned_k(sv_dtype dtype, int ns, int m);
+void batch_set_tuned_k(sv_dtype dtype, int ns, int m, int k);
+
+// Sec. III-A step 4 from [P(ancilla = 1), pad, y_0.re, y_0.im, ...]:
+// x_hat = Re(y) / ||Re(y)|| over the first dim entries, scale = ||b|| ||Re y|| / C.
+sv_status recover_solution(const HHLParams &h, const double *p1_y, double *x_hat, int dim,
+                           sv_solution_info *info);
+
+}  // namespace hhlsv

@@ -3,6 +3,7 @@
 
 #include <complex>
 #include <cstdint>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -26,6 +27,23 @@ struct Gate {
     int kind = 0;                 // sv_gate_kind
     std::vector<int> qubits;      // as given (DENSE/DIAG after fusion: sorted)
     std::vector<double> params;   // angles, or interleaved complex entries
+    // HHL evolution gates e^{iAt 2^j} (CDENSE on the system register): j and
+    // whether it is the inverse.  With empty params the matrix is "deferred":
+    // it is built from the circuit's eigen-decomposition where it is needed
+    // (on the device when applied, on the host by materialize()).
+    int evo_j = -1;
+    bool evo_inv = false;
+};
+
+inline bool gate_deferred(const Gate &g) { return g.evo_j >= 0 && g.params.empty(); }
+
+// Eigen-decomposition of the padded system matrix, A' = V diag(w) V^T, with
+// the eigenvectors as the rows of Vt (Vt[k * D + i] = V[i][k]).
+struct Spectral {
+    int D = 0;
+    std::vector<double> Vt;
+    std::vector<double> w;
+    double t = 0;
 };
 
 // Parameters an HHL circuit was built with (Sec. III-A step 1).
@@ -33,7 +51,14 @@ struct HHLParams {
     bool is_hhl = false;
     int dim = 0, ns = 0, m = 0, j0 = 0, n_qpe_est = 0;
     double t = 0, C = 0, lambda_lo = 0, lambda_hi = 0, kappa = 0, b_norm = 0;
+    std::shared_ptr<const Spectral> spec;
 };
+
+// Interleaved complex entries of e^{+-i A' t 2^j} = V diag(e^{+-i phi}) V^T,
+// phi_k = fmod(w_k t 2^j, 2 pi) (FP64, on the host).
+std::vector<double> evolution_params(const Spectral &sp, int j, bool inverse);
+// Fill a deferred gate's params from the circuit's eigen-decomposition.
+void materialize(Gate &g, const HHLParams &h);
 
 struct DeviceProgram;  // device copy of a circuit's tables (device.hip)
 

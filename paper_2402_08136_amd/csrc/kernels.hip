@@ -11,13 +11,10 @@
 #include <cstring>
 #include <mutex>
 
+#include "device_common.hpp"
 #include "kernels.hpp"
 
 namespace hhlsv {
-
-template <typename R> struct V2;
-template <> struct V2<double> { typedef double type __attribute__((ext_vector_type(2))); };
-template <> struct V2<float> { typedef float type __attribute__((ext_vector_type(2))); };
 
 #define HIPCK(x)                                                                   \
     do {                                                                           \
@@ -27,39 +24,6 @@ template <> struct V2<float> { typedef float type __attribute__((ext_vector_type
     } while (0)
 
 namespace {
-
-template <typename T>
-__device__ __forceinline__ T ld_nt(const T *p) { return __builtin_nontemporal_load(p); }
-template <typename T>
-__device__ __forceinline__ void st_nt(T v, T *p) { __builtin_nontemporal_store(v, p); }
-
-// acc += m * v (complex), as four fused multiply-adds.
-template <typename C>
-__device__ __forceinline__ void cmac(C &acc, const C m, const C v)
-{
-    acc.x = __builtin_fma(m.x, v.x, acc.x);
-    acc.x = __builtin_fma(-m.y, v.y, acc.x);
-    acc.y = __builtin_fma(m.x, v.y, acc.y);
-    acc.y = __builtin_fma(m.y, v.x, acc.y);
-}
-
-// Offset the (uniform) matrix pointer by a zero the optimiser cannot see
-// through, so loads of the matrix are not hoisted out of the tile loop (which
-// would pin the whole gate matrix in registers).  The pointer keeps its
-// global address space and stays uniform, so the loads remain scalar.
-template <typename T>
-__device__ __forceinline__ const T *opaque(const T *p)
-{
-    int z = 0;
-    asm volatile("" : "+s"(z));
-    return p + z;
-}
-
-__device__ __forceinline__ uint64_t insert_zero(uint64_t x, int p)
-{
-    const uint64_t lo = x & ((uint64_t(1) << p) - 1);
-    return ((x >> p) << (p + 1)) | lo;
-}
 
 // ---------------------------------------------------------------------------
 // Dense k-qubit gate, tiled for 64-lane waves (n >= 6 + k).
@@ -225,7 +189,8 @@ __global__ __launch_bounds__(256) void k_diag(typename V2<R>::type *__restrict__
 // Wide dense gate (k up to 12 targets, optional control), e.g. the
 // controlled e^{iAt 2^j} of phase estimation on the whole system register.
 // One workgroup per group: the 2^k amplitudes are staged in LDS, each thread
-// produces rows of U v, and writes them back in place.
+// produces rows of U v, and writes them back in place.  The table holds U^T
+// (column-major U).  Used for 2^k outside [32, 512].
 // ---------------------------------------------------------------------------
 struct WideArgs {
     uint64_t ngroups;
@@ -262,13 +227,141 @@ __global__ __launch_bounds__(256) void k_wide(typename V2<R>::type *__restrict__
         __syncthreads();
         for (int r = threadIdx.x; r < K; r += blockDim.x) {
             C acc = {0, 0};
-            const C *row = U + (size_t)r * K;
-            for (int c = 0; c < K; ++c) cmac(acc, row[c], v[c]);
+            for (int c = 0; c < K; ++c) cmac(acc, U[(size_t)c * K + r], v[c]);
             uint64_t off = 0;
             for (int j = 0; j < a.k; ++j) off |= (uint64_t)((r >> j) & 1) << a.q[j];
             psi[base + off] = acc;
         }
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Wide dense gate as a register-blocked complex GEMM, for 32 <= 2^k <= 512.
+// With the group ("row") index g over the non-target bits, out[g][i] =
+// sum_c U[i][c] in[g][c], i.e. OUT = IN U^T.  A wave owns RW rows (times
+// 64/D sub-rows when D < 64) and all D columns of them: lane l owns columns
+// l % 64 + 64 t (t < CT).  Each step c loads column c of U (row c of the
+// stored U^T, coalesced across lanes) and one amplitude per row (the same
+// address across the lanes of a row), then does RW*CT complex FMAs.  A row
+// is read and written only by its own wave, so the in-place update needs no
+// workgroup barrier.
+// ---------------------------------------------------------------------------
+struct WideGemmArgs {
+    uint64_t ngroups;
+    int k;
+    int q[kMaxDenseQubits];
+    int control;      // -1: none
+    int contiguous;   // targets are q[0], q[0]+1, ...
+};
+
+template <typename R, int CT, int RW>
+__global__ __launch_bounds__(256) void k_wide_gemm(typename V2<R>::type *__restrict__ psi,
+                                                   const typename V2<R>::type *__restrict__ UT,
+                                                   WideGemmArgs a)
+{
+    typedef typename V2<R>::type C;
+    const int D = 1 << a.k;
+    const int lpr = D < 64 ? D : 64;          // lanes per row
+    const int rps = 64 / lpr;                 // rows per wave step
+    const int lane = threadIdx.x & 63;
+    const int j0 = lane % lpr;
+    const int sub = lane / lpr;
+    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    const uint64_t rows_per_wave = (uint64_t)RW * rps;
+    auto off = [&](uint64_t c) -> uint64_t {
+        if (a.contiguous) return c << a.q[0];
+        uint64_t o = 0;
+        for (int j = 0; j < a.k; ++j) o |= ((c >> j) & 1) << a.q[j];
+        return o;
+    };
+    auto gbase = [&](uint64_t g) -> uint64_t {
+        uint64_t b = g;
+        bool placed = a.control < 0;
+        for (int j = 0; j < a.k; ++j) {
+            if (!placed && a.control < a.q[j]) {
+                b = insert_zero(b, a.control) | (uint64_t(1) << a.control);
+                placed = true;
+            }
+            b = insert_zero(b, a.q[j]);
+        }
+        if (!placed) b = insert_zero(b, a.control) | (uint64_t(1) << a.control);
+        return b;
+    };
+    for (uint64_t rb = wave * rows_per_wave; rb < a.ngroups; rb += nwaves * rows_per_wave) {
+        uint64_t gb[RW];
+        bool ok[RW];
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const uint64_t g = rb + sub + (uint64_t)rps * r;
+            ok[r] = g < a.ngroups;
+            gb[r] = ok[r] ? gbase(g) : 0;
+        }
+        C acc[RW][CT];
+#pragma unroll
+        for (int r = 0; r < RW; ++r)
+#pragma unroll
+            for (int t = 0; t < CT; ++t) acc[r][t] = C{0, 0};
+        for (int c = 0; c < D; ++c) {
+            const uint64_t oc = off(c);
+            C u[CT];
+#pragma unroll
+            for (int t = 0; t < CT; ++t) u[t] = UT[(size_t)c * D + j0 + 64 * t];
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                const C x = ok[r] ? psi[gb[r] | oc] : C{0, 0};
+#pragma unroll
+                for (int t = 0; t < CT; ++t) cmac(acc[r][t], u[t], x);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < CT; ++t) {
+            const uint64_t oj = off(j0 + 64 * t);
+#pragma unroll
+            for (int r = 0; r < RW; ++r)
+                if (ok[r]) psi[gb[r] | oj] = acc[r][t];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Evolution tables on the device: U[a][b] = sum_k V[a][k] V[b][k] e^{+-i phi_k}
+// with phi_k = fmod(w_k t 2^j, 2 pi), accumulated in FP64 and stored in the
+// program dtype.  U is symmetric, so the stored U is also U^T (the OP_WIDE
+// layout).  One job per blockIdx.y.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(256) void k_build_evolution(const EvoJob *__restrict__ jobs,
+                                                         const double *__restrict__ spec,
+                                                         unsigned char *__restrict__ tables)
+{
+    typedef typename V2<R>::type C;
+    extern __shared__ double ph[];
+    const EvoJob jb = jobs[blockIdx.y];
+    const int D = jb.D;
+    const double tj = jb.t * (double)(1ull << jb.j);
+    const double two_pi = 6.28318530717958647692;
+    for (int k = threadIdx.x; k < D; k += blockDim.x) {
+        const double a = fmod(spec[jb.w_off + k] * tj, two_pi);
+        double sn, cs;
+        sincos(a, &sn, &cs);
+        ph[2 * k] = cs;
+        ph[2 * k + 1] = jb.inv ? -sn : sn;
+    }
+    __syncthreads();
+    const double *vt = spec + jb.vt_off;
+    C *out = reinterpret_cast<C *>(tables + jb.out_off);
+    const uint32_t total = (uint32_t)D * (uint32_t)D;
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
+        const uint32_t a = idx / D, b = idx % D;
+        double re = 0.0, im = 0.0;
+        for (int k = 0; k < D; ++k) {
+            const double vv = vt[(size_t)k * D + a] * vt[(size_t)k * D + b];
+            re = __builtin_fma(vv, ph[2 * k], re);
+            im = __builtin_fma(vv, ph[2 * k + 1], im);
+        }
+        out[idx] = C{(R)re, (R)im};
     }
 }
 
@@ -499,12 +592,55 @@ sv_status launch_op_t(const DevOp &op, const DeviceProgram &prog, void *psi, int
     }
     case OP_WIDE: {
         *family = SV_KERNEL_WIDE;
+        const uint64_t ngroups = uint64_t(1) << (n - op.k - (op.control >= 0 ? 1 : 0));
+        if (op.k >= 5 && op.k <= 9) {
+            WideGemmArgs a;
+            std::memset(&a, 0, sizeof(a));
+            a.ngroups = ngroups;
+            a.k = op.k;
+            for (int j = 0; j < op.k; ++j) a.q[j] = op.q[j];
+            a.control = op.control;
+            a.contiguous = 1;
+            for (int j = 1; j < op.k; ++j)
+                if (op.q[j] != op.q[0] + j) a.contiguous = 0;
+            const int D = 1 << op.k;
+            const int rps = D < 64 ? 64 / D : 1;
+            C *p = static_cast<C *>(psi);
+            const C *u = static_cast<const C *>(tab);
+            // rows per wave: as many as keep >= ~1024 waves busy (reuse of
+            // each loaded U column across rows vs parallelism)
+            auto waves_for = [&](int rw) { return (ngroups + (uint64_t)rw * rps - 1) / ((uint64_t)rw * rps); };
+            int rw = 8;
+            while (rw > 1 && waves_for(rw) < 1024) rw >>= 1;
+            const unsigned grid = grid_for(waves_for(rw), 4, 8192);
+#define WIDE_GO(CT, RWV) hipLaunchKernelGGL((k_wide_gemm<R, CT, RWV>), dim3(grid), dim3(256), 0, st, p, u, a)
+#define WIDE_RW(CT)                          \
+    switch (rw) {                            \
+    case 8: WIDE_GO(CT, 8); break;           \
+    case 4: WIDE_GO(CT, 4); break;           \
+    case 2: WIDE_GO(CT, 2); break;           \
+    default: WIDE_GO(CT, 1); break;          \
+    }
+            if (D <= 64) {
+                WIDE_RW(1)
+            } else if (D == 128) {
+                WIDE_RW(2)
+            } else if (D == 256) {
+                WIDE_RW(4)
+            } else {
+                if (rw > 4) rw = 4;
+                WIDE_RW(8)
+            }
+#undef WIDE_RW
+#undef WIDE_GO
+            break;
+        }
         WideArgs a;
         std::memset(&a, 0, sizeof(a));
         a.k = op.k;
         for (int j = 0; j < op.k; ++j) a.q[j] = op.q[j];
         a.control = op.control;
-        a.ngroups = uint64_t(1) << (n - op.k - (op.control >= 0 ? 1 : 0));
+        a.ngroups = ngroups;
         const int K = 1 << op.k;
         const unsigned threads = (unsigned)std::min(256, std::max(64, K));
         const size_t smem = sizeof(C) * (size_t)K;
@@ -539,6 +675,17 @@ sv_status launch_op_t(const DevOp &op, const DeviceProgram &prog, void *psi, int
 // ---------------------------------------------------------------------------
 // Lowering: circuit gates -> device ops with FP64-built tables.
 // ---------------------------------------------------------------------------
+// Square matrix transpose (row-major in, row-major out).
+std::vector<cd> transpose(const std::vector<cd> &M)
+{
+    size_t D = 1;
+    while (D * D < M.size()) ++D;
+    std::vector<cd> T(M.size());
+    for (size_t r = 0; r < D; ++r)
+        for (size_t c = 0; c < D; ++c) T[c * D + r] = M[r * D + c];
+    return T;
+}
+
 // Reorder a matrix over qubit list gq to the ascending order of its qubits.
 std::vector<cd> to_sorted(const std::vector<cd> &M, const std::vector<int> &gq, std::vector<int> &sorted)
 {
@@ -559,14 +706,33 @@ std::vector<cd> to_sorted(const std::vector<cd> &M, const std::vector<int> &gq, 
     return out;
 }
 
-struct Lowered {
-    DevOp op;
-    std::vector<cd> table;   // complex entries (UCRY: (cos, sin) pairs)
-};
+}  // namespace
 
-Lowered lower_gate(const Gate &g)
+LoweredOp lower_gate_op(const Gate &g0, const HHLParams &h)
 {
-    Lowered L;
+    LoweredOp L;
+    if (gate_deferred(g0) && g0.kind == SV_GATE_CDENSE && (int)g0.qubits.size() > 5) {
+        // Evolution on the whole system register, built on the device.
+        std::vector<int> tq(g0.qubits.begin() + 1, g0.qubits.end());
+        std::sort(tq.begin(), tq.end());
+        DevOp &op = L.op;
+        op.type = OP_WIDE;
+        op.k = (int)tq.size();
+        for (int l = 0; l < op.k; ++l) op.q[l] = tq[l];
+        op.control = g0.qubits[0];
+        L.deferred = true;
+        L.evo_j = g0.evo_j;
+        L.evo_inv = g0.evo_inv;
+        // The builder writes U in the order of the sorted targets; the
+        // evolution's own target list is the ascending system register.
+        return L;
+    }
+    Gate gm;
+    if (gate_deferred(g0)) {
+        gm = g0;
+        materialize(gm, h);
+    }
+    const Gate &g = gate_deferred(g0) ? gm : g0;
     DevOp &op = L.op;
     std::vector<int> sorted;
     if (g.kind == SV_GATE_UCRY) {
@@ -603,7 +769,7 @@ Lowered lower_gate(const Gate &g)
         std::vector<int> tq(g.qubits.begin() + 1, g.qubits.end());
         std::vector<cd> U(g.params.size() / 2);
         for (size_t i = 0; i < U.size(); ++i) U[i] = cd(g.params[2 * i], g.params[2 * i + 1]);
-        L.table = to_sorted(U, tq, sorted);
+        L.table = transpose(to_sorted(U, tq, sorted));
         op.type = OP_WIDE;
         op.k = (int)sorted.size();
         for (int l = 0; l < op.k; ++l) op.q[l] = sorted[l];
@@ -614,15 +780,18 @@ Lowered lower_gate(const Gate &g)
     op.k = (int)sorted.size();
     for (int l = 0; l < op.k; ++l) op.q[l] = sorted[l];
     op.type = op.k <= 5 ? OP_DENSE : OP_WIDE;
+    if (op.type == OP_WIDE) L.table = transpose(L.table);
     op.control = -1;
     return L;
 }
 
-}  // namespace
-
 Circuit::~Circuit()
 {
     for (DeviceProgram *p : dev) {
+        for (GraphEntry &g : p->graphs) {
+            if (g.exec) (void)hipGraphExecDestroy(g.exec);
+            if (g.graph) (void)hipGraphDestroy(g.graph);
+        }
         if (p->dbuf) {
             int cur = -1;
             (void)hipGetDevice(&cur);
@@ -632,6 +801,84 @@ Circuit::~Circuit()
         }
         delete p;
     }
+}
+
+sv_status build_program_image(const Circuit &c, sv_dtype dtype, std::vector<DevOp> &ops,
+                              std::vector<unsigned char> &image, std::vector<EvoJob> &jobs, int *max_D)
+{
+    const size_t csz = dtype == SV_C128 ? 16 : 8;
+    std::vector<LoweredOp> low;
+    low.reserve(c.gates.size());
+    size_t bytes = 0;
+    for (const Gate &g : c.gates) {
+        low.push_back(lower_gate_op(g, c.hhl));
+        LoweredOp &L = low.back();
+        bytes = (bytes + 255) & ~size_t(255);
+        L.op.off = bytes;
+        bytes += (L.deferred ? ((size_t)1 << (2 * L.op.k)) : L.table.size()) * csz;
+    }
+    image.assign(std::max<size_t>(bytes, 256), 0);
+    ops.clear();
+    jobs.clear();
+    *max_D = 0;
+    for (auto &L : low) {
+        unsigned char *dst = image.data() + L.op.off;
+        if (L.deferred) {
+            if (!c.hhl.spec || c.hhl.spec->D != (1 << L.op.k))
+                return fail(SV_ERR_INVALID, "deferred evolution without a matching eigen-decomposition");
+            EvoJob jb;
+            std::memset(&jb, 0, sizeof(jb));
+            jb.vt_off = 0;
+            jb.w_off = (unsigned long long)c.hhl.spec->D * c.hhl.spec->D;
+            jb.out_off = L.op.off;
+            jb.D = 1 << L.op.k;
+            jb.j = L.evo_j;
+            jb.inv = L.evo_inv ? 1 : 0;
+            jb.t = c.hhl.spec->t;
+            jobs.push_back(jb);
+            *max_D = std::max(*max_D, jb.D);
+        } else if (dtype == SV_C128) {
+            for (size_t i = 0; i < L.table.size(); ++i) {
+                const double v[2] = {L.table[i].real(), L.table[i].imag()};
+                std::memcpy(dst + 16 * i, v, 16);
+            }
+        } else {
+            for (size_t i = 0; i < L.table.size(); ++i) {
+                const float v[2] = {(float)L.table[i].real(), (float)L.table[i].imag()};
+                std::memcpy(dst + 8 * i, v, 8);
+            }
+        }
+        ops.push_back(L.op);
+    }
+    return SV_OK;
+}
+
+sv_status upload_program_image(const Circuit &c, const std::vector<unsigned char> &image,
+                               const std::vector<EvoJob> &jobs, int max_D, void *d_image, sv_dtype dtype,
+                               hipStream_t st)
+{
+    HIPCK(hipMemcpyAsync(d_image, image.data(), image.size(), hipMemcpyHostToDevice, st));
+    if (jobs.empty()) return hipStreamSynchronize(st) == hipSuccess ? SV_OK : fail(SV_ERR_HIP, "upload sync");
+    // eigen-decomposition (Vt then w) and the job list, then one launch
+    const Spectral &sp = *c.hhl.spec;
+    std::vector<double> specbuf(sp.Vt);
+    specbuf.insert(specbuf.end(), sp.w.begin(), sp.w.end());
+    void *d_spec = nullptr, *d_jobs = nullptr;
+    hipError_t e = hipMallocAsync(&d_spec, specbuf.size() * sizeof(double), st);
+    if (e == hipSuccess) e = hipMallocAsync(&d_jobs, jobs.size() * sizeof(EvoJob), st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_spec, specbuf.data(), specbuf.size() * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_jobs, jobs.data(), jobs.size() * sizeof(EvoJob), hipMemcpyHostToDevice, st);
+    sv_status bst = SV_OK;
+    if (e == hipSuccess)
+        bst = launch_build_evolutions(static_cast<const EvoJob *>(d_jobs), (int)jobs.size(), max_D,
+                                      static_cast<const double *>(d_spec), d_image, dtype, st);
+    if (d_spec) (void)hipFreeAsync(d_spec, st);
+    if (d_jobs) (void)hipFreeAsync(d_jobs, st);
+    hipError_t e2 = hipStreamSynchronize(st);
+    if (bst != SV_OK) return bst;
+    if (e != hipSuccess || e2 != hipSuccess)
+        return fail(SV_ERR_HIP, std::string("program upload: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    return SV_OK;
 }
 
 DeviceProgram *get_device_program(const Circuit &c, sv_dtype dtype, sv_status *st)
@@ -647,50 +894,88 @@ DeviceProgram *get_device_program(const Circuit &c, sv_dtype dtype, sv_status *s
     auto *prog = new DeviceProgram;
     prog->device = device;
     prog->dtype = dtype;
-    const size_t rsz = dtype == SV_C128 ? 8 : 4;
-    std::vector<Lowered> low;
-    low.reserve(c.gates.size());
-    size_t bytes = 0;
-    for (const Gate &g : c.gates) {
-        low.push_back(lower_gate(g));
-        bytes = (bytes + 255) & ~size_t(255);
-        low.back().op.off = bytes;
-        bytes += low.back().table.size() * 2 * rsz;
+    std::vector<unsigned char> image;
+    std::vector<EvoJob> jobs;
+    int max_D = 0;
+    *st = build_program_image(c, dtype, prog->ops, image, jobs, &max_D);
+    if (*st != SV_OK) {
+        delete prog;
+        return nullptr;
     }
-    std::vector<unsigned char> host(std::max<size_t>(bytes, 256), 0);
-    for (auto &L : low) {
-        unsigned char *dst = host.data() + L.op.off;
-        if (dtype == SV_C128) {
-            for (size_t i = 0; i < L.table.size(); ++i) {
-                const double v[2] = {L.table[i].real(), L.table[i].imag()};
-                std::memcpy(dst + 16 * i, v, 16);
-            }
-        } else {
-            for (size_t i = 0; i < L.table.size(); ++i) {
-                const float v[2] = {(float)L.table[i].real(), (float)L.table[i].imag()};
-                std::memcpy(dst + 8 * i, v, 8);
-            }
-        }
-        prog->ops.push_back(L.op);
-    }
-    prog->bytes = host.size();
+    prog->bytes = image.size();
     hipError_t e = hipMalloc(&prog->dbuf, prog->bytes);
     if (e != hipSuccess) {
+        (void)hipGetLastError();
         delete prog;
         *st = fail(e == hipErrorOutOfMemory ? SV_ERR_OOM : SV_ERR_HIP,
                    std::string("device program allocation: ") + hipGetErrorString(e));
         return nullptr;
     }
-    e = hipMemcpy(prog->dbuf, host.data(), prog->bytes, hipMemcpyHostToDevice);
+    hipStream_t ups = nullptr;
+    e = hipStreamCreateWithFlags(&ups, hipStreamNonBlocking);
     if (e != hipSuccess) {
         (void)hipFree(prog->dbuf);
         delete prog;
-        *st = fail(SV_ERR_HIP, std::string("device program upload: ") + hipGetErrorString(e));
+        *st = fail(SV_ERR_HIP, std::string("device program upload stream: ") + hipGetErrorString(e));
+        return nullptr;
+    }
+    *st = upload_program_image(c, image, jobs, max_D, prog->dbuf, dtype, ups);
+    (void)hipStreamDestroy(ups);
+    if (*st != SV_OK) {
+        (void)hipFree(prog->dbuf);
+        delete prog;
         return nullptr;
     }
     c.dev.push_back(prog);
-    *st = SV_OK;
     return prog;
+}
+
+sv_status launch_program_graph(const Circuit &c, DeviceProgram &prog, void *psi, int n,
+                               sv_dtype dtype, hipStream_t stream)
+{
+    hipGraphExec_t exec = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(c.dev_mu);
+        for (GraphEntry &g : prog.graphs)
+            if (g.psi == psi && g.n == n) exec = g.exec;
+    }
+    if (!exec) {
+        // Capture on a private stream so the caller's stream never sees a
+        // half-captured state; replay on the caller's stream.
+        hipStream_t cap = nullptr;
+        HIPCK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        sv_status st = SV_OK;
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            for (const DevOp &op : prog.ops) {
+                st = launch_op(op, prog, psi, n, dtype, cap, nullptr);
+                if (st != SV_OK) break;
+            }
+        }
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(cap, &graph) : e;
+        (void)hipStreamDestroy(cap);
+        if (st != SV_OK || e != hipSuccess || e2 != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            if (st != SV_OK) return st;
+            return fail(SV_ERR_HIP, std::string("sv_apply: graph capture: ") +
+                                        hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return fail(SV_ERR_HIP, std::string("sv_apply: graph instantiate: ") + hipGetErrorString(e));
+        }
+        std::lock_guard<std::mutex> lk(c.dev_mu);
+        if (prog.graphs.size() >= 8) {  // bounded cache: drop the oldest
+            (void)hipGraphExecDestroy(prog.graphs.front().exec);
+            (void)hipGraphDestroy(prog.graphs.front().graph);
+            prog.graphs.erase(prog.graphs.begin());
+        }
+        prog.graphs.push_back(GraphEntry{psi, n, graph, exec});
+    }
+    HIPCK(hipGraphLaunch(exec, stream));
+    return SV_OK;
 }
 
 sv_status launch_op(const DevOp &op, const DeviceProgram &prog, void *psi, int n,
@@ -700,6 +985,22 @@ sv_status launch_op(const DevOp &op, const DeviceProgram &prog, void *psi, int n
     int *fam = family ? family : &fam_local;
     if (dtype == SV_C128) return launch_op_t<double>(op, prog, psi, n, stream, fam);
     return launch_op_t<float>(op, prog, psi, n, stream, fam);
+}
+
+sv_status launch_build_evolutions(const EvoJob *d_jobs, int njobs, int max_D, const double *d_spec,
+                                  void *d_tables, sv_dtype dtype, hipStream_t st)
+{
+    if (njobs <= 0) return SV_OK;
+    const unsigned gx = grid_for((uint64_t)max_D * max_D, 256, 256);
+    const size_t smem = 2 * sizeof(double) * (size_t)max_D;
+    if (dtype == SV_C128)
+        hipLaunchKernelGGL((k_build_evolution<double>), dim3(gx, njobs), dim3(256), smem, st, d_jobs, d_spec,
+                           static_cast<unsigned char *>(d_tables));
+    else
+        hipLaunchKernelGGL((k_build_evolution<float>), dim3(gx, njobs), dim3(256), smem, st, d_jobs, d_spec,
+                           static_cast<unsigned char *>(d_tables));
+    HIPCK(hipGetLastError());
+    return SV_OK;
 }
 
 sv_status launch_init_zero_state(void *psi, int n, sv_dtype dtype, hipStream_t s)

@@ -28,17 +28,67 @@ struct DevOp {
     size_t off = 0;          // byte offset of the op's table in the buffer
 };
 
+// A captured replay of a program's launches on one state buffer.
+struct GraphEntry {
+    void *psi = nullptr;
+    int n = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 struct DeviceProgram {
     int device = -1;
     sv_dtype dtype = SV_C128;
     void *dbuf = nullptr;    // one allocation holding every table
     size_t bytes = 0;
     std::vector<DevOp> ops;
+    std::vector<GraphEntry> graphs;   // guarded by the circuit's dev_mu
 };
+
+// Launch a program on a state through a cached hipGraph (captured on first
+// use for this state buffer).
+sv_status launch_program_graph(const Circuit &c, DeviceProgram &prog, void *psi, int n,
+                               sv_dtype dtype, hipStream_t stream);
+
+// One gate lowered to a device op plus its FP64 table (complex entries; UCRY:
+// (cos, sin) of the half angles; OP_WIDE: U^T, i.e. U column-major).
+struct LoweredOp {
+    DevOp op;
+    std::vector<cd> table;
+    // OP_WIDE evolution gate whose table is built on the device (the table
+    // region of 4^k entries is reserved, table is empty).
+    bool deferred = false;
+    int evo_j = -1;
+    bool evo_inv = false;
+};
+LoweredOp lower_gate_op(const Gate &g, const HHLParams &h);
+
+// Device construction of evolution tables e^{+-i A' t 2^j} (FP64, stored in
+// the program dtype) from an eigen-decomposition already on the device.
+struct EvoJob {
+    unsigned long long vt_off;   // doubles into the spectral buffer
+    unsigned long long w_off;    // doubles into the spectral buffer
+    unsigned long long out_off;  // bytes into the table buffer
+    int D, j, inv, pad;
+    double t;
+};
+sv_status launch_build_evolutions(const EvoJob *d_jobs, int njobs, int max_D, const double *d_spec,
+                                  void *d_tables, sv_dtype dtype, hipStream_t st);
 
 // Lower a circuit to device ops and upload its tables (FP64 built, rounded
 // once to FP32 for SV_C64).  Returns nullptr and sets the error on failure.
 DeviceProgram *get_device_program(const Circuit &c, sv_dtype dtype, sv_status *st);
+
+// Lower a circuit into device ops and one table image (offsets in ops[i].off);
+// evolution tables to build on the device are listed in jobs (spectral
+// offsets relative to [Vt | w] of the circuit's eigen-decomposition).
+sv_status build_program_image(const Circuit &c, sv_dtype dtype, std::vector<DevOp> &ops,
+                              std::vector<unsigned char> &image, std::vector<EvoJob> &jobs, int *max_D);
+// Copy an image to d_image on stream st and build its evolution tables there;
+// synchronises st.
+sv_status upload_program_image(const Circuit &c, const std::vector<unsigned char> &image,
+                               const std::vector<EvoJob> &jobs, int max_D, void *d_image, sv_dtype dtype,
+                               hipStream_t st);
 
 // Launch one op on a 2^n state on the given stream; *family (may be NULL)
 // receives the sv_kernel_family used.

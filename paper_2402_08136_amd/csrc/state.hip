@@ -5,9 +5,13 @@
 #include <cstring>
 #include <new>
 
+#include "hhlsv_batch.hpp"
 #include "kernels.hpp"
 
 using namespace hhlsv;
+
+// States of at most this many qubits apply circuits through a cached hipGraph.
+constexpr int kGraphMaxQubits = 24;
 
 struct sv_state {
     int n = 0;
@@ -200,6 +204,10 @@ static sv_status apply_impl(sv_state *s, const sv_circuit *c, double *launch_ms,
     DeviceProgram *prog = get_device_program(c->c, s->dtype, &st);
     if (!prog) return st;
     if (!launch_ms) {
+        // Small states are launch-bound: replay the whole op sequence as one
+        // captured hipGraph.  Large states run kernel by kernel.
+        if (s->n <= kGraphMaxQubits && prog->ops.size() >= 4)
+            return launch_program_graph(c->c, *prog, s->psi, s->n, s->dtype, s->stream);
         for (const DevOp &op : prog->ops) {
             st = launch_op(op, *prog, s->psi, s->n, s->dtype, s->stream);
             if (st != SV_OK) return st;
@@ -256,40 +264,19 @@ extern "C" sv_status sv_postselect_solution(sv_state *s, const sv_circuit *hhl, 
     const int n = s->n;
     const uint64_t base = uint64_t(1) << (n - 1);
     const size_t D = size_t(1) << h.ns;
-    // P(ancilla = 1): device reduction in double.
-    double p1 = 0.0;
-    sv_status st = range_norm2(s, base, uint64_t(1) << n, &p1);
+    // P(ancilla = 1): device reduction in double; y_s = psi[2^{n-1} + s]
+    // (ancilla 1, clock 0) copied out and widened to double.
+    std::vector<double> buf(2 + 2 * D, 0.0);
+    sv_status st = range_norm2(s, base, uint64_t(1) << n, &buf[0]);
     if (st != SV_OK) return st;
-    // y_s = psi[2^{n-1} + s]: the ancilla-1, clock-0 block.
-    std::vector<double> y(2 * D);
     if (s->dtype == SV_C128) {
-        st = sv_get_amplitudes(s, base, D, y.data());
+        st = sv_get_amplitudes(s, base, D, buf.data() + 2);
     } else {
         std::vector<float> yf(2 * D);
         st = sv_get_amplitudes(s, base, D, yf.data());
-        for (size_t i = 0; i < 2 * D; ++i) y[i] = yf[i];
+        for (size_t i = 0; i < 2 * D; ++i) buf[2 + i] = yf[i];
     }
     if (st != SV_OK) return st;
-    double p10 = 0.0, max_imag = 0.0, leak = 0.0, re2 = 0.0;
-    for (size_t i = 0; i < D; ++i) {
-        const double re = y[2 * i], im = y[2 * i + 1];
-        p10 += re * re + im * im;
-        max_imag = std::max(max_imag, std::fabs(im));
-        if ((int)i >= dim)
-            leak += re * re + im * im;
-        else
-            re2 += re * re;
-    }
-    const double rn = std::sqrt(re2);
-    for (int i = 0; i < dim; ++i) x_hat[i] = rn > 0.0 ? y[2 * i] / rn : 0.0;
-    if (info) {
-        // Step 4: the |1> amplitude of eigen-component i is C b_i / lambda_i,
-        // so x = ||b|| Re(y) / C.
-        info->scale = h.b_norm * rn / h.C;
-        info->p_anc1 = p1;
-        info->p_anc1_clock0 = p10;
-        info->max_imag = max_imag;
-        info->pad_leak = std::sqrt(leak);
-    }
+    return recover_solution(h, buf.data(), x_hat, dim, info);
     return SV_OK;
 }

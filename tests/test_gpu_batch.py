@@ -1,0 +1,170 @@
+"""GPU tests of batched persistent execution: parity with the oracle and with
+the one-circuit path on a mix of shapes, LDS- and HBM-resident states,
+bitwise equality alone vs in a mix, and hipGraph replay."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _hs():
+    import paper_2402_08136_amd as hs
+    return hs
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+# (ns, m): n = ns + m + 1 from 3 to 17; n >= 14 at c128 (>= 15 at c64) runs
+# with the state in HBM.
+SHAPES = [(1, 1), (1, 3), (2, 4), (3, 5), (2, 8), (4, 6), (5, 7), (6, 6), (3, 10), (6, 8), (5, 10), (6, 10)]
+
+
+def _systems():
+    out = []
+    for i, (ns, m) in enumerate(SHAPES):
+        A, b = W.dc_powerflow(max(2, 1 << ns), 300 + i) if ns > 1 else W.dc_powerflow(3, 300 + i)
+        out.append((A, b, m))
+    return out
+
+
+def _oracle_refs(systems):
+    refs = []
+    for A, b, m in systems:
+        _, _, xh, info = oracle.hhl_solve(A, b, m, want_state=False)
+        refs.append((xh, info))
+    return refs
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("k", [1, 3, 5])
+def test_batch_matches_oracle_and_single_path(k, dtype):
+    hs = _hs()
+    systems = _systems()
+    refs = _oracle_refs(systems)
+    bt = hs.Batch(dtype, k)
+    circs = []
+    for A, b, m in systems:
+        c = hs.circuit_build_hhl(A, b, m)
+        circs.append(c)
+        bt.add(c)
+    ms = bt.run()
+    _say(f"batch k={k} {dtype}: {len(bt)} instances in {ms:.3f} ms")
+    tol = 1e-10 if dtype == "c128" else 2e-5
+    for i, (c, (xh_ref, info_ref)) in enumerate(zip(circs, refs)):
+        x_hat, info = bt.solution(i)
+        # x_hat = Re(y) / ||Re y||: an amplitude error e moves x_hat by ~e/||Re y||
+        scale = np.sqrt(max(info_ref["p10"], 1e-30))
+        assert np.max(np.abs(x_hat - xh_ref)) * scale <= tol, (i, SHAPES[i])
+        assert abs(info["p_anc1"] - info_ref["p1"]) <= tol
+        assert abs(info["p_anc1_clock0"] - info_ref["p10"]) <= tol
+        # same circuit through the one-state path
+        s = hs.sv_create(c.n_qubits, dtype)
+        s.apply(hs.fuse(c, k))
+        x1, info1 = s.postselect_solution(c, c.info()["dim"])
+        s.close()
+        assert np.max(np.abs(x_hat - x1)) * scale <= (1e-12 if dtype == "c128" else 2e-5)
+        assert abs(info["p_anc1"] - info1["p_anc1"]) <= (1e-12 if dtype == "c128" else 2e-5)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_alone_equals_in_mix_bitwise(dtype):
+    hs = _hs()
+    systems = _systems()
+    circs = [hs.circuit_build_hhl(A, b, m) for A, b, m in systems]
+    mix = hs.Batch(dtype, 3)
+    for c in circs:
+        mix.add(c)
+    # a mix with the instances in another order and duplicates
+    mix2 = hs.Batch(dtype, 3)
+    order = list(range(len(circs)))[::-1]
+    for i in order:
+        mix2.add(circs[i])
+        mix2.add(circs[i])
+    mix.run()
+    mix2.run()
+    for i, c in enumerate(circs):
+        alone = hs.Batch(dtype, 3)
+        alone.add(c)
+        alone.run()
+        xa, ia = alone.solution(0)
+        xm, im = mix.solution(i)
+        j = 2 * order.index(i)
+        xm2, im2 = mix2.solution(j)
+        assert np.array_equal(xa, xm) and np.array_equal(xa, xm2)
+        assert ia == im == im2
+
+
+def test_batch_graph_replay_and_growth():
+    hs = _hs()
+    systems = _systems()[:6]
+    bt = hs.Batch("c128", 2)
+    circs = [hs.circuit_build_hhl(A, b, m) for A, b, m in systems]
+    for c in circs:
+        bt.add(c)
+    bt.run()
+    first = [bt.solution(i) for i in range(len(circs))]
+    for _ in range(3):
+        bt.run()
+        again = [bt.solution(i) for i in range(len(circs))]
+        for (x0, i0), (x1, i1) in zip(first, again):
+            assert np.array_equal(x0, x1) and i0 == i1
+    A, b = W.dc_powerflow(16, 999)
+    bt.add(hs.circuit_build_hhl(A, b, 6))
+    bt.run()
+    for i in range(len(circs)):
+        x1, i1 = bt.solution(i)
+        assert np.array_equal(first[i][0], x1) and first[i][1] == i1
+    _, _, xh, _ = oracle.hhl_solve(A, b, 6, want_state=False)
+    x_new, _ = bt.solution(len(circs))
+    assert np.max(np.abs(x_new - xh)) < 1e-10
+
+
+def test_autotune_picks_a_width():
+    hs = _hs()
+    A, b = W.dc_powerflow(8, 5)
+    c = hs.circuit_build_hhl(A, b, 5)
+    k, ms = hs.svb_autotune("c128", c, copies=32)
+    _say(f"autotune ns=3 m=5: best k={k}, ms per k={np.round(ms, 4).tolist()}")
+    assert 1 <= k <= 5 and np.all(ms > 0)
+    bt = hs.Batch("c128", 0)
+    bt.add(c)
+    bt.run()
+    x, info = bt.solution(0)
+    _, _, xh, _ = oracle.hhl_solve(A, b, 5, want_state=False)
+    assert np.max(np.abs(x - xh)) < 1e-10
+
+
+def test_batch_errors():
+    hs = _hs()
+    with pytest.raises(hs.HHLSVError, match="INVALID"):
+        hs.Batch("c128", 6)
+    bt = hs.Batch("c128", 2)
+    with pytest.raises(hs.HHLSVError, match="INVALID"):
+        bt.run()
+    with pytest.raises(hs.HHLSVError, match="INVALID"):
+        bt.add(hs.circuit_create(5))
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_with_device_evolutions(dtype):
+    hs = _hs()
+    systems = _systems()
+    refs = _oracle_refs(systems)
+    bt = hs.Batch(dtype, 3)
+    for A, b, m in systems:
+        bt.add(hs.circuit_build_hhl(A, b, m, device_evolutions=True))
+    bt.run()
+    tol = 1e-10 if dtype == "c128" else 2e-5
+    for i, (xh_ref, info_ref) in enumerate(refs):
+        x_hat, info = bt.solution(i)
+        scale = np.sqrt(max(info_ref["p10"], 1e-30))
+        assert np.max(np.abs(x_hat - xh_ref)) * scale <= tol, (i, SHAPES[i])
+        assert abs(info["p_anc1"] - info_ref["p1"]) <= tol

@@ -1,0 +1,154 @@
+"""GPU tests of the serving loop: oracle parity on a mix of request sizes,
+results identical alone and in the mix, admission under a small HBM budget,
+failure isolation (oversize request, injected allocation failure), queue-limit
+rejection and cancellation."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+# (ns, m): n = 7..17; at complex128 n >= 14 runs through the sweep kernels.
+MIX = [(2, 4), (3, 6), (6, 10), (4, 8), (2, 6), (5, 8), (3, 10), (6, 7), (4, 5), (5, 10), (3, 3), (6, 6)]
+
+
+def _hs():
+    import paper_2402_08136_amd as hs
+    return hs
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _systems(shapes, seed0=500):
+    out = []
+    for i, (ns, m) in enumerate(shapes):
+        A, b = W.dc_powerflow(1 << ns, seed0 + i)
+        out.append((A, b, m))
+    return out
+
+
+def _wait_all(srv, tickets, timeout=120.0):
+    res = {}
+    t0 = time.time()
+    while len(res) < len(tickets):
+        for t in tickets:
+            if t in res:
+                continue
+            try:
+                r = srv.poll(t)
+            except Exception as e:     # noqa: BLE001 - failures are results here
+                res[t] = e
+                continue
+            if r is not None:
+                res[t] = r
+        assert time.time() - t0 < timeout, "requests did not finish"
+        time.sleep(0.002)
+    return res
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_serving_matches_oracle(dtype):
+    hs = _hs()
+    systems = _systems(MIX)
+    srv = hs.Server(dtype, k_max=3)
+    tickets = [srv.submit(A, b, m) for A, b, m in systems]
+    res = _wait_all(srv, tickets)
+    tol = 1e-10 if dtype == "c128" else 2e-5
+    for t, (A, b, m) in zip(tickets, systems):
+        _, _, xh, info_ref = oracle.hhl_solve(A, b, m, want_state=False)
+        x_hat, info = res[t]
+        scale = np.sqrt(max(info_ref["p10"], 1e-30))
+        assert np.max(np.abs(x_hat - xh)) * scale <= tol
+        assert abs(info["p_anc1"] - info_ref["p1"]) <= tol
+        assert float(np.dot(x_hat, xh) ** 2) >= 0.999
+    st = srv.stats()
+    _say(f"serve {dtype}: {st}")
+    assert st["done"] == len(systems) and st["failed"] == 0 and st["p50_s"] <= st["p99_s"]
+    srv.stop()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_serving_alone_equals_mix_bitwise(dtype):
+    hs = _hs()
+    systems = _systems(MIX, seed0=700)
+    srv = hs.Server(dtype, k_max=3, streams=4, max_batch=5)
+    # the mix: everything at once, twice over
+    tickets = [srv.submit(A, b, m) for A, b, m in systems + systems]
+    mix = _wait_all(srv, tickets)
+    for i, (A, b, m) in enumerate(systems):
+        t = srv.submit(A, b, m)
+        alone = _wait_all(srv, [t])[t]
+        for tm in (tickets[i], tickets[i + len(systems)]):
+            x_m, info_m = mix[tm]
+            assert np.array_equal(alone[0], x_m)
+            assert alone[1] == info_m
+    srv.stop()
+
+
+def test_admission_under_small_budget_and_oversize():
+    hs = _hs()
+    big = _systems([(6, 10)] * 6, seed0=900)        # 17 qubits: 2 MiB state + tables
+    srv = hs.Server("c128", hbm_budget_bytes=8 << 20, k_max=3)
+    tickets = [srv.submit(A, b, m) for A, b, m in big]
+    res = _wait_all(srv, tickets)
+    for t, (A, b, m) in zip(tickets, big):
+        _, _, xh, _ = oracle.hhl_solve(A, b, m, want_state=False)
+        assert float(np.dot(res[t][0], xh) ** 2) >= 0.999
+    # a request that can never fit: 21 qubits = 32 MiB state
+    A, b = W.dc_powerflow(256, 3)
+    t = srv.submit(A, b, 12)
+    r = _wait_all(srv, [t])[t]
+    assert isinstance(r, hs.HHLSVError) and "OOM" in str(r)
+    srv.stop()
+
+
+def test_injected_allocation_failure_is_isolated():
+    hs = _hs()
+    systems = _systems(MIX[:6], seed0=1100)
+    srv = hs.Server("c128", k_max=2, prep_threads=1, fail_alloc_at=3)
+    tickets = [srv.submit(A, b, m) for A, b, m in systems]
+    res = _wait_all(srv, tickets)
+    failed = [t for t in tickets if isinstance(res[t], Exception)]
+    assert len(failed) == 1 and failed[0] == tickets[2] and "OOM" in str(res[failed[0]])
+    for t, (A, b, m) in zip(tickets, systems):
+        if t in failed:
+            continue
+        _, _, xh, _ = oracle.hhl_solve(A, b, m, want_state=False)
+        assert float(np.dot(res[t][0], xh) ** 2) >= 0.999
+    st = srv.stats()
+    assert st["failed"] == 1 and st["done"] == len(systems) - 1
+    srv.stop()
+
+
+def test_queue_limit_and_cancel():
+    hs = _hs()
+    A, b = W.dc_powerflow(64, 1)
+    srv = hs.Server("c128", k_max=3, prep_threads=1, queue_limit=4)
+    tickets, rejected = [], 0
+    for _ in range(40):
+        try:
+            tickets.append(srv.submit(A, b, 10))
+        except hs.HHLSVError as e:
+            assert "BUSY" in str(e)
+            rejected += 1
+    assert rejected > 0 and srv.stats()["rejected"] == rejected
+    cancelled = 0
+    for t in tickets[::-1]:
+        try:
+            srv.cancel(t)
+            cancelled += 1
+        except hs.HHLSVError:
+            pass              # already admitted: runs to completion
+    res = _wait_all(srv, tickets)
+    n_cancel = sum(isinstance(r, Exception) and "cancelled" in str(r) for r in res.values())
+    assert n_cancel == cancelled
+    assert all(not isinstance(r, Exception) or "cancelled" in str(r) for r in res.values())
+    srv.stop()

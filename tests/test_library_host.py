@@ -255,3 +255,17 @@ def test_sym_eig_against_numpy():
     w = np.linalg.eigvalsh(A)
     assert abs(info["lambda_lo"] - w[0]) < 1e-12 * w[-1]
     assert abs(info["lambda_hi"] - w[-1]) < 1e-12 * w[-1]
+
+
+# ------------------------------------------------ deferred evolution tables ---
+@pytest.mark.parametrize("nbus,m", [(4, 4), (32, 6), (64, 8)])
+def test_deferred_evolutions_materialise_identically(nbus, m):
+    """With the device-evolution flag the host builds the matrices only on
+    demand (serialize, fusion into small gates); they equal the eager ones."""
+    A, b = W.dc_powerflow(nbus, 4)
+    eager = hs.circuit_build_hhl(A, b, m)
+    lazy = hs.circuit_build_hhl(A, b, m, device_evolutions=True)
+    assert eager.serialize() == lazy.serialize()
+    for k in (2, 5):
+        assert hs.fuse(eager, k).serialize() == hs.fuse(lazy, k).serialize()
+    assert eager.info() == lazy.info()
