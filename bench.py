@@ -27,12 +27,15 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "fused-gate HBM GB/s (33q SV); HHL solves/s + p99 latency, FP64 vs FP32"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2402_08136_amd", "csrc", "kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2402_08136_amd", "csrc", f)
+               for f in ("kernels.hip", "device_common.hpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fused_sweep_33q.txt")
 
 
@@ -41,8 +44,12 @@ def log(*a):
 
 
 def kernel_source_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the sources the sweep kernels are compiled from."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(label):

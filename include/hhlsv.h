@@ -276,7 +276,9 @@ sv_status svb_destroy(svb *bt);
  * device footprint fits in the HBM budget and a slot is free (admission),
  * and upload it.  A scheduler keeps several micro-batches in flight on
  * separate streams: requests whose state fits in LDS run together in the
- * batched persistent kernel, larger ones alone through the sweep kernels.
+ * batched persistent kernel (optionally also larger ones with their state in
+ * HBM); the others run alone through the sweep kernels, launched by the prep
+ * thread that prepared them on its own stream.
  * Requests that arrive while others are on the GPU are admitted as memory
  * and slots free up.  A request's result does not depend on what else is
  * in flight.  All svs_* calls are thread-safe.
@@ -303,10 +305,13 @@ enum {
     SVS_OPT_PREP_THREADS = 1,  /* host build threads (default min(12, cores-1)) */
     SVS_OPT_K_MAX = 2,         /* fusion width (0: autotuned per shape, else 3) */
     SVS_OPT_MAX_BATCH = 3,     /* requests per batched launch (default 256)      */
-    SVS_OPT_STREAMS = 4,       /* micro-batches in flight (default 4)            */
+    SVS_OPT_STREAMS = 4,       /* micro-batches in flight (default 8)            */
     SVS_OPT_QUEUE_LIMIT = 5,   /* queued, not yet admitted requests              */
-    SVS_OPT_FAIL_ALLOC_AT = 6  /* failure injection: the n-th request device
+    SVS_OPT_FAIL_ALLOC_AT = 6, /* failure injection: the n-th request device
                                   allocation fails as out of memory (0 = off)  */
+    SVS_OPT_BATCH_MAX_QUBITS = 7 /* also batch requests of up to this many
+                                  qubits with the state in HBM (default 0:
+                                  batch only states that fit in LDS)          */
 };
 sv_status svs_start(size_t hbm_budget_bytes, int max_slots, sv_dtype dtype,
                     svs **out);
@@ -321,6 +326,11 @@ sv_status svs_stats(svs *srv, double *p50_s, double *p99_s,
                     double *solves_per_s, uint64_t *n_rejected);
 sv_status svs_counts(svs *srv, uint64_t *done, uint64_t *failed,
                      uint64_t *pending);
+/* Mean seconds per successful request in each phase: out[0] queue (submit
+ * to prep start), out[1] build + fuse + admission wait, out[2] upload,
+ * out[3] resident to launched, out[4] launched to results back; out[5] /
+ * out[6] requests run batched / alone; out[7] prep threads.  cap >= 8. */
+sv_status svs_profile(svs *srv, double *out, int cap);
 sv_status svs_stop(svs *srv);
 
 /* Autotuner: time a batch of `copies` copies of `sample` at k_max = 1..5,

@@ -124,6 +124,7 @@ _proto("svs_drain", _vp, ctypes.c_double)
 _proto("svs_stats", _vp, _dp, _dp, _dp, ctypes.POINTER(_u64))
 _proto("svs_counts", _vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64), ctypes.POINTER(_u64))
 _proto("svs_stop", _vp)
+_proto("svs_profile", _vp, _dp, ctypes.c_int)
 
 
 def _check(rc, where):
@@ -418,7 +419,7 @@ def svb_autotune(dtype, sample: Circuit, copies: int = 64):
 
 # ------------------------------------------------------------------- serving
 SVS_OPT = {"prep_threads": 1, "k_max": 2, "max_batch": 3, "streams": 4, "queue_limit": 5,
-           "fail_alloc_at": 6}
+           "fail_alloc_at": 6, "batch_max_qubits": 7}
 
 
 class Server:
@@ -470,6 +471,12 @@ class Server:
         return {"p50_s": p50.value, "p99_s": p99.value, "solves_per_s": sps.value,
                 "rejected": rej.value, "done": done.value, "failed": failed.value,
                 "pending": pending.value}
+
+    def profile(self):
+        v = np.zeros(8)
+        _check(_lib.svs_profile(self.handle, _dptr(v), 8), "svs_profile")
+        keys = ["queue_s", "prep_s", "upload_s", "ready_wait_s", "gpu_s", "batched", "alone", "prep_threads"]
+        return dict(zip(keys, v.tolist()))
 
     def stop(self):
         h = getattr(self, "handle", None)

@@ -90,7 +90,7 @@ __device__ void b_diag(C *psi, int n, const BOp &op, const C *d)
 // (column c of U) coalesced.  Thread (i, s) produces output i of R groups
 // per pass, with the group amplitudes read from the state by broadcast.
 template <typename C>
-__device__ void b_wide(C *psi, int n, const BOp &op, const C *UT)
+__device__ void b_wide_generic(C *psi, int n, const BOp &op, const C *UT)
 {
     constexpr int R = 4;
     const int k = op.k;
@@ -150,6 +150,83 @@ __device__ void b_wide(C *psi, int n, const BOp &op, const C *UT)
     }
 }
 
+// Wide gate with 2^k <= 256: each wave owns RW rows (groups) and all their
+// columns (lane l: column l % 64 + 64 t), so rows are read and written by one
+// wave only.  Column steps are unrolled to keep several loads in flight.
+template <typename C>
+__device__ void b_wide(C *psi, int n, const BOp &op, const C *UT)
+{
+    const int k = op.k;
+    const int D = 1 << k;
+    if (D > 256) {
+        b_wide_generic(psi, n, op, UT);
+        return;
+    }
+    constexpr int RW = 4;
+    const uint32_t ngroups = 1u << (n - k - (op.control >= 0 ? 1 : 0));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lpr = D < 64 ? D : 64, rps = 64 / lpr;
+    const int j0 = lane % lpr, sub = lane / lpr;
+    const int CT = D > 64 ? D / 64 : 1;
+    auto off = [&](uint32_t c) -> uint32_t {
+        if (op.contiguous) return c << op.q[0];
+        uint32_t o = 0;
+        for (int j = 0; j < k; ++j) o |= ((c >> j) & 1u) << op.q[j];
+        return o;
+    };
+    auto gbase = [&](uint32_t g) -> uint32_t {
+        uint32_t b = g;
+        bool placed = op.control < 0;
+        for (int j = 0; j < k; ++j) {
+            if (!placed && op.control < op.q[j]) {
+                b = insert_zero32(b, op.control) | (1u << op.control);
+                placed = true;
+            }
+            b = insert_zero32(b, op.q[j]);
+        }
+        if (!placed) b = insert_zero32(b, op.control) | (1u << op.control);
+        return b;
+    };
+    const uint32_t step = (uint32_t)(RW * rps);
+    for (uint32_t rb = (uint32_t)wave * step; rb < ngroups; rb += (uint32_t)nw * step) {
+        uint32_t gb[RW];
+        bool ok[RW];
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const uint32_t g = rb + sub + (uint32_t)rps * r;
+            ok[r] = g < ngroups;
+            gb[r] = ok[r] ? gbase(g) : 0;
+        }
+        C acc[RW][4];
+#pragma unroll
+        for (int r = 0; r < RW; ++r)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[r][t] = C{0, 0};
+#pragma unroll 4
+        for (int c = 0; c < D; ++c) {
+            const uint32_t oc = off(c);
+            C u[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) u[t] = t < CT ? UT[c * D + j0 + 64 * t] : C{0, 0};
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                const C x = ok[r] ? psi[gb[r] | oc] : C{0, 0};
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (t < CT) cmac(acc[r][t], u[t], x);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (t >= CT) continue;
+            const uint32_t oj = off(j0 + 64 * t);
+#pragma unroll
+            for (int r = 0; r < RW; ++r)
+                if (ok[r]) psi[gb[r] | oj] = acc[r][t];
+        }
+    }
+}
+
 template <typename C>
 __device__ void b_ucry(C *psi, int n, const BOp &op, const C *cs)
 {
@@ -174,7 +251,7 @@ __device__ void b_ucry(C *psi, int n, const BOp &op, const C *cs)
     }
 }
 
-template <typename R, bool RESIDENT>
+template <typename R, bool RESIDENT, int KMAX>
 __global__ __launch_bounds__(kThreads) void k_batch(const BInst *__restrict__ insts,
                                                     const int *__restrict__ order, int count)
 {
@@ -197,8 +274,8 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BInst *__restrict__ in
                 case 1: b_dense<C, 1>(psi, in.n, op, tab); break;
                 case 2: b_dense<C, 2>(psi, in.n, op, tab); break;
                 case 3: b_dense<C, 3>(psi, in.n, op, tab); break;
-                case 4: b_dense<C, 4>(psi, in.n, op, tab); break;
-                default: b_dense<C, 5>(psi, in.n, op, tab); break;
+                case 4: if (KMAX >= 4) b_dense<C, (KMAX >= 4 ? 4 : 1)>(psi, in.n, op, tab); break;
+                default: if (KMAX >= 5) b_dense<C, (KMAX >= 5 ? 5 : 1)>(psi, in.n, op, tab); break;
                 }
                 break;
             case OP_DIAG: b_diag(psi, in.n, op, tab); break;
@@ -291,16 +368,29 @@ sv_status set_lds_attr()
     static std::once_flag once;
     static hipError_t err = hipSuccess;
     std::call_once(once, [] {
-        err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch<R, true>),
+        err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch<R, true, 5>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, kBatchLdsLimit);
+        if (err == hipSuccess)
+            err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch<R, true, 3>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, kBatchLdsLimit);
     });
     if (err != hipSuccess) return fail(SV_ERR_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(err));
     return SV_OK;
 }
+
+template <typename R, int KMAX>
+void launch_k(bool resident, int grid, size_t lds, hipStream_t st, const BInst *d_insts, const int *d_order,
+              int count)
+{
+    if (resident)
+        hipLaunchKernelGGL((k_batch<R, true, KMAX>), dim3(grid), dim3(kThreads), lds, st, d_insts, d_order, count);
+    else
+        hipLaunchKernelGGL((k_batch<R, false, KMAX>), dim3(grid), dim3(kThreads), lds, st, d_insts, d_order, count);
+}
 }  // namespace
 
-sv_status launch_batch_class(const BInst *d_insts, const int *d_order, int count, int n, sv_dtype dtype,
-                             hipStream_t st)
+sv_status launch_batch_class(const BInst *d_insts, const int *d_order, int count, int n, int kmax,
+                             sv_dtype dtype, hipStream_t st)
 {
     bool resident = false;
     const size_t lds = batch_lds_bytes(n, dtype, &resident);
@@ -308,16 +398,17 @@ sv_status launch_batch_class(const BInst *d_insts, const int *d_order, int count
     const int grid = std::max(1, std::min(count, 256 * (resident ? per_cu : 2)));
     sv_status s = dtype == SV_C128 ? set_lds_attr<double>() : set_lds_attr<float>();
     if (s != SV_OK) return s;
+    const bool lean = kmax <= 3;
     if (dtype == SV_C128) {
-        if (resident)
-            hipLaunchKernelGGL((k_batch<double, true>), dim3(grid), dim3(kThreads), lds, st, d_insts, d_order, count);
+        if (lean)
+            launch_k<double, 3>(resident, grid, lds, st, d_insts, d_order, count);
         else
-            hipLaunchKernelGGL((k_batch<double, false>), dim3(grid), dim3(kThreads), lds, st, d_insts, d_order, count);
+            launch_k<double, 5>(resident, grid, lds, st, d_insts, d_order, count);
     } else {
-        if (resident)
-            hipLaunchKernelGGL((k_batch<float, true>), dim3(grid), dim3(kThreads), lds, st, d_insts, d_order, count);
+        if (lean)
+            launch_k<float, 3>(resident, grid, lds, st, d_insts, d_order, count);
         else
-            hipLaunchKernelGGL((k_batch<float, false>), dim3(grid), dim3(kThreads), lds, st, d_insts, d_order, count);
+            launch_k<float, 5>(resident, grid, lds, st, d_insts, d_order, count);
     }
     HIPCK(hipGetLastError());
     return SV_OK;
@@ -333,7 +424,7 @@ std::map<std::tuple<int, int, int>, int> g_tune;
 }  // namespace
 
 struct BatchClass {
-    int n = 0;
+    int n = 0, kmax = 0;
     int first = 0, count = 0;   // range in the order array
 };
 
@@ -354,7 +445,7 @@ struct svb {
     std::vector<BOp> ops;
     std::vector<unsigned char> tables;
     struct Meta {
-        int n, ns, op_begin, op_count;
+        int n, ns, op_begin, op_count, kmax;
         size_t state_off, out_off;
     };
     std::vector<Meta> insts;
@@ -429,6 +520,7 @@ sv_status upload(svb *b)
         std::stable_sort(v.begin(), v.end(), [&](int x, int y) { return b->insts[x].op_count > b->insts[y].op_count; });
         BatchClass cl;
         cl.n = kv.first;
+        for (int i : v) cl.kmax = std::max(cl.kmax, b->insts[i].kmax);
         cl.first = (int)order.size();
         cl.count = (int)v.size();
         order.insert(order.end(), v.begin(), v.end());
@@ -521,7 +613,7 @@ sv_status capture(svb *b)
     for (int i = 0; i < nside && e == hipSuccess; ++i) e = hipStreamWaitEvent(b->side[i], b->ev[0], 0);
     for (size_t c = 0; c < b->classes.size() && e == hipSuccess; ++c) {
         const BatchClass &cl = b->classes[c];
-        if (launch_batch_class(b->d_insts, b->d_order + cl.first, cl.count, cl.n, b->dtype,
+        if (launch_batch_class(b->d_insts, b->d_order + cl.first, cl.count, cl.n, cl.kmax, b->dtype,
                                b->side[c % nside]) != SV_OK)
             e = hipErrorLaunchFailure;
     }
@@ -614,6 +706,7 @@ extern "C" sv_status svb_add(svb *b, const sv_circuit *hhl, int *index_out)
         std::memcpy(b->tables.data() + base, tab.data(), tab.size());
         for (BOp &op : ops) {
             op.off += base;
+            if (op.type == OP_DENSE) in.kmax = std::max(in.kmax, op.k);
             b->ops.push_back(op);
         }
         for (EvoJob &jb : evo) {

@@ -40,9 +40,10 @@ inline size_t batch_lds_bytes(int n, sv_dtype d, bool *resident)
 }
 
 // Launch the batch kernel over count instances (insts[order[i]]) that all
-// have n qubits; grid chosen from the LDS footprint.
-sv_status launch_batch_class(const BInst *d_insts, const int *d_order, int count, int n, sv_dtype dtype,
-                             hipStream_t st);
+// have n qubits and whose dense ops are at most kmax qubits wide; grid
+// chosen from the LDS footprint, a leaner kernel when kmax <= 3.
+sv_status launch_batch_class(const BInst *d_insts, const int *d_order, int count, int n, int kmax,
+                             sv_dtype dtype, hipStream_t st);
 
 // Lower a (fused) HHL circuit into batch ops and a table image.  Deferred
 // evolutions get a reserved table region and an entry in evo (out_off set,

@@ -7,9 +7,10 @@
 // fuses it, waits until the request's device footprint fits the HBM budget
 // and a slot is free (admission), then uploads its program so that it is
 // resident on the device.  A scheduler thread keeps up to `streams`
-// micro-batches in flight: all resident requests whose state fits in LDS go
-// together through the batched persistent kernel (one workgroup per
-// request), larger requests run alone through the whole-GPU sweep kernels.
+// micro-batches in flight: resident requests of up to batch_max_qubits go
+// together through the batched persistent kernel (one workgroup per request,
+// the state in LDS when it fits, else in HBM), larger requests run alone
+// through the whole-GPU sweep kernels.
 // New requests are admitted and launched while earlier ones are still on the
 // GPU.  When a micro-batch finishes its postselected outputs are copied back,
 // x is recovered (step 4), latency is recorded and the memory and slots are
@@ -70,17 +71,23 @@ __global__ __launch_bounds__(256) void k_copy_y(const typename V2<R>::type *__re
     if (blockIdx.x == 0 && threadIdx.x == 0) out[1] = 0.0;
 }
 
+// How a request runs: in a batched launch with its state in LDS, in a
+// batched launch with its state in HBM (one workgroup per request), or alone
+// through the whole-GPU sweep kernels.
+enum { kBatchLds = 0, kBatchHbm = 1, kAlone = 2 };
+
 struct Req {
     uint64_t ticket = 0;
     std::vector<double> A, b;
     int dim = 0, m = 0;
     double t = 0;
     double t_arrive = 0, t_done = 0;
+    double t_prep0 = 0, t_admit = 0, t_ready = 0, t_launch = 0;
     bool cancelled = false;
     // prepared
     HHLParams h;
-    int n = 0, ns = 0;
-    bool small = true;
+    int n = 0, ns = 0, kmax = 0;
+    int kind = 0;                // kBatchLds / kBatchHbm / kAlone
     size_t footprint = 0;
     bool admitted = false;
     void *dmem = nullptr;
@@ -90,6 +97,8 @@ struct Req {
     void *state = nullptr;       // large
     double *partials = nullptr;  // large: reduction scratch (kReducePartials + 1)
     double *out = nullptr;       // device [p1, 0, y...]
+    hipEvent_t done = nullptr;   // alone: completion of its launches
+    hipStream_t run = nullptr;   // alone: the stream it was launched on
     // result
     sv_status status = SV_OK;
     std::string err;
@@ -119,7 +128,8 @@ struct svs {
     int prep_threads = 8;
     int k_max = 0;
     int max_batch = 256;
-    int nstreams = 4;
+    int nstreams = 8;
+    int batch_max_qubits = 0;    // 0: batch only LDS-resident requests; larger run alone
     size_t queue_limit = 1 << 20;
     long fail_alloc_at = 0;   // test hook: the n-th device allocation fails (0 = off)
     // state
@@ -127,6 +137,7 @@ struct svs {
     std::condition_variable cv_prep, cv_budget, cv_sched, cv_done;
     std::deque<std::shared_ptr<Req>> prep_q;
     std::deque<std::shared_ptr<Req>> ready_q;
+    std::vector<std::shared_ptr<Req>> alone_inflight;   // launched by prep threads
     std::unordered_map<uint64_t, std::shared_ptr<Req>> all;
     uint64_t next_ticket = 1;
     size_t hbm_used = 0;
@@ -141,6 +152,9 @@ struct svs {
     std::vector<double> latencies;
     double first_arrival = 0, last_done = 0;
     uint64_t n_rejected = 0, n_failed = 0, n_done = 0;
+    // phase times summed over successful requests (seconds)
+    double sum_queue = 0, sum_prep = 0, sum_admit = 0, sum_upload = 0, sum_ready = 0, sum_gpu = 0;
+    uint64_t n_small = 0, n_large = 0;
 };
 
 namespace {
@@ -155,6 +169,15 @@ void finish(svs *s, const std::shared_ptr<Req> &r, sv_status st, const std::stri
         s->latencies.push_back(r->t_done - r->t_arrive);
         s->last_done = std::max(s->last_done, r->t_done);
         ++s->n_done;
+        s->sum_queue += r->t_prep0 - r->t_arrive;
+        s->sum_prep += r->t_admit - r->t_prep0;
+        s->sum_upload += r->t_ready - r->t_admit;
+        s->sum_ready += r->t_launch - r->t_ready;
+        s->sum_gpu += r->t_done - r->t_launch;
+        if (r->kind != kAlone)
+            ++s->n_small;
+        else
+            ++s->n_large;
     } else {
         ++s->n_failed;
     }
@@ -203,7 +226,7 @@ bool prepare(svs *s, Req &r, hipStream_t up, sv_status &st, std::string &err)
     }
     bool resident = false;
     batch_lds_bytes(r.n, s->dtype, &resident);
-    r.small = resident;
+    r.kind = resident ? kBatchLds : (r.n <= s->batch_max_qubits ? kBatchHbm : kAlone);
     const size_t out_bytes = sizeof(double) * (2 + (2u << r.ns));
     const size_t asz = s->dtype == SV_C128 ? 16 : 8;
     std::vector<BOp> bops;
@@ -211,8 +234,10 @@ bool prepare(svs *s, Req &r, hipStream_t up, sv_status &st, std::string &err)
     std::vector<EvoJob> jobs;
     int max_D = 0;
     size_t ops_bytes = 0, tab_bytes = 0, state_bytes = 0;
-    if (r.small) {
+    if (r.kind != kAlone) {
         lower_for_batch(f->c, s->dtype, bops, tables, jobs);
+        for (const BOp &op : bops)
+            if (op.type == OP_DENSE) r.kmax = std::max(r.kmax, op.k);
         for (EvoJob &jb : jobs) {
             jb.vt_off = 0;
             jb.w_off = (unsigned long long)r.h.spec->D * r.h.spec->D;
@@ -220,6 +245,7 @@ bool prepare(svs *s, Req &r, hipStream_t up, sv_status &st, std::string &err)
         }
         ops_bytes = align256(bops.size() * sizeof(BOp));
         tab_bytes = align256(tables.size());
+        if (r.kind == kBatchHbm) state_bytes = align256(asz << r.n);
     } else {
         st = build_program_image(f->c, s->dtype, r.ops, image, jobs, &max_D);
         if (st != SV_OK) {
@@ -252,6 +278,7 @@ bool prepare(svs *s, Req &r, hipStream_t up, sv_status &st, std::string &err)
         ++s->slots_used;
         r.admitted = true;
     }
+    r.t_admit = now_s();
     const long nth = ++s->alloc_count;
     hipError_t e = (s->fail_alloc_at > 0 && nth == s->fail_alloc_at) ? hipErrorOutOfMemory
                                                                      : hipMallocAsync(&r.dmem, r.footprint, up);
@@ -263,10 +290,11 @@ bool prepare(svs *s, Req &r, hipStream_t up, sv_status &st, std::string &err)
         return false;
     }
     unsigned char *base = static_cast<unsigned char *>(r.dmem);
-    if (r.small) {
+    if (r.kind != kAlone) {
         BOp *d_ops = reinterpret_cast<BOp *>(base);
         unsigned char *d_tab = base + ops_bytes;
-        r.out = reinterpret_cast<double *>(base + ops_bytes + tab_bytes);
+        unsigned char *d_state = r.kind == kBatchHbm ? base + ops_bytes + tab_bytes : nullptr;
+        r.out = reinterpret_cast<double *>(base + ops_bytes + tab_bytes + state_bytes);
         e = hipMemcpyAsync(d_ops, bops.data(), bops.size() * sizeof(BOp), hipMemcpyHostToDevice, up);
         if (e == hipSuccess) e = hipMemcpyAsync(d_tab, tables.data(), tables.size(), hipMemcpyHostToDevice, up);
         if (e != hipSuccess) {
@@ -287,7 +315,7 @@ bool prepare(svs *s, Req &r, hipStream_t up, sv_status &st, std::string &err)
         r.inst.op_count = (int)bops.size();
         r.inst.ops = d_ops;
         r.inst.tables = d_tab;
-        r.inst.state = nullptr;
+        r.inst.state = d_state;
         r.inst.out = r.out;
     } else {
         r.prog.dbuf = base;
@@ -311,11 +339,39 @@ bool prepare(svs *s, Req &r, hipStream_t up, sv_status &st, std::string &err)
     return true;
 }
 
+// Launch a request that runs alone (init, every op, postselection into its
+// device output block) on the calling prep thread's execution stream.
+sv_status launch_alone(svs *s, Req &r, hipStream_t run)
+{
+    sv_status st = launch_init_zero_state(r.state, r.n, s->dtype, run);
+    for (const DevOp &op : r.ops) {
+        if (st != SV_OK) return st;
+        st = launch_op(op, r.prog, r.state, r.n, s->dtype, run);
+    }
+    const uint64_t half = uint64_t(1) << (r.n - 1);
+    if (st == SV_OK) st = launch_norm2_range(r.state, half, half << 1, s->dtype, r.partials, r.out, run);
+    if (st != SV_OK) return st;
+    const int D = 1 << r.ns;
+    if (s->dtype == SV_C128)
+        hipLaunchKernelGGL((k_copy_y<double>), dim3((D + 255) / 256), dim3(256), 0, run,
+                           static_cast<const V2<double>::type *>(r.state), half, D, r.out);
+    else
+        hipLaunchKernelGGL((k_copy_y<float>), dim3((D + 255) / 256), dim3(256), 0, run,
+                           static_cast<const V2<float>::type *>(r.state), half, D, r.out);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&r.done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(r.done, run);
+    if (e != hipSuccess) return fail(SV_ERR_HIP, std::string("svs: launch: ") + hipGetErrorString(e));
+    r.run = run;
+    return SV_OK;
+}
+
 void prep_main(svs *s)
 {
     (void)hipSetDevice(s->device);
-    hipStream_t up = nullptr;
+    hipStream_t up = nullptr, run = nullptr;
     (void)hipStreamCreateWithFlags(&up, hipStreamNonBlocking);
+    (void)hipStreamCreateWithFlags(&run, hipStreamNonBlocking);
     for (;;) {
         std::shared_ptr<Req> r;
         {
@@ -327,13 +383,27 @@ void prep_main(svs *s)
         }
         sv_status st = SV_OK;
         std::string err;
+        r->t_prep0 = now_s();
         bool ok = !r->cancelled && prepare(s, *r, up, st, err);
+        r->t_ready = now_s();
         if (!ok && r->cancelled && st == SV_OK) {
             st = SV_ERR_INVALID;
             err = "svs: request cancelled";
         }
+        if (ok && r->kind == kAlone) {
+            r->t_launch = now_s();
+            st = launch_alone(s, *r, run);
+            if (st != SV_OK) {
+                ok = false;
+                err = sv_last_error();
+                (void)hipStreamSynchronize(run);
+            }
+        }
         std::lock_guard<std::mutex> lk(s->mu);
-        if (ok) {
+        if (ok && r->kind == kAlone) {
+            s->alone_inflight.push_back(r);
+            s->cv_sched.notify_all();
+        } else if (ok) {
             s->ready_q.push_back(r);
             s->cv_sched.notify_all();
         } else {
@@ -342,7 +412,9 @@ void prep_main(svs *s)
         }
     }
     (void)hipStreamSynchronize(up);
+    (void)hipStreamSynchronize(run);
     (void)hipStreamDestroy(up);
+    (void)hipStreamDestroy(run);
     std::lock_guard<std::mutex> lk(s->mu);
     --s->preps_alive;
     s->cv_sched.notify_all();
@@ -364,7 +436,7 @@ sv_status launch_slot(svs *s, Slot &sl)
     if (e == hipSuccess)
         e = hipMemcpyAsync(sl.d_offs, sl.h_offs, cnt * sizeof(unsigned long long), hipMemcpyHostToDevice, sl.stream);
     if (e != hipSuccess) return fail(SV_ERR_HIP, std::string("svs: launch: ") + hipGetErrorString(e));
-    if (sl.reqs[0]->small) {
+    if (sl.reqs[0]->kind != kAlone) {
         // order by n (one launch per size class), longest programs first
         std::vector<int> idx(cnt);
         for (int i = 0; i < cnt; ++i) idx[i] = i;
@@ -378,9 +450,10 @@ sv_status launch_slot(svs *s, Slot &sl)
         int first = 0;
         while (first < cnt) {
             const int n = sl.reqs[idx[first]]->n;
-            int last = first;
-            while (last < cnt && sl.reqs[idx[last]]->n == n) ++last;
-            sv_status st = launch_batch_class(sl.d_insts, sl.d_order + first, last - first, n, s->dtype, sl.stream);
+            int last = first, kmax = 0;
+            while (last < cnt && sl.reqs[idx[last]]->n == n) kmax = std::max(kmax, sl.reqs[idx[last++]]->kmax);
+            sv_status st = launch_batch_class(sl.d_insts, sl.d_order + first, last - first, n, kmax, s->dtype,
+                                              sl.stream);
             if (st != SV_OK) return st;
             first = last;
         }
@@ -453,14 +526,44 @@ void sched_main(svs *s)
                 any_busy = true;
             }
         }
+        // retire requests that prep threads launched alone
+        for (size_t i = 0; i < s->alone_inflight.size();) {
+            std::shared_ptr<Req> r = s->alone_inflight[i];
+            const hipError_t q = hipEventQuery(r->done);
+            if (q == hipErrorNotReady) {
+                any_busy = true;
+                ++i;
+                continue;
+            }
+            sv_status st = SV_OK;
+            std::string msg;
+            if (q == hipSuccess) {
+                r->result.resize(2 + (2u << r->ns));
+                const hipError_t e = hipMemcpy(r->result.data(), r->out, r->result.size() * sizeof(double),
+                                               hipMemcpyDeviceToHost);
+                if (e != hipSuccess) {
+                    st = SV_ERR_HIP;
+                    msg = std::string("svs: result copy: ") + hipGetErrorString(e);
+                }
+            } else {
+                st = SV_ERR_HIP;
+                msg = std::string("svs: device error: ") + hipGetErrorString(q);
+            }
+            (void)hipEventDestroy(r->done);
+            r->done = nullptr;
+            release(s, r, r->run);
+            finish(s, r, st, msg);
+            s->alone_inflight[i] = s->alone_inflight.back();
+            s->alone_inflight.pop_back();
+        }
         // launch new micro-batches on free slots
         for (Slot &sl : s->slots) {
             if (sl.busy || s->ready_q.empty()) continue;
             // the oldest ready request decides the kind of this micro-batch
-            const bool small = s->ready_q.front()->small;
-            if (small) {
+            const int kind = s->ready_q.front()->kind;
+            if (kind != kAlone) {
                 for (auto it = s->ready_q.begin(); it != s->ready_q.end() && (int)sl.reqs.size() < s->max_batch;) {
-                    if ((*it)->small) {
+                    if ((*it)->kind == kind) {
                         sl.reqs.push_back(*it);
                         it = s->ready_q.erase(it);
                     } else {
@@ -471,6 +574,8 @@ void sched_main(svs *s)
                 sl.reqs.push_back(s->ready_q.front());
                 s->ready_q.pop_front();
             }
+            const double tl = now_s();
+            for (auto &r : sl.reqs) r->t_launch = tl;
             const sv_status st = launch_slot(s, sl);
             if (st != SV_OK) {
                 const std::string msg = sv_last_error();
@@ -485,7 +590,8 @@ void sched_main(svs *s)
                 any_busy = true;
             }
         }
-        if (s->stopping && s->preps_alive == 0 && s->ready_q.empty() && !any_busy) break;
+        if (s->stopping && s->preps_alive == 0 && s->ready_q.empty() && s->alone_inflight.empty() && !any_busy)
+            break;
         if (any_busy)
             s->cv_sched.wait_for(lk, std::chrono::microseconds(50));
         else
@@ -569,12 +675,16 @@ extern "C" sv_status svs_configure(svs *s, int option, double value)
         s->max_batch = (int)value;
         return SV_OK;
     case SVS_OPT_STREAMS:
-        if (value < 1 || value > 16) return fail(SV_ERR_INVALID, "svs_configure: streams in [1, 16]");
+        if (value < 1 || value > 32) return fail(SV_ERR_INVALID, "svs_configure: streams in [1, 32]");
         s->nstreams = (int)value;
         return SV_OK;
     case SVS_OPT_QUEUE_LIMIT:
         if (value < 1) return fail(SV_ERR_INVALID, "svs_configure: queue limit >= 1");
         s->queue_limit = (size_t)value;
+        return SV_OK;
+    case SVS_OPT_BATCH_MAX_QUBITS:
+        if (value < 1 || value > 24) return fail(SV_ERR_INVALID, "svs_configure: batch qubit limit in [1, 24]");
+        s->batch_max_qubits = (int)value;
         return SV_OK;
     case SVS_OPT_FAIL_ALLOC_AT:
         if (value < 0) return fail(SV_ERR_INVALID, "svs_configure: allocation index >= 0");
@@ -696,6 +806,22 @@ extern "C" sv_status svs_counts(svs *s, uint64_t *done, uint64_t *failed, uint64
     if (done) *done = s->n_done;
     if (failed) *failed = s->n_failed;
     if (pending) *pending = s->pending;
+    return SV_OK;
+}
+
+extern "C" sv_status svs_profile(svs *s, double *out, int cap)
+{
+    if (!s || !out || cap < 8) return fail(SV_ERR_INVALID, "svs_profile: need an output array of 8");
+    std::lock_guard<std::mutex> lk(s->mu);
+    const double n = s->n_done ? (double)s->n_done : 1.0;
+    out[0] = s->sum_queue / n;    // submit -> prep start
+    out[1] = s->sum_prep / n;     // build + fuse + lower + admission wait
+    out[2] = s->sum_upload / n;   // allocation + upload + device evolution tables
+    out[3] = s->sum_ready / n;    // resident -> launched
+    out[4] = s->sum_gpu / n;      // launched -> results back
+    out[5] = (double)s->n_small;
+    out[6] = (double)s->n_large;
+    out[7] = (double)s->prep_threads;
     return SV_OK;
 }
 

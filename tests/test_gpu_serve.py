@@ -13,8 +13,10 @@ import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-# (ns, m): n = 7..17; at complex128 n >= 14 runs through the sweep kernels.
-MIX = [(2, 4), (3, 6), (6, 10), (4, 8), (2, 6), (5, 8), (3, 10), (6, 7), (4, 5), (5, 10), (3, 3), (6, 6)]
+# (ns, m): n = 7..19.  n <= 13 (complex128) runs batched with the state in
+# LDS, 14..17 batched with the state in HBM, 18 and 19 alone.
+MIX = [(2, 4), (3, 6), (6, 10), (4, 8), (2, 6), (5, 8), (3, 10), (6, 7), (4, 5), (5, 10), (3, 3), (6, 6),
+       (7, 10), (8, 10)]
 
 
 def _hs():
@@ -55,10 +57,11 @@ def _wait_all(srv, tickets, timeout=120.0):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_serving_matches_oracle(dtype):
+@pytest.mark.parametrize("hbm_batch", [False, True])
+def test_serving_matches_oracle(dtype, hbm_batch):
     hs = _hs()
     systems = _systems(MIX)
-    srv = hs.Server(dtype, k_max=3)
+    srv = hs.Server(dtype, k_max=3, batch_max_qubits=17 if hbm_batch else 0)
     tickets = [srv.submit(A, b, m) for A, b, m in systems]
     res = _wait_all(srv, tickets)
     tol = 1e-10 if dtype == "c128" else 2e-5
@@ -70,8 +73,12 @@ def test_serving_matches_oracle(dtype):
         assert abs(info["p_anc1"] - info_ref["p1"]) <= tol
         assert float(np.dot(x_hat, xh) ** 2) >= 0.999
     st = srv.stats()
-    _say(f"serve {dtype}: {st}")
+    prof = srv.profile()
+    _say(f"serve {dtype}: {st} {prof}")
     assert st["done"] == len(systems) and st["failed"] == 0 and st["p50_s"] <= st["p99_s"]
+    lds_limit = 13 if dtype == "c128" else 14
+    n_alone = sum(ns + m + 1 > (17 if hbm_batch else lds_limit) for ns, m in MIX)
+    assert prof["alone"] == n_alone and prof["batched"] == len(systems) - n_alone
     srv.stop()
 
 
@@ -79,7 +86,7 @@ def test_serving_matches_oracle(dtype):
 def test_serving_alone_equals_mix_bitwise(dtype):
     hs = _hs()
     systems = _systems(MIX, seed0=700)
-    srv = hs.Server(dtype, k_max=3, streams=4, max_batch=5)
+    srv = hs.Server(dtype, k_max=3, streams=4, max_batch=5, batch_max_qubits=15)
     # the mix: everything at once, twice over
     tickets = [srv.submit(A, b, m) for A, b, m in systems + systems]
     mix = _wait_all(srv, tickets)
