@@ -15,6 +15,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
+HHL_SIGNED = 1   # two's-complement clock (sign qubit)
+HHL_DILATE = 2   # [[0, A'], [A'^T, 0]] for a general square A
+
 KIND = {"h": 0, "x": 1, "ry": 2, "rz": 3, "p": 4, "u3": 5, "cx": 6, "cp": 7,
         "swap": 8, "dense": 9, "cdense": 10, "ucry": 11}
 
@@ -36,7 +39,8 @@ class HHLInfo(ctypes.Structure):
                 ("lambda_hi", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("p1", ctypes.c_double), ("p10", ctypes.c_double),
                 ("max_imag", ctypes.c_double), ("pad_leak", ctypes.c_double),
-                ("x_norm", ctypes.c_double)]
+                ("x_norm", ctypes.c_double), ("x_off", ctypes.c_int),
+                ("sign_qubit", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -70,6 +74,14 @@ def lib():
                                     ctypes.POINTER(HHLInfo)]
         L.orc_hhl_params.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int,
                                      ctypes.c_double, ctypes.POINTER(HHLInfo)]
+        L.orc_hhl_solve_ex.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_double, ctypes.c_int, dp, dp,
+                                       dp, ctypes.POINTER(HHLInfo)]
+        L.orc_hhl_params_ex.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_double, ctypes.c_int,
+                                        ctypes.POINTER(HHLInfo)]
+        L.orc_hhl_system.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, dp,
+                                     dp, ip]
         _lib = L
     return _lib
 
@@ -152,28 +164,46 @@ def qubit_count(dim: int, kappa: float, has_negative: bool):
     return int(a[0]), int(a[1]), int(a[2])
 
 
-def hhl_params(A, b, m: int, t: float = 0.0) -> dict:
+def hhl_params(A, b, m: int, t: float = 0.0, flags: int = 0) -> dict:
     A = np.ascontiguousarray(A, dtype=np.float64)
     b = np.ascontiguousarray(b, dtype=np.float64)
     info = HHLInfo()
-    _check(lib().orc_hhl_params(_dp(A), _dp(b), b.size, m, t,
-                                ctypes.byref(info)), "hhl_params")
+    _check(lib().orc_hhl_params_ex(_dp(A), _dp(b), b.size, m, t, flags,
+                                   ctypes.byref(info)), "hhl_params")
     return info.as_dict()
 
 
-def hhl_solve(A, b, m: int, t: float = 0.0, want_state: bool = True):
+def hhl_system(A, b, flags: int = 0):
+    """The Hermitian system the circuit encodes: (H, b_hat, x_off)."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    L = lib()
+    null = ctypes.POINTER(ctypes.c_double)()
+    d = _check(L.orc_hhl_system(_dp(A), _dp(b), b.size, flags, null, null,
+                                ctypes.POINTER(ctypes.c_int)()), "hhl_system")
+    H = np.zeros((d, d))
+    bh = np.zeros(d)
+    xo = np.zeros(1, dtype=np.int32)
+    _check(L.orc_hhl_system(_dp(A), _dp(b), b.size, flags, _dp(H), _dp(bh),
+                            _ip(xo)), "hhl_system")
+    return H, bh, int(xo[0])
+
+
+def hhl_solve(A, b, m: int, t: float = 0.0, want_state: bool = True,
+              flags: int = 0):
     """Full HHL solve: returns (psi or None, x_hhl, x_hat, info dict)."""
     A = np.ascontiguousarray(A, dtype=np.float64)
     b = np.ascontiguousarray(b, dtype=np.float64)
     N = b.size
     info = HHLInfo()
-    pr = hhl_params(A, b, m, t)
+    pr = hhl_params(A, b, m, t, flags)
     n = pr["n"]
     psi = np.zeros(1 << n, dtype=np.complex128) if want_state else None
     x_hhl = np.zeros(N)
     x_hat = np.zeros(N)
     psi_p = (_dp(psi.view(np.float64)) if want_state
              else ctypes.POINTER(ctypes.c_double)())
-    _check(lib().orc_hhl_solve(_dp(A), _dp(b), N, m, t, psi_p, _dp(x_hhl),
-                               _dp(x_hat), ctypes.byref(info)), "hhl_solve")
+    _check(lib().orc_hhl_solve_ex(_dp(A), _dp(b), N, m, t, flags, psi_p,
+                                  _dp(x_hhl), _dp(x_hat), ctypes.byref(info)),
+           "hhl_solve")
     return psi, x_hhl, x_hat, info.as_dict()

@@ -15,7 +15,8 @@
  *   - the "Practical HHL procedures" box of Sec. III-A: normalise b and keep
  *     ||b|| (step 1), pad to a power of two (step 1b), build the circuit
  *     (step 2, Fig. 5), read the state vector directly (step 3, simulator
- *     case), recover the norm and x (step 4);
+ *     case), recover the norm and x (step 4); the Hermitian dilation of
+ *     step 1c for a general A and the sign qubit of Sec. III-B;
  *   - the qubit-count estimate of Sec. III-B and Table I.
  * Readings where the paper is silent or inconsistent are stated at each
  * function (register order, QFT convention, choice of t, norm recovery).
@@ -444,8 +445,10 @@ int orc_qubit_count(int dim, double kappa, int has_negative, int *n_data,
  * ---------------------------------------------------------------------- */
 typedef struct {
     int N, ns, dim, m, n;
-    double *Ap;    /* padded A, dim x dim                                  */
-    double *bh;    /* normalised padded b                                  */
+    int sgn;       /* clock value read in two's complement (sign qubit)   */
+    int x_off;     /* x occupies system indices x_off .. x_off + N - 1    */
+    double *Ap;    /* the Hermitian system matrix, dim x dim              */
+    double *bh;    /* normalised padded right-hand side                   */
     double *V;     /* eigenvectors (columns)                               */
     double *lam;   /* eigenvalues                                          */
     double beta, t, C, lambda_lo, lambda_hi, kappa;
@@ -457,66 +460,127 @@ static void prep_free(hhl_prep *h)
     free(h->Ap); free(h->bh); free(h->V); free(h->lam);
 }
 
-/* Step 1 and the spectral parameters the circuit needs.
- *   - step 1: b_hat = b / ||b||, beta = ||b||;
- *   - step 1b: N -> dim = 2^ns with A' = A (+) I and b zero-padded;
- *   - A must be symmetric (the Hermitian case of step 1c; the dilation for
- *     non-Hermitian A is not part of this reference);
- *   - lambda_lo / lambda_hi: the smallest / largest eigenvalue among the
- *     eigenvectors b_hat overlaps (weight (v_i . b_hat)^2 > 1e-20).  This is
- *     "the smallest-magnitude eigenvalue of the matrix input" of step 4a once
- *     the pad block, which b_hat never reaches, is excluded;
- *   - t (reading; the paper does not give its rule): when
- *     kappa <= 2^m - 1, j0 = floor((2^m - 1) / kappa) and
- *     t = 2 pi j0 / (2^m lambda_lo), so lambda_lo lands on clock value j0 and
- *     lambda_hi at most on 2^m - 1; otherwise t = 2 pi (2^m - 1) /
- *     (2^m lambda_hi).  A caller-given t > 0 overrides the rule.  Then
- *     j0 = max(1, round(lambda_lo t 2^m / 2 pi)) and
- *     C = 2 pi j0 / (t 2^m), the eigenvalue clock value j0 stands for. */
-static int hhl_prepare(const double *A, const double *b, int N, int m,
-                       double t_in, hhl_prep *h)
+/* Step 1 of the procedure box: the Hermitian system the circuit encodes.
+ *   - b_hat = b / ||b||, beta = ||b||;
+ *   - step 1b: A is padded to the next power of two, A' = A (+) I, with b
+ *     zero-padded;
+ *   - step 1c (flag ORC_HHL_DILATE): the padded A' is replaced by the
+ *     symmetric dilation H = [[0, A'], [A'^T, 0]] (A real, so A^dagger =
+ *     A^T) and the right-hand side by [b_hat; 0]; since H [0; x] = [b; 0]
+ *     exactly when A x = b, x is read from the second half (x_off = size
+ *     of A').  The paper lists padding (1b) before the dilation (1c); that
+ *     order is kept, so a 29 x 29 A becomes 32 x 32 and then 64 x 64,
+ *     the 6 data qubits of Table I's preconditioned 30-bus case.
+ *   - without the flag A must be symmetric. */
+static int hhl_system(const double *A, const double *b, int N, int flags,
+                      hhl_prep *h)
 {
-    memset(h, 0, sizeof(*h));
-    if (N < 1 || m < 1 || m > 20)
-        return ORC_EINVAL;
-    int ns = 0;
-    while ((1 << ns) < N)
-        ++ns;
-    if (ns < 1)
-        ns = 1;
-    int dim = 1 << ns;
-    h->N = N; h->ns = ns; h->dim = dim; h->m = m; h->n = ns + m + 1;
-    double amax = 0.0, asym = 0.0;
-    for (int i = 0; i < N; ++i)
-        for (int j = 0; j < N; ++j) {
-            amax = fmax(amax, fabs(A[i * N + j]));
-            asym = fmax(asym, fabs(A[i * N + j] - A[j * N + i]));
-        }
-    if (asym > 1e-12 * amax)
-        return ORC_ENOTSYM;
+    const int dilate = (flags & ORC_HHL_DILATE) != 0;
+    int na = 0;
+    while ((1 << na) < N)
+        ++na;
+    if (!dilate && na < 1)
+        na = 1;
+    const int pa = 1 << na;               /* size of the padded A'       */
+    const int ns = dilate ? na + 1 : na;
+    const int dim = 1 << ns;
+    h->N = N; h->ns = ns; h->dim = dim;
+    h->x_off = dilate ? pa : 0;
+    if (!dilate) {
+        double amax = 0.0, asym = 0.0;
+        for (int i = 0; i < N; ++i)
+            for (int j = 0; j < N; ++j) {
+                amax = fmax(amax, fabs(A[i * N + j]));
+                asym = fmax(asym, fabs(A[i * N + j] - A[j * N + i]));
+            }
+        if (asym > 1e-12 * amax)
+            return ORC_ENOTSYM;
+    }
     h->Ap = (double *)calloc((size_t)dim * dim, sizeof(double));
     h->bh = (double *)calloc((size_t)dim, sizeof(double));
     h->V = (double *)calloc((size_t)dim * dim, sizeof(double));
     h->lam = (double *)calloc((size_t)dim, sizeof(double));
-    if (!h->Ap || !h->bh || !h->V || !h->lam) {
-        prep_free(h);
+    if (!h->Ap || !h->bh || !h->V || !h->lam)
         return ORC_ENOMEM;
-    }
-    for (int i = 0; i < dim; ++i)
-        for (int j = 0; j < dim; ++j)
-            h->Ap[i * dim + j] = (i < N && j < N) ? A[i * N + j]
-                                                  : (i == j ? 1.0 : 0.0);
+    for (int i = 0; i < pa; ++i)
+        for (int j = 0; j < pa; ++j) {
+            double a = (i < N && j < N) ? A[i * N + j] : (i == j ? 1.0 : 0.0);
+            if (dilate) {
+                h->Ap[i * dim + (pa + j)] = a;   /* upper right: A'        */
+                h->Ap[(pa + j) * dim + i] = a;   /* lower left: A'^T       */
+            } else {
+                h->Ap[i * dim + j] = a;
+            }
+        }
     double bb = 0.0;
     for (int i = 0; i < N; ++i)
         bb += b[i] * b[i];
     h->beta = sqrt(bb);
-    if (!(h->beta > 0.0)) {
-        prep_free(h);
+    if (!(h->beta > 0.0))
         return ORC_EINVAL;
-    }
     for (int i = 0; i < N; ++i)
         h->bh[i] = b[i] / h->beta;
-    int rc = orc_jacobi(h->Ap, dim, h->V, h->lam, NULL);
+    return ORC_OK;
+}
+
+int orc_hhl_system(const double *A, const double *b, int N, int flags,
+                   double *H, double *b_hat, int *x_off)
+{
+    hhl_prep h;
+    memset(&h, 0, sizeof(h));
+    if (N < 1 || (flags & ~(ORC_HHL_SIGNED | ORC_HHL_DILATE)))
+        return ORC_EINVAL;
+    int rc = hhl_system(A, b, N, flags, &h);
+    if (rc >= 0) {
+        if (H)
+            memcpy(H, h.Ap, sizeof(double) * (size_t)h.dim * h.dim);
+        if (b_hat)
+            memcpy(b_hat, h.bh, sizeof(double) * (size_t)h.dim);
+        if (x_off)
+            *x_off = h.x_off;
+        rc = h.dim;
+    }
+    prep_free(&h);
+    return rc;
+}
+
+/* Step 1 and the spectral parameters the circuit needs.
+ *   - the system of hhl_system;
+ *   - lambda_lo / lambda_hi: the smallest / largest eigenvalue among the
+ *     eigenvectors b_hat overlaps (weight (v_i . b_hat)^2 > 1e-20).  This is
+ *     "the smallest-magnitude eigenvalue of the matrix input" of step 4a once
+ *     the pad block, which b_hat never reaches, is excluded.  With the sign
+ *     qubit both are taken over |lambda|;
+ *   - sign qubit (the n_neg qubit of Sec. III-B, flag ORC_HHL_SIGNED, implied
+ *     by the dilation, whose spectrum is +-sigma): the paper only says that
+ *     one qubit is added when A has negative eigenvalues.  Reading: the m
+ *     clock qubits (the sign qubit among them, as in Table I's n_QPE) hold a
+ *     two's-complement value.  A negative eigenvalue's phase lambda t / 2 pi
+ *     wraps to 1 + lambda t / 2 pi, so its clock value c = 2^m + v decodes
+ *     to v = lambda t 2^m / 2 pi < 0; magnitudes get m - 1 bits;
+ *   - t (reading; the paper does not give its rule): with top = 2^m - 1
+ *     (2^{m-1} - 1 with the sign qubit), when kappa <= top,
+ *     j0 = floor(top / kappa) and t = 2 pi j0 / (2^m lambda_lo), so
+ *     lambda_lo lands on clock value j0 and lambda_hi at most on top;
+ *     otherwise t = 2 pi top / (2^m lambda_hi).  A caller-given t > 0
+ *     overrides the rule.  Then j0 = max(1, round(lambda_lo t 2^m / 2 pi))
+ *     and C = 2 pi j0 / (t 2^m), the eigenvalue clock value j0 stands for. */
+static int hhl_prepare(const double *A, const double *b, int N, int m,
+                       double t_in, int flags, hhl_prep *h)
+{
+    memset(h, 0, sizeof(*h));
+    const int sgn = (flags & (ORC_HHL_SIGNED | ORC_HHL_DILATE)) != 0;
+    if (N < 1 || m < 1 || m > 20 || (sgn && m < 2) ||
+        (flags & ~(ORC_HHL_SIGNED | ORC_HHL_DILATE)))
+        return ORC_EINVAL;
+    int rc = hhl_system(A, b, N, flags, h);
+    if (rc < 0) {
+        prep_free(h);
+        return rc;
+    }
+    const int dim = h->dim;
+    h->m = m; h->n = h->ns + m + 1; h->sgn = sgn;
+    rc = orc_jacobi(h->Ap, dim, h->V, h->lam, NULL);
     if (rc < 0) {
         prep_free(h);
         return rc;
@@ -527,17 +591,18 @@ static int hhl_prepare(const double *A, const double *b, int N, int m,
         for (int i = 0; i < dim; ++i)
             ov += h->V[i * dim + k] * h->bh[i];
         if (ov * ov > 1e-20) {
-            if (!found || h->lam[k] < h->lambda_lo) h->lambda_lo = h->lam[k];
-            if (!found || h->lam[k] > h->lambda_hi) h->lambda_hi = h->lam[k];
+            double l = sgn ? fabs(h->lam[k]) : h->lam[k];
+            if (!found || l < h->lambda_lo) h->lambda_lo = l;
+            if (!found || l > h->lambda_hi) h->lambda_hi = l;
             found = 1;
         }
     }
     if (!found || !(h->lambda_lo > 0.0)) {
         prep_free(h);
-        return ORC_ENOTPD;
+        return sgn ? ORC_ESINGULAR : ORC_ENOTPD;
     }
     h->kappa = h->lambda_hi / h->lambda_lo;
-    const double top = (double)((1L << m) - 1);
+    const double top = (double)((1L << (sgn ? m - 1 : m)) - 1);
     const double two_m = (double)(1L << m);
     if (t_in > 0.0) {
         h->t = t_in;
@@ -553,20 +618,25 @@ static int hhl_prepare(const double *A, const double *b, int N, int m,
     return ORC_OK;
 }
 
-int orc_hhl_params(const double *A, const double *b, int N, int m, double t,
-                   orc_hhl_info *info)
+static void fill_info(const hhl_prep *h, orc_hhl_info *info)
+{
+    memset(info, 0, sizeof(*info));
+    info->ns = h->ns; info->m = h->m; info->n = h->n; info->j0 = h->j0;
+    info->beta = h->beta; info->t = h->t; info->C = h->C;
+    info->lambda_lo = h->lambda_lo; info->lambda_hi = h->lambda_hi;
+    info->kappa = h->kappa;
+    info->x_off = h->x_off; info->sign_qubit = h->sgn;
+}
+
+int orc_hhl_params_ex(const double *A, const double *b, int N, int m, double t,
+                      int flags, orc_hhl_info *info)
 {
     hhl_prep h;
-    int rc = hhl_prepare(A, b, N, m, t, &h);
+    int rc = hhl_prepare(A, b, N, m, t, flags, &h);
     if (rc < 0)
         return rc;
-    if (info) {
-        memset(info, 0, sizeof(*info));
-        info->ns = h.ns; info->m = h.m; info->n = h.n; info->j0 = h.j0;
-        info->beta = h.beta; info->t = h.t; info->C = h.C;
-        info->lambda_lo = h.lambda_lo; info->lambda_hi = h.lambda_hi;
-        info->kappa = h.kappa;
-    }
+    if (info)
+        fill_info(&h, info);
     prep_free(&h);
     return ORC_OK;
 }
@@ -596,12 +666,18 @@ static void build_u(const hhl_prep *h, int j, int conj, cplx *U)
     free(ph);
 }
 
-int orc_hhl_solve(const double *A, const double *b, int N, int m, double t_in,
-                  double *psi_out, double *x_hhl, double *x_hat,
-                  orc_hhl_info *info)
+int orc_hhl_params(const double *A, const double *b, int N, int m, double t,
+                   orc_hhl_info *info)
+{
+    return orc_hhl_params_ex(A, b, N, m, t, 0, info);
+}
+
+int orc_hhl_solve_ex(const double *A, const double *b, int N, int m,
+                     double t_in, int flags, double *psi_out, double *x_hhl,
+                     double *x_hat, orc_hhl_info *info)
 {
     hhl_prep h;
-    int rc = hhl_prepare(A, b, N, m, t_in, &h);
+    int rc = hhl_prepare(A, b, N, m, t_in, flags, &h);
     if (rc < 0)
         return rc;
     const int ns = h.ns, n = h.n, d = h.dim;
@@ -631,13 +707,21 @@ int orc_hhl_solve(const double *A, const double *b, int N, int m, double t_in,
     }
     if (rc >= 0)
         rc = orc_qft((double *)psi, n, ns, m, 1);
-    /* Eigenvalue inversion: clock value c stands for lambda = C c / j0, and
-     * the ancilla is rotated so that its |1> amplitude is C / lambda =
-     * j0 / c (clamped to 1; c = 0 is left alone). */
+    /* Eigenvalue inversion: clock value c decodes to v (v = c, or with the
+     * sign qubit the two's-complement value, c - 2^m for c >= 2^{m-1}), which
+     * stands for lambda = C v / j0; the ancilla is rotated so that its |1>
+     * amplitude is C / lambda = j0 / v (clamped to [-1, 1]; v = 0 is left
+     * alone).  A negative v gives a negative angle, so the amplitude keeps
+     * lambda's sign. */
     theta[0] = 0.0;
     for (long c = 1; c < (1L << m); ++c) {
-        double a = (double)h.j0 / (double)c;
-        theta[c] = 2.0 * asin(a < 1.0 ? a : 1.0);
+        long v = (h.sgn && c >= (1L << (m - 1))) ? c - (1L << m) : c;
+        double a = (double)h.j0 / (double)v;
+        if (a > 1.0)
+            a = 1.0;
+        if (a < -1.0)
+            a = -1.0;
+        theta[c] = 2.0 * asin(a);
     }
     for (int j = 0; j < m; ++j)
         q[1 + j] = ns + j;
@@ -660,8 +744,10 @@ int orc_hhl_solve(const double *A, const double *b, int N, int m, double t_in,
         return rc;
     }
     /* Step 3: read the state.  Postselect ancilla = 1, clock = 0:
-     * y_s = psi[2^{n-1} + s]. */
+     * y_s = psi[2^{n-1} + s]; x is y over s = x_off .. x_off + N - 1 (the
+     * second half after the dilation). */
     const long base = 1L << (n - 1);
+    const long xb = base + h.x_off;
     double p1 = 0.0, p10 = 0.0, max_imag = 0.0, leak = 0.0, re_norm = 0.0;
     for (long i = base; i < dim; ++i)
         p1 += c_abs2(psi[i]);
@@ -670,7 +756,7 @@ int orc_hhl_solve(const double *A, const double *b, int N, int m, double t_in,
         p10 += c_abs2(y);
         if (fabs(y.im) > max_imag)
             max_imag = fabs(y.im);
-        if (s >= N)
+        if (s < h.x_off || s >= h.x_off + N)
             leak += c_abs2(y);
         else
             re_norm += y.re * y.re;
@@ -681,7 +767,7 @@ int orc_hhl_solve(const double *A, const double *b, int N, int m, double t_in,
      * x = beta * Re(y) / C (the printed |lambda_0| sqrt(P) is read as
      * sqrt(P) / |lambda_0|, with C standing for lambda_0). */
     for (int s = 0; s < N; ++s) {
-        double y = psi[base + s].re;
+        double y = psi[xb + s].re;
         if (x_hhl)
             x_hhl[s] = h.beta * y / h.C;
         if (x_hat)
@@ -690,14 +776,18 @@ int orc_hhl_solve(const double *A, const double *b, int N, int m, double t_in,
     if (psi_out)
         memcpy(psi_out, psi, sizeof(cplx) * (size_t)dim);
     if (info) {
-        info->ns = ns; info->m = m; info->n = n; info->j0 = h.j0;
-        info->beta = h.beta; info->t = h.t; info->C = h.C;
-        info->lambda_lo = h.lambda_lo; info->lambda_hi = h.lambda_hi;
-        info->kappa = h.kappa;
+        fill_info(&h, info);
         info->p1 = p1; info->p10 = p10; info->max_imag = max_imag;
         info->pad_leak = sqrt(leak);
         info->x_norm = h.beta * sqrt(p10) / h.C;
     }
     free(psi); free(U); free(q); free(theta); prep_free(&h);
     return ORC_OK;
+}
+
+int orc_hhl_solve(const double *A, const double *b, int N, int m, double t,
+                  double *psi_out, double *x_hhl, double *x_hat,
+                  orc_hhl_info *info)
+{
+    return orc_hhl_solve_ex(A, b, N, m, t, 0, psi_out, x_hhl, x_hat, info);
 }

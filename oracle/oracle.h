@@ -47,7 +47,16 @@ enum {
     ORC_EINVAL = -1,
     ORC_ENOMEM = -2,
     ORC_ENOTSYM = -4,
-    ORC_ENOTPD = -5
+    ORC_ENOTPD = -5,
+    ORC_ESINGULAR = -6
+};
+
+/* HHL variants (Sec. III-A step 1c, Sec. III-B n_neg). */
+enum {
+    ORC_HHL_SIGNED = 1,  /* sign qubit: the m clock qubits hold a two's-
+                            complement eigenvalue estimate (m >= 2)       */
+    ORC_HHL_DILATE = 2   /* solve [[0, A'], [A'^T, 0]] [0; x] = [b; 0]
+                            for a general square A (implies SIGNED)      */
 };
 
 /* Apply one gate to psi (2^n complex).  nparams counts doubles. */
@@ -89,10 +98,12 @@ typedef struct {
     double max_imag;  /* max |Im y_s| over the postselected block         */
     double pad_leak;  /* norm of y over the padded system indices         */
     double x_norm;    /* ||x|| recovered as sqrt(p10) / C times beta      */
+    int x_off;        /* x sits at system indices x_off .. x_off + N - 1  */
+    int sign_qubit;   /* 1 if the clock value is read in two's complement */
 } orc_hhl_info;
 
-/* Full HHL solve of A x = b (A symmetric positive definite, N x N) with m
- * clock qubits.  t > 0 fixes the evolution time; t <= 0 selects the
+/* Full HHL solve of A x = b (A symmetric positive definite on the span of b,
+ * N x N) with m clock qubits.  t > 0 fixes the evolution time; t <= 0 selects the
  * automatic rule.  Outputs (each may be NULL): psi_out (2^n complex final
  * state), x_hhl (N, the recovered solution), x_hat (N, unit norm). */
 int orc_hhl_solve(const double *A, const double *b, int N, int m, double t,
@@ -100,9 +111,25 @@ int orc_hhl_solve(const double *A, const double *b, int N, int m, double t,
                   orc_hhl_info *info);
 
 /* Spectral parameters only (no state): fills ns, m, n, j0, beta, t, C,
- * lambda_lo, lambda_hi, kappa. */
+ * lambda_lo, lambda_hi, kappa, x_off, sign_qubit. */
 int orc_hhl_params(const double *A, const double *b, int N, int m, double t,
                    orc_hhl_info *info);
+
+/* The same with ORC_HHL_* flags (0 = the calls above).  With the sign
+ * qubit, lambda_lo / lambda_hi / kappa are over |lambda|; a zero eigenvalue
+ * that b reaches gives ORC_ESINGULAR. */
+int orc_hhl_solve_ex(const double *A, const double *b, int N, int m,
+                     double t, int flags, double *psi_out, double *x_hhl,
+                     double *x_hat, orc_hhl_info *info);
+int orc_hhl_params_ex(const double *A, const double *b, int N, int m,
+                      double t, int flags, orc_hhl_info *info);
+
+/* The Hermitian system the circuit encodes (padded, dilated with
+ * ORC_HHL_DILATE): H (dim x dim, row-major) and the normalised right-hand
+ * side b_hat (dim), either may be NULL; *x_off as in orc_hhl_info.
+ * Returns dim (> 0) or an error. */
+int orc_hhl_system(const double *A, const double *b, int N, int flags,
+                   double *H, double *b_hat, int *x_off);
 
 #ifdef __cplusplus
 }

@@ -245,3 +245,176 @@ def test_hhl_rejects_bad_inputs():
         oracle.hhl_solve(A, np.ones(2), 3)
     with pytest.raises(RuntimeError):
         oracle.hhl_solve(np.eye(2), np.zeros(2), 3)
+
+
+# ------------------------------------------ dilation and the sign qubit ---
+@pytest.mark.parametrize("ns,m,seed", [(1, 4, 0), (2, 5, 1), (3, 6, 2), (4, 7, 3), (5, 8, 4)])
+def test_hhl_signed_exact_spectrum(ns, m, seed):
+    """Eigenvalues of both signs on the two's-complement clock grid: HHL with
+    the sign qubit returns A^{-1} b exactly, signs included."""
+    A, b, t, k = W.signed_spectrum_system(ns, m, seed)
+    assert (k < 0).any() and (k > 0).any()
+    psi, x, xh, info = oracle.hhl_solve(A, b, m, t, flags=oracle.HHL_SIGNED)
+    xs = np.linalg.solve(A, b)
+    assert info["sign_qubit"] == 1 and info["x_off"] == 0
+    assert abs(info["lambda_lo"] - 0.25 * np.abs(k).min()) < 1e-12
+    assert abs(info["lambda_hi"] - 0.25 * np.abs(k).max()) < 1e-12
+    assert np.linalg.norm(x - xs) <= 1e-12 * np.linalg.norm(xs)
+    bh = b / np.linalg.norm(b)
+    p_expected = info["C"] ** 2 * np.linalg.norm(np.linalg.solve(A, bh)) ** 2
+    assert abs(info["p10"] - p_expected) < 1e-12
+    assert abs(info["p1"] - p_expected) < 1e-12
+    assert info["max_imag"] < 1e-12
+    assert abs(np.vdot(psi, psi).real - 1) < 2 * m * (1 << ns) * 2.3e-16
+
+
+def test_hhl_signed_unsigned_clock_differ():
+    """The same indefinite system without the sign qubit is refused, and a
+    positive definite one solved with it still gives A^{-1} b."""
+    A, b, t, k = W.signed_spectrum_system(2, 5, 7)
+    with pytest.raises(RuntimeError):
+        oracle.hhl_solve(A, b, 5, t)
+    A, b, t, k = W.exact_spectrum_system(2, 4, 3)
+    # magnitudes < 2^4 fit the 4 magnitude bits of a 5-bit signed clock
+    _, x, _, info = oracle.hhl_solve(A, b, 5, t / 2, flags=oracle.HHL_SIGNED)
+    xs = np.linalg.solve(A, b)
+    assert np.linalg.norm(x - xs) <= 1e-12 * np.linalg.norm(xs)
+
+
+@pytest.mark.parametrize("N", [2, 5])
+def test_hhl_negative_definite(N):
+    """-A for a positive definite A: every eigenvalue negative, x = -x(A)."""
+    rng = np.random.default_rng(N)
+    lam = -0.5 * rng.integers(1, 8, size=N)      # -0.5 .. -3.5: grid of delta 0.5
+    q = np.linalg.qr(rng.standard_normal((N, N)))[0]
+    A = (q * lam) @ q.T
+    A = 0.5 * (A + A.T)
+    b = rng.standard_normal(N)
+    m = 5
+    t = 2 * math.pi / ((1 << m) * 0.5)
+    _, x, _, info = oracle.hhl_solve(A, b, m, t, flags=oracle.HHL_SIGNED)
+    xs = np.linalg.solve(A, b)
+    assert np.linalg.norm(x - xs) <= 1e-12 * np.linalg.norm(xs)
+    _, x2, _, _ = oracle.hhl_solve(-A, b, m, t, flags=oracle.HHL_SIGNED)
+    assert np.linalg.norm(x2 + xs) <= 1e-12 * np.linalg.norm(xs)
+
+
+@pytest.mark.parametrize("N,seed", [(1, 0), (2, 1), (3, 2), (4, 3), (6, 4), (8, 5), (13, 6)])
+def test_dilation_identity(N, seed):
+    """Step 1c: H = [[0, A'], [A'^T, 0]] is symmetric, H [0; x] = [b_hat; 0]
+    for the solution x of A x = b_hat, and its spectrum is +- the singular
+    values of A' (those of A plus 1 for the pad)."""
+    A, b = W.general_system(N, seed, kappa=30.0)
+    H, bh, xo = oracle.hhl_system(A, b, oracle.HHL_DILATE)
+    pa = 1 << max(0, math.ceil(math.log2(N)))
+    assert H.shape == (2 * pa, 2 * pa) and xo == pa
+    assert np.array_equal(H, H.T)
+    x = np.linalg.solve(A, b / np.linalg.norm(b))
+    v = np.zeros(2 * pa)
+    v[pa:pa + N] = x
+    rhs = np.zeros(2 * pa)
+    rhs[:N] = b / np.linalg.norm(b)
+    assert np.allclose(bh, rhs, rtol=0, atol=1e-15)
+    assert np.linalg.norm(H @ v - rhs) < 1e-12 * np.linalg.norm(x) * 30
+    sv = np.concatenate([np.linalg.svd(A, compute_uv=False), np.ones(pa - N)])
+    ev = np.sort(np.linalg.eigvalsh(H))
+    assert np.allclose(ev, np.sort(np.concatenate([sv, -sv])), rtol=0, atol=1e-12 * 30)
+    # without the flag: the padded symmetric A (+) I
+    S, bs = W.general_system(N, seed, kappa=30.0, symmetric=True)
+    H2, bh2, xo2 = oracle.hhl_system(S, bs, 0)
+    d = 1 << max(1, math.ceil(math.log2(N)))
+    ref = np.eye(d)
+    ref[:N, :N] = S
+    assert xo2 == 0 and np.array_equal(H2, ref)
+
+
+@pytest.mark.parametrize("N,m,seed", [(1, 4, 0), (2, 5, 1), (3, 6, 2), (4, 6, 3), (6, 7, 4), (8, 7, 5)])
+def test_hhl_dilation_exact(N, m, seed):
+    """A non-symmetric A whose singular values sit on the clock grid: the
+    dilated solve returns A^{-1} b exactly from the second half of the
+    system register, with nothing left in the first half."""
+    A, b, t, k = W.nonsymmetric_exact_system(N, m, seed)
+    assert np.abs(A - A.T).max() > 1e-3 or N == 1
+    _, x, xh, info = oracle.hhl_solve(A, b, m, t, flags=oracle.HHL_DILATE)
+    xs = np.linalg.solve(A, b)
+    assert info["sign_qubit"] == 1
+    assert info["x_off"] == 1 << max(0, math.ceil(math.log2(N)))
+    assert info["ns"] == math.ceil(math.log2(N)) + 1
+    sv = np.linalg.svd(A, compute_uv=False)
+    assert abs(info["lambda_lo"] - sv.min()) < 1e-12 * sv.max()
+    assert abs(info["lambda_hi"] - sv.max()) < 1e-12 * sv.max()
+    assert np.linalg.norm(x - xs) <= 1e-12 * np.linalg.norm(xs)
+    assert info["pad_leak"] < 1e-12
+    assert info["max_imag"] < 1e-12
+
+
+def test_hhl_dilation_symmetric_input():
+    """Dilating a symmetric A gives the same x as solving it directly."""
+    A, b, t, k = W.signed_spectrum_system(2, 6, 11)
+    _, x1, _, _ = oracle.hhl_solve(A, b, 6, t, flags=oracle.HHL_SIGNED)
+    _, x2, _, info = oracle.hhl_solve(A, b, 6, t, flags=oracle.HHL_DILATE)
+    xs = np.linalg.solve(A, b)
+    assert np.linalg.norm(x1 - xs) <= 1e-12 * np.linalg.norm(xs)
+    assert np.linalg.norm(x2 - xs) <= 1e-12 * np.linalg.norm(xs)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_hhl_dilation_converges_with_clock_bits(seed):
+    """Off the grid, the dilated solve approaches A^{-1} b as clock qubits
+    are added (phase-estimation error shrinks with resolution)."""
+    A, b = W.general_system(4, seed, kappa=6.0)
+    xs = np.linalg.solve(A, b)
+    errs = []
+    for m in (5, 8, 11):
+        _, x, _, _ = oracle.hhl_solve(A, b, m, flags=oracle.HHL_DILATE,
+                                      want_state=False)
+        errs.append(np.linalg.norm(x - xs) / np.linalg.norm(xs))
+    assert errs[2] < errs[0]
+    assert errs[2] < 0.05
+
+
+def test_hhl_signed_rejects_bad_inputs():
+    A, b, t, k = W.signed_spectrum_system(1, 4, 0)
+    with pytest.raises(RuntimeError):      # no magnitude bit left
+        oracle.hhl_solve(A, b, 1, flags=oracle.HHL_SIGNED)
+    with pytest.raises(RuntimeError):      # b reaches a zero eigenvalue
+        oracle.hhl_solve(np.diag([1.0, 0.0]), np.ones(2), 4, flags=oracle.HHL_SIGNED)
+    with pytest.raises(RuntimeError):      # unknown flag
+        oracle.hhl_solve(np.eye(2), np.ones(2), 4, flags=8)
+    # a zero eigenvalue b does not reach is harmless
+    _, x, _, _ = oracle.hhl_solve(np.diag([2.0, 0.0]), np.array([1.0, 0.0]), 4,
+                                  flags=oracle.HHL_SIGNED)
+    assert abs(x[0] - 0.5) < 1e-12 and abs(x[1]) < 1e-12
+
+
+@pytest.mark.parametrize("m", [2, 3, 5])
+def test_hhl_signed_clock_range_ends(m):
+    """The m-bit two's-complement clock spans -2^{m-1} .. 2^{m-1} - 1: an
+    eigenvalue at exactly -2^{m-1} steps (phase -1/2) and one at +1 step are
+    both inverted exactly, with their signs."""
+    delta = 0.5
+    lam = np.array([-(1 << (m - 1)) * delta, delta])
+    q = np.linalg.qr(np.random.default_rng(m).standard_normal((2, 2)))[0]
+    A = (q * lam) @ q.T
+    A = 0.5 * (A + A.T)
+    b = np.array([0.6, -0.8])
+    t = 2 * math.pi / ((1 << m) * delta)
+    _, x, _, info = oracle.hhl_solve(A, b, m, t, flags=oracle.HHL_SIGNED)
+    xs = np.linalg.solve(A, b)
+    assert info["j0"] == 1
+    assert np.linalg.norm(x - xs) <= 1e-12 * np.linalg.norm(xs)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_hhl_dilation_leak_accounting(seed):
+    """Off the grid: x is read from the second half only, and pad_leak is
+    the norm of every other postselected amplitude."""
+    A, b = W.general_system(3, seed, kappa=5.0)
+    psi, x, xh, info = oracle.hhl_solve(A, b, 6, flags=oracle.HHL_DILATE)
+    n, xo = info["n"], info["x_off"]
+    y = psi[1 << (n - 1):(1 << (n - 1)) + (1 << info["ns"])]
+    keep = np.zeros(y.size, dtype=bool)
+    keep[xo:xo + 3] = True
+    assert abs(info["pad_leak"] - np.linalg.norm(y[~keep])) < 1e-14
+    assert np.allclose(x, info["beta"] * y[keep].real / info["C"], rtol=0, atol=1e-14)
+    assert abs(info["p10"] - np.vdot(y, y).real) < 1e-14

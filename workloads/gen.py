@@ -37,7 +37,8 @@ __all__ = [
     "Gate", "dc_powerflow", "layered_circuit", "random_unitary",
     "random_state", "random_circuit", "wide_gate_circuit", "batch_specs",
     "serve_specs", "exact_spectrum_system", "split_register_circuit",
-    "flatten_circuit", "TWO_PI",
+    "flatten_circuit", "TWO_PI", "signed_spectrum_system",
+    "nonsymmetric_exact_system", "general_system",
 ]
 
 TWO_PI = 2.0 * math.pi
@@ -119,6 +120,92 @@ def exact_spectrum_system(ns: int, m: int, seed: int, k_lo: int | None = None,
     b = rng.standard_normal(dim)
     t = TWO_PI / ((1 << m) * delta)
     return A, b, t, k
+
+
+def _orthogonal(dim: int, rng: np.random.Generator) -> np.ndarray:
+    """Haar-distributed real orthogonal ``dim x dim`` matrix."""
+    z = rng.standard_normal((dim, dim))
+    q, r = np.linalg.qr(z)
+    return q * np.sign(np.diag(r))
+
+
+def signed_spectrum_system(ns: int, m: int, seed: int, k_lo: int | None = None,
+                           delta: float = 0.25):
+    """Symmetric indefinite system with eigenvalues ``+-delta * k_i``.
+
+    ``k_i`` are integers in ``[k_lo, 2^(m-1) - 1]`` with seeded signs (both
+    signs present when the dimension allows), so with
+    ``t = 2*pi / (2^m * delta)`` every eigenvalue maps to an integer clock
+    value that fits an m-bit two's-complement register.  Returns
+    ``(A, b, t, signed_k)``.
+    """
+    rng = np.random.default_rng(seed)
+    dim = 1 << ns
+    top = (1 << (m - 1)) - 1
+    if k_lo is None:
+        k_lo = max(1, top // 8)
+    k = rng.integers(k_lo, top + 1, size=dim)
+    k[0] = k_lo
+    sg = rng.choice([-1, 1], size=dim)
+    if dim > 1:
+        sg[0], sg[1] = -1, 1
+    else:
+        sg[0] = -1
+    q = _orthogonal(dim, rng)
+    lam = delta * sg * k
+    A = (q * lam) @ q.T
+    A = 0.5 * (A + A.T)
+    b = rng.standard_normal(dim)
+    t = TWO_PI / ((1 << m) * delta)
+    return A, b, t, sg * k
+
+
+def nonsymmetric_exact_system(N: int, m: int, seed: int,
+                              k_lo: int | None = None, delta: float = 0.25):
+    """Non-symmetric ``N x N`` system ``A = U diag(delta * k) W^T``.
+
+    ``U`` and ``W`` are independent seeded random orthogonal matrices and
+    ``k_i`` integers in ``[k_lo, 2^(m-1) - 1]``, so the singular values, and
+    with them the +- eigenvalues of the dilated system, sit on the clock grid
+    of ``t = 2*pi / (2^m * delta)``.  Returns ``(A, b, t, k)``.
+    """
+    rng = np.random.default_rng(seed)
+    top = (1 << (m - 1)) - 1
+    if k_lo is None:
+        k_lo = max(1, top // 8)
+    k = rng.integers(k_lo, top + 1, size=N)
+    k[0] = k_lo
+    u = _orthogonal(N, rng)
+    w = _orthogonal(N, rng)
+    A = (u * (delta * k)) @ w.T
+    b = rng.standard_normal(N)
+    t = TWO_PI / ((1 << m) * delta)
+    return A, b, t, k
+
+
+def general_system(N: int, seed: int, kappa: float = 20.0,
+                   symmetric: bool = False, negative_frac: float = 0.5):
+    """Seeded well-posed system with condition number ``kappa``.
+
+    ``symmetric=False``: ``A = U diag(s) W^T`` with singular values ``s``
+    log-uniform in ``[1, kappa]`` (the extremes present).
+    ``symmetric=True``: ``A = Q diag(s * sign) Q^T`` with about
+    ``negative_frac`` of the eigenvalues negative.  Returns ``(A, b)``.
+    """
+    rng = np.random.default_rng(seed)
+    s = np.exp(rng.uniform(0.0, math.log(kappa), size=N))
+    s[0] = 1.0
+    if N > 1:
+        s[-1] = kappa
+    if symmetric:
+        sg = np.where(rng.uniform(size=N) < negative_frac, -1.0, 1.0)
+        q = _orthogonal(N, rng)
+        A = (q * (s * sg)) @ q.T
+        A = 0.5 * (A + A.T)
+    else:
+        A = (_orthogonal(N, rng) * s) @ _orthogonal(N, rng).T
+    b = rng.standard_normal(N)
+    return A, b
 
 
 # --------------------------------------------------------------------------
