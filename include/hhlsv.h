@@ -55,7 +55,8 @@ typedef enum {
     SV_ERR_NOT_SYMMETRIC = -4,
     SV_ERR_NOT_POSDEF = -5,
     SV_ERR_SHAPE = -6,
-    SV_ERR_BUSY = -7
+    SV_ERR_BUSY = -7,
+    SV_ERR_SINGULAR = -8     /* b reaches a zero eigenvalue (signed HHL)  */
 } sv_status;
 
 typedef enum { SV_C128 = 0, SV_C64 = 1 } sv_dtype;
@@ -101,6 +102,10 @@ typedef struct {
     double C;         /* inversion constant: ancilla |1> amplitude C/lambda  */
     double lambda_lo, lambda_hi, kappa;  /* over the eigenvectors b reaches */
     double b_norm;    /* ||b|| (step 1)                                     */
+    int x_offset;     /* x is read at system indices x_offset .. + dim - 1 */
+    int sign_qubit;   /* 1: the clock holds a two's-complement value       */
+    int dilated;      /* 1: the circuit solves [[0, A'], [A'^T, 0]]        */
+    int preconditioned; /* 1: Gauss-Seidel, the circuit solves M^{-1}A    */
 } sv_hhl_info;
 
 /* Result of postselection (Sec. III-A steps 3-4). */
@@ -175,7 +180,31 @@ enum {
      * applied or added to a batch, instead of on the host at build time.
      * Host consumers that need them (circuit_serialize, fuse when the gate
      * fits in k_max) build them on demand. */
-    SV_HHL_DEVICE_EVOLUTIONS = 1
+    SV_HHL_DEVICE_EVOLUTIONS = 1,
+    /* Sign qubit (the n_neg qubit of Sec. III-B) for a symmetric A with
+     * eigenvalues of either sign: the m clock qubits hold the eigenvalue
+     * estimate in two's complement (-2^{m-1} .. 2^{m-1} - 1, m >= 2), the
+     * automatic t maps max|lambda| to at most 2^{m-1} - 1, and the
+     * inversion angle for decoded value v != 0 is 2 asin(clamp(j0 / v)),
+     * negative for v < 0.  lambda_lo / lambda_hi / kappa are over |lambda|.
+     * SV_ERR_SINGULAR when b reaches a zero eigenvalue. */
+    SV_HHL_SIGNED = 2,
+    /* Hermitian dilation (Sec. III-A step 1c) for a general square A: A is
+     * padded to A' = A (+) I of size 2^k >= dim (step 1b), then the circuit
+     * solves [[0, A'], [A'^T, 0]] [0; x] = [b; 0] on k + 1 system qubits
+     * with the sign qubit (implies SV_HHL_SIGNED), and postselection reads
+     * x from the second half (x_offset = 2^k).  dim <= 2048. */
+    SV_HHL_DILATE = 4,
+    /* Choose per input: SV_HHL_DILATE when A is not symmetric, else
+     * SV_HHL_SIGNED when an eigenvalue b reaches is <= 0, else neither. */
+    SV_HHL_AUTO = 8,
+    /* Gauss-Seidel preconditioning (Sec. III-A step 1a, Sec. III-B): with
+     * M = D + L, the lower triangle of A including the diagonal, the circuit
+     * solves (M^{-1} A) x = M^{-1} b, which has the same solution and
+     * usually a lower condition number.  M^{-1} A is not symmetric, so this
+     * implies SV_HHL_DILATE; lambda_lo / lambda_hi / kappa / b_norm describe
+     * the preconditioned system.  SV_ERR_SINGULAR on a zero diagonal entry. */
+    SV_HHL_GAUSS_SEIDEL = 16
 };
 
 /* circuit_build_hhl with flags (0 = circuit_build_hhl). */
@@ -309,9 +338,12 @@ enum {
     SVS_OPT_QUEUE_LIMIT = 5,   /* queued, not yet admitted requests              */
     SVS_OPT_FAIL_ALLOC_AT = 6, /* failure injection: the n-th request device
                                   allocation fails as out of memory (0 = off)  */
-    SVS_OPT_BATCH_MAX_QUBITS = 7 /* also batch requests of up to this many
+    SVS_OPT_BATCH_MAX_QUBITS = 7, /* also batch requests of up to this many
                                   qubits with the state in HBM (default 0:
                                   batch only states that fit in LDS)          */
+    SVS_OPT_HHL_FLAGS = 8      /* SV_HHL_SIGNED | _DILATE | _AUTO |
+                                  _GAUSS_SEIDEL for every request's circuit
+                                  (default 0)                                 */
 };
 sv_status svs_start(size_t hbm_budget_bytes, int max_slots, sv_dtype dtype,
                     svs **out);

@@ -17,6 +17,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 HHL_SIGNED = 1   # two's-complement clock (sign qubit)
 HHL_DILATE = 2   # [[0, A'], [A'^T, 0]] for a general square A
+HHL_GS = 4       # Gauss-Seidel left preconditioning, then the dilation
 
 KIND = {"h": 0, "x": 1, "ry": 2, "rz": 3, "p": 4, "u3": 5, "cx": 6, "cp": 7,
         "swap": 8, "dense": 9, "cdense": 10, "ucry": 11}

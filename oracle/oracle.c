@@ -461,7 +461,9 @@ static void prep_free(hhl_prep *h)
 }
 
 /* Step 1 of the procedure box: the Hermitian system the circuit encodes.
- *   - b_hat = b / ||b||, beta = ||b||;
+ *   - step 1a (flag ORC_HHL_GS): A, b -> M^{-1} A, M^{-1} b (gauss_seidel),
+ *     then the dilation, since M^{-1} A is not symmetric;
+ *   - b_hat = b / ||b||, beta = ||b|| (of the preconditioned b with GS);
  *   - step 1b: A is padded to the next power of two, A' = A (+) I, with b
  *     zero-padded;
  *   - step 1c (flag ORC_HHL_DILATE): the padded A' is replaced by the
@@ -472,10 +474,57 @@ static void prep_free(hhl_prep *h)
  *     order is kept, so a 29 x 29 A becomes 32 x 32 and then 64 x 64,
  *     the 6 data qubits of Table I's preconditioned 30-bus case.
  *   - without the flag A must be symmetric. */
-static int hhl_system(const double *A, const double *b, int N, int flags,
-                      hhl_prep *h)
+/* Gauss-Seidel preconditioning (step 1a, Sec. III-B): with M = D + L, the
+ * lower triangle of A including its diagonal, the system becomes
+ * (M^{-1} A) x = M^{-1} b, which has the same solution.  The paper names the
+ * preconditioner but gives no formula; this is the textbook left
+ * Gauss-Seidel splitting.  M^{-1} A and M^{-1} b come from forward
+ * substitution, one column at a time.  Returns ORC_ESINGULAR for a zero
+ * diagonal entry. */
+static int gauss_seidel(const double *A, const double *b, int N, double *At,
+                        double *bt)
 {
-    const int dilate = (flags & ORC_HHL_DILATE) != 0;
+    for (int i = 0; i < N; ++i)
+        if (A[i * N + i] == 0.0)
+            return ORC_ESINGULAR;
+    for (int col = 0; col <= N; ++col) {
+        /* column col of A, or b for col == N */
+        for (int i = 0; i < N; ++i) {
+            double r = col < N ? A[i * N + col] : b[i];
+            for (int k = 0; k < i; ++k)
+                r -= A[i * N + k] * (col < N ? At[k * N + col] : bt[k]);
+            r /= A[i * N + i];
+            if (col < N)
+                At[i * N + col] = r;
+            else
+                bt[i] = r;
+        }
+    }
+    return ORC_OK;
+}
+
+static int hhl_system(const double *A_in, const double *b_in, int N,
+                      int flags, hhl_prep *h)
+{
+    const int gs = (flags & ORC_HHL_GS) != 0;
+    const int dilate = gs || (flags & ORC_HHL_DILATE) != 0;
+    const double *A = A_in, *b = b_in;
+    double *At = NULL, *bt = NULL;
+    if (gs) {
+        At = (double *)malloc(sizeof(double) * (size_t)N * N);
+        bt = (double *)malloc(sizeof(double) * (size_t)N);
+        if (!At || !bt) {
+            free(At); free(bt);
+            return ORC_ENOMEM;
+        }
+        int rc = gauss_seidel(A_in, b_in, N, At, bt);
+        if (rc < 0) {
+            free(At); free(bt);
+            return rc;
+        }
+        A = At;
+        b = bt;
+    }
     int na = 0;
     while ((1 << na) < N)
         ++na;
@@ -493,15 +542,19 @@ static int hhl_system(const double *A, const double *b, int N, int flags,
                 amax = fmax(amax, fabs(A[i * N + j]));
                 asym = fmax(asym, fabs(A[i * N + j] - A[j * N + i]));
             }
-        if (asym > 1e-12 * amax)
+        if (asym > 1e-12 * amax) {
+            free(At); free(bt);
             return ORC_ENOTSYM;
+        }
     }
     h->Ap = (double *)calloc((size_t)dim * dim, sizeof(double));
     h->bh = (double *)calloc((size_t)dim, sizeof(double));
     h->V = (double *)calloc((size_t)dim * dim, sizeof(double));
     h->lam = (double *)calloc((size_t)dim, sizeof(double));
-    if (!h->Ap || !h->bh || !h->V || !h->lam)
+    if (!h->Ap || !h->bh || !h->V || !h->lam) {
+        free(At); free(bt);
         return ORC_ENOMEM;
+    }
     for (int i = 0; i < pa; ++i)
         for (int j = 0; j < pa; ++j) {
             double a = (i < N && j < N) ? A[i * N + j] : (i == j ? 1.0 : 0.0);
@@ -516,11 +569,11 @@ static int hhl_system(const double *A, const double *b, int N, int flags,
     for (int i = 0; i < N; ++i)
         bb += b[i] * b[i];
     h->beta = sqrt(bb);
-    if (!(h->beta > 0.0))
-        return ORC_EINVAL;
-    for (int i = 0; i < N; ++i)
-        h->bh[i] = b[i] / h->beta;
-    return ORC_OK;
+    if (h->beta > 0.0)
+        for (int i = 0; i < N; ++i)
+            h->bh[i] = b[i] / h->beta;
+    free(At); free(bt);
+    return h->beta > 0.0 ? ORC_OK : ORC_EINVAL;
 }
 
 int orc_hhl_system(const double *A, const double *b, int N, int flags,
@@ -528,7 +581,7 @@ int orc_hhl_system(const double *A, const double *b, int N, int flags,
 {
     hhl_prep h;
     memset(&h, 0, sizeof(h));
-    if (N < 1 || (flags & ~(ORC_HHL_SIGNED | ORC_HHL_DILATE)))
+    if (N < 1 || (flags & ~(ORC_HHL_SIGNED | ORC_HHL_DILATE | ORC_HHL_GS)))
         return ORC_EINVAL;
     int rc = hhl_system(A, b, N, flags, &h);
     if (rc >= 0) {
@@ -569,9 +622,9 @@ static int hhl_prepare(const double *A, const double *b, int N, int m,
                        double t_in, int flags, hhl_prep *h)
 {
     memset(h, 0, sizeof(*h));
-    const int sgn = (flags & (ORC_HHL_SIGNED | ORC_HHL_DILATE)) != 0;
+    const int sgn = (flags & (ORC_HHL_SIGNED | ORC_HHL_DILATE | ORC_HHL_GS)) != 0;
     if (N < 1 || m < 1 || m > 20 || (sgn && m < 2) ||
-        (flags & ~(ORC_HHL_SIGNED | ORC_HHL_DILATE)))
+        (flags & ~(ORC_HHL_SIGNED | ORC_HHL_DILATE | ORC_HHL_GS)))
         return ORC_EINVAL;
     int rc = hhl_system(A, b, N, flags, h);
     if (rc < 0) {

@@ -55,8 +55,11 @@ enum {
 enum {
     ORC_HHL_SIGNED = 1,  /* sign qubit: the m clock qubits hold a two's-
                             complement eigenvalue estimate (m >= 2)       */
-    ORC_HHL_DILATE = 2   /* solve [[0, A'], [A'^T, 0]] [0; x] = [b; 0]
+    ORC_HHL_DILATE = 2,  /* solve [[0, A'], [A'^T, 0]] [0; x] = [b; 0]
                             for a general square A (implies SIGNED)      */
+    ORC_HHL_GS = 4       /* Gauss-Seidel: solve (M^{-1} A) x = M^{-1} b,
+                            M = lower triangle of A with the diagonal
+                            (implies DILATE); beta = ||M^{-1} b||        */
 };
 
 /* Apply one gate to psi (2^n complex).  nparams counts doubles. */

@@ -36,7 +36,7 @@ KERNEL_FAMILY = {0: "dense_direct", 1: "dense_lds", 2: "dense_small", 3: "diag",
                  4: "wide", 5: "ucry"}
 STATUS = {0: "SV_OK", 1: "SV_PENDING", -1: "SV_ERR_INVALID", -2: "SV_ERR_OOM",
           -3: "SV_ERR_HIP", -4: "SV_ERR_NOT_SYMMETRIC", -5: "SV_ERR_NOT_POSDEF",
-          -6: "SV_ERR_SHAPE", -7: "SV_ERR_BUSY"}
+          -6: "SV_ERR_SHAPE", -7: "SV_ERR_BUSY", -8: "SV_ERR_SINGULAR"}
 
 
 class HHLSVError(RuntimeError):
@@ -53,7 +53,9 @@ class HHLInfo(ctypes.Structure):
                 ("j0", ctypes.c_int), ("t", ctypes.c_double),
                 ("C", ctypes.c_double), ("lambda_lo", ctypes.c_double),
                 ("lambda_hi", ctypes.c_double), ("kappa", ctypes.c_double),
-                ("b_norm", ctypes.c_double)]
+                ("b_norm", ctypes.c_double), ("x_offset", ctypes.c_int),
+                ("sign_qubit", ctypes.c_int), ("dilated", ctypes.c_int),
+                ("preconditioned", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -221,18 +223,34 @@ def circuit_from_gates(n_qubits: int, gates) -> Circuit:
 
 
 SV_HHL_DEVICE_EVOLUTIONS = 1
+SV_HHL_SIGNED = 2
+SV_HHL_DILATE = 4
+SV_HHL_AUTO = 8
+SV_HHL_GAUSS_SEIDEL = 16
+HHL_MODES = {"spd": 0, "signed": SV_HHL_SIGNED, "dilate": SV_HHL_DILATE, "auto": SV_HHL_AUTO,
+             "gauss_seidel": SV_HHL_GAUSS_SEIDEL}
+
+
+def _hhl_flags(mode: str) -> int:
+    try:
+        return HHL_MODES[mode]
+    except KeyError:
+        raise ValueError(f"mode must be one of {sorted(HHL_MODES)}") from None
 
 
 def circuit_build_hhl(A, b, clock_bits: int, t: float = 0.0,
-                      device_evolutions: bool = False) -> Circuit:
+                      device_evolutions: bool = False, mode: str = "spd") -> Circuit:
     """HHL circuit for A x = b.  device_evolutions=True keeps the
-    eigen-decomposition and builds the controlled e^{iAt 2^j} on the GPU."""
+    eigen-decomposition and builds the controlled e^{iAt 2^j} on the GPU.
+    mode: "spd" (symmetric, positive on b's span), "signed" (sign qubit),
+    "dilate" (general square A through [[0, A'], [A'^T, 0]]), "auto", or
+    "gauss_seidel" (left Gauss-Seidel preconditioning, then the dilation)."""
     A = np.ascontiguousarray(A, dtype=np.float64)
     b = np.ascontiguousarray(b, dtype=np.float64).ravel()
     if A.shape != (b.size, b.size):
         raise ValueError("A must be dim x dim with dim = len(b)")
     h = _vp()
-    flags = SV_HHL_DEVICE_EVOLUTIONS if device_evolutions else 0
+    flags = (SV_HHL_DEVICE_EVOLUTIONS if device_evolutions else 0) | _hhl_flags(mode)
     _check(_lib.circuit_build_hhl_ex(_dptr(A), _dptr(b), b.size, clock_bits, float(t), flags,
                                      ctypes.byref(h)), "circuit_build_hhl")
     return Circuit(h.value)
@@ -350,11 +368,12 @@ def sv_postselect_solution(s: State, hhl: Circuit, dim: int):
     return s.postselect_solution(hhl, dim)
 
 
-def solve(A, b, clock_bits: int, dtype="c128", k_max: int | None = None, t: float = 0.0):
+def solve(A, b, clock_bits: int, dtype="c128", k_max: int | None = None, t: float = 0.0,
+          mode: str = "spd"):
     """One HHL solve end to end: build, (fuse), apply, postselect.
 
     Returns (x, x_hat, solution_info, hhl_info)."""
-    c = circuit_build_hhl(A, b, clock_bits, t)
+    c = circuit_build_hhl(A, b, clock_bits, t, mode=mode)
     run = fuse(c, k_max) if k_max else c
     s = sv_create(c.n_qubits, dtype)
     s.apply(run)
@@ -419,17 +438,20 @@ def svb_autotune(dtype, sample: Circuit, copies: int = 64):
 
 # ------------------------------------------------------------------- serving
 SVS_OPT = {"prep_threads": 1, "k_max": 2, "max_batch": 3, "streams": 4, "queue_limit": 5,
-           "fail_alloc_at": 6, "batch_max_qubits": 7}
+           "fail_alloc_at": 6, "batch_max_qubits": 7, "hhl_flags": 8}
 
 
 class Server:
     """Owning wrapper of an ``svs*`` continuous-batching server."""
 
-    def __init__(self, dtype="c128", hbm_budget_bytes: int = 0, max_slots: int = 4096, **options):
+    def __init__(self, dtype="c128", hbm_budget_bytes: int = 0, max_slots: int = 4096,
+                 mode: str = "spd", **options):
         h = _vp()
         _check(_lib.svs_start(hbm_budget_bytes, max_slots, DTYPES[dtype], ctypes.byref(h)), "svs_start")
         self.handle = h
         self.dims = {}
+        if mode != "spd":
+            options = dict(options, hhl_flags=_hhl_flags(mode))
         for k, v in options.items():
             _check(_lib.svs_configure(self.handle, SVS_OPT[k], float(v)), "svs_configure")
 

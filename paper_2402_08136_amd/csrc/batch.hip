@@ -771,20 +771,23 @@ extern "C" sv_status svb_size(const svb *b, int *count)
 sv_status hhlsv::recover_solution(const HHLParams &h, const double *p1_y, double *x_hat, int dim,
                                   sv_solution_info *info)
 {
+    // y_s for s < 2^ns; x occupies s = x_off .. x_off + dim - 1 (the second
+    // half after the dilation), every other entry counts as leak.
     const size_t D = (size_t)1 << h.ns;
+    const size_t xo = (size_t)h.x_off;
     const double *y = p1_y + 2;
     double p10 = 0.0, max_imag = 0.0, leak = 0.0, re2 = 0.0;
     for (size_t i = 0; i < D; ++i) {
         const double re = y[2 * i], im = y[2 * i + 1];
         p10 += re * re + im * im;
         max_imag = std::max(max_imag, std::fabs(im));
-        if ((int)i >= dim)
+        if (i < xo || i >= xo + (size_t)dim)
             leak += re * re + im * im;
         else
             re2 += re * re;
     }
     const double rn = std::sqrt(re2);
-    for (int i = 0; i < dim; ++i) x_hat[i] = rn > 0.0 ? y[2 * i] / rn : 0.0;
+    for (int i = 0; i < dim; ++i) x_hat[i] = rn > 0.0 ? y[2 * (xo + i)] / rn : 0.0;
     if (info) {
         info->scale = h.b_norm * rn / h.C;
         info->p_anc1 = p1_y[0];

@@ -298,6 +298,10 @@ extern "C" sv_status circuit_info(const sv_circuit *c, sv_hhl_info *out)
         out->lambda_hi = h.lambda_hi;
         out->kappa = h.kappa;
         out->b_norm = h.b_norm;
+        out->x_offset = h.x_off;
+        out->sign_qubit = h.sign_qubit ? 1 : 0;
+        out->dilated = h.dilated ? 1 : 0;
+        out->preconditioned = h.preconditioned ? 1 : 0;
     }
     return SV_OK;
 }

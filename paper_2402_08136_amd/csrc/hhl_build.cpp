@@ -302,6 +302,43 @@ extern "C" sv_status sv_qubit_estimate(int dim, double kappa, int has_negative,
     return SV_OK;
 }
 
+namespace {
+
+// Step 1a with the Gauss-Seidel splitting A = (D + L) + U: the system becomes
+// (D + L)^{-1} A x = (D + L)^{-1} b.  Rows of X = (D + L)^{-1} [A | b] by
+// forward substitution, X_i = (row_i - sum_{k<i} a_ik X_k) / a_ii, each
+// update an AXPY over a contiguous row.  False on a zero diagonal entry.
+bool gauss_seidel_precondition(const double *A, const double *b, int dim, std::vector<double> &At,
+                               std::vector<double> &bt)
+{
+    const size_t w = (size_t)dim + 1;  // [A | b]
+    std::vector<double> X((size_t)dim * w);
+    for (int i = 0; i < dim; ++i) {
+        const double d = A[(size_t)i * dim + i];
+        if (d == 0.0) return false;
+        double *xi = &X[(size_t)i * w];
+        for (int j = 0; j < dim; ++j) xi[j] = A[(size_t)i * dim + j];
+        xi[dim] = b[i];
+        for (int k = 0; k < i; ++k) {
+            const double l = A[(size_t)i * dim + k];
+            if (l == 0.0) continue;
+            const double *xk = &X[(size_t)k * w];
+            for (size_t j = 0; j < w; ++j) xi[j] -= l * xk[j];
+        }
+        const double inv = 1.0 / d;
+        for (size_t j = 0; j < w; ++j) xi[j] *= inv;
+    }
+    At.assign((size_t)dim * dim, 0.0);
+    bt.assign(dim, 0.0);
+    for (int i = 0; i < dim; ++i) {
+        for (int j = 0; j < dim; ++j) At[(size_t)i * dim + j] = X[(size_t)i * w + j];
+        bt[i] = X[(size_t)i * w + dim];
+    }
+    return true;
+}
+
+}  // namespace
+
 extern "C" sv_status circuit_build_hhl(const double *A, const double *b, int dim,
                                        int clock_bits, double t, sv_circuit **out)
 {
@@ -317,15 +354,22 @@ extern "C" sv_status circuit_build_hhl_ex(const double *A, const double *b, int 
     if (dim < 1 || dim > (1 << 16)) return fail(SV_ERR_INVALID, "circuit_build_hhl: dim out of range");
     const int m = clock_bits;
     if (m < 1 || m > 16) return fail(SV_ERR_INVALID, "circuit_build_hhl: clock_bits must be in [1, 16]");
-    const int ns = std::max(1, ceil_log2(dim));
-    const int n = ns + m + 1;
-    if (n > kMaxQubits) return fail(SV_ERR_INVALID, "circuit_build_hhl: more than 34 qubits");
-    if (ns > kMaxDenseQubits) return fail(SV_ERR_INVALID, "circuit_build_hhl: system register wider than 12 qubits");
     if (!std::isfinite(t)) return fail(SV_ERR_INVALID, "circuit_build_hhl: t is not finite");
-    if (flags & ~SV_HHL_DEVICE_EVOLUTIONS) return fail(SV_ERR_INVALID, "circuit_build_hhl_ex: unknown flags");
+    if (flags & ~(SV_HHL_DEVICE_EVOLUTIONS | SV_HHL_SIGNED | SV_HHL_DILATE | SV_HHL_AUTO | SV_HHL_GAUSS_SEIDEL))
+        return fail(SV_ERR_INVALID, "circuit_build_hhl_ex: unknown flags");
+    std::vector<double> Ags, bgs;
+    if (flags & SV_HHL_GAUSS_SEIDEL) {
+        for (int i = 0; i < dim; ++i)
+            if (!std::isfinite(A[(size_t)i * dim + i]) || !std::isfinite(b[i]))
+                return fail(SV_ERR_INVALID, "circuit_build_hhl: non-finite input");
+        if (!gauss_seidel_precondition(A, b, dim, Ags, bgs))
+            return fail(SV_ERR_SINGULAR, "circuit_build_hhl: Gauss-Seidel needs a nonzero diagonal");
+        A = Ags.data();
+        b = bgs.data();
+        flags |= SV_HHL_DILATE;
+    }
 
-    // Step 1: symmetry (the Hermitian case), ||b||, pad to 2^ns with a unit
-    // diagonal and zero entries of b.
+    // Step 1: inspect A (finite, symmetric?) and b.
     double amax = 0.0, asym = 0.0;
     for (int i = 0; i < dim; ++i)
         for (int j = 0; j < dim; ++j) {
@@ -334,7 +378,11 @@ extern "C" sv_status circuit_build_hhl_ex(const double *A, const double *b, int 
             amax = std::max(amax, std::fabs(aij));
             asym = std::max(asym, std::fabs(aij - A[(size_t)j * dim + i]));
         }
-    if (asym > 1e-12 * amax) return fail(SV_ERR_NOT_SYMMETRIC, "circuit_build_hhl: A is not symmetric");
+    const bool symmetric = asym <= 1e-12 * amax;
+    const bool autoflags = (flags & SV_HHL_AUTO) != 0;
+    const bool dilate = (flags & SV_HHL_DILATE) || (autoflags && !symmetric);
+    bool sgn = dilate || (flags & SV_HHL_SIGNED);
+    if (!dilate && !symmetric) return fail(SV_ERR_NOT_SYMMETRIC, "circuit_build_hhl: A is not symmetric");
     double bb = 0.0;
     for (int i = 0; i < dim; ++i) {
         if (!std::isfinite(b[i])) return fail(SV_ERR_INVALID, "circuit_build_hhl: b has non-finite entries");
@@ -342,32 +390,64 @@ extern "C" sv_status circuit_build_hhl_ex(const double *A, const double *b, int 
     }
     const double beta = std::sqrt(bb);
     if (!(beta > 0.0)) return fail(SV_ERR_INVALID, "circuit_build_hhl: b is zero");
+
+    // Step 1b: pad to a power of two with a unit diagonal and zero entries
+    // of b; step 1c: replace the padded A' by [[0, A'], [A'^T, 0]] and b by
+    // [b; 0], so that x comes out in the second half.
+    const int na = dilate ? ceil_log2(dim) : std::max(1, ceil_log2(dim));
+    const int ns = dilate ? na + 1 : na;
+    const int n = ns + m + 1;
+    if (n > kMaxQubits) return fail(SV_ERR_INVALID, "circuit_build_hhl: more than 34 qubits");
+    if (ns > kMaxDenseQubits) return fail(SV_ERR_INVALID, "circuit_build_hhl: system register wider than 12 qubits");
+    const int P = 1 << na;
     const int D = 1 << ns;
     std::vector<double> Ap((size_t)D * D, 0.0), bh(D, 0.0);
-    for (int i = 0; i < D; ++i)
-        for (int j = 0; j < D; ++j)
-            Ap[(size_t)i * D + j] = (i < dim && j < dim) ? A[(size_t)i * dim + j] : (i == j ? 1.0 : 0.0);
+    for (int i = 0; i < P; ++i)
+        for (int j = 0; j < P; ++j) {
+            const double a = (i < dim && j < dim) ? A[(size_t)i * dim + j] : (i == j ? 1.0 : 0.0);
+            if (dilate) {
+                Ap[(size_t)i * D + P + j] = a;
+                Ap[(size_t)(P + j) * D + i] = a;
+            } else {
+                Ap[(size_t)i * D + j] = a;
+            }
+        }
     for (int i = 0; i < dim; ++i) bh[i] = b[i] / beta;
 
-    // Spectral parameters.
+    // Spectral parameters over the eigenvectors b reaches (|lambda| with the
+    // sign qubit, whose clock spends one bit on the sign).
     std::vector<double> w, V;
     if (!sym_eig(Ap, D, w, V)) return fail(SV_ERR_INVALID, "circuit_build_hhl: eigensolver did not converge");
+    std::vector<char> reached(D, 0);
     bool any = false;
-    double lo = 0.0, hi = 0.0;
+    double lo = 0.0, hi = 0.0, wmin = 0.0;
     for (int k = 0; k < D; ++k) {
         double ov = 0.0;
         for (int i = 0; i < D; ++i) ov += V[(size_t)i * D + k] * bh[i];
         if (ov * ov > 1e-20) {
-            if (!any || w[k] < lo) lo = w[k];
-            if (!any || w[k] > hi) hi = w[k];
+            reached[k] = 1;
+            if (!any || w[k] < wmin) wmin = w[k];
             any = true;
         }
     }
-    if (!any || !(lo > 0.0))
+    if (!any) return fail(SV_ERR_INVALID, "circuit_build_hhl: b reaches no eigenvector");
+    if (autoflags && wmin <= 0.0) sgn = true;
+    bool first = true;
+    for (int k = 0; k < D; ++k) {
+        if (!reached[k]) continue;
+        const double l = sgn ? std::fabs(w[k]) : w[k];
+        if (first || l < lo) lo = l;
+        if (first || l > hi) hi = l;
+        first = false;
+    }
+    if (sgn && m < 2) return fail(SV_ERR_INVALID, "circuit_build_hhl: the sign qubit needs clock_bits >= 2");
+    if (sgn && !(lo > 0.0))
+        return fail(SV_ERR_SINGULAR, "circuit_build_hhl: b reaches a zero eigenvalue");
+    if (!(lo > 0.0))
         return fail(SV_ERR_NOT_POSDEF, "circuit_build_hhl: A is not positive definite on the span of b");
     const double kappa = hi / lo;
     const double two_m = std::ldexp(1.0, m);
-    const double top = two_m - 1.0;
+    const double top = std::ldexp(1.0, sgn ? m - 1 : m) - 1.0;
     double tt = t;
     if (!(tt > 0.0)) {
         if (kappa <= top) {
@@ -389,9 +469,13 @@ extern "C" sv_status circuit_build_hhl_ex(const double *A, const double *b, int 
     h.is_hhl = true;
     h.dim = dim; h.ns = ns; h.m = m; h.j0 = j0;
     h.t = tt; h.C = C; h.lambda_lo = lo; h.lambda_hi = hi; h.kappa = kappa; h.b_norm = beta;
+    h.x_off = dilate ? P : 0;
+    h.sign_qubit = sgn;
+    h.dilated = dilate;
+    h.preconditioned = (flags & SV_HHL_GAUSS_SEIDEL) != 0;
     {
         int nd, nq, nt;
-        sv_qubit_estimate(D, std::max(1.0, kappa), 0, &nd, &nq, &nt);
+        sv_qubit_estimate(D, std::max(1.0, kappa), sgn ? 1 : 0, &nd, &nq, &nt);
         h.n_qpe_est = nq;
     }
     {
@@ -422,13 +506,19 @@ extern "C" sv_status circuit_build_hhl_ex(const double *A, const double *b, int 
     for (int j = 0; j < m; ++j) add(c, SV_GATE_H, {ns + j});
     for (int j = 0; j < m; ++j) evo(ns + j, j, false);
     add_qft(c, ns, m, true);
-    // Eigenvalue inversion: clock value c stands for lambda = C c / j0, and
-    // the ancilla's |1> amplitude becomes C / lambda = j0 / c (clamped).
+    // Eigenvalue inversion: clock value c decodes to v (c itself, or its
+    // two's-complement value with the sign qubit) standing for
+    // lambda = C v / j0, and the ancilla's |1> amplitude becomes
+    // C / lambda = j0 / v, clamped to [-1, 1].
     {
         std::vector<double> theta((size_t)1 << m);
         theta[0] = 0.0;
-        for (size_t cv = 1; cv < theta.size(); ++cv)
-            theta[cv] = 2.0 * std::asin(std::min(1.0, double(j0) / double(cv)));
+        const long long half = 1ll << (m - 1);
+        for (size_t cv = 1; cv < theta.size(); ++cv) {
+            const long long v = (sgn && (long long)cv >= half) ? (long long)cv - 2 * half : (long long)cv;
+            const double a = std::max(-1.0, std::min(1.0, double(j0) / double(v)));
+            theta[cv] = 2.0 * std::asin(a);
+        }
         std::vector<int> q{n - 1};
         for (int j = 0; j < m; ++j) q.push_back(ns + j);
         add(c, SV_GATE_UCRY, q, theta);

@@ -51,6 +51,8 @@ struct HHLParams {
     bool is_hhl = false;
     int dim = 0, ns = 0, m = 0, j0 = 0, n_qpe_est = 0;
     double t = 0, C = 0, lambda_lo = 0, lambda_hi = 0, kappa = 0, b_norm = 0;
+    int x_off = 0;          // x sits at system indices x_off .. x_off + dim - 1
+    bool sign_qubit = false, dilated = false, preconditioned = false;
     std::shared_ptr<const Spectral> spec;
 };
 

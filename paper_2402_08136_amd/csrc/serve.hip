@@ -130,6 +130,7 @@ struct svs {
     int max_batch = 256;
     int nstreams = 8;
     int batch_max_qubits = 0;    // 0: batch only LDS-resident requests; larger run alone
+    int hhl_flags = 0;           // SV_HHL_SIGNED / _DILATE / _AUTO / _GAUSS_SEIDEL per request
     size_t queue_limit = 1 << 20;
     long fail_alloc_at = 0;   // test hook: the n-th device allocation fails (0 = off)
     // state
@@ -208,7 +209,8 @@ void release(svs *s, const std::shared_ptr<Req> &r, hipStream_t st)
 bool prepare(svs *s, Req &r, hipStream_t up, sv_status &st, std::string &err)
 {
     sv_circuit *c = nullptr, *f = nullptr;
-    st = circuit_build_hhl_ex(r.A.data(), r.b.data(), r.dim, r.m, r.t, SV_HHL_DEVICE_EVOLUTIONS, &c);
+    st = circuit_build_hhl_ex(r.A.data(), r.b.data(), r.dim, r.m, r.t, SV_HHL_DEVICE_EVOLUTIONS | s->hhl_flags,
+                              &c);
     if (st != SV_OK) {
         err = sv_last_error();
         return false;
@@ -683,9 +685,17 @@ extern "C" sv_status svs_configure(svs *s, int option, double value)
         s->queue_limit = (size_t)value;
         return SV_OK;
     case SVS_OPT_BATCH_MAX_QUBITS:
-        if (value < 1 || value > 24) return fail(SV_ERR_INVALID, "svs_configure: batch qubit limit in [1, 24]");
+        if (value < 0 || value > 24) return fail(SV_ERR_INVALID, "svs_configure: batch qubit limit in [0, 24]");
         s->batch_max_qubits = (int)value;
         return SV_OK;
+    case SVS_OPT_HHL_FLAGS: {
+        const int f = (int)value;
+        if (value < 0 || f != value || (f & ~(SV_HHL_SIGNED | SV_HHL_DILATE | SV_HHL_AUTO | SV_HHL_GAUSS_SEIDEL)))
+            return fail(SV_ERR_INVALID,
+                        "svs_configure: HHL flags must combine SV_HHL_SIGNED, _DILATE, _AUTO, _GAUSS_SEIDEL");
+        s->hhl_flags = f;
+        return SV_OK;
+    }
     case SVS_OPT_FAIL_ALLOC_AT:
         if (value < 0) return fail(SV_ERR_INVALID, "svs_configure: allocation index >= 0");
         s->fail_alloc_at = (long)value;

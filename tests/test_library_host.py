@@ -269,3 +269,118 @@ def test_deferred_evolutions_materialise_identically(nbus, m):
     for k in (2, 5):
         assert hs.fuse(eager, k).serialize() == hs.fuse(lazy, k).serialize()
     assert eager.info() == lazy.info()
+
+
+# ------------------------------------------ dilation and the sign qubit ---
+def _general_cases():
+    A1, b1, t1, _ = W.signed_spectrum_system(3, 7, 1)
+    A2, b2, t2, _ = W.nonsymmetric_exact_system(5, 7, 2)
+    A3, b3 = W.general_system(6, 3, kappa=40.0)
+    A4, b4 = W.general_system(7, 4, kappa=15.0, symmetric=True)
+    A5, b5 = W.dc_powerflow(8, 5)
+    A6, b6 = W.dc_powerflow(14, 6)
+    return [("signed", A1, b1, 7, t1, oracle.HHL_SIGNED),
+            ("dilate", A2, b2, 7, t2, oracle.HHL_DILATE),
+            ("dilate", A3, b3, 8, 0.0, oracle.HHL_DILATE),
+            ("signed", A4, b4, 6, 0.0, oracle.HHL_SIGNED),
+            ("signed", -A5, b5, 7, 0.0, oracle.HHL_SIGNED),
+            ("dilate", A5, b5, 6, 0.0, oracle.HHL_DILATE),
+            ("gauss_seidel", A6, b6, 6, 0.0, oracle.HHL_GS)]
+
+
+@pytest.mark.parametrize("case", range(7))
+def test_signed_dilated_parameters_match_oracle(case):
+    mode, A, b, m, t, oflags = _general_cases()[case]
+    info = hs.circuit_build_hhl(A, b, m, t, mode=mode).info()
+    ref = oracle.hhl_params(A, b, m, t, flags=oflags)
+    assert info["n_sys"] == ref["ns"] and info["j0"] == ref["j0"]
+    assert info["x_offset"] == ref["x_off"] and info["sign_qubit"] == ref["sign_qubit"] == 1
+    assert info["dilated"] == (mode in ("dilate", "gauss_seidel"))
+    assert info["preconditioned"] == (mode == "gauss_seidel")
+    assert info["n_total"] == ref["n"]
+    for key_l, key_o in [("t", "t"), ("C", "C"), ("lambda_lo", "lambda_lo"),
+                         ("lambda_hi", "lambda_hi"), ("kappa", "kappa"), ("b_norm", "beta")]:
+        assert abs(info[key_l] - ref[key_o]) <= 1e-11 * abs(ref[key_o]), key_l
+
+
+@pytest.mark.parametrize("case", [0, 1, 3, 4, 6])
+def test_signed_dilated_numpy_evaluation_matches_oracle(case):
+    """The library's gate list (signed inversion angles, dilated evolutions)
+    evaluated gate by gate with numpy equals the oracle's final state."""
+    mode, A, b, m, t, oflags = _general_cases()[case]
+    c = hs.circuit_build_hhl(A, b, m, t, mode=mode)
+    psi = np.zeros(1 << c.n_qubits, dtype=complex)
+    psi[0] = 1
+    psi = np_run(c, psi)
+    ref, _, _, _ = oracle.hhl_solve(A, b, m, t, flags=oflags)
+    assert max_abs_diff(psi, ref) < 1e-12
+
+
+def test_signed_inversion_angles():
+    """Clock value c decodes to c, or c - 2^m for c >= 2^{m-1}; the angle is
+    2 asin(clamp(j0 / v)) and negative for negative v."""
+    A, b, t, _ = W.signed_spectrum_system(2, 5, 9)
+    c = hs.circuit_build_hhl(A, b, 5, t, mode="signed")
+    j0 = c.info()["j0"]
+    uc = [g for g in c.gates() if g[0] == "ucry" and g[1][0] == c.n_qubits - 1]
+    assert len(uc) == 1          # the state-preparation tree targets system qubits
+    th = np.asarray(uc[0][2])
+    v = np.arange(32)
+    v = np.where(v >= 16, v - 32, v)
+    want = np.zeros(32)
+    nz = v != 0
+    want[nz] = 2 * np.arcsin(np.clip(j0 / v[nz], -1, 1))
+    assert np.allclose(th, want, rtol=0, atol=1e-15)
+    assert th[16] < 0 and th[15] > 0
+
+
+def test_auto_mode_choices():
+    Aspd, b = W.dc_powerflow(8, 1)
+    i = hs.circuit_build_hhl(Aspd, b, 6, mode="auto").info()
+    assert (i["sign_qubit"], i["dilated"], i["x_offset"]) == (0, 0, 0)
+    i = hs.circuit_build_hhl(-Aspd, b, 6, mode="auto").info()
+    assert (i["sign_qubit"], i["dilated"]) == (1, 0)
+    S, bs = W.general_system(8, 2, kappa=10.0, symmetric=True)
+    i = hs.circuit_build_hhl(S, bs, 6, mode="auto").info()
+    assert (i["sign_qubit"], i["dilated"]) == (1, 0)
+    G, bg = W.general_system(6, 3, kappa=10.0)
+    i = hs.circuit_build_hhl(G, bg, 6, mode="auto").info()
+    assert (i["sign_qubit"], i["dilated"], i["x_offset"], i["n_sys"]) == (1, 1, 8, 4)
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 8, 13, 29])
+def test_dilated_register_sizes(N):
+    """Pad first (step 1b), then dilate (step 1c): 29 -> 32 -> 64 is the six
+    data qubits of the preconditioned 30-bus row of Table I."""
+    G, bg = W.general_system(N, N, kappa=5.0)
+    c = hs.circuit_build_hhl(G, bg, 5, mode="dilate")
+    i = c.info()
+    k = math.ceil(math.log2(N)) if N > 1 else 0
+    assert i["n_sys"] == k + 1 and i["x_offset"] == 1 << k
+    assert c.n_qubits == k + 1 + 5 + 1
+    m = 5
+    assert c.n_gates == (k + 1) + 6 * m + m * (m - 1) + 2 * (m // 2) + 1
+
+
+def test_signed_dilated_errors():
+    A, b, t, _ = W.signed_spectrum_system(2, 5, 0)
+    with pytest.raises(hs.HHLSVError, match="NOT_POSDEF"):
+        hs.circuit_build_hhl(A, b, 5)
+    with pytest.raises(hs.HHLSVError, match="INVALID"):
+        hs.circuit_build_hhl(A, b, 1, mode="signed")
+    with pytest.raises(hs.HHLSVError, match="SINGULAR"):
+        hs.circuit_build_hhl(np.diag([1.0, 0.0]), np.ones(2), 4, mode="signed")
+    G, bg = W.general_system(5, 0)
+    with pytest.raises(hs.HHLSVError, match="NOT_SYMMETRIC"):
+        hs.circuit_build_hhl(G, bg, 5, mode="signed")
+    with pytest.raises(hs.HHLSVError, match="SINGULAR"):
+        hs.circuit_build_hhl(np.array([[0.0, 1.0], [1.0, 2.0]]), np.ones(2), 5, mode="gauss_seidel")
+    big = np.eye(2049)
+    with pytest.raises(hs.HHLSVError, match="INVALID"):
+        hs.circuit_build_hhl(big, np.ones(2049), 4, mode="dilate")
+    with pytest.raises(ValueError):
+        hs.circuit_build_hhl(A, b, 5, mode="bogus")
+    h = hs._vp()
+    Ac = np.ascontiguousarray(A)
+    rc = hs._lib.circuit_build_hhl_ex(hs._dptr(Ac), hs._dptr(b), b.size, 5, 0.0, 64, hs.ctypes.byref(h))
+    assert rc == -1

@@ -418,3 +418,65 @@ def test_hhl_dilation_leak_accounting(seed):
     assert abs(info["pad_leak"] - np.linalg.norm(y[~keep])) < 1e-14
     assert np.allclose(x, info["beta"] * y[keep].real / info["C"], rtol=0, atol=1e-14)
     assert abs(info["p10"] - np.vdot(y, y).real) < 1e-14
+
+
+# ------------------------------------------------ Gauss-Seidel (step 1a) ---
+@pytest.mark.parametrize("sym", [True, False])
+@pytest.mark.parametrize("N,seed", [(1, 0), (3, 1), (5, 2), (13, 3), (29, 4)])
+def test_gauss_seidel_system(N, seed, sym):
+    """The preconditioned system is (M^{-1} A) x = M^{-1} b with M the lower
+    triangle of A (numpy tril): M times the oracle's blocks gives back A and
+    b, the solution is unchanged, and it is solved through the dilation.
+    Symmetric (power flow) and non-symmetric inputs."""
+    if N == 1:
+        A, b = np.array([[2.5]]), np.array([1.5])
+    elif sym:
+        A, b = W.dc_powerflow(N + 1, seed)
+    else:
+        A, b = W.general_system(N, seed, kappa=10.0)
+        A = A + 3.0 * np.eye(N)          # keep the diagonal away from zero
+    info = oracle.hhl_params(A, b, 6, flags=oracle.HHL_GS)
+    H, bh, xo = oracle.hhl_system(A, b, oracle.HHL_GS)
+    pa = 1 << math.ceil(math.log2(N)) if N > 1 else 1
+    assert xo == pa and H.shape == (2 * pa, 2 * pa)
+    At = H[:N, pa:pa + N]
+    assert np.array_equal(H[pa:pa + N, :N], At.T)
+    M = np.tril(A)
+    assert np.abs(M @ At - A).max() < 1e-12 * np.abs(A).max()
+    bt = info["beta"] * bh[:N]
+    assert np.abs(M @ bt - b).max() < 1e-12 * np.abs(b).max() * N
+    x = np.linalg.solve(A, b)
+    assert np.linalg.norm(At @ x - bt) < 1e-11 * np.linalg.norm(bt) * np.linalg.cond(A)
+    assert info["sign_qubit"] == 1
+
+
+@pytest.mark.parametrize("nbus,seed", [(14, 0), (30, 0), (30, 1), (64, 2)])
+def test_gauss_seidel_condition_number(nbus, seed):
+    """kappa of the preconditioned system is cond(M^{-1} A) (numpy SVD), and
+    on the DC power-flow matrices it is lower than kappa(A), the effect
+    Sec. IV reports for the 30-bus case (492.5 -> 109.3)."""
+    A, b = W.dc_powerflow(nbus, seed)
+    info = oracle.hhl_params(A, b, 8, flags=oracle.HHL_GS)
+    kgs = np.linalg.cond(np.linalg.solve(np.tril(A), A))
+    assert abs(info["kappa"] - kgs) < 1e-9 * kgs
+    assert info["kappa"] < np.linalg.cond(A)
+
+
+def test_gauss_seidel_hhl_converges_and_qubits():
+    """The 30-bus shape: 29 unknowns -> 32 -> 64 (6 data qubits, Table I's
+    30-bus* row); with enough clock qubits the preconditioned HHL solution
+    approaches A^{-1} b."""
+    A, b = W.dc_powerflow(30, 1)
+    xs = np.linalg.solve(A, b)
+    errs = []
+    for m in (7, 9):
+        _, x, _, info = oracle.hhl_solve(A, b, m, flags=oracle.HHL_GS, want_state=False)
+        assert info["ns"] == 6 and info["x_off"] == 32
+        errs.append(np.linalg.norm(x - xs) / np.linalg.norm(xs))
+    assert errs[1] < errs[0] < 1.0
+
+
+def test_gauss_seidel_rejects_zero_diagonal():
+    A = np.array([[0.0, 1.0], [1.0, 2.0]])
+    with pytest.raises(RuntimeError):
+        oracle.hhl_solve(A, np.ones(2), 5, flags=oracle.HHL_GS)
