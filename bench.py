@@ -131,11 +131,17 @@ def hhl_single(hs, W, reps=40):
                 s.apply(run)
                 s.postselect_solution(c, 63)
             dt = (time.perf_counter() - t0) / reps
+            x_hat, info = s.postselect_solution(c, 63)
             s.close()
             if best is None or dt < best[1]:
-                best = (k, dt)
-        out[dtype] = {"solves_per_s": round(1.0 / best[1], 1), "ms_per_solve": round(best[1] * 1e3, 4),
-                      "k_max": best[0]}
+                best = (k, dt, x_hat, info)
+        xs = np.linalg.solve(A, b)
+        k, dt, x_hat, info = best
+        x = info["scale"] * x_hat
+        out[dtype] = {"solves_per_s": round(1.0 / dt, 1), "ms_per_solve": round(dt * 1e3, 4),
+                      "k_max": k,
+                      "fidelity_vs_Ainv_b": float(np.dot(x_hat, xs / np.linalg.norm(xs)) ** 2),
+                      "rel_err_vs_Ainv_b": float(np.linalg.norm(x - xs) / np.linalg.norm(xs))}
     return out
 
 
@@ -184,7 +190,7 @@ def hhl_serve(hs, W, seconds, rate=2000.0, pool_per_size=48):
         pool[ns] = [W.dc_powerflow(1 << ns, 50000 + 100 * ns + i) for i in range(pool_per_size)]
     out = {"offered_rate_per_s": rate, "duration_s": seconds, "requests": len(sched)}
     for dtype in ("c128", "c64"):
-        srv = hs.Server(dtype, k_max=3)
+        srv = hs.Server(dtype)
         t_start = time.perf_counter()
         rejected = 0
         for i, (ta, ns, m, _) in enumerate(sched):
@@ -227,6 +233,10 @@ def main():
     ap.add_argument("--layers", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hhl", action="store_true", help="skip the HHL solves/s part")
+    ap.add_argument("--no-k-sweep", action="store_true",
+                    help="skip the per-sweep rates at the other fusion widths")
+    ap.add_argument("--k-sweep-layers", type=int, default=10,
+                    help="layers of the circuit used for the per-k sweep rates")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the Poisson arrival window (the full schedule is 60 s)")
     args = ap.parse_args()
@@ -322,6 +332,25 @@ def main():
             "traffic": traffic,
         },
     }
+    if not args.no_k_sweep:
+        # per-sweep rates at every fusion width on a shorter circuit of the
+        # same generator (the rate of a sweep does not depend on the depth)
+        by_k = {str(k): {"sweeps": n_sweeps // max(1, args.steps),
+                         "median_GBps": round(float(np.median(per_sweep)), 1),
+                         "min_GBps": round(float(per_sweep.min()), 1),
+                         "max_GBps": round(float(per_sweep.max()), 1), "layers": args.layers}}
+        short = hs.circuit_from_gates(n, W.layered_circuit(n, args.k_sweep_layers, 2402))
+        for kk in (2, 3, 4, 5):
+            if kk == k:
+                continue
+            fk = hs.fuse(short, kk)
+            msk, _ = state.apply_timed(fk)
+            rate = bytes_per_sweep / (msk * 1e-3) / 1e9
+            by_k[str(kk)] = {"sweeps": fk.n_gates, "median_GBps": round(float(np.median(rate)), 1),
+                             "min_GBps": round(float(rate.min()), 1), "max_GBps": round(float(rate.max()), 1),
+                             "layers": args.k_sweep_layers}
+            log(f"[bench] k={kk}: {fk.n_gates} sweeps, median {np.median(rate):.0f} GB/s")
+        out["config"]["per_sweep_GBps_by_k"] = dict(sorted(by_k.items()))
     state.close()
     if not args.no_hhl:
         log("[bench] HHL: one-circuit-at-a-time path")

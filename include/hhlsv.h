@@ -306,8 +306,10 @@ sv_status svb_destroy(svb *bt);
  * and upload it.  A scheduler keeps several micro-batches in flight on
  * separate streams: requests whose state fits in LDS run together in the
  * batched persistent kernel (optionally also larger ones with their state in
- * HBM); the others run alone through the sweep kernels, launched by the prep
- * thread that prepared them on its own stream.
+ * HBM); the others run through the sweep kernels, launched by a few launcher
+ * threads with a stream each, and requests of the same shape waiting
+ * together share launches (each fused op applied to every member's state,
+ * with that member's own matrices, in one launch).
  * Requests that arrive while others are on the GPU are admitted as memory
  * and slots free up.  A request's result does not depend on what else is
  * in flight.  All svs_* calls are thread-safe.
@@ -331,8 +333,9 @@ sv_status svb_destroy(svb *bt);
  *   solves/s = successful requests / (last finish - first submit).
  * svs_stop: drains, joins the threads and frees the server. */
 enum {
-    SVS_OPT_PREP_THREADS = 1,  /* host build threads (default min(12, cores-1)) */
-    SVS_OPT_K_MAX = 2,         /* fusion width (0: autotuned per shape, else 3) */
+    SVS_OPT_PREP_THREADS = 1,  /* host build threads (default min(8, cores/2)) */
+    SVS_OPT_K_MAX = 2,         /* fusion width (0: the tuned width for batched
+                                  shapes, 4 for the others; default 0)       */
     SVS_OPT_MAX_BATCH = 3,     /* requests per batched launch (default 256)      */
     SVS_OPT_STREAMS = 4,       /* micro-batches in flight (default 8)            */
     SVS_OPT_QUEUE_LIMIT = 5,   /* queued, not yet admitted requests              */
@@ -341,9 +344,14 @@ enum {
     SVS_OPT_BATCH_MAX_QUBITS = 7, /* also batch requests of up to this many
                                   qubits with the state in HBM (default 0:
                                   batch only states that fit in LDS)          */
-    SVS_OPT_HHL_FLAGS = 8      /* SV_HHL_SIGNED | _DILATE | _AUTO |
+    SVS_OPT_HHL_FLAGS = 8,     /* SV_HHL_SIGNED | _DILATE | _AUTO |
                                   _GAUSS_SEIDEL for every request's circuit
                                   (default 0)                                 */
+    SVS_OPT_LAUNCHERS = 9,     /* threads (each with its own stream) that
+                                  launch the requests not batched (default 4) */
+    SVS_OPT_GROUP_WINDOW_US = 10 /* microseconds a request not batched may
+                                  wait for others of its shape to share its
+                                  launches (default 0: launch at once)        */
 };
 sv_status svs_start(size_t hbm_budget_bytes, int max_slots, sv_dtype dtype,
                     svs **out);
@@ -361,7 +369,9 @@ sv_status svs_counts(svs *srv, uint64_t *done, uint64_t *failed,
 /* Mean seconds per successful request in each phase: out[0] queue (submit
  * to prep start), out[1] build + fuse + admission wait, out[2] upload,
  * out[3] resident to launched, out[4] launched to results back; out[5] /
- * out[6] requests run batched / alone; out[7] prep threads.  cap >= 8. */
+ * out[6] requests run batched / through the sweep kernels; out[7] prep
+ * threads; with cap >= 10, out[8] / out[9] grouped launches of two or more
+ * same-shape requests / the requests in them.  cap >= 8. */
 sv_status svs_profile(svs *srv, double *out, int cap);
 sv_status svs_stop(svs *srv);
 

@@ -438,7 +438,8 @@ def svb_autotune(dtype, sample: Circuit, copies: int = 64):
 
 # ------------------------------------------------------------------- serving
 SVS_OPT = {"prep_threads": 1, "k_max": 2, "max_batch": 3, "streams": 4, "queue_limit": 5,
-           "fail_alloc_at": 6, "batch_max_qubits": 7, "hhl_flags": 8}
+           "fail_alloc_at": 6, "batch_max_qubits": 7, "hhl_flags": 8, "launchers": 9,
+           "group_window_us": 10}
 
 
 class Server:
@@ -495,9 +496,10 @@ class Server:
                 "pending": pending.value}
 
     def profile(self):
-        v = np.zeros(8)
-        _check(_lib.svs_profile(self.handle, _dptr(v), 8), "svs_profile")
-        keys = ["queue_s", "prep_s", "upload_s", "ready_wait_s", "gpu_s", "batched", "alone", "prep_threads"]
+        v = np.zeros(10)
+        _check(_lib.svs_profile(self.handle, _dptr(v), 10), "svs_profile")
+        keys = ["queue_s", "prep_s", "upload_s", "ready_wait_s", "gpu_s", "batched", "alone", "prep_threads",
+                "groups", "grouped"]
         return dict(zip(keys, v.tolist()))
 
     def stop(self):

@@ -316,11 +316,31 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BInst *__restrict__ in
 }  // namespace
 
 void lower_for_batch(const Circuit &f, sv_dtype dtype, std::vector<BOp> &ops, std::vector<unsigned char> &tables,
-                     std::vector<EvoJob> &evo)
+                     std::vector<EvoJob> &evo, size_t *device_bytes)
 {
     const size_t as = dtype == SV_C128 ? 16 : 8;
-    for (const Gate &g : f.gates) {
-        LoweredOp L = lower_gate_op(g, f.hhl);
+    std::vector<LoweredOp> low;
+    low.reserve(f.gates.size());
+    for (const Gate &g : f.gates) low.push_back(lower_gate_op(g, f.hhl));
+    // host-built tables first, then the regions the device fills
+    std::vector<size_t> offs(low.size());
+    size_t bytes = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1) {
+            bytes = (bytes + 255) & ~size_t(255);
+            tables.assign(bytes, 0);
+        }
+        for (size_t i = 0; i < low.size(); ++i) {
+            const LoweredOp &L = low[i];
+            if (L.deferred != (pass == 1)) continue;
+            bytes = (bytes + 255) & ~size_t(255);
+            offs[i] = bytes;
+            bytes += (L.deferred ? ((size_t)1 << (2 * L.op.k)) : L.table.size()) * as;
+        }
+    }
+    *device_bytes = std::max((bytes + 255) & ~size_t(255), tables.size());
+    for (size_t li = 0; li < low.size(); ++li) {
+        const LoweredOp &L = low[li];
         BOp op;
         std::memset(&op, 0, sizeof(op));
         op.type = L.op.type;
@@ -331,10 +351,7 @@ void lower_for_batch(const Circuit &f, sv_dtype dtype, std::vector<BOp> &ops, st
         op.contiguous = 1;
         for (int j = 1; j < L.op.k; ++j)
             if (op.q[j] != op.q[0] + j) op.contiguous = 0;
-        const size_t entries = L.deferred ? ((size_t)1 << (2 * L.op.k)) : L.table.size();
-        const size_t off = (tables.size() + 255) & ~size_t(255);
-        tables.resize(off + entries * as);
-        unsigned char *dst = tables.data() + off;
+        const size_t off = offs[li];
         if (L.deferred) {
             EvoJob jb;
             std::memset(&jb, 0, sizeof(jb));
@@ -345,6 +362,7 @@ void lower_for_batch(const Circuit &f, sv_dtype dtype, std::vector<BOp> &ops, st
             jb.t = f.hhl.spec->t;
             evo.push_back(jb);
         } else {
+            unsigned char *dst = tables.data() + off;
             const std::vector<cd> &tab = L.table;   // OP_WIDE tables hold U^T
             for (size_t i = 0; i < tab.size(); ++i) {
                 if (dtype == SV_C128) {
@@ -700,9 +718,10 @@ extern "C" sv_status svb_add(svb *b, const sv_circuit *hhl, int *index_out)
         std::vector<BOp> ops;
         std::vector<unsigned char> tab;
         std::vector<EvoJob> evo;
-        lower_for_batch(f->c, b->dtype, ops, tab, evo);
+        size_t dev_bytes = 0;
+        lower_for_batch(f->c, b->dtype, ops, tab, evo, &dev_bytes);
         const size_t base = (b->tables.size() + 255) & ~size_t(255);
-        b->tables.resize(base + tab.size());
+        b->tables.resize(base + dev_bytes);
         std::memcpy(b->tables.data() + base, tab.data(), tab.size());
         for (BOp &op : ops) {
             op.off += base;

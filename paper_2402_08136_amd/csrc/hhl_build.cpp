@@ -14,95 +14,97 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 
-// Householder reduction of a symmetric matrix (dense, row-major, destroyed)
-// to tridiagonal form: A = Q T Q^T with T = tridiag(e, d, e).  Returns
-// Qt = Q^T (row-major).  Golub & Van Loan, Sec. 8.3.1: for each column a
-// reflector I - 2 v v^T, with p = A v, w = p - (v.p) v, A -= 2 (v w^T + w v^T)
-// on the trailing block.
+// Householder tridiagonalisation of a symmetric matrix held in its upper
+// triangle (row-major, destroyed): A = Q T Q^T, T = tridiag(e, d, e).  Each
+// step k forms the reflector I - 2 v v^T that zeroes row k beyond k+1, then
+// p = A22 v (symmetric product from the upper triangle), w = p - (v.p) v and
+// A22 -= 2 (v w^T + w v^T) on the upper triangle only.  Q is accumulated
+// backwards (Q = H_0 (H_1 (... H_{N-3}))), so each reflector touches only the
+// trailing block; the result is returned transposed, Zt = Q^T (rows are the
+// columns of Q), ready for the row rotations of the QR sweeps.
+__attribute__((target_clones("arch=haswell", "default")))
 void tridiagonalise(std::vector<double> &A, int N, std::vector<double> &d, std::vector<double> &e,
-                    std::vector<double> &Qt)
+                    std::vector<double> &Zt)
 {
     d.assign(N, 0.0);
     e.assign(N > 1 ? N - 1 : 0, 0.0);
-    std::vector<double> vs((size_t)N * N, 0.0);   // reflector k in row k (offset k+1)
+    std::vector<double> vs((size_t)N * N, 0.0);   // reflector k in row k, entries k+1..N-1
     std::vector<char> used(N, 0);
     std::vector<double> p(N), w(N);
     for (int k = 0; k + 2 < N; ++k) {
-        const int L = N - k - 1;
-        double *v = &vs[(size_t)k * N];            // v[0..L)
-        const double *col = &A[(size_t)k * N + k + 1];  // row k = column k (symmetric)
+        const int L = N - k - 1, o = k + 1;
+        double *v = &vs[(size_t)k * N + o];       // v[0..L)
+        const double *row = &A[(size_t)k * N + o];
         double xn = 0.0;
-        for (int j = 0; j < L; ++j) xn += col[j] * col[j];
+        for (int j = 0; j < L; ++j) xn += row[j] * row[j];
         xn = std::sqrt(xn);
-        if (xn == 0.0) {
-            e[k] = 0.0;
-            continue;
-        }
-        const double alpha = col[0] >= 0.0 ? -xn : xn;
-        for (int j = 0; j < L; ++j) v[j] = col[j];
+        const double alpha = row[0] >= 0.0 ? -xn : xn;
+        e[k] = alpha;
+        if (xn == 0.0) { e[k] = 0.0; continue; }
+        for (int j = 0; j < L; ++j) v[j] = row[j];
         v[0] -= alpha;
         double vn = 0.0;
         for (int j = 0; j < L; ++j) vn += v[j] * v[j];
         vn = std::sqrt(vn);
-        if (vn == 0.0) {
-            e[k] = alpha;
-            continue;
-        }
-        for (int j = 0; j < L; ++j) v[j] /= vn;
+        if (vn == 0.0) continue;
+        const double inv = 1.0 / vn;
+        for (int j = 0; j < L; ++j) v[j] *= inv;
         used[k] = 1;
-        // p = A_sub v (rows of the trailing block are contiguous)
-        double kv = 0.0;
+        // p = A22 v from the upper triangle: row i contributes its diagonal,
+        // a dot product with v[i+1..] to p[i] and an axpy into p[i+1..].
+        std::fill(p.begin(), p.begin() + L, 0.0);
         for (int i = 0; i < L; ++i) {
-            const double *row = &A[(size_t)(k + 1 + i) * N + k + 1];
-            double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-            int j = 0;
-            for (; j + 3 < L; j += 4) {
-                s0 += row[j] * v[j];
-                s1 += row[j + 1] * v[j + 1];
-                s2 += row[j + 2] * v[j + 2];
-                s3 += row[j + 3] * v[j + 3];
+            const double *ri = &A[(size_t)(o + i) * N + o];
+            const double vi = v[i];
+            double acc = ri[i] * vi;
+            for (int j = i + 1; j < L; ++j) {
+                acc += ri[j] * v[j];
+                p[j] += ri[j] * vi;
             }
-            for (; j < L; ++j) s0 += row[j] * v[j];
-            p[i] = (s0 + s1) + (s2 + s3);
-            kv += v[i] * p[i];
+            p[i] += acc;
         }
+        double kv = 0.0;
+        for (int i = 0; i < L; ++i) kv += v[i] * p[i];
         for (int i = 0; i < L; ++i) w[i] = p[i] - kv * v[i];
         for (int i = 0; i < L; ++i) {
-            double *row = &A[(size_t)(k + 1 + i) * N + k + 1];
+            double *ri = &A[(size_t)(o + i) * N + o];
             const double vi = 2.0 * v[i], wi = 2.0 * w[i];
-            for (int j = 0; j < L; ++j) row[j] -= vi * w[j] + wi * v[j];
+            for (int j = i; j < L; ++j) ri[j] -= vi * w[j] + wi * v[j];
         }
-        e[k] = alpha;
     }
     for (int k = 0; k < N; ++k) d[k] = A[(size_t)k * N + k];
     if (N >= 2) e[N - 2] = A[(size_t)(N - 2) * N + N - 1];
-    // Q^T = H_{N-3} ... H_0: apply the reflectors from the left, last first is
-    // not needed since each acts on a trailing block: M <- H_k M for k = 0, 1, ...
-    Qt.assign((size_t)N * N, 0.0);
-    for (int i = 0; i < N; ++i) Qt[(size_t)i * N + i] = 1.0;
-    std::vector<double> sv(N);
-    for (int k = 0; k + 2 < N; ++k) {
+    // Q = H_0 H_1 ... H_{N-3}, accumulated from the last reflector: M <- H_k M
+    // changes rows and columns k+1.. of M only.
+    std::vector<double> Q((size_t)N * N, 0.0);
+    for (int i = 0; i < N; ++i) Q[(size_t)i * N + i] = 1.0;
+    std::vector<double> s(N);
+    for (int k = N - 3; k >= 0; --k) {
         if (!used[k]) continue;
-        const int L = N - k - 1;
-        const double *v = &vs[(size_t)k * N];
-        std::fill(sv.begin(), sv.end(), 0.0);
-        for (int i = 0; i < L; ++i) {
-            const double *row = &Qt[(size_t)(k + 1 + i) * N];
+        const int L = N - k - 1, o = k + 1;
+        const double *v = &vs[(size_t)k * N + o];
+        std::fill(s.begin(), s.begin() + L, 0.0);
+        for (int i = 0; i < L; ++i) {           // s = v^T M22
+            const double *ri = &Q[(size_t)(o + i) * N + o];
             const double vi = v[i];
-            for (int j = 0; j < N; ++j) sv[j] += vi * row[j];
+            for (int j = 0; j < L; ++j) s[j] += vi * ri[j];
         }
-        for (int i = 0; i < L; ++i) {
-            double *row = &Qt[(size_t)(k + 1 + i) * N];
+        for (int i = 0; i < L; ++i) {           // M22 -= 2 v s^T
+            double *ri = &Q[(size_t)(o + i) * N + o];
             const double vi = 2.0 * v[i];
-            for (int j = 0; j < N; ++j) row[j] -= vi * sv[j];
+            for (int j = 0; j < L; ++j) ri[j] -= vi * s[j];
         }
     }
+    Zt.resize((size_t)N * N);
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) Zt[(size_t)j * N + i] = Q[(size_t)i * N + j];
 }
 
 // Implicit symmetric QR with Wilkinson shifts on T = tridiag(e, d, e)
 // (Golub & Van Loan, Alg. 8.3.2): each step chases a bulge down the active
 // block with Givens rotations G(p, p+1) = [[c, s], [-s, c]], T <- G T G^T,
 // applied to d / e in O(1) and to the rows p, p+1 of Z^T in O(N).
+__attribute__((target_clones("arch=haswell", "default")))
 bool tridiagonal_qr(std::vector<double> &d, std::vector<double> &e, std::vector<double> &Zt, int N)
 {
     const double eps = 2.220446049250313e-16;

@@ -45,12 +45,13 @@ inline size_t batch_lds_bytes(int n, sv_dtype d, bool *resident)
 sv_status launch_batch_class(const BInst *d_insts, const int *d_order, int count, int n, int kmax,
                              sv_dtype dtype, hipStream_t st);
 
-// Lower a (fused) HHL circuit into batch ops and a table image.  Deferred
-// evolutions get a reserved table region and an entry in evo (out_off set,
-// vt_off / w_off left for the caller).
+// Lower a (fused) HHL circuit into batch ops and a table buffer of
+// *device_bytes.  tables holds the host-built tables (its first
+// tables.size() bytes); deferred evolutions get a region after them and an
+// entry in evo (out_off set, vt_off / w_off left for the caller).
 struct EvoJob;
 void lower_for_batch(const Circuit &f, sv_dtype dtype, std::vector<BOp> &ops, std::vector<unsigned char> &tables,
-                     std::vector<EvoJob> &evo);
+                     std::vector<EvoJob> &evo, size_t *device_bytes);
 
 // k_max used for batch instances when the batch was created with k_max = 0
 // and the autotuner has no entry for the instance's shape.

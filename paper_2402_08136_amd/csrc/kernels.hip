@@ -56,11 +56,11 @@ __device__ __forceinline__ uint64_t tile_base(uint64_t w, const int *rpos, int k
 }
 
 template <typename R, int K>
-__global__ __launch_bounds__(256) void k_dense_direct(typename V2<R>::type *__restrict__ psi,
-                                                      const typename V2<R>::type *__restrict__ mat,
-                                                      TileArgs a)
+__global__ __launch_bounds__(256) void k_dense_direct(Ptrs pp, TileArgs a)
 {
     typedef typename V2<R>::type C;
+    C *__restrict__ psi = member_ptr<C>(pp.a);
+    const C *__restrict__ mat = member_ptr<const C>(pp.b);
     constexpr int NR = 1 << K;
     const int lane = threadIdx.x & 63;
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -87,11 +87,11 @@ __global__ __launch_bounds__(256) void k_dense_direct(typename V2<R>::type *__re
 __device__ __forceinline__ int lds_phys(int s) { return s + (s >> 6); }
 
 template <typename R, int K>
-__global__ __launch_bounds__(64) void k_dense_lds(typename V2<R>::type *__restrict__ psi,
-                                                  const typename V2<R>::type *__restrict__ mat,
-                                                  TileArgs a)
+__global__ __launch_bounds__(64) void k_dense_lds(Ptrs pp, TileArgs a)
 {
     typedef typename V2<R>::type C;
+    C *__restrict__ psi = member_ptr<C>(pp.a);
+    const C *__restrict__ mat = member_ptr<const C>(pp.b);
     constexpr int NR = 1 << K;
     __shared__ C tile[NR * 65];
     const int lane = threadIdx.x;
@@ -132,11 +132,11 @@ struct GenericArgs {
 };
 
 template <typename R, int K>
-__global__ __launch_bounds__(256) void k_dense_generic(typename V2<R>::type *__restrict__ psi,
-                                                       const typename V2<R>::type *__restrict__ mat,
-                                                       GenericArgs a)
+__global__ __launch_bounds__(256) void k_dense_generic(Ptrs pp, GenericArgs a)
 {
     typedef typename V2<R>::type C;
+    C *__restrict__ psi = member_ptr<C>(pp.a);
+    const C *__restrict__ mat = member_ptr<const C>(pp.b);
     constexpr int NR = 1 << K;
     for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.ngroups;
          g += (uint64_t)gridDim.x * blockDim.x) {
@@ -167,11 +167,11 @@ struct DiagArgs {
 };
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_diag(typename V2<R>::type *__restrict__ psi,
-                                              const typename V2<R>::type *__restrict__ d,
-                                              DiagArgs a)
+__global__ __launch_bounds__(256) void k_diag(Ptrs pp, DiagArgs a)
 {
     typedef typename V2<R>::type C;
+    C *__restrict__ psi = member_ptr<C>(pp.a);
+    const C *__restrict__ d = member_ptr<const C>(pp.b);
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.namps;
          i += (uint64_t)gridDim.x * blockDim.x) {
         int v = 0;
@@ -200,11 +200,11 @@ struct WideArgs {
 };
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_wide(typename V2<R>::type *__restrict__ psi,
-                                              const typename V2<R>::type *__restrict__ U,
-                                              WideArgs a)
+__global__ __launch_bounds__(256) void k_wide(Ptrs pp, WideArgs a)
 {
     typedef typename V2<R>::type C;
+    C *__restrict__ psi = member_ptr<C>(pp.a);
+    const C *__restrict__ U = member_ptr<const C>(pp.b);
     extern __shared__ unsigned char smem_raw[];
     C *v = reinterpret_cast<C *>(smem_raw);
     const int K = 1 << a.k;
@@ -256,11 +256,11 @@ struct WideGemmArgs {
 };
 
 template <typename R, int CT, int RW>
-__global__ __launch_bounds__(256) void k_wide_gemm(typename V2<R>::type *__restrict__ psi,
-                                                   const typename V2<R>::type *__restrict__ UT,
-                                                   WideGemmArgs a)
+__global__ __launch_bounds__(256) void k_wide_gemm(Ptrs pp, WideGemmArgs a)
 {
     typedef typename V2<R>::type C;
+    C *__restrict__ psi = member_ptr<C>(pp.a);
+    const C *__restrict__ UT = member_ptr<const C>(pp.b);
     const int D = 1 << a.k;
     const int lpr = D < 64 ? D : 64;          // lanes per row
     const int rps = 64 / lpr;                 // rows per wave step
@@ -378,11 +378,11 @@ struct UcryArgs {
 };
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_ucry(typename V2<R>::type *__restrict__ psi,
-                                              const typename V2<R>::type *__restrict__ cs,
-                                              UcryArgs a)
+__global__ __launch_bounds__(256) void k_ucry(Ptrs pp, UcryArgs a)
 {
     typedef typename V2<R>::type C;
+    C *__restrict__ psi = member_ptr<C>(pp.a);
+    const C *__restrict__ cs = member_ptr<const C>(pp.b);
     const uint64_t tbit = uint64_t(1) << a.target;
     for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < a.npairs;
          p += (uint64_t)gridDim.x * blockDim.x) {
@@ -410,9 +410,10 @@ __global__ __launch_bounds__(256) void k_ucry(typename V2<R>::type *__restrict__
 // Utility kernels.
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(256) void k_zero_state(typename V2<R>::type *__restrict__ psi, uint64_t namps)
+__global__ __launch_bounds__(256) void k_zero_state(Ptrs pp, uint64_t namps)
 {
     typedef typename V2<R>::type C;
+    C *__restrict__ psi = member_ptr<C>(pp.a);
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < namps;
          i += (uint64_t)gridDim.x * blockDim.x) {
         C z = {(R)(i == 0 ? 1 : 0), (R)0};
@@ -421,9 +422,10 @@ __global__ __launch_bounds__(256) void k_zero_state(typename V2<R>::type *__rest
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_norm2_partial(const typename V2<R>::type *__restrict__ psi,
-                                                       uint64_t lo, uint64_t hi, double *partials)
+__global__ __launch_bounds__(256) void k_norm2_partial(Ptrs pp, uint64_t lo, uint64_t hi)
 {
+    const typename V2<R>::type *__restrict__ psi = member_ptr<const typename V2<R>::type>(pp.a);
+    double *__restrict__ partials = member_ptr<double>(pp.b);
     __shared__ double red[256];
     double s = 0.0;
     for (uint64_t i = lo + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi;
@@ -440,8 +442,10 @@ __global__ __launch_bounds__(256) void k_norm2_partial(const typename V2<R>::typ
     if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
 }
 
-__global__ __launch_bounds__(256) void k_sum_partials(const double *partials, int n, double *out)
+__global__ __launch_bounds__(256) void k_sum_partials(Ptrs pp, int n)
 {
+    const double *__restrict__ partials = member_ptr<const double>(pp.a);
+    double *__restrict__ out = member_ptr<double>(pp.b);
     __shared__ double red[256];
     double s = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) s += partials[i];
@@ -474,12 +478,23 @@ inline unsigned grid_for(uint64_t work, unsigned per_block, unsigned cap)
 // ---------------------------------------------------------------------------
 // Launch helpers.
 // ---------------------------------------------------------------------------
-template <typename R>
-sv_status launch_dense_t(const DevOp &op, const void *mat, void *psi, int n, hipStream_t st, int *family)
+// Per-member (state, op table) pointers of a grouped launch.
+Ptrs op_ptrs(const DevOp &op, const Group &g)
 {
-    typedef typename V2<R>::type C;
-    C *p = static_cast<C *>(psi);
-    const C *m = static_cast<const C *>(mat);
+    Ptrs pp;
+    std::memset(&pp, 0, sizeof(pp));
+    for (int i = 0; i < g.count; ++i) {
+        pp.a[i] = reinterpret_cast<unsigned long long>(g.psi[i]);
+        pp.b[i] = reinterpret_cast<unsigned long long>(g.dbuf[i] + op.off);
+    }
+    return pp;
+}
+
+template <typename R>
+sv_status launch_dense_t(const DevOp &op, const Group &g, int n, hipStream_t st, int *family)
+{
+    const Ptrs pp = op_ptrs(op, g);
+    const unsigned cnt = (unsigned)g.count;
     const int k = op.k;
     if (n >= 6 + k) {
         TileArgs a;
@@ -508,11 +523,11 @@ sv_status launch_dense_t(const DevOp &op, const void *mat, void *psi, int n, hip
             *family = SV_KERNEL_DENSE_DIRECT;
             const unsigned grid = grid_for(a.ntiles, 4, 8192);
             switch (k) {
-            case 1: hipLaunchKernelGGL((k_dense_direct<R, 1>), dim3(grid), dim3(256), 0, st, p, m, a); break;
-            case 2: hipLaunchKernelGGL((k_dense_direct<R, 2>), dim3(grid), dim3(256), 0, st, p, m, a); break;
-            case 3: hipLaunchKernelGGL((k_dense_direct<R, 3>), dim3(grid), dim3(256), 0, st, p, m, a); break;
-            case 4: hipLaunchKernelGGL((k_dense_direct<R, 4>), dim3(grid), dim3(256), 0, st, p, m, a); break;
-            case 5: hipLaunchKernelGGL((k_dense_direct<R, 5>), dim3(grid), dim3(256), 0, st, p, m, a); break;
+            case 1: hipLaunchKernelGGL((k_dense_direct<R, 1>), dim3(grid, cnt), dim3(256), 0, st, pp, a); break;
+            case 2: hipLaunchKernelGGL((k_dense_direct<R, 2>), dim3(grid, cnt), dim3(256), 0, st, pp, a); break;
+            case 3: hipLaunchKernelGGL((k_dense_direct<R, 3>), dim3(grid, cnt), dim3(256), 0, st, pp, a); break;
+            case 4: hipLaunchKernelGGL((k_dense_direct<R, 4>), dim3(grid, cnt), dim3(256), 0, st, pp, a); break;
+            case 5: hipLaunchKernelGGL((k_dense_direct<R, 5>), dim3(grid, cnt), dim3(256), 0, st, pp, a); break;
             default: return fail(SV_ERR_INVALID, "dense op wider than 5 qubits");
             }
         } else {
@@ -536,11 +551,11 @@ sv_status launch_dense_t(const DevOp &op, const void *mat, void *psi, int n, hip
             *family = SV_KERNEL_DENSE_LDS;
             const unsigned grid = grid_for(a.ntiles, 1, 16384);
             switch (k) {
-            case 1: hipLaunchKernelGGL((k_dense_lds<R, 1>), dim3(grid), dim3(64), 0, st, p, m, a); break;
-            case 2: hipLaunchKernelGGL((k_dense_lds<R, 2>), dim3(grid), dim3(64), 0, st, p, m, a); break;
-            case 3: hipLaunchKernelGGL((k_dense_lds<R, 3>), dim3(grid), dim3(64), 0, st, p, m, a); break;
-            case 4: hipLaunchKernelGGL((k_dense_lds<R, 4>), dim3(grid), dim3(64), 0, st, p, m, a); break;
-            case 5: hipLaunchKernelGGL((k_dense_lds<R, 5>), dim3(grid), dim3(64), 0, st, p, m, a); break;
+            case 1: hipLaunchKernelGGL((k_dense_lds<R, 1>), dim3(grid, cnt), dim3(64), 0, st, pp, a); break;
+            case 2: hipLaunchKernelGGL((k_dense_lds<R, 2>), dim3(grid, cnt), dim3(64), 0, st, pp, a); break;
+            case 3: hipLaunchKernelGGL((k_dense_lds<R, 3>), dim3(grid, cnt), dim3(64), 0, st, pp, a); break;
+            case 4: hipLaunchKernelGGL((k_dense_lds<R, 4>), dim3(grid, cnt), dim3(64), 0, st, pp, a); break;
+            case 5: hipLaunchKernelGGL((k_dense_lds<R, 5>), dim3(grid, cnt), dim3(64), 0, st, pp, a); break;
             default: return fail(SV_ERR_INVALID, "dense op wider than 5 qubits");
             }
         }
@@ -558,11 +573,11 @@ sv_status launch_dense_t(const DevOp &op, const void *mat, void *psi, int n, hip
         *family = SV_KERNEL_DENSE_SMALL;
         const unsigned grid = grid_for(a.ngroups, 256, 8192);
         switch (k) {
-        case 1: hipLaunchKernelGGL((k_dense_generic<R, 1>), dim3(grid), dim3(256), 0, st, p, m, a); break;
-        case 2: hipLaunchKernelGGL((k_dense_generic<R, 2>), dim3(grid), dim3(256), 0, st, p, m, a); break;
-        case 3: hipLaunchKernelGGL((k_dense_generic<R, 3>), dim3(grid), dim3(256), 0, st, p, m, a); break;
-        case 4: hipLaunchKernelGGL((k_dense_generic<R, 4>), dim3(grid), dim3(256), 0, st, p, m, a); break;
-        case 5: hipLaunchKernelGGL((k_dense_generic<R, 5>), dim3(grid), dim3(256), 0, st, p, m, a); break;
+        case 1: hipLaunchKernelGGL((k_dense_generic<R, 1>), dim3(grid, cnt), dim3(256), 0, st, pp, a); break;
+        case 2: hipLaunchKernelGGL((k_dense_generic<R, 2>), dim3(grid, cnt), dim3(256), 0, st, pp, a); break;
+        case 3: hipLaunchKernelGGL((k_dense_generic<R, 3>), dim3(grid, cnt), dim3(256), 0, st, pp, a); break;
+        case 4: hipLaunchKernelGGL((k_dense_generic<R, 4>), dim3(grid, cnt), dim3(256), 0, st, pp, a); break;
+        case 5: hipLaunchKernelGGL((k_dense_generic<R, 5>), dim3(grid, cnt), dim3(256), 0, st, pp, a); break;
         default: return fail(SV_ERR_INVALID, "dense op wider than 5 qubits");
         }
     }
@@ -571,14 +586,14 @@ sv_status launch_dense_t(const DevOp &op, const void *mat, void *psi, int n, hip
 }
 
 template <typename R>
-sv_status launch_op_t(const DevOp &op, const DeviceProgram &prog, void *psi, int n, hipStream_t st,
-                      int *family)
+sv_status launch_op_t(const DevOp &op, const Group &g, int n, hipStream_t st, int *family)
 {
     typedef typename V2<R>::type C;
-    const void *tab = static_cast<const char *>(prog.dbuf) + op.off;
+    const Ptrs pp = op_ptrs(op, g);
+    const unsigned cnt = (unsigned)g.count;
     switch (op.type) {
     case OP_DENSE:
-        return launch_dense_t<R>(op, tab, psi, n, st, family);
+        return launch_dense_t<R>(op, g, n, st, family);
     case OP_DIAG: {
         *family = SV_KERNEL_DIAG;
         DiagArgs a;
@@ -586,8 +601,7 @@ sv_status launch_op_t(const DevOp &op, const DeviceProgram &prog, void *psi, int
         a.namps = uint64_t(1) << n;
         a.k = op.k;
         for (int j = 0; j < op.k; ++j) a.q[j] = op.q[j];
-        hipLaunchKernelGGL((k_diag<R>), dim3(grid_for(a.namps, 256, 16384)), dim3(256), 0, st,
-                           static_cast<C *>(psi), static_cast<const C *>(tab), a);
+        hipLaunchKernelGGL((k_diag<R>), dim3(grid_for(a.namps, 256, 16384), cnt), dim3(256), 0, st, pp, a);
         break;
     }
     case OP_WIDE: {
@@ -605,15 +619,13 @@ sv_status launch_op_t(const DevOp &op, const DeviceProgram &prog, void *psi, int
                 if (op.q[j] != op.q[0] + j) a.contiguous = 0;
             const int D = 1 << op.k;
             const int rps = D < 64 ? 64 / D : 1;
-            C *p = static_cast<C *>(psi);
-            const C *u = static_cast<const C *>(tab);
             // rows per wave: as many as keep >= ~1024 waves busy (reuse of
             // each loaded U column across rows vs parallelism)
             auto waves_for = [&](int rw) { return (ngroups + (uint64_t)rw * rps - 1) / ((uint64_t)rw * rps); };
             int rw = 8;
             while (rw > 1 && waves_for(rw) < 1024) rw >>= 1;
             const unsigned grid = grid_for(waves_for(rw), 4, 8192);
-#define WIDE_GO(CT, RWV) hipLaunchKernelGGL((k_wide_gemm<R, CT, RWV>), dim3(grid), dim3(256), 0, st, p, u, a)
+#define WIDE_GO(CT, RWV) hipLaunchKernelGGL((k_wide_gemm<R, CT, RWV>), dim3(grid, cnt), dim3(256), 0, st, pp, a)
 #define WIDE_RW(CT)                          \
     switch (rw) {                            \
     case 8: WIDE_GO(CT, 8); break;           \
@@ -644,8 +656,8 @@ sv_status launch_op_t(const DevOp &op, const DeviceProgram &prog, void *psi, int
         const int K = 1 << op.k;
         const unsigned threads = (unsigned)std::min(256, std::max(64, K));
         const size_t smem = sizeof(C) * (size_t)K;
-        hipLaunchKernelGGL((k_wide<R>), dim3(grid_for(a.ngroups, 1, 16384)), dim3(threads), smem, st,
-                           static_cast<C *>(psi), static_cast<const C *>(tab), a);
+        hipLaunchKernelGGL((k_wide<R>), dim3(grid_for(a.ngroups, 1, 16384), cnt), dim3(threads), smem, st, pp,
+                           a);
         break;
     }
     case OP_UCRY: {
@@ -661,8 +673,7 @@ sv_status launch_op_t(const DevOp &op, const DeviceProgram &prog, void *psi, int
             if (l > 0 && op.q[l] != op.q[0] + l) a.contiguous = 0;
         }
         if (op.k == 0) a.ctl[0] = 0;
-        hipLaunchKernelGGL((k_ucry<R>), dim3(grid_for(a.npairs, 256, 16384)), dim3(256), 0, st,
-                           static_cast<C *>(psi), static_cast<const C *>(tab), a);
+        hipLaunchKernelGGL((k_ucry<R>), dim3(grid_for(a.npairs, 256, 16384), cnt), dim3(256), 0, st, pp, a);
         break;
     }
     default:
@@ -804,25 +815,34 @@ Circuit::~Circuit()
 }
 
 sv_status build_program_image(const Circuit &c, sv_dtype dtype, std::vector<DevOp> &ops,
-                              std::vector<unsigned char> &image, std::vector<EvoJob> &jobs, int *max_D)
+                              std::vector<unsigned char> &image, std::vector<EvoJob> &jobs, int *max_D,
+                              size_t *device_bytes)
 {
     const size_t csz = dtype == SV_C128 ? 16 : 8;
     std::vector<LoweredOp> low;
     low.reserve(c.gates.size());
+    for (const Gate &g : c.gates) low.push_back(lower_gate_op(g, c.hhl));
+    // host-built tables first (the part that is copied), then the regions
+    // the device fills (evolution tables), which are never copied
     size_t bytes = 0;
-    for (const Gate &g : c.gates) {
-        low.push_back(lower_gate_op(g, c.hhl));
-        LoweredOp &L = low.back();
-        bytes = (bytes + 255) & ~size_t(255);
-        L.op.off = bytes;
-        bytes += (L.deferred ? ((size_t)1 << (2 * L.op.k)) : L.table.size()) * csz;
+    for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1) {
+            bytes = (bytes + 255) & ~size_t(255);
+            image.assign(std::max<size_t>(bytes, 256), 0);
+        }
+        for (LoweredOp &L : low) {
+            if (L.deferred != (pass == 1)) continue;
+            bytes = (bytes + 255) & ~size_t(255);
+            L.op.off = bytes;
+            bytes += (L.deferred ? ((size_t)1 << (2 * L.op.k)) : L.table.size()) * csz;
+        }
     }
-    image.assign(std::max<size_t>(bytes, 256), 0);
+    *device_bytes = std::max<size_t>((bytes + 255) & ~size_t(255), image.size());
     ops.clear();
     jobs.clear();
     *max_D = 0;
     for (auto &L : low) {
-        unsigned char *dst = image.data() + L.op.off;
+        unsigned char *dst = L.deferred ? nullptr : image.data() + L.op.off;
         if (L.deferred) {
             if (!c.hhl.spec || c.hhl.spec->D != (1 << L.op.k))
                 return fail(SV_ERR_INVALID, "deferred evolution without a matching eigen-decomposition");
@@ -857,7 +877,7 @@ sv_status upload_program_image(const Circuit &c, const std::vector<unsigned char
                                const std::vector<EvoJob> &jobs, int max_D, void *d_image, sv_dtype dtype,
                                hipStream_t st)
 {
-    HIPCK(hipMemcpyAsync(d_image, image.data(), image.size(), hipMemcpyHostToDevice, st));
+    if (!image.empty()) HIPCK(hipMemcpyAsync(d_image, image.data(), image.size(), hipMemcpyHostToDevice, st));
     if (jobs.empty()) return hipStreamSynchronize(st) == hipSuccess ? SV_OK : fail(SV_ERR_HIP, "upload sync");
     // eigen-decomposition (Vt then w) and the job list, then one launch
     const Spectral &sp = *c.hhl.spec;
@@ -897,12 +917,13 @@ DeviceProgram *get_device_program(const Circuit &c, sv_dtype dtype, sv_status *s
     std::vector<unsigned char> image;
     std::vector<EvoJob> jobs;
     int max_D = 0;
-    *st = build_program_image(c, dtype, prog->ops, image, jobs, &max_D);
+    size_t device_bytes = 0;
+    *st = build_program_image(c, dtype, prog->ops, image, jobs, &max_D, &device_bytes);
     if (*st != SV_OK) {
         delete prog;
         return nullptr;
     }
-    prog->bytes = image.size();
+    prog->bytes = device_bytes;
     hipError_t e = hipMalloc(&prog->dbuf, prog->bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -978,13 +999,24 @@ sv_status launch_program_graph(const Circuit &c, DeviceProgram &prog, void *psi,
     return SV_OK;
 }
 
+sv_status launch_op_group(const DevOp &op, const Group &g, int n, sv_dtype dtype, hipStream_t stream,
+                          int *family)
+{
+    if (g.count < 1 || g.count > kMaxGroup) return fail(SV_ERR_INVALID, "launch: bad group size");
+    int fam_local = -1;
+    int *fam = family ? family : &fam_local;
+    if (dtype == SV_C128) return launch_op_t<double>(op, g, n, stream, fam);
+    return launch_op_t<float>(op, g, n, stream, fam);
+}
+
 sv_status launch_op(const DevOp &op, const DeviceProgram &prog, void *psi, int n,
                     sv_dtype dtype, hipStream_t stream, int *family)
 {
-    int fam_local = -1;
-    int *fam = family ? family : &fam_local;
-    if (dtype == SV_C128) return launch_op_t<double>(op, prog, psi, n, stream, fam);
-    return launch_op_t<float>(op, prog, psi, n, stream, fam);
+    Group g;
+    g.count = 1;
+    g.psi[0] = psi;
+    g.dbuf[0] = static_cast<const unsigned char *>(prog.dbuf);
+    return launch_op_group(op, g, n, dtype, stream, family);
 }
 
 sv_status launch_build_evolutions(const EvoJob *d_jobs, int njobs, int max_D, const double *d_spec,
@@ -1003,16 +1035,49 @@ sv_status launch_build_evolutions(const EvoJob *d_jobs, int njobs, int max_D, co
     return SV_OK;
 }
 
+sv_status launch_init_zero_group(const Group &g, int n, sv_dtype dtype, hipStream_t s)
+{
+    if (g.count < 1 || g.count > kMaxGroup) return fail(SV_ERR_INVALID, "launch: bad group size");
+    Ptrs pp;
+    std::memset(&pp, 0, sizeof(pp));
+    for (int i = 0; i < g.count; ++i) pp.a[i] = reinterpret_cast<unsigned long long>(g.psi[i]);
+    const uint64_t namps = uint64_t(1) << n;
+    const dim3 grid(grid_for(namps, 256, 16384), (unsigned)g.count);
+    if (dtype == SV_C128)
+        hipLaunchKernelGGL((k_zero_state<double>), grid, dim3(256), 0, s, pp, namps);
+    else
+        hipLaunchKernelGGL((k_zero_state<float>), grid, dim3(256), 0, s, pp, namps);
+    HIPCK(hipGetLastError());
+    return SV_OK;
+}
+
 sv_status launch_init_zero_state(void *psi, int n, sv_dtype dtype, hipStream_t s)
 {
-    const uint64_t namps = uint64_t(1) << n;
-    const unsigned grid = grid_for(namps, 256, 16384);
+    Group g;
+    g.count = 1;
+    g.psi[0] = psi;
+    return launch_init_zero_group(g, n, dtype, s);
+}
+
+sv_status launch_norm2_group(const Group &g, uint64_t lo, uint64_t hi, sv_dtype dtype, hipStream_t s)
+{
+    if (g.count < 1 || g.count > kMaxGroup) return fail(SV_ERR_INVALID, "launch: bad group size");
+    Ptrs p1, p2;
+    std::memset(&p1, 0, sizeof(p1));
+    std::memset(&p2, 0, sizeof(p2));
+    for (int i = 0; i < g.count; ++i) {
+        p1.a[i] = reinterpret_cast<unsigned long long>(g.psi[i]);
+        p1.b[i] = reinterpret_cast<unsigned long long>(g.partials[i]);
+        p2.a[i] = p1.b[i];
+        p2.b[i] = reinterpret_cast<unsigned long long>(g.out[i]);
+    }
+    const unsigned cnt = (unsigned)g.count;
     if (dtype == SV_C128)
-        hipLaunchKernelGGL((k_zero_state<double>), dim3(grid), dim3(256), 0, s,
-                           static_cast<V2<double>::type *>(psi), namps);
+        hipLaunchKernelGGL((k_norm2_partial<double>), dim3(kReducePartials, cnt), dim3(256), 0, s, p1, lo, hi);
     else
-        hipLaunchKernelGGL((k_zero_state<float>), dim3(grid), dim3(256), 0, s,
-                           static_cast<V2<float>::type *>(psi), namps);
+        hipLaunchKernelGGL((k_norm2_partial<float>), dim3(kReducePartials, cnt), dim3(256), 0, s, p1, lo, hi);
+    HIPCK(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_partials, dim3(1, cnt), dim3(256), 0, s, p2, kReducePartials);
     HIPCK(hipGetLastError());
     return SV_OK;
 }
@@ -1020,16 +1085,12 @@ sv_status launch_init_zero_state(void *psi, int n, sv_dtype dtype, hipStream_t s
 sv_status launch_norm2_range(const void *psi, uint64_t lo, uint64_t hi, sv_dtype dtype,
                              double *dev_partials, double *dev_out, hipStream_t s)
 {
-    if (dtype == SV_C128)
-        hipLaunchKernelGGL((k_norm2_partial<double>), dim3(kReducePartials), dim3(256), 0, s,
-                           static_cast<const V2<double>::type *>(psi), lo, hi, dev_partials);
-    else
-        hipLaunchKernelGGL((k_norm2_partial<float>), dim3(kReducePartials), dim3(256), 0, s,
-                           static_cast<const V2<float>::type *>(psi), lo, hi, dev_partials);
-    HIPCK(hipGetLastError());
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, dev_partials, kReducePartials, dev_out);
-    HIPCK(hipGetLastError());
-    return SV_OK;
+    Group g;
+    g.count = 1;
+    g.psi[0] = const_cast<void *>(psi);
+    g.partials[0] = dev_partials;
+    g.out[0] = dev_out;
+    return launch_norm2_group(g, lo, hi, dtype, s);
 }
 
 sv_status launch_gather(const void *psi, const uint64_t *dev_idx, size_t count,

@@ -11,6 +11,31 @@
 
 namespace hhlsv {
 
+// Grouped launches: one launch applies the same op to up to kMaxGroup states
+// of the same size, each with its own table (blockIdx.y selects the member).
+// A member's arithmetic does not depend on the group it runs in.
+constexpr int kMaxGroup = 16;
+struct Ptrs {
+    unsigned long long a[kMaxGroup];   // per member: the state (or primary buffer)
+    unsigned long long b[kMaxGroup];   // per member: the op's table (or secondary buffer)
+};
+
+template <typename T>
+__device__ __forceinline__ T *member_ptr(const unsigned long long (&p)[kMaxGroup])
+{
+    return reinterpret_cast<T *>(p[blockIdx.y]);
+}
+
+// Host description of a group: members share n, dtype and the op list (same
+// table offsets in their program images).
+struct Group {
+    int count = 0;
+    void *psi[kMaxGroup] = {};
+    const unsigned char *dbuf[kMaxGroup] = {};   // program image of each member
+    double *partials[kMaxGroup] = {};            // kReducePartials doubles each
+    double *out[kMaxGroup] = {};                 // one double each (norm result)
+};
+
 // One device operation, lowered from a circuit gate.
 enum OpType : int {
     OP_DENSE = 0,   // dense 2^k x 2^k matrix on sorted targets, k <= 5
@@ -79,11 +104,14 @@ sv_status launch_build_evolutions(const EvoJob *d_jobs, int njobs, int max_D, co
 // once to FP32 for SV_C64).  Returns nullptr and sets the error on failure.
 DeviceProgram *get_device_program(const Circuit &c, sv_dtype dtype, sv_status *st);
 
-// Lower a circuit into device ops and one table image (offsets in ops[i].off);
-// evolution tables to build on the device are listed in jobs (spectral
-// offsets relative to [Vt | w] of the circuit's eigen-decomposition).
+// Lower a circuit into device ops and one table buffer of *device_bytes
+// (offsets in ops[i].off).  image holds the host-built tables, the first
+// image.size() bytes of the buffer; the evolution tables the device builds
+// follow them and are listed in jobs (spectral offsets relative to [Vt | w]
+// of the circuit's eigen-decomposition).
 sv_status build_program_image(const Circuit &c, sv_dtype dtype, std::vector<DevOp> &ops,
-                              std::vector<unsigned char> &image, std::vector<EvoJob> &jobs, int *max_D);
+                              std::vector<unsigned char> &image, std::vector<EvoJob> &jobs, int *max_D,
+                              size_t *device_bytes);
 // Copy an image to d_image on stream st and build its evolution tables there;
 // synchronises st.
 sv_status upload_program_image(const Circuit &c, const std::vector<unsigned char> &image,
@@ -94,6 +122,9 @@ sv_status upload_program_image(const Circuit &c, const std::vector<unsigned char
 // receives the sv_kernel_family used.
 sv_status launch_op(const DevOp &op, const DeviceProgram &prog, void *psi, int n,
                     sv_dtype dtype, hipStream_t stream, int *family = nullptr);
+// The same op on every member of a group (1 <= count <= kMaxGroup).
+sv_status launch_op_group(const DevOp &op, const Group &g, int n, sv_dtype dtype, hipStream_t stream,
+                          int *family = nullptr);
 
 // Kernels used by the state runtime.
 sv_status launch_init_zero_state(void *psi, int n, sv_dtype dtype, hipStream_t s);
@@ -102,6 +133,10 @@ sv_status launch_init_zero_state(void *psi, int n, sv_dtype dtype, hipStream_t s
 constexpr int kReducePartials = 1024;
 sv_status launch_norm2_range(const void *psi, uint64_t lo, uint64_t hi, sv_dtype dtype,
                              double *dev_partials, double *dev_out, hipStream_t s);
+// Group forms: |0...0> on every member; sum |psi_i|^2 over [lo, hi) of each
+// member into its out[] through its partials[].
+sv_status launch_init_zero_group(const Group &g, int n, sv_dtype dtype, hipStream_t s);
+sv_status launch_norm2_group(const Group &g, uint64_t lo, uint64_t hi, sv_dtype dtype, hipStream_t s);
 sv_status launch_gather(const void *psi, const uint64_t *dev_idx, size_t count,
                         void *dev_out, sv_dtype dtype, hipStream_t s);
 

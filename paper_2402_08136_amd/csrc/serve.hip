@@ -9,8 +9,11 @@
 // resident on the device.  A scheduler thread keeps up to `streams`
 // micro-batches in flight: resident requests of up to batch_max_qubits go
 // together through the batched persistent kernel (one workgroup per request,
-// the state in LDS when it fits, else in HBM), larger requests run alone
-// through the whole-GPU sweep kernels.
+// the state in LDS when it fits, else in HBM).  Larger requests go to a few
+// launcher threads, each with its own stream, which run them through the
+// whole-GPU sweep kernels; requests of the same shape (same size and fused op
+// list) waiting together are launched as one group, each op applied to every
+// member's state with that member's own matrices in a single launch.
 // New requests are admitted and launched while earlier ones are still on the
 // GPU.  When a micro-batch finishes its postselected outputs are copied back,
 // x is recovered (step 4), latency is recorded and the memory and slots are
@@ -60,9 +63,10 @@ __global__ __launch_bounds__(256) void k_gather_outputs(const BInst *__restrict_
 // Postselected block of a large request: out = [P(anc=1) (already there), 0,
 // y_0.re, y_0.im, ...] with y_s = psi[2^{n-1} + s], widened to double.
 template <typename R>
-__global__ __launch_bounds__(256) void k_copy_y(const typename V2<R>::type *__restrict__ psi, uint64_t half,
-                                                int D, double *__restrict__ out)
+__global__ __launch_bounds__(256) void k_copy_y(Ptrs pp, uint64_t half, int D)
 {
+    const typename V2<R>::type *__restrict__ psi = member_ptr<const typename V2<R>::type>(pp.a);
+    double *__restrict__ out = member_ptr<double>(pp.b);
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < D; i += gridDim.x * blockDim.x) {
         const auto y = psi[half + i];
         out[2 + 2 * i] = (double)y.x;
@@ -75,6 +79,7 @@ __global__ __launch_bounds__(256) void k_copy_y(const typename V2<R>::type *__re
 // batched launch with its state in HBM (one workgroup per request), or alone
 // through the whole-GPU sweep kernels.
 enum { kBatchLds = 0, kBatchHbm = 1, kAlone = 2 };
+constexpr int kAloneK = 4;   // fusion width for kAlone requests when k_max is automatic
 
 struct Req {
     uint64_t ticket = 0;
@@ -97,8 +102,11 @@ struct Req {
     void *state = nullptr;       // large
     double *partials = nullptr;  // large: reduction scratch (kReducePartials + 1)
     double *out = nullptr;       // device [p1, 0, y...]
-    hipEvent_t done = nullptr;   // alone: completion of its launches
-    hipStream_t run = nullptr;   // alone: the stream it was launched on
+    uint64_t sig = 0;            // alone: hash of (n, op list) for grouping
+    // host data an asynchronous upload reads, and the event that marks the
+    // upload done (later work on other streams waits for it)
+    std::vector<unsigned char> up_bytes;
+    hipEvent_t uploaded = nullptr;
     // result
     sv_status status = SV_OK;
     std::string err;
@@ -130,15 +138,17 @@ struct svs {
     int max_batch = 256;
     int nstreams = 8;
     int batch_max_qubits = 0;    // 0: batch only LDS-resident requests; larger run alone
+    int nlaunchers = 4;          // threads (and streams) launching the larger requests
+    double group_window = 0;     // seconds a larger request may wait for same-shape company
     int hhl_flags = 0;           // SV_HHL_SIGNED / _DILATE / _AUTO / _GAUSS_SEIDEL per request
     size_t queue_limit = 1 << 20;
     long fail_alloc_at = 0;   // test hook: the n-th device allocation fails (0 = off)
     // state
     std::mutex mu;
-    std::condition_variable cv_prep, cv_budget, cv_sched, cv_done;
+    std::condition_variable cv_prep, cv_budget, cv_sched, cv_done, cv_launch;
     std::deque<std::shared_ptr<Req>> prep_q;
     std::deque<std::shared_ptr<Req>> ready_q;
-    std::vector<std::shared_ptr<Req>> alone_inflight;   // launched by prep threads
+    std::deque<std::shared_ptr<Req>> alone_q;   // prepared larger requests, not yet launched
     std::unordered_map<uint64_t, std::shared_ptr<Req>> all;
     uint64_t next_ticket = 1;
     size_t hbm_used = 0;
@@ -146,6 +156,7 @@ struct svs {
     std::atomic<long> alloc_count{0};
     bool started = false, stopping = false;
     int preps_alive = 0;
+    uint64_t n_groups = 0, n_grouped = 0;   // launcher groups and the requests in them
     size_t pending = 0;   // submitted, not yet finished
     std::vector<std::thread> threads;
     std::vector<Slot> slots;
@@ -191,11 +202,28 @@ void finish(svs *s, const std::shared_ptr<Req> &r, sv_status st, const std::stri
     s->cv_done.notify_all();
 }
 
-void release(svs *s, const std::shared_ptr<Req> &r, hipStream_t st)
+// Device resources of finished requests, freed after the server lock is
+// released (HIP calls are kept out of the lock).
+struct Dead {
+    std::vector<void *> mem;
+    std::vector<hipEvent_t> ev;
+    void flush(hipStream_t st)
+    {
+        for (void *p : mem) (void)hipFreeAsync(p, st);   // st is ordered after the request's work
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        mem.clear();
+        ev.clear();
+    }
+};
+
+void release(svs *s, const std::shared_ptr<Req> &r, Dead &dead)
 {
     // caller holds s->mu
-    if (r->dmem) (void)hipFreeAsync(r->dmem, st);
+    if (r->dmem) dead.mem.push_back(r->dmem);
     r->dmem = nullptr;
+    if (r->uploaded) dead.ev.push_back(r->uploaded);
+    r->uploaded = nullptr;
+    r->up_bytes = std::vector<unsigned char>();
     if (r->admitted) {
         s->hbm_used -= r->footprint;
         --s->slots_used;
@@ -204,9 +232,83 @@ void release(svs *s, const std::shared_ptr<Req> &r, hipStream_t st)
     }
 }
 
+// Pinned host staging for uploads, one ring per prep thread: a request's
+// host data is copied into the ring and from there to the device with one
+// asynchronous copy (copies from pageable memory block the calling thread).
+// A region is reused once the copy that read it has completed.
+struct StagingRing {
+    unsigned char *buf = nullptr;
+    size_t cap = 0, head = 0;
+    struct Use {
+        size_t begin, end;
+        hipEvent_t ev;
+    };
+    std::deque<Use> uses;
+    std::vector<hipEvent_t> spare;
+
+    ~StagingRing()
+    {
+        for (Use &u : uses) {
+            (void)hipEventSynchronize(u.ev);
+            (void)hipEventDestroy(u.ev);
+        }
+        for (hipEvent_t e : spare) (void)hipEventDestroy(e);
+        if (buf) (void)hipHostFree(buf);
+    }
+    // A region of `bytes` no copy still reads, or nullptr if it cannot fit.
+    unsigned char *take(size_t bytes, size_t *begin)
+    {
+        if (!buf || bytes > cap) return nullptr;
+        if (head + bytes > cap) head = 0;
+        const size_t b = head, e = head + bytes;
+        for (auto it = uses.begin(); it != uses.end();) {
+            const bool overlap = it->begin < e && b < it->end;
+            if (overlap) (void)hipEventSynchronize(it->ev);
+            if (overlap || hipEventQuery(it->ev) == hipSuccess) {
+                spare.push_back(it->ev);
+                it = uses.erase(it);
+            } else {
+                ++it;
+            }
+        }
+        *begin = b;
+        return buf + b;
+    }
+    // The copy of [begin, begin + bytes) has been enqueued on st.
+    hipError_t commit(size_t begin, size_t bytes, hipStream_t st)
+    {
+        hipEvent_t ev = nullptr;
+        if (!spare.empty()) {
+            ev = spare.back();
+            spare.pop_back();
+        } else {
+            const hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e != hipSuccess) return e;
+        }
+        const hipError_t e = hipEventRecord(ev, st);
+        if (e != hipSuccess) {
+            spare.push_back(ev);
+            return e;
+        }
+        uses.push_back({begin, begin + bytes, ev});
+        head = begin + bytes;
+        return hipSuccess;
+    }
+};
+
+constexpr size_t kStagingBytes = 16u << 20;   // per prep thread
+
 // Prepare one request: build, fuse, admit, upload.  Returns false with
 // (st, err) set when the request fails.
-bool prepare(svs *s, Req &r, hipStream_t up, sv_status &st, std::string &err)
+//
+// Device layout of a request (one allocation, its footprint):
+//   [spec | jobs | ops | host-built tables | device-built tables | state |
+//    partials | out]
+// spec = [V^T | w] of the eigen-decomposition and jobs = the evolution-table
+// jobs (only with device-built tables), ops = the batch op list (batched
+// kinds), state and partials only where the request needs them.  The first
+// four parts are copied with one asynchronous copy.
+bool prepare(svs *s, Req &r, hipStream_t up, StagingRing &ring, sv_status &st, std::string &err)
 {
     sv_circuit *c = nullptr, *f = nullptr;
     st = circuit_build_hhl_ex(r.A.data(), r.b.data(), r.dim, r.m, r.t, SV_HHL_DEVICE_EVOLUTIONS | s->hhl_flags,
@@ -218,7 +320,14 @@ bool prepare(svs *s, Req &r, hipStream_t up, sv_status &st, std::string &err)
     r.h = c->c.hhl;
     r.n = c->c.n;
     r.ns = r.h.ns;
-    int k = s->k_max ? s->k_max : batch_tuned_k(s->dtype, r.ns, r.m);
+    bool resident = false;
+    batch_lds_bytes(r.n, s->dtype, &resident);
+    r.kind = resident ? kBatchLds : (r.n <= s->batch_max_qubits ? kBatchHbm : kAlone);
+    // fusion width: the configured one, else the tuned one for batched
+    // shapes; requests run through the sweep kernels are launch-bound at
+    // these sizes, so they fuse wider (fewer launches)
+    int k = s->k_max;
+    if (k == 0) k = r.kind == kAlone ? kAloneK : batch_tuned_k(s->dtype, r.ns, r.m);
     if (k == 0) k = kDefaultBatchK;
     st = fuse(c, k, &f);
     circuit_destroy(c);
@@ -226,40 +335,48 @@ bool prepare(svs *s, Req &r, hipStream_t up, sv_status &st, std::string &err)
         err = sv_last_error();
         return false;
     }
-    bool resident = false;
-    batch_lds_bytes(r.n, s->dtype, &resident);
-    r.kind = resident ? kBatchLds : (r.n <= s->batch_max_qubits ? kBatchHbm : kAlone);
-    const size_t out_bytes = sizeof(double) * (2 + (2u << r.ns));
     const size_t asz = s->dtype == SV_C128 ? 16 : 8;
     std::vector<BOp> bops;
-    std::vector<unsigned char> tables, image;
+    std::vector<unsigned char> host_tab;
     std::vector<EvoJob> jobs;
     int max_D = 0;
-    size_t ops_bytes = 0, tab_bytes = 0, state_bytes = 0;
+    size_t dev_tab = 0;
     if (r.kind != kAlone) {
-        lower_for_batch(f->c, s->dtype, bops, tables, jobs);
+        lower_for_batch(f->c, s->dtype, bops, host_tab, jobs, &dev_tab);
         for (const BOp &op : bops)
             if (op.type == OP_DENSE) r.kmax = std::max(r.kmax, op.k);
-        for (EvoJob &jb : jobs) {
-            jb.vt_off = 0;
-            jb.w_off = (unsigned long long)r.h.spec->D * r.h.spec->D;
-            max_D = std::max(max_D, jb.D);
-        }
-        ops_bytes = align256(bops.size() * sizeof(BOp));
-        tab_bytes = align256(tables.size());
-        if (r.kind == kBatchHbm) state_bytes = align256(asz << r.n);
     } else {
-        st = build_program_image(f->c, s->dtype, r.ops, image, jobs, &max_D);
+        st = build_program_image(f->c, s->dtype, r.ops, host_tab, jobs, &max_D, &dev_tab);
         if (st != SV_OK) {
             err = sv_last_error();
             circuit_destroy(f);
             return false;
         }
-        tab_bytes = align256(image.size());
-        state_bytes = align256(asz << r.n) + align256(sizeof(double) * (kReducePartials + 1));
     }
     circuit_destroy(f);
-    r.footprint = ops_bytes + tab_bytes + state_bytes + align256(out_bytes);
+    const Spectral *sp = r.h.spec.get();
+    const size_t D = sp ? (size_t)sp->D : 0;
+    for (EvoJob &jb : jobs) {
+        jb.vt_off = 0;
+        jb.w_off = (unsigned long long)(D * D);
+        max_D = std::max(max_D, jb.D);
+    }
+    // layout
+    const size_t spec_bytes = jobs.empty() ? 0 : align256((D * D + D) * sizeof(double));
+    const size_t jobs_bytes = align256(jobs.size() * sizeof(EvoJob));
+    const size_t ops_bytes = align256(bops.size() * sizeof(BOp));
+    const size_t off_jobs = spec_bytes, off_ops = off_jobs + jobs_bytes, off_tab = off_ops + ops_bytes;
+    const size_t copy_bytes = off_tab + host_tab.size();
+    const size_t off_state = off_tab + align256(dev_tab);
+    size_t state_bytes = 0, part_bytes = 0;
+    if (r.kind == kBatchHbm) state_bytes = align256(asz << r.n);
+    if (r.kind == kAlone) {
+        state_bytes = align256(asz << r.n);
+        part_bytes = align256(sizeof(double) * (kReducePartials + 1));
+    }
+    const size_t off_out = off_state + state_bytes + part_bytes;
+    const size_t out_bytes = sizeof(double) * (2 + (2u << r.ns));
+    r.footprint = off_out + align256(out_bytes);
     // admission: wait for budget and a slot
     {
         std::unique_lock<std::mutex> lk(s->mu);
@@ -292,88 +409,303 @@ bool prepare(svs *s, Req &r, hipStream_t up, sv_status &st, std::string &err)
         return false;
     }
     unsigned char *base = static_cast<unsigned char *>(r.dmem);
-    if (r.kind != kAlone) {
-        BOp *d_ops = reinterpret_cast<BOp *>(base);
-        unsigned char *d_tab = base + ops_bytes;
-        unsigned char *d_state = r.kind == kBatchHbm ? base + ops_bytes + tab_bytes : nullptr;
-        r.out = reinterpret_cast<double *>(base + ops_bytes + tab_bytes + state_bytes);
-        e = hipMemcpyAsync(d_ops, bops.data(), bops.size() * sizeof(BOp), hipMemcpyHostToDevice, up);
-        if (e == hipSuccess) e = hipMemcpyAsync(d_tab, tables.data(), tables.size(), hipMemcpyHostToDevice, up);
-        if (e != hipSuccess) {
-            st = SV_ERR_HIP;
-            err = std::string("svs: upload: ") + hipGetErrorString(e);
-            return false;
-        }
-        Circuit tmp;   // only its hhl.spec is read by the uploader
-        tmp.hhl = r.h;
-        st = upload_program_image(tmp, {}, jobs, max_D, d_tab, s->dtype, up);
+    // host image of [spec | jobs | ops | host tables]: in the staging ring
+    // when it fits, else kept with the request until the copy is done
+    size_t ring_begin = 0;
+    unsigned char *hbuf = ring.take(copy_bytes, &ring_begin);
+    if (!hbuf) {
+        r.up_bytes.assign(copy_bytes, 0);
+        hbuf = r.up_bytes.data();
+    }
+    if (spec_bytes) {
+        std::memcpy(hbuf, sp->Vt.data(), D * D * sizeof(double));
+        std::memcpy(hbuf + D * D * sizeof(double), sp->w.data(), D * sizeof(double));
+    }
+    if (!jobs.empty()) std::memcpy(hbuf + off_jobs, jobs.data(), jobs.size() * sizeof(EvoJob));
+    if (!bops.empty()) std::memcpy(hbuf + off_ops, bops.data(), bops.size() * sizeof(BOp));
+    if (!host_tab.empty()) std::memcpy(hbuf + off_tab, host_tab.data(), host_tab.size());
+    e = hipMemcpyAsync(base, hbuf, copy_bytes, hipMemcpyHostToDevice, up);
+    if (e == hipSuccess && r.up_bytes.empty()) e = ring.commit(ring_begin, copy_bytes, up);
+    if (e != hipSuccess) {
+        st = SV_ERR_HIP;
+        err = std::string("svs: upload: ") + hipGetErrorString(e);
+        return false;
+    }
+    unsigned char *d_tab = base + off_tab;
+    if (!jobs.empty()) {
+        st = launch_build_evolutions(reinterpret_cast<const EvoJob *>(base + off_jobs), (int)jobs.size(), max_D,
+                                     reinterpret_cast<const double *>(base), d_tab, s->dtype, up);
         if (st != SV_OK) {
             err = sv_last_error();
             return false;
         }
-        std::memset(&r.inst, 0, sizeof(r.inst));
+    }
+    r.out = reinterpret_cast<double *>(base + off_out);
+    std::memset(&r.inst, 0, sizeof(r.inst));
+    r.inst.ns = r.ns;
+    r.inst.out = r.out;
+    if (r.kind != kAlone) {
         r.inst.n = r.n;
-        r.inst.ns = r.ns;
         r.inst.op_count = (int)bops.size();
-        r.inst.ops = d_ops;
+        r.inst.ops = reinterpret_cast<BOp *>(base + off_ops);
         r.inst.tables = d_tab;
-        r.inst.state = d_state;
-        r.inst.out = r.out;
+        r.inst.state = r.kind == kBatchHbm ? base + off_state : nullptr;
     } else {
-        r.prog.dbuf = base;
+        r.prog.dbuf = d_tab;
         r.prog.dtype = s->dtype;
         r.prog.device = s->device;
-        r.state = base + tab_bytes;
-        r.partials = reinterpret_cast<double *>(base + tab_bytes + align256(asz << r.n));
-        r.out = reinterpret_cast<double *>(base + tab_bytes + state_bytes);
-        Circuit tmp;
-        tmp.hhl = r.h;
-        st = upload_program_image(tmp, image, jobs, max_D, r.prog.dbuf, s->dtype, up);
-        if (st != SV_OK) {
-            err = sv_last_error();
-            return false;
-        }
-        std::memset(&r.inst, 0, sizeof(r.inst));
-        r.inst.ns = r.ns;
-        r.inst.out = r.out;
+        r.state = base + off_state;
+        r.partials = reinterpret_cast<double *>(base + off_state + state_bytes);
+    }
+    e = hipEventCreateWithFlags(&r.uploaded, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(r.uploaded, up);
+    if (e != hipSuccess) {
+        st = SV_ERR_HIP;
+        err = std::string("svs: upload event: ") + hipGetErrorString(e);
+        return false;
     }
     r.h.spec.reset();   // the eigen-decomposition lives on the device now
     return true;
 }
 
-// Launch a request that runs alone (init, every op, postselection into its
-// device output block) on the calling prep thread's execution stream.
-sv_status launch_alone(svs *s, Req &r, hipStream_t run)
+// Shape signature of a larger request: two requests with equal signatures
+// (and equal op lists) can share grouped launches.
+uint64_t op_signature(int n, const std::vector<DevOp> &ops)
 {
-    sv_status st = launch_init_zero_state(r.state, r.n, s->dtype, run);
-    for (const DevOp &op : r.ops) {
-        if (st != SV_OK) return st;
-        st = launch_op(op, r.prog, r.state, r.n, s->dtype, run);
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= (v >> (8 * b)) & 0xff;
+            h *= 1099511628211ull;
+        }
+    };
+    mix((uint64_t)n);
+    mix(ops.size());
+    for (const DevOp &op : ops) {
+        mix((uint64_t)op.type | ((uint64_t)op.k << 8) | ((uint64_t)(op.target + 1) << 16) |
+            ((uint64_t)(op.control + 1) << 32));
+        for (int j = 0; j < op.k; ++j) mix((uint64_t)op.q[j]);
+        mix(op.off);
     }
-    const uint64_t half = uint64_t(1) << (r.n - 1);
-    if (st == SV_OK) st = launch_norm2_range(r.state, half, half << 1, s->dtype, r.partials, r.out, run);
-    if (st != SV_OK) return st;
-    const int D = 1 << r.ns;
+    return h;
+}
+
+bool same_ops(const std::vector<DevOp> &a, const std::vector<DevOp> &b)
+{
+    if (a.size() != b.size()) return false;
+    for (size_t i = 0; i < a.size(); ++i) {
+        const DevOp &x = a[i], &y = b[i];
+        if (x.type != y.type || x.k != y.k || x.target != y.target || x.control != y.control || x.off != y.off)
+            return false;
+        for (int j = 0; j < x.k; ++j)
+            if (x.q[j] != y.q[j]) return false;
+    }
+    return true;
+}
+
+constexpr size_t kOutMax = 2 + 2 * 4096;   // [p1, 0, y] doubles for up to 12 system qubits
+
+// One group of larger requests in flight on a launcher's stream.
+struct Flight {
+    hipEvent_t done = nullptr;
+    double *h_out = nullptr;   // pinned, kMaxGroup * kOutMax doubles
+    std::vector<std::shared_ptr<Req>> reqs;
+    bool busy = false;
+};
+
+// Launch a group of same-shape requests: |0>, every fused op (one launch per
+// op for the whole group), P(ancilla = 1) and the postselected block into
+// each member's device output, then its copy to the flight's pinned buffer.
+sv_status launch_group(svs *s, Flight &f, hipStream_t st)
+{
+    const Req &r0 = *f.reqs[0];
+    Group g;
+    g.count = (int)f.reqs.size();
+    Ptrs py;
+    std::memset(&py, 0, sizeof(py));
+    for (int i = 0; i < g.count; ++i) {
+        const Req &r = *f.reqs[i];
+        g.psi[i] = r.state;
+        g.dbuf[i] = static_cast<const unsigned char *>(r.prog.dbuf);
+        g.partials[i] = r.partials;
+        g.out[i] = r.out;
+        py.a[i] = reinterpret_cast<unsigned long long>(r.state);
+        py.b[i] = reinterpret_cast<unsigned long long>(r.out);
+    }
+    for (int i = 0; i < g.count; ++i)
+        if (hipStreamWaitEvent(st, f.reqs[i]->uploaded, 0) != hipSuccess)
+            return fail(SV_ERR_HIP, "svs: wait for upload failed");
+    sv_status rc = launch_init_zero_group(g, r0.n, s->dtype, st);
+    for (const DevOp &op : r0.ops) {
+        if (rc != SV_OK) return rc;
+        rc = launch_op_group(op, g, r0.n, s->dtype, st);
+    }
+    const uint64_t half = uint64_t(1) << (r0.n - 1);
+    if (rc == SV_OK) rc = launch_norm2_group(g, half, half << 1, s->dtype, st);
+    if (rc != SV_OK) return rc;
+    const int D = 1 << r0.ns;
+    const dim3 grid((D + 255) / 256, (unsigned)g.count);
     if (s->dtype == SV_C128)
-        hipLaunchKernelGGL((k_copy_y<double>), dim3((D + 255) / 256), dim3(256), 0, run,
-                           static_cast<const V2<double>::type *>(r.state), half, D, r.out);
+        hipLaunchKernelGGL((k_copy_y<double>), grid, dim3(256), 0, st, py, half, D);
     else
-        hipLaunchKernelGGL((k_copy_y<float>), dim3((D + 255) / 256), dim3(256), 0, run,
-                           static_cast<const V2<float>::type *>(r.state), half, D, r.out);
+        hipLaunchKernelGGL((k_copy_y<float>), grid, dim3(256), 0, st, py, half, D);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&r.done, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventRecord(r.done, run);
+    const size_t len = 2 + (2u << r0.ns);
+    for (int i = 0; i < g.count && e == hipSuccess; ++i)
+        e = hipMemcpyAsync(f.h_out + (size_t)i * kOutMax, f.reqs[i]->out, len * sizeof(double),
+                           hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipEventRecord(f.done, st);
     if (e != hipSuccess) return fail(SV_ERR_HIP, std::string("svs: launch: ") + hipGetErrorString(e));
-    r.run = run;
     return SV_OK;
+}
+
+void launcher_main(svs *s)
+{
+    (void)hipSetDevice(s->device);
+    hipStream_t st = nullptr;
+    constexpr int kFlights = 8;
+    std::vector<Flight> fl(kFlights);
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    for (Flight &f : fl) {
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&f.done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&f.h_out, kMaxGroup * kOutMax * sizeof(double));
+    }
+    const std::string setup_err = e == hipSuccess ? "" : std::string("svs: launcher setup: ") + hipGetErrorString(e);
+    Dead dead;
+    std::vector<hipError_t> q(kFlights);
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        // poll this launcher's own flights without the server lock
+        lk.unlock();
+        bool busy = false, any_done = false;
+        for (int i = 0; i < kFlights; ++i) {
+            q[i] = fl[i].busy ? hipEventQuery(fl[i].done) : hipErrorNotReady;
+            if (fl[i].busy && q[i] == hipErrorNotReady) busy = true;
+            if (fl[i].busy && q[i] != hipErrorNotReady) any_done = true;
+            if (fl[i].busy && q[i] == hipSuccess)
+                for (size_t j = 0; j < fl[i].reqs.size(); ++j) {
+                    const double *o = fl[i].h_out + j * kOutMax;
+                    fl[i].reqs[j]->result.assign(o, o + 2 + (2u << fl[i].reqs[j]->ns));
+                }
+        }
+        lk.lock();
+        // retire finished groups
+        for (int i = 0; i < kFlights && any_done; ++i) {
+            Flight &f = fl[i];
+            if (!f.busy || q[i] == hipErrorNotReady) continue;
+            for (const std::shared_ptr<Req> &r : f.reqs) {
+                release(s, r, dead);
+                if (q[i] == hipSuccess)
+                    finish(s, r, SV_OK, "");
+                else
+                    finish(s, r, SV_ERR_HIP, std::string("svs: device error: ") + hipGetErrorString(q[i]));
+            }
+            f.reqs.clear();
+            f.busy = false;
+        }
+        // launch waiting requests on free flights, same shapes together
+        double wake = 5e-3;
+        for (Flight &f : fl) {
+            if (f.busy || s->alone_q.empty()) continue;
+            // The oldest waiting request leads and takes the same-shape
+            // requests behind it.  With a group window, a request whose group
+            // is not full waits (up to the window) for more of its shape, and
+            // the next shape in line goes first.
+            size_t lead = SIZE_MAX;
+            std::vector<size_t> mates;   // positions in alone_q, ascending
+            std::vector<uint64_t> collecting;
+            for (size_t i = 0; i < s->alone_q.size() && i < 64; ++i) {
+                const Req &L = *s->alone_q[i];
+                if (std::find(collecting.begin(), collecting.end(), L.sig) != collecting.end()) continue;
+                mates.clear();
+                for (size_t j = i + 1; j < s->alone_q.size() && j <= i + 512 && (int)mates.size() + 1 < kMaxGroup;
+                     ++j) {
+                    const Req &r = *s->alone_q[j];
+                    if (r.sig == L.sig && r.n == L.n && same_ops(r.ops, L.ops)) mates.push_back(j);
+                }
+                if (s->group_window > 0 && (int)mates.size() + 1 < kMaxGroup && !s->stopping) {
+                    const double left = L.t_ready + s->group_window - now_s();
+                    if (left > 0) {
+                        wake = std::min(wake, left);
+                        collecting.push_back(L.sig);
+                        continue;
+                    }
+                }
+                lead = i;
+                break;
+            }
+            if (lead == SIZE_MAX) break;   // every waiting shape is still collecting
+            f.reqs.push_back(s->alone_q[lead]);
+            for (size_t i : mates) f.reqs.push_back(s->alone_q[i]);
+            if (lead == 0 && mates.empty()) {
+                s->alone_q.pop_front();
+            } else {
+                // drop the lead and its mates, keeping the others in order
+                std::deque<std::shared_ptr<Req>> rest;
+                size_t mi = 0;
+                for (size_t i = 0; i < s->alone_q.size(); ++i) {
+                    if (i == lead) continue;
+                    if (mi < mates.size() && mates[mi] == i) {
+                        ++mi;
+                        continue;
+                    }
+                    rest.push_back(std::move(s->alone_q[i]));
+                }
+                s->alone_q.swap(rest);
+            }
+            const double tl = now_s();
+            for (auto &r : f.reqs) r->t_launch = tl;
+            if (f.reqs.size() > 1) {
+                ++s->n_groups;
+                s->n_grouped += f.reqs.size();
+            }
+            lk.unlock();
+            dead.flush(st);
+            const sv_status rc = setup_err.empty() ? launch_group(s, f, st) : fail(SV_ERR_HIP, setup_err);
+            const std::string msg = rc == SV_OK ? "" : sv_last_error();
+            if (rc != SV_OK) (void)hipStreamSynchronize(st);
+            lk.lock();
+            if (rc != SV_OK) {
+                for (auto &r : f.reqs) {
+                    release(s, r, dead);
+                    finish(s, r, rc, msg);
+                }
+                f.reqs.clear();
+            } else {
+                f.busy = true;
+                busy = true;
+            }
+        }
+        const bool quit = s->stopping && s->preps_alive == 0 && s->alone_q.empty() && !busy;
+        if (!dead.mem.empty() || !dead.ev.empty()) {
+            lk.unlock();
+            dead.flush(st);
+            lk.lock();
+        }
+        if (quit) break;
+        if (busy) wake = std::min(wake, 100e-6);
+        s->cv_launch.wait_for(lk, std::chrono::duration<double>(std::max(wake, 10e-6)));
+    }
+    lk.unlock();
+    dead.flush(st);
+    (void)hipStreamSynchronize(st);
+    for (Flight &f : fl) {
+        if (f.done) (void)hipEventDestroy(f.done);
+        if (f.h_out) (void)hipHostFree(f.h_out);
+    }
+    if (st) (void)hipStreamDestroy(st);
 }
 
 void prep_main(svs *s)
 {
     (void)hipSetDevice(s->device);
-    hipStream_t up = nullptr, run = nullptr;
+    hipStream_t up = nullptr;
     (void)hipStreamCreateWithFlags(&up, hipStreamNonBlocking);
-    (void)hipStreamCreateWithFlags(&run, hipStreamNonBlocking);
+    StagingRing ring;
+    if (hipHostMalloc((void **)&ring.buf, kStagingBytes) == hipSuccess)
+        ring.cap = kStagingBytes;
+    else
+        ring.buf = nullptr;   // every upload then goes through pageable memory
     for (;;) {
         std::shared_ptr<Req> r;
         {
@@ -386,40 +718,36 @@ void prep_main(svs *s)
         sv_status st = SV_OK;
         std::string err;
         r->t_prep0 = now_s();
-        bool ok = !r->cancelled && prepare(s, *r, up, st, err);
+        bool ok = !r->cancelled && prepare(s, *r, up, ring, st, err);
         r->t_ready = now_s();
         if (!ok && r->cancelled && st == SV_OK) {
             st = SV_ERR_INVALID;
             err = "svs: request cancelled";
         }
-        if (ok && r->kind == kAlone) {
-            r->t_launch = now_s();
-            st = launch_alone(s, *r, run);
-            if (st != SV_OK) {
-                ok = false;
-                err = sv_last_error();
-                (void)hipStreamSynchronize(run);
+        if (ok && r->kind == kAlone) r->sig = op_signature(r->n, r->ops);
+        if (!ok) (void)hipStreamSynchronize(up);   // an upload may still read its host buffers
+        Dead dead;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            if (ok && r->kind == kAlone) {
+                s->alone_q.push_back(r);
+                s->cv_launch.notify_one();
+            } else if (ok) {
+                s->ready_q.push_back(r);
+                s->cv_sched.notify_all();
+            } else {
+                release(s, r, dead);
+                finish(s, r, st, err);
             }
         }
-        std::lock_guard<std::mutex> lk(s->mu);
-        if (ok && r->kind == kAlone) {
-            s->alone_inflight.push_back(r);
-            s->cv_sched.notify_all();
-        } else if (ok) {
-            s->ready_q.push_back(r);
-            s->cv_sched.notify_all();
-        } else {
-            release(s, r, up);
-            finish(s, r, st, err);
-        }
+        dead.flush(up);
     }
     (void)hipStreamSynchronize(up);
-    (void)hipStreamSynchronize(run);
     (void)hipStreamDestroy(up);
-    (void)hipStreamDestroy(run);
     std::lock_guard<std::mutex> lk(s->mu);
     --s->preps_alive;
     s->cv_sched.notify_all();
+    s->cv_launch.notify_all();
 }
 
 // Launch one micro-batch on a free slot (caller holds s->mu).
@@ -434,50 +762,32 @@ sv_status launch_slot(svs *s, Slot &sl)
         off += 2 + (2u << sl.reqs[i]->ns);
     }
     if (off > sl.out_cap) return fail(SV_ERR_INVALID, "svs: micro-batch output larger than its staging buffer");
+    for (int i = 0; i < cnt; ++i)
+        if (hipStreamWaitEvent(sl.stream, sl.reqs[i]->uploaded, 0) != hipSuccess)
+            return fail(SV_ERR_HIP, "svs: wait for upload failed");
     hipError_t e = hipMemcpyAsync(sl.d_insts, sl.h_insts, cnt * sizeof(BInst), hipMemcpyHostToDevice, sl.stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(sl.d_offs, sl.h_offs, cnt * sizeof(unsigned long long), hipMemcpyHostToDevice, sl.stream);
     if (e != hipSuccess) return fail(SV_ERR_HIP, std::string("svs: launch: ") + hipGetErrorString(e));
-    if (sl.reqs[0]->kind != kAlone) {
-        // order by n (one launch per size class), longest programs first
-        std::vector<int> idx(cnt);
-        for (int i = 0; i < cnt; ++i) idx[i] = i;
-        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
-            if (sl.reqs[a]->n != sl.reqs[b]->n) return sl.reqs[a]->n < sl.reqs[b]->n;
-            return sl.reqs[a]->inst.op_count > sl.reqs[b]->inst.op_count;
-        });
-        for (int i = 0; i < cnt; ++i) sl.h_order[i] = idx[i];
-        e = hipMemcpyAsync(sl.d_order, sl.h_order, cnt * sizeof(int), hipMemcpyHostToDevice, sl.stream);
-        if (e != hipSuccess) return fail(SV_ERR_HIP, std::string("svs: launch: ") + hipGetErrorString(e));
-        int first = 0;
-        while (first < cnt) {
-            const int n = sl.reqs[idx[first]]->n;
-            int last = first, kmax = 0;
-            while (last < cnt && sl.reqs[idx[last]]->n == n) kmax = std::max(kmax, sl.reqs[idx[last++]]->kmax);
-            sv_status st = launch_batch_class(sl.d_insts, sl.d_order + first, last - first, n, kmax, s->dtype,
-                                              sl.stream);
-            if (st != SV_OK) return st;
-            first = last;
-        }
-    } else {
-        Req &r = *sl.reqs[0];
-        sv_status st = launch_init_zero_state(r.state, r.n, s->dtype, sl.stream);
-        for (const DevOp &op : r.ops) {
-            if (st != SV_OK) break;
-            st = launch_op(op, r.prog, r.state, r.n, s->dtype, sl.stream);
-        }
-        const uint64_t half = uint64_t(1) << (r.n - 1);
-        if (st == SV_OK)
-            st = launch_norm2_range(r.state, half, half << 1, s->dtype, r.partials, r.out, sl.stream);
+    // order by n (one launch per size class), longest programs first
+    std::vector<int> idx(cnt);
+    for (int i = 0; i < cnt; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+        if (sl.reqs[a]->n != sl.reqs[b]->n) return sl.reqs[a]->n < sl.reqs[b]->n;
+        return sl.reqs[a]->inst.op_count > sl.reqs[b]->inst.op_count;
+    });
+    for (int i = 0; i < cnt; ++i) sl.h_order[i] = idx[i];
+    e = hipMemcpyAsync(sl.d_order, sl.h_order, cnt * sizeof(int), hipMemcpyHostToDevice, sl.stream);
+    if (e != hipSuccess) return fail(SV_ERR_HIP, std::string("svs: launch: ") + hipGetErrorString(e));
+    int first = 0;
+    while (first < cnt) {
+        const int n = sl.reqs[idx[first]]->n;
+        int last = first, kmax = 0;
+        while (last < cnt && sl.reqs[idx[last]]->n == n) kmax = std::max(kmax, sl.reqs[idx[last++]]->kmax);
+        sv_status st = launch_batch_class(sl.d_insts, sl.d_order + first, last - first, n, kmax, s->dtype,
+                                          sl.stream);
         if (st != SV_OK) return st;
-        const int D = 1 << r.ns;
-        if (s->dtype == SV_C128)
-            hipLaunchKernelGGL((k_copy_y<double>), dim3((D + 255) / 256), dim3(256), 0, sl.stream,
-                               static_cast<const V2<double>::type *>(r.state), half, D, r.out);
-        else
-            hipLaunchKernelGGL((k_copy_y<float>), dim3((D + 255) / 256), dim3(256), 0, sl.stream,
-                               static_cast<const V2<float>::type *>(r.state), half, D, r.out);
-        if ((e = hipGetLastError()) != hipSuccess) return fail(SV_ERR_HIP, std::string("svs: ") + hipGetErrorString(e));
+        first = last;
     }
     hipLaunchKernelGGL(k_gather_outputs, dim3(std::min(cnt, 1024)), dim3(256), 0, sl.stream, sl.d_insts, cnt,
                        sl.d_offs, sl.d_out);
@@ -489,15 +799,12 @@ sv_status launch_slot(svs *s, Slot &sl)
     return SV_OK;
 }
 
-void complete_slot(svs *s, Slot &sl)
+void complete_slot(svs *s, Slot &sl, Dead &dead)
 {
-    // caller holds s->mu; the slot's event has completed
-    size_t off = 0;
+    // caller holds s->mu; the slot's event has completed and the results
+    // have been copied into the requests
     for (auto &r : sl.reqs) {
-        const size_t len = 2 + (2u << r->ns);
-        r->result.assign(sl.h_out + off, sl.h_out + off + len);
-        off += len;
-        release(s, r, sl.stream);
+        release(s, r, dead);
         finish(s, r, SV_OK, "");
     }
     sl.reqs.clear();
@@ -507,98 +814,96 @@ void complete_slot(svs *s, Slot &sl)
 void sched_main(svs *s)
 {
     (void)hipSetDevice(s->device);
+    const size_t ns = s->slots.size();
+    std::vector<hipError_t> q(ns);
+    std::vector<Slot *> to_launch;
+    Dead dead;
+    hipStream_t free_stream = ns ? s->slots[0].stream : nullptr;
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
-        // retire finished micro-batches
+        // poll the scheduler's own slots without the server lock
+        lk.unlock();
         bool any_busy = false;
-        for (Slot &sl : s->slots) {
-            if (!sl.busy) continue;
-            const hipError_t q = hipEventQuery(sl.done);
-            if (q == hipSuccess) {
-                complete_slot(s, sl);
-            } else if (q != hipErrorNotReady) {
-                const std::string msg = std::string("svs: device error: ") + hipGetErrorString(q);
+        for (size_t i = 0; i < ns; ++i) {
+            Slot &sl = s->slots[i];
+            q[i] = sl.busy ? hipEventQuery(sl.done) : hipErrorNotReady;
+            if (sl.busy && q[i] == hipErrorNotReady) any_busy = true;
+            if (sl.busy && q[i] == hipSuccess) {
+                size_t off = 0;
                 for (auto &r : sl.reqs) {
-                    release(s, r, sl.stream);
+                    const size_t len = 2 + (2u << r->ns);
+                    r->result.assign(sl.h_out + off, sl.h_out + off + len);
+                    off += len;
+                }
+            }
+        }
+        lk.lock();
+        // retire finished micro-batches
+        for (size_t i = 0; i < ns; ++i) {
+            Slot &sl = s->slots[i];
+            if (!sl.busy || q[i] == hipErrorNotReady) continue;
+            if (q[i] == hipSuccess) {
+                complete_slot(s, sl, dead);
+            } else {
+                const std::string msg = std::string("svs: device error: ") + hipGetErrorString(q[i]);
+                for (auto &r : sl.reqs) {
+                    release(s, r, dead);
                     finish(s, r, SV_ERR_HIP, msg);
                 }
                 sl.reqs.clear();
                 sl.busy = false;
-            } else {
-                any_busy = true;
             }
         }
-        // retire requests that prep threads launched alone
-        for (size_t i = 0; i < s->alone_inflight.size();) {
-            std::shared_ptr<Req> r = s->alone_inflight[i];
-            const hipError_t q = hipEventQuery(r->done);
-            if (q == hipErrorNotReady) {
-                any_busy = true;
-                ++i;
-                continue;
-            }
-            sv_status st = SV_OK;
-            std::string msg;
-            if (q == hipSuccess) {
-                r->result.resize(2 + (2u << r->ns));
-                const hipError_t e = hipMemcpy(r->result.data(), r->out, r->result.size() * sizeof(double),
-                                               hipMemcpyDeviceToHost);
-                if (e != hipSuccess) {
-                    st = SV_ERR_HIP;
-                    msg = std::string("svs: result copy: ") + hipGetErrorString(e);
-                }
-            } else {
-                st = SV_ERR_HIP;
-                msg = std::string("svs: device error: ") + hipGetErrorString(q);
-            }
-            (void)hipEventDestroy(r->done);
-            r->done = nullptr;
-            release(s, r, r->run);
-            finish(s, r, st, msg);
-            s->alone_inflight[i] = s->alone_inflight.back();
-            s->alone_inflight.pop_back();
-        }
-        // launch new micro-batches on free slots
+        // form micro-batches for free slots: the oldest ready request decides
+        // the kind (LDS or HBM state) of each
+        to_launch.clear();
         for (Slot &sl : s->slots) {
             if (sl.busy || s->ready_q.empty()) continue;
-            // the oldest ready request decides the kind of this micro-batch
             const int kind = s->ready_q.front()->kind;
-            if (kind != kAlone) {
-                for (auto it = s->ready_q.begin(); it != s->ready_q.end() && (int)sl.reqs.size() < s->max_batch;) {
-                    if ((*it)->kind == kind) {
-                        sl.reqs.push_back(*it);
-                        it = s->ready_q.erase(it);
-                    } else {
-                        ++it;
-                    }
+            for (auto it = s->ready_q.begin(); it != s->ready_q.end() && (int)sl.reqs.size() < s->max_batch;) {
+                if ((*it)->kind == kind) {
+                    sl.reqs.push_back(*it);
+                    it = s->ready_q.erase(it);
+                } else {
+                    ++it;
                 }
-            } else {
-                sl.reqs.push_back(s->ready_q.front());
-                s->ready_q.pop_front();
             }
             const double tl = now_s();
             for (auto &r : sl.reqs) r->t_launch = tl;
-            const sv_status st = launch_slot(s, sl);
-            if (st != SV_OK) {
-                const std::string msg = sv_last_error();
-                (void)hipStreamSynchronize(sl.stream);
-                for (auto &r : sl.reqs) {
-                    release(s, r, sl.stream);
-                    finish(s, r, st, msg);
-                }
-                sl.reqs.clear();
-                sl.busy = false;
-            } else {
-                any_busy = true;
-            }
+            sl.busy = true;   // owned by this thread until launched or failed
+            to_launch.push_back(&sl);
         }
-        if (s->stopping && s->preps_alive == 0 && s->ready_q.empty() && s->alone_inflight.empty() && !any_busy)
-            break;
+        const bool quit = s->stopping && s->preps_alive == 0 && s->ready_q.empty() && !any_busy &&
+                          to_launch.empty();
+        lk.unlock();
+        dead.flush(free_stream);
+        for (Slot *sl : to_launch) {
+            const sv_status st = launch_slot(s, *sl);
+            if (st == SV_OK) {
+                any_busy = true;
+                continue;
+            }
+            const std::string msg = sv_last_error();
+            (void)hipStreamSynchronize(sl->stream);
+            lk.lock();
+            for (auto &r : sl->reqs) {
+                release(s, r, dead);
+                finish(s, r, st, msg);
+            }
+            lk.unlock();
+            dead.flush(sl->stream);
+            sl->reqs.clear();
+            sl->busy = false;
+        }
+        lk.lock();
+        if (quit) break;
         if (any_busy)
-            s->cv_sched.wait_for(lk, std::chrono::microseconds(50));
+            s->cv_sched.wait_for(lk, std::chrono::microseconds(100));
         else
             s->cv_sched.wait_for(lk, std::chrono::milliseconds(5));
     }
+    lk.unlock();
+    dead.flush(free_stream);
 }
 
 sv_status start_threads(svs *s)
@@ -623,6 +928,7 @@ sv_status start_threads(svs *s)
     s->preps_alive = s->prep_threads;
     for (int i = 0; i < s->prep_threads; ++i) s->threads.emplace_back(prep_main, s);
     s->threads.emplace_back(sched_main, s);
+    for (int i = 0; i < s->nlaunchers; ++i) s->threads.emplace_back(launcher_main, s);
     s->started = true;
     return SV_OK;
 }
@@ -652,8 +958,16 @@ extern "C" sv_status svs_start(size_t hbm_budget_bytes, int max_slots, sv_dtype 
         hbm_budget_bytes = free_b / 2;
     }
     s->budget = hbm_budget_bytes;
+    // Requests allocate and free through the stream-ordered pool; keep freed
+    // memory mapped in the pool (it is trimmed again at svs_stop) instead of
+    // returning it to the driver at every synchronisation.
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, s->device) == hipSuccess && pool) {
+        uint64_t keep = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
     const unsigned hw = std::max(2u, std::thread::hardware_concurrency());
-    s->prep_threads = (int)std::max(1u, std::min(12u, hw - 1));
+    s->prep_threads = (int)std::max(1u, std::min(8u, hw / 2));
     *out = s;
     return SV_OK;
 }
@@ -687,6 +1001,14 @@ extern "C" sv_status svs_configure(svs *s, int option, double value)
     case SVS_OPT_BATCH_MAX_QUBITS:
         if (value < 0 || value > 24) return fail(SV_ERR_INVALID, "svs_configure: batch qubit limit in [0, 24]");
         s->batch_max_qubits = (int)value;
+        return SV_OK;
+    case SVS_OPT_GROUP_WINDOW_US:
+        if (value < 0 || value > 1e7) return fail(SV_ERR_INVALID, "svs_configure: group window in [0, 1e7] us");
+        s->group_window = value * 1e-6;
+        return SV_OK;
+    case SVS_OPT_LAUNCHERS:
+        if (value < 1 || value > 16) return fail(SV_ERR_INVALID, "svs_configure: launchers in [1, 16]");
+        s->nlaunchers = (int)value;
         return SV_OK;
     case SVS_OPT_HHL_FLAGS: {
         const int f = (int)value;
@@ -832,6 +1154,10 @@ extern "C" sv_status svs_profile(svs *s, double *out, int cap)
     out[5] = (double)s->n_small;
     out[6] = (double)s->n_large;
     out[7] = (double)s->prep_threads;
+    if (cap >= 10) {
+        out[8] = (double)s->n_groups;    // launcher groups of two or more requests
+        out[9] = (double)s->n_grouped;   // requests launched in those groups
+    }
     return SV_OK;
 }
 
@@ -844,6 +1170,7 @@ extern "C" sv_status svs_stop(svs *s)
         s->cv_prep.notify_all();
         s->cv_budget.notify_all();
         s->cv_sched.notify_all();
+        s->cv_launch.notify_all();
     }
     for (auto &t : s->threads) t.join();
     for (Slot &sl : s->slots) {
@@ -858,6 +1185,13 @@ extern "C" sv_status svs_stop(svs *s)
         if (sl.h_out) (void)hipHostFree(sl.h_out);
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    }
+    // every server stream has drained: hand the pool's free memory back
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, s->device) == hipSuccess && pool) {
+        uint64_t zero = 0;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &zero);
+        (void)hipMemPoolTrimTo(pool, 0);
     }
     delete s;
     return SV_OK;

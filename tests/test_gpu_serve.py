@@ -100,6 +100,37 @@ def test_serving_alone_equals_mix_bitwise(dtype):
     srv.stop()
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_grouped_launches_equal_single_launches_bitwise(dtype):
+    """Same-shape requests that share launches (one launch per fused op for
+    the whole group, each member with its own matrices) give the same bits
+    as the same requests launched one at a time, and match the oracle."""
+    hs = _hs()
+    shapes = [(4, 10)] * 6 + [(5, 9)] * 5 + [(3, 11)]    # n = 15 (two op lists) and 15
+    systems = _systems(shapes, seed0=900)
+    grouped = hs.Server(dtype, k_max=3, launchers=1, group_window_us=300000)
+    tickets = [grouped.submit(A, b, m) for A, b, m in systems]
+    res_g = _wait_all(grouped, tickets)
+    prof = grouped.profile()
+    grouped.stop()
+    _say(f"grouped {dtype}: {prof}")
+    assert prof["groups"] >= 2 and prof["grouped"] >= 6
+    single = hs.Server(dtype, k_max=3, launchers=1)
+    tol = 1e-10 if dtype == "c128" else 2e-5
+    for t, (A, b, m) in zip(tickets, systems):
+        t1 = single.submit(A, b, m)
+        x1, info1 = _wait_all(single, [t1])[t1]
+        xg, info_g = res_g[t]
+        assert np.array_equal(x1, xg)
+        assert info1 == info_g
+        _, _, xh, info_ref = oracle.hhl_solve(A, b, m, want_state=False)
+        scale = np.sqrt(max(info_ref["p10"], 1e-30))
+        assert np.max(np.abs(xg - xh)) * scale <= tol
+        assert abs(info_g["p_anc1"] - info_ref["p1"]) <= tol
+    assert single.profile()["groups"] == 0
+    single.stop()
+
+
 def test_admission_under_small_budget_and_oversize():
     hs = _hs()
     big = _systems([(6, 10)] * 6, seed0=900)        # 17 qubits: 2 MiB state + tables
