@@ -237,6 +237,8 @@ def main():
                     help="skip the per-sweep rates at the other fusion widths")
     ap.add_argument("--k-sweep-layers", type=int, default=10,
                     help="layers of the circuit used for the per-k sweep rates")
+    ap.add_argument("--part", choices=["all", "single", "batch", "serve"], default="all",
+                    help="run one HHL leg alone (for profiling); prints that leg's JSON, not the bench line")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the Poisson arrival window (the full schedule is 60 s)")
     args = ap.parse_args()
@@ -249,6 +251,12 @@ def main():
 
     import paper_2402_08136_amd as hs
     import workloads as W
+
+    if args.part != "all":
+        leg = {"single": lambda: hhl_single(hs, W), "batch": lambda: hhl_batch(hs, W),
+               "serve": lambda: hhl_serve(hs, W, args.serve_seconds)}[args.part]
+        print(json.dumps({"part": args.part, "result": leg()}), flush=True)
+        return
 
     n, k = args.n, args.k
     log(f"[bench] building {args.layers}-layer circuit on {n} qubits")

@@ -56,11 +56,10 @@ __device__ __forceinline__ uint64_t tile_base(uint64_t w, const int *rpos, int k
 }
 
 template <typename R, int K>
-__global__ __launch_bounds__(256) void k_dense_direct(Ptrs pp, TileArgs a)
+__device__ __forceinline__ void k_dense_direct_body(typename V2<R>::type *__restrict__ psi,
+                                                 const typename V2<R>::type *__restrict__ mat, const TileArgs &a)
 {
     typedef typename V2<R>::type C;
-    C *__restrict__ psi = member_ptr<C>(pp.a);
-    const C *__restrict__ mat = member_ptr<const C>(pp.b);
     constexpr int NR = 1 << K;
     const int lane = threadIdx.x & 63;
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -84,14 +83,28 @@ __global__ __launch_bounds__(256) void k_dense_direct(Ptrs pp, TileArgs a)
     }
 }
 
+template <typename R, int K>
+__global__ __launch_bounds__(256) void k_dense_direct(typename V2<R>::type *__restrict__ psi,
+                                                            const typename V2<R>::type *__restrict__ mat, TileArgs a)
+{
+    k_dense_direct_body<R, K>(psi, mat, a);
+}
+
+// Grouped form: member blockIdx.y of up to kMaxGroup states.
+template <typename R, int K>
+__global__ __launch_bounds__(256) void k_dense_direct_g(Ptrs pp, TileArgs a)
+{
+    typedef typename V2<R>::type C;
+    k_dense_direct_body<R, K>(member_ptr<C>(pp.a), member_ptr<const C>(pp.b), a);
+}
+
 __device__ __forceinline__ int lds_phys(int s) { return s + (s >> 6); }
 
 template <typename R, int K>
-__global__ __launch_bounds__(64) void k_dense_lds(Ptrs pp, TileArgs a)
+__device__ __forceinline__ void k_dense_lds_body(typename V2<R>::type *__restrict__ psi,
+                                              const typename V2<R>::type *__restrict__ mat, const TileArgs &a)
 {
     typedef typename V2<R>::type C;
-    C *__restrict__ psi = member_ptr<C>(pp.a);
-    const C *__restrict__ mat = member_ptr<const C>(pp.b);
     constexpr int NR = 1 << K;
     __shared__ C tile[NR * 65];
     const int lane = threadIdx.x;
@@ -124,6 +137,21 @@ __global__ __launch_bounds__(64) void k_dense_lds(Ptrs pp, TileArgs a)
     }
 }
 
+template <typename R, int K>
+__global__ __launch_bounds__(64) void k_dense_lds(typename V2<R>::type *__restrict__ psi,
+                                                        const typename V2<R>::type *__restrict__ mat, TileArgs a)
+{
+    k_dense_lds_body<R, K>(psi, mat, a);
+}
+
+// Grouped form: member blockIdx.y of up to kMaxGroup states.
+template <typename R, int K>
+__global__ __launch_bounds__(64) void k_dense_lds_g(Ptrs pp, TileArgs a)
+{
+    typedef typename V2<R>::type C;
+    k_dense_lds_body<R, K>(member_ptr<C>(pp.a), member_ptr<const C>(pp.b), a);
+}
+
 // Dense k-qubit gate, one thread per group (any n >= k; used for small states).
 struct GenericArgs {
     uint64_t ngroups;
@@ -132,11 +160,10 @@ struct GenericArgs {
 };
 
 template <typename R, int K>
-__global__ __launch_bounds__(256) void k_dense_generic(Ptrs pp, GenericArgs a)
+__device__ __forceinline__ void k_dense_generic_body(typename V2<R>::type *__restrict__ psi,
+                                                  const typename V2<R>::type *__restrict__ mat, const GenericArgs &a)
 {
     typedef typename V2<R>::type C;
-    C *__restrict__ psi = member_ptr<C>(pp.a);
-    const C *__restrict__ mat = member_ptr<const C>(pp.b);
     constexpr int NR = 1 << K;
     for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.ngroups;
          g += (uint64_t)gridDim.x * blockDim.x) {
@@ -157,6 +184,21 @@ __global__ __launch_bounds__(256) void k_dense_generic(Ptrs pp, GenericArgs a)
     }
 }
 
+template <typename R, int K>
+__global__ __launch_bounds__(256) void k_dense_generic(typename V2<R>::type *__restrict__ psi,
+                                                             const typename V2<R>::type *__restrict__ mat, GenericArgs a)
+{
+    k_dense_generic_body<R, K>(psi, mat, a);
+}
+
+// Grouped form: member blockIdx.y of up to kMaxGroup states.
+template <typename R, int K>
+__global__ __launch_bounds__(256) void k_dense_generic_g(Ptrs pp, GenericArgs a)
+{
+    typedef typename V2<R>::type C;
+    k_dense_generic_body<R, K>(member_ptr<C>(pp.a), member_ptr<const C>(pp.b), a);
+}
+
 // ---------------------------------------------------------------------------
 // Diagonal gate: psi_i *= d[bits of i at the targets].  Pure streaming.
 // ---------------------------------------------------------------------------
@@ -167,11 +209,11 @@ struct DiagArgs {
 };
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_diag(Ptrs pp, DiagArgs a)
+__device__ __forceinline__ void k_diag_body(typename V2<R>::type *__restrict__ psi,
+                                         const typename V2<R>::type *__restrict__ mat, const DiagArgs &a)
 {
     typedef typename V2<R>::type C;
-    C *__restrict__ psi = member_ptr<C>(pp.a);
-    const C *__restrict__ d = member_ptr<const C>(pp.b);
+    const C *__restrict__ d = mat;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.namps;
          i += (uint64_t)gridDim.x * blockDim.x) {
         int v = 0;
@@ -183,6 +225,21 @@ __global__ __launch_bounds__(256) void k_diag(Ptrs pp, DiagArgs a)
         y.y = m.x * x.y + m.y * x.x;
         st_nt(y, psi + i);
     }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_diag(typename V2<R>::type *__restrict__ psi,
+                                                    const typename V2<R>::type *__restrict__ mat, DiagArgs a)
+{
+    k_diag_body<R>(psi, mat, a);
+}
+
+// Grouped form: member blockIdx.y of up to kMaxGroup states.
+template <typename R>
+__global__ __launch_bounds__(256) void k_diag_g(Ptrs pp, DiagArgs a)
+{
+    typedef typename V2<R>::type C;
+    k_diag_body<R>(member_ptr<C>(pp.a), member_ptr<const C>(pp.b), a);
 }
 
 // ---------------------------------------------------------------------------
@@ -200,11 +257,11 @@ struct WideArgs {
 };
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_wide(Ptrs pp, WideArgs a)
+__device__ __forceinline__ void k_wide_body(typename V2<R>::type *__restrict__ psi,
+                                         const typename V2<R>::type *__restrict__ mat, const WideArgs &a)
 {
     typedef typename V2<R>::type C;
-    C *__restrict__ psi = member_ptr<C>(pp.a);
-    const C *__restrict__ U = member_ptr<const C>(pp.b);
+    const C *__restrict__ U = mat;
     extern __shared__ unsigned char smem_raw[];
     C *v = reinterpret_cast<C *>(smem_raw);
     const int K = 1 << a.k;
@@ -236,6 +293,21 @@ __global__ __launch_bounds__(256) void k_wide(Ptrs pp, WideArgs a)
     }
 }
 
+template <typename R>
+__global__ __launch_bounds__(256) void k_wide(typename V2<R>::type *__restrict__ psi,
+                                                    const typename V2<R>::type *__restrict__ mat, WideArgs a)
+{
+    k_wide_body<R>(psi, mat, a);
+}
+
+// Grouped form: member blockIdx.y of up to kMaxGroup states.
+template <typename R>
+__global__ __launch_bounds__(256) void k_wide_g(Ptrs pp, WideArgs a)
+{
+    typedef typename V2<R>::type C;
+    k_wide_body<R>(member_ptr<C>(pp.a), member_ptr<const C>(pp.b), a);
+}
+
 // ---------------------------------------------------------------------------
 // Wide dense gate as a register-blocked complex GEMM, for 32 <= 2^k <= 512.
 // With the group ("row") index g over the non-target bits, out[g][i] =
@@ -256,11 +328,11 @@ struct WideGemmArgs {
 };
 
 template <typename R, int CT, int RW>
-__global__ __launch_bounds__(256) void k_wide_gemm(Ptrs pp, WideGemmArgs a)
+__device__ __forceinline__ void k_wide_gemm_body(typename V2<R>::type *__restrict__ psi,
+                                              const typename V2<R>::type *__restrict__ mat, const WideGemmArgs &a)
 {
     typedef typename V2<R>::type C;
-    C *__restrict__ psi = member_ptr<C>(pp.a);
-    const C *__restrict__ UT = member_ptr<const C>(pp.b);
+    const C *__restrict__ UT = mat;
     const int D = 1 << a.k;
     const int lpr = D < 64 ? D : 64;          // lanes per row
     const int rps = 64 / lpr;                 // rows per wave step
@@ -325,6 +397,21 @@ __global__ __launch_bounds__(256) void k_wide_gemm(Ptrs pp, WideGemmArgs a)
     }
 }
 
+template <typename R, int CT, int RW>
+__global__ __launch_bounds__(256) void k_wide_gemm(typename V2<R>::type *__restrict__ psi,
+                                                         const typename V2<R>::type *__restrict__ mat, WideGemmArgs a)
+{
+    k_wide_gemm_body<R, CT, RW>(psi, mat, a);
+}
+
+// Grouped form: member blockIdx.y of up to kMaxGroup states.
+template <typename R, int CT, int RW>
+__global__ __launch_bounds__(256) void k_wide_gemm_g(Ptrs pp, WideGemmArgs a)
+{
+    typedef typename V2<R>::type C;
+    k_wide_gemm_body<R, CT, RW>(member_ptr<C>(pp.a), member_ptr<const C>(pp.b), a);
+}
+
 // ---------------------------------------------------------------------------
 // Evolution tables on the device: U[a][b] = sum_k V[a][k] V[b][k] e^{+-i phi_k}
 // with phi_k = fmod(w_k t 2^j, 2 pi), accumulated in FP64 and stored in the
@@ -378,11 +465,11 @@ struct UcryArgs {
 };
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_ucry(Ptrs pp, UcryArgs a)
+__device__ __forceinline__ void k_ucry_body(typename V2<R>::type *__restrict__ psi,
+                                         const typename V2<R>::type *__restrict__ mat, const UcryArgs &a)
 {
     typedef typename V2<R>::type C;
-    C *__restrict__ psi = member_ptr<C>(pp.a);
-    const C *__restrict__ cs = member_ptr<const C>(pp.b);
+    const C *__restrict__ cs = mat;
     const uint64_t tbit = uint64_t(1) << a.target;
     for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < a.npairs;
          p += (uint64_t)gridDim.x * blockDim.x) {
@@ -404,6 +491,21 @@ __global__ __launch_bounds__(256) void k_ucry(Ptrs pp, UcryArgs a)
         psi[i0] = y0;
         psi[i0 | tbit] = y1;
     }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_ucry(typename V2<R>::type *__restrict__ psi,
+                                                    const typename V2<R>::type *__restrict__ mat, UcryArgs a)
+{
+    k_ucry_body<R>(psi, mat, a);
+}
+
+// Grouped form: member blockIdx.y of up to kMaxGroup states.
+template <typename R>
+__global__ __launch_bounds__(256) void k_ucry_g(Ptrs pp, UcryArgs a)
+{
+    typedef typename V2<R>::type C;
+    k_ucry_body<R>(member_ptr<C>(pp.a), member_ptr<const C>(pp.b), a);
 }
 
 // ---------------------------------------------------------------------------
@@ -478,6 +580,19 @@ inline unsigned grid_for(uint64_t work, unsigned per_block, unsigned cap)
 // ---------------------------------------------------------------------------
 // Launch helpers.
 // ---------------------------------------------------------------------------
+// One op on a group: the plain kernel (pointer arguments) for a single
+// state, the grouped form (member pointers from the table) for several.
+template <typename T, typename A>
+void launch2(void (*direct)(T *, const T *, A), void (*grouped)(Ptrs, A), unsigned gx, unsigned block,
+             size_t smem, hipStream_t st, const Ptrs &pp, unsigned cnt, const A &args)
+{
+    if (cnt == 1)
+        hipLaunchKernelGGL(direct, dim3(gx), dim3(block), smem, st, reinterpret_cast<T *>(pp.a[0]),
+                           reinterpret_cast<const T *>(pp.b[0]), args);
+    else
+        hipLaunchKernelGGL(grouped, dim3(gx, cnt), dim3(block), smem, st, pp, args);
+}
+
 // Per-member (state, op table) pointers of a grouped launch.
 Ptrs op_ptrs(const DevOp &op, const Group &g)
 {
@@ -523,11 +638,11 @@ sv_status launch_dense_t(const DevOp &op, const Group &g, int n, hipStream_t st,
             *family = SV_KERNEL_DENSE_DIRECT;
             const unsigned grid = grid_for(a.ntiles, 4, 8192);
             switch (k) {
-            case 1: hipLaunchKernelGGL((k_dense_direct<R, 1>), dim3(grid, cnt), dim3(256), 0, st, pp, a); break;
-            case 2: hipLaunchKernelGGL((k_dense_direct<R, 2>), dim3(grid, cnt), dim3(256), 0, st, pp, a); break;
-            case 3: hipLaunchKernelGGL((k_dense_direct<R, 3>), dim3(grid, cnt), dim3(256), 0, st, pp, a); break;
-            case 4: hipLaunchKernelGGL((k_dense_direct<R, 4>), dim3(grid, cnt), dim3(256), 0, st, pp, a); break;
-            case 5: hipLaunchKernelGGL((k_dense_direct<R, 5>), dim3(grid, cnt), dim3(256), 0, st, pp, a); break;
+            case 1: launch2(&k_dense_direct<R, 1>, &k_dense_direct_g<R, 1>, grid, 256, 0, st, pp, cnt, a); break;
+            case 2: launch2(&k_dense_direct<R, 2>, &k_dense_direct_g<R, 2>, grid, 256, 0, st, pp, cnt, a); break;
+            case 3: launch2(&k_dense_direct<R, 3>, &k_dense_direct_g<R, 3>, grid, 256, 0, st, pp, cnt, a); break;
+            case 4: launch2(&k_dense_direct<R, 4>, &k_dense_direct_g<R, 4>, grid, 256, 0, st, pp, cnt, a); break;
+            case 5: launch2(&k_dense_direct<R, 5>, &k_dense_direct_g<R, 5>, grid, 256, 0, st, pp, cnt, a); break;
             default: return fail(SV_ERR_INVALID, "dense op wider than 5 qubits");
             }
         } else {
@@ -551,11 +666,11 @@ sv_status launch_dense_t(const DevOp &op, const Group &g, int n, hipStream_t st,
             *family = SV_KERNEL_DENSE_LDS;
             const unsigned grid = grid_for(a.ntiles, 1, 16384);
             switch (k) {
-            case 1: hipLaunchKernelGGL((k_dense_lds<R, 1>), dim3(grid, cnt), dim3(64), 0, st, pp, a); break;
-            case 2: hipLaunchKernelGGL((k_dense_lds<R, 2>), dim3(grid, cnt), dim3(64), 0, st, pp, a); break;
-            case 3: hipLaunchKernelGGL((k_dense_lds<R, 3>), dim3(grid, cnt), dim3(64), 0, st, pp, a); break;
-            case 4: hipLaunchKernelGGL((k_dense_lds<R, 4>), dim3(grid, cnt), dim3(64), 0, st, pp, a); break;
-            case 5: hipLaunchKernelGGL((k_dense_lds<R, 5>), dim3(grid, cnt), dim3(64), 0, st, pp, a); break;
+            case 1: launch2(&k_dense_lds<R, 1>, &k_dense_lds_g<R, 1>, grid, 64, 0, st, pp, cnt, a); break;
+            case 2: launch2(&k_dense_lds<R, 2>, &k_dense_lds_g<R, 2>, grid, 64, 0, st, pp, cnt, a); break;
+            case 3: launch2(&k_dense_lds<R, 3>, &k_dense_lds_g<R, 3>, grid, 64, 0, st, pp, cnt, a); break;
+            case 4: launch2(&k_dense_lds<R, 4>, &k_dense_lds_g<R, 4>, grid, 64, 0, st, pp, cnt, a); break;
+            case 5: launch2(&k_dense_lds<R, 5>, &k_dense_lds_g<R, 5>, grid, 64, 0, st, pp, cnt, a); break;
             default: return fail(SV_ERR_INVALID, "dense op wider than 5 qubits");
             }
         }
@@ -573,11 +688,11 @@ sv_status launch_dense_t(const DevOp &op, const Group &g, int n, hipStream_t st,
         *family = SV_KERNEL_DENSE_SMALL;
         const unsigned grid = grid_for(a.ngroups, 256, 8192);
         switch (k) {
-        case 1: hipLaunchKernelGGL((k_dense_generic<R, 1>), dim3(grid, cnt), dim3(256), 0, st, pp, a); break;
-        case 2: hipLaunchKernelGGL((k_dense_generic<R, 2>), dim3(grid, cnt), dim3(256), 0, st, pp, a); break;
-        case 3: hipLaunchKernelGGL((k_dense_generic<R, 3>), dim3(grid, cnt), dim3(256), 0, st, pp, a); break;
-        case 4: hipLaunchKernelGGL((k_dense_generic<R, 4>), dim3(grid, cnt), dim3(256), 0, st, pp, a); break;
-        case 5: hipLaunchKernelGGL((k_dense_generic<R, 5>), dim3(grid, cnt), dim3(256), 0, st, pp, a); break;
+        case 1: launch2(&k_dense_generic<R, 1>, &k_dense_generic_g<R, 1>, grid, 256, 0, st, pp, cnt, a); break;
+        case 2: launch2(&k_dense_generic<R, 2>, &k_dense_generic_g<R, 2>, grid, 256, 0, st, pp, cnt, a); break;
+        case 3: launch2(&k_dense_generic<R, 3>, &k_dense_generic_g<R, 3>, grid, 256, 0, st, pp, cnt, a); break;
+        case 4: launch2(&k_dense_generic<R, 4>, &k_dense_generic_g<R, 4>, grid, 256, 0, st, pp, cnt, a); break;
+        case 5: launch2(&k_dense_generic<R, 5>, &k_dense_generic_g<R, 5>, grid, 256, 0, st, pp, cnt, a); break;
         default: return fail(SV_ERR_INVALID, "dense op wider than 5 qubits");
         }
     }
@@ -601,7 +716,7 @@ sv_status launch_op_t(const DevOp &op, const Group &g, int n, hipStream_t st, in
         a.namps = uint64_t(1) << n;
         a.k = op.k;
         for (int j = 0; j < op.k; ++j) a.q[j] = op.q[j];
-        hipLaunchKernelGGL((k_diag<R>), dim3(grid_for(a.namps, 256, 16384), cnt), dim3(256), 0, st, pp, a);
+        launch2(&k_diag<R>, &k_diag_g<R>, grid_for(a.namps, 256, 16384), 256, 0, st, pp, cnt, a);
         break;
     }
     case OP_WIDE: {
@@ -625,7 +740,7 @@ sv_status launch_op_t(const DevOp &op, const Group &g, int n, hipStream_t st, in
             int rw = 8;
             while (rw > 1 && waves_for(rw) < 1024) rw >>= 1;
             const unsigned grid = grid_for(waves_for(rw), 4, 8192);
-#define WIDE_GO(CT, RWV) hipLaunchKernelGGL((k_wide_gemm<R, CT, RWV>), dim3(grid, cnt), dim3(256), 0, st, pp, a)
+#define WIDE_GO(CT, RWV) launch2(&k_wide_gemm<R, CT, RWV>, &k_wide_gemm_g<R, CT, RWV>, grid, 256, 0, st, pp, cnt, a)
 #define WIDE_RW(CT)                          \
     switch (rw) {                            \
     case 8: WIDE_GO(CT, 8); break;           \
@@ -656,8 +771,7 @@ sv_status launch_op_t(const DevOp &op, const Group &g, int n, hipStream_t st, in
         const int K = 1 << op.k;
         const unsigned threads = (unsigned)std::min(256, std::max(64, K));
         const size_t smem = sizeof(C) * (size_t)K;
-        hipLaunchKernelGGL((k_wide<R>), dim3(grid_for(a.ngroups, 1, 16384), cnt), dim3(threads), smem, st, pp,
-                           a);
+        launch2(&k_wide<R>, &k_wide_g<R>, grid_for(a.ngroups, 1, 16384), threads, smem, st, pp, cnt, a);
         break;
     }
     case OP_UCRY: {
@@ -673,7 +787,7 @@ sv_status launch_op_t(const DevOp &op, const Group &g, int n, hipStream_t st, in
             if (l > 0 && op.q[l] != op.q[0] + l) a.contiguous = 0;
         }
         if (op.k == 0) a.ctl[0] = 0;
-        hipLaunchKernelGGL((k_ucry<R>), dim3(grid_for(a.npairs, 256, 16384), cnt), dim3(256), 0, st, pp, a);
+        launch2(&k_ucry<R>, &k_ucry_g<R>, grid_for(a.npairs, 256, 16384), 256, 0, st, pp, cnt, a);
         break;
     }
     default:

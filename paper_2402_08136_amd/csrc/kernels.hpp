@@ -23,7 +23,10 @@ struct Ptrs {
 template <typename T>
 __device__ __forceinline__ T *member_ptr(const unsigned long long (&p)[kMaxGroup])
 {
-    return reinterpret_cast<T *>(p[blockIdx.y]);
+    // the table holds device (global) addresses; saying so lets the accesses
+    // compile to global rather than flat memory instructions
+    typedef __attribute__((address_space(1))) T GT;
+    return (T *)reinterpret_cast<GT *>(p[blockIdx.y]);
 }
 
 // Host description of a group: members share n, dtype and the op list (same
