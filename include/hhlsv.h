@@ -274,11 +274,13 @@ sv_status sv_postselect_solution(sv_state *s, const sv_circuit *hhl,
 sv_status circuit_destroy(sv_circuit *c);
 
 /* ---- batched solves --------------------------------------------------- */
-/* Many small HHL solves in persistent launches: each workgroup runs a whole
- * circuit on one state held in LDS (n <= 13 at complex128, n <= 14 at
- * complex64) or in HBM, one launch per size class on its own stream, the
- * whole run captured once in a hipGraph and replayed by later svb_run calls.
- * Every instance's arithmetic is independent of the rest of the batch.
+/* Many small HHL solves in persistent launches, captured once in a hipGraph
+ * and replayed by later svb_run calls.  Instances whose state fits in 64 KiB
+ * (n <= 12 at complex128, n <= 13 at complex64) run one workgroup per state
+ * with the state in LDS, one launch per size class; larger ones run through
+ * the whole-GPU sweep kernels in groups of up to 64 same-shape instances
+ * (one launch per fused op for the group).  Every instance's arithmetic is
+ * independent of the rest of the batch.
  *
  * svb_create: k_max in 1..5 fuses every instance with that width; 0 uses the
  * width svb_autotune chose for the instance's (ns, m), else 3.  hip_stream may

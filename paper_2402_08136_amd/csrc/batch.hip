@@ -1,8 +1,8 @@
 // Batched execution of many small HHL solves in persistent launches.
 //
-// Each workgroup runs one whole circuit at a time on one state: the state
-// lives in LDS when it fits (2^n amplitudes of up to 128 KiB, i.e. n <= 13 at
-// complex128 and n <= 14 at complex64) and in HBM otherwise; the gate program
+// Each workgroup runs one whole circuit at a time on one state held in LDS
+// (states of up to 64 KiB, i.e. n <= 12 at complex128 and n <= 13 at
+// complex64; larger ones run as grouped whole-GPU sweeps, see svb); the gate program
 // (fused ops with FP64-built tables) is read from device memory; the
 // postselected block y and P(ancilla = 1) (Sec. III-A steps 3-4 of Zheng et
 // al., PESGM 2024) are written out at the end.  Instances are grouped by size
@@ -464,7 +464,7 @@ struct svb {
     std::vector<unsigned char> tables;
     struct Meta {
         int n, ns, op_begin, op_count, kmax;
-        size_t state_off, out_off;
+        size_t state_off, out_off, tab_base;
     };
     std::vector<Meta> insts;
     std::vector<HHLParams> params;
@@ -482,6 +482,18 @@ struct svb {
     double *d_out = nullptr;
     double *h_out = nullptr;   // pinned
     std::vector<BatchClass> classes;
+    // Instances whose state does not fit in LDS run through the whole-GPU
+    // sweep kernels instead, in groups of up to kMaxGroup instances of the
+    // same shape (same size and fused op list): one launch per op for the
+    // whole group, each member with its own tables.
+    struct Swept {
+        int n = 0, ns = 0;
+        std::vector<DevOp> ops;     // table offsets relative to a member's table base
+        std::vector<int> members;   // instance indices
+        size_t part_first = 0;      // first reduction-scratch slot
+    };
+    std::vector<Swept> swept;
+    double *d_partials = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool have_result = false;
@@ -502,6 +514,9 @@ void release_device(svb *b)
     (void)hipFree(b->d_order);
     (void)hipFree(b->d_states);
     (void)hipFree(b->d_out);
+    (void)hipFree(b->d_partials);
+    b->d_partials = nullptr;
+    b->swept.clear();
     if (b->h_out) (void)hipHostFree(b->h_out);
     b->d_ops = nullptr;
     b->d_tables = nullptr;
@@ -513,21 +528,78 @@ void release_device(svb *b)
     b->uploaded = false;
 }
 
+// The op list of instance i as sweep-kernel ops, offsets relative to its
+// table base.
+std::vector<DevOp> swept_ops(const svb *b, const svb::Meta &in)
+{
+    std::vector<DevOp> ops(in.op_count);
+    for (int o = 0; o < in.op_count; ++o) {
+        const BOp &bo = b->ops[in.op_begin + o];
+        DevOp &d = ops[o];
+        d.type = bo.type;
+        d.k = bo.k;
+        for (int j = 0; j < kMaxUcryControls; ++j) d.q[j] = bo.q[j];
+        d.target = bo.target;
+        d.control = bo.control;
+        d.off = bo.off - in.tab_base;
+    }
+    return ops;
+}
+
+bool same_ops(const std::vector<DevOp> &x, const std::vector<DevOp> &y)
+{
+    if (x.size() != y.size()) return false;
+    for (size_t i = 0; i < x.size(); ++i) {
+        const DevOp &a = x[i], &c = y[i];
+        if (a.type != c.type || a.k != c.k || a.target != c.target || a.control != c.control || a.off != c.off)
+            return false;
+        for (int j = 0; j < a.k; ++j)
+            if (a.q[j] != c.q[j]) return false;
+    }
+    return true;
+}
+
 sv_status upload(svb *b)
 {
-    // state arena offsets for instances that do not fit in LDS
-    size_t arena = 0;
+    // state arena offsets for instances that do not fit in LDS; those run as
+    // swept groups, the others in per-size classes of the batched kernel
+    size_t arena = 0, nparts = 0;
     std::map<int, std::vector<int>> by_n;
+    b->swept.clear();
+    std::map<int, std::vector<size_t>> swept_by_n;   // n -> indices into b->swept
     for (size_t i = 0; i < b->insts.size(); ++i) {
         svb::Meta &in = b->insts[i];
         bool resident = false;
         batch_lds_bytes(in.n, b->dtype, &resident);
         in.state_off = 0;
-        if (!resident) {
-            in.state_off = arena;
-            arena += ((amp_size(b->dtype) << in.n) + 255) & ~size_t(255);
+        if (resident) {
+            by_n[in.n].push_back((int)i);
+            continue;
         }
-        by_n[in.n].push_back((int)i);
+        in.state_off = arena;
+        arena += ((amp_size(b->dtype) << in.n) + 255) & ~size_t(255);
+        std::vector<DevOp> ops = swept_ops(b, in);
+        svb::Swept *grp = nullptr;
+        for (size_t gi : swept_by_n[in.n]) {
+            svb::Swept &sw = b->swept[gi];
+            if ((int)sw.members.size() < kMaxGroup && same_ops(sw.ops, ops)) {
+                grp = &sw;
+                break;
+            }
+        }
+        if (!grp) {
+            swept_by_n[in.n].push_back(b->swept.size());
+            b->swept.emplace_back();
+            grp = &b->swept.back();
+            grp->n = in.n;
+            grp->ns = in.ns;
+            grp->ops = std::move(ops);
+        }
+        grp->members.push_back((int)i);
+    }
+    for (svb::Swept &sw : b->swept) {
+        sw.part_first = nparts;
+        nparts += sw.members.size();
     }
     b->state_bytes = arena;
     std::vector<int> order;
@@ -560,6 +632,7 @@ sv_status upload(svb *b)
     if ((st = alloc((void **)&b->d_order, order.size() * sizeof(int))) != SV_OK) return st;
     if ((st = alloc((void **)&b->d_states, arena)) != SV_OK) return st;
     if ((st = alloc((void **)&b->d_out, b->out_doubles * sizeof(double))) != SV_OK) return st;
+    if ((st = alloc((void **)&b->d_partials, nparts * (kReducePartials + 1) * sizeof(double))) != SV_OK) return st;
     HIPCK(hipHostMalloc((void **)&b->h_out, std::max<size_t>(b->out_doubles, 1) * sizeof(double)));
     std::vector<BInst> dev(b->insts.size());
     for (size_t i = 0; i < b->insts.size(); ++i) {
@@ -635,6 +708,24 @@ sv_status capture(svb *b)
                                b->side[c % nside]) != SV_OK)
             e = hipErrorLaunchFailure;
     }
+    // swept groups, spread over the side streams after the classes
+    for (size_t gi = 0; gi < b->swept.size() && e == hipSuccess; ++gi) {
+        const svb::Swept &sw = b->swept[gi];
+        const hipStream_t st = b->side[(b->classes.size() + gi) % nside];
+        Group g;
+        g.count = (int)sw.members.size();
+        for (int i = 0; i < g.count; ++i) {
+            const svb::Meta &in = b->insts[sw.members[i]];
+            g.psi[i] = b->d_states + in.state_off;
+            g.dbuf[i] = b->d_tables + in.tab_base;
+            g.partials[i] = b->d_partials + (sw.part_first + i) * (kReducePartials + 1);
+            g.out[i] = b->d_out + in.out_off;
+        }
+        sv_status ls = launch_init_zero_group(g, sw.n, b->dtype, st);
+        for (size_t o = 0; o < sw.ops.size() && ls == SV_OK; ++o) ls = launch_op_group(sw.ops[o], g, sw.n, b->dtype, st);
+        if (ls == SV_OK) ls = launch_postselect_group(g, sw.n, sw.ns, b->dtype, st);
+        if (ls != SV_OK) e = hipErrorLaunchFailure;
+    }
     for (int i = 0; i < nside && e == hipSuccess; ++i) {
         e = hipEventRecord(b->ev[1 + i], b->side[i]);
         if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev[1 + i], 0);
@@ -668,7 +759,7 @@ extern "C" sv_status svb_create(sv_dtype dtype, int k_max, void *hip_stream, svb
     hipError_t e = hipGetDevice(&b->device);
     if (e == hipSuccess && !hip_stream) e = hipStreamCreateWithFlags(&b->own_stream, hipStreamNonBlocking);
     b->stream = hip_stream ? static_cast<hipStream_t>(hip_stream) : b->own_stream;
-    b->side.resize(4, nullptr);
+    b->side.resize(8, nullptr);
     b->ev.resize(1 + b->side.size(), nullptr);
     for (auto &s : b->side)
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
@@ -721,6 +812,7 @@ extern "C" sv_status svb_add(svb *b, const sv_circuit *hhl, int *index_out)
         size_t dev_bytes = 0;
         lower_for_batch(f->c, b->dtype, ops, tab, evo, &dev_bytes);
         const size_t base = (b->tables.size() + 255) & ~size_t(255);
+        in.tab_base = base;
         b->tables.resize(base + dev_bytes);
         std::memcpy(b->tables.data() + base, tab.data(), tab.size());
         for (BOp &op : ops) {

@@ -28,14 +28,17 @@ struct BInst {
     double *out;            // [P(ancilla=1), 0, y_0.re, y_0.im, ...], 2 + 2^(ns+1) doubles
 };
 
-// LDS budget of one batch workgroup and whether an n-qubit state fits in it.
+// LDS budget of one batch workgroup and whether an n-qubit state runs in it.
+// States above kResidentStateMax would fit (up to 128 KiB) but leave one
+// workgroup per CU; they run faster through the grouped sweep kernels.
 constexpr int kBatchThreads = 256;
 constexpr int kBatchLdsLimit = 160 * 1024;
+constexpr size_t kResidentStateMax = 64 * 1024;
 inline size_t batch_lds_bytes(int n, sv_dtype d, bool *resident)
 {
     const size_t red = kBatchThreads * 8;
     const size_t sb = (d == SV_C128 ? size_t(16) : size_t(8)) << n;
-    *resident = sb + red <= (size_t)kBatchLdsLimit;
+    *resident = sb <= kResidentStateMax && sb + red <= (size_t)kBatchLdsLimit;
     return red + (*resident ? sb : 0);
 }
 

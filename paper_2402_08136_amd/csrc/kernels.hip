@@ -375,6 +375,7 @@ __device__ __forceinline__ void k_wide_gemm_body(typename V2<R>::type *__restric
         for (int r = 0; r < RW; ++r)
 #pragma unroll
             for (int t = 0; t < CT; ++t) acc[r][t] = C{0, 0};
+#pragma unroll 4
         for (int c = 0; c < D; ++c) {
             const uint64_t oc = off(c);
             C u[CT];
@@ -560,6 +561,22 @@ __global__ __launch_bounds__(256) void k_sum_partials(Ptrs pp, int n)
     if (threadIdx.x == 0) *out = red[0];
 }
 
+// Postselected block of each member: out = [P(anc = 1) (written by the
+// norm reduction), 0, y_0.re, y_0.im, ...] with y_s = psi[2^{n-1} + s],
+// widened to double.  Member pointers: a = state, b = its output block.
+template <typename R>
+__global__ __launch_bounds__(256) void k_copy_block(Ptrs pp, uint64_t half, int D)
+{
+    const typename V2<R>::type *__restrict__ psi = member_ptr<const typename V2<R>::type>(pp.a);
+    double *__restrict__ out = member_ptr<double>(pp.b);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < D; i += gridDim.x * blockDim.x) {
+        const auto y = psi[half + i];
+        out[2 + 2 * i] = (double)y.x;
+        out[3 + 2 * i] = (double)y.y;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[1] = 0.0;
+}
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_gather(const typename V2<R>::type *__restrict__ psi,
                                                 const uint64_t *__restrict__ idx, size_t count,
@@ -722,7 +739,7 @@ sv_status launch_op_t(const DevOp &op, const Group &g, int n, hipStream_t st, in
     case OP_WIDE: {
         *family = SV_KERNEL_WIDE;
         const uint64_t ngroups = uint64_t(1) << (n - op.k - (op.control >= 0 ? 1 : 0));
-        if (op.k >= 5 && op.k <= 9) {
+        if (op.k >= 2 && op.k <= 9) {
             WideGemmArgs a;
             std::memset(&a, 0, sizeof(a));
             a.ngroups = ngroups;
@@ -734,11 +751,12 @@ sv_status launch_op_t(const DevOp &op, const Group &g, int n, hipStream_t st, in
                 if (op.q[j] != op.q[0] + j) a.contiguous = 0;
             const int D = 1 << op.k;
             const int rps = D < 64 ? 64 / D : 1;
-            // rows per wave: as many as keep >= ~1024 waves busy (reuse of
-            // each loaded U column across rows vs parallelism)
+            // rows per wave: as many as keep >= ~1024 waves busy over the
+            // whole group (reuse of each loaded U column across rows vs
+            // parallelism); a row's arithmetic does not depend on it
             auto waves_for = [&](int rw) { return (ngroups + (uint64_t)rw * rps - 1) / ((uint64_t)rw * rps); };
             int rw = 8;
-            while (rw > 1 && waves_for(rw) < 1024) rw >>= 1;
+            while (rw > 1 && cnt * waves_for(rw) < 1024) rw >>= 1;
             const unsigned grid = grid_for(waves_for(rw), 4, 8192);
 #define WIDE_GO(CT, RWV) launch2(&k_wide_gemm<R, CT, RWV>, &k_wide_gemm_g<R, CT, RWV>, grid, 256, 0, st, pp, cnt, a)
 #define WIDE_RW(CT)                          \
@@ -836,7 +854,10 @@ std::vector<cd> to_sorted(const std::vector<cd> &M, const std::vector<int> &gq, 
 LoweredOp lower_gate_op(const Gate &g0, const HHLParams &h)
 {
     LoweredOp L;
-    if (gate_deferred(g0) && g0.kind == SV_GATE_CDENSE && (int)g0.qubits.size() > 5) {
+    // A controlled gate on two or more targets (the controlled e^{iAt 2^j})
+    // is a wide op with a control: only the control = 1 half is read and
+    // written, instead of a dense matrix with an identity block.
+    if (gate_deferred(g0) && g0.kind == SV_GATE_CDENSE && (int)g0.qubits.size() >= 3) {
         // Evolution on the whole system register, built on the device.
         std::vector<int> tq(g0.qubits.begin() + 1, g0.qubits.end());
         std::sort(tq.begin(), tq.end());
@@ -890,7 +911,7 @@ LoweredOp lower_gate_op(const Gate &g0, const HHLParams &h)
         for (size_t l = 0; l < k; ++l) op.q[l] = sorted[l];
         return L;
     }
-    if (g.kind == SV_GATE_CDENSE && (int)g.qubits.size() > 5) {
+    if (g.kind == SV_GATE_CDENSE && (int)g.qubits.size() >= 3) {
         std::vector<int> tq(g.qubits.begin() + 1, g.qubits.end());
         std::vector<cd> U(g.params.size() / 2);
         for (size_t i = 0; i < U.size(); ++i) U[i] = cd(g.params[2 * i], g.params[2 * i + 1]);
@@ -1205,6 +1226,27 @@ sv_status launch_norm2_range(const void *psi, uint64_t lo, uint64_t hi, sv_dtype
     g.partials[0] = dev_partials;
     g.out[0] = dev_out;
     return launch_norm2_group(g, lo, hi, dtype, s);
+}
+
+sv_status launch_postselect_group(const Group &g, int n, int ns, sv_dtype dtype, hipStream_t s)
+{
+    const uint64_t half = uint64_t(1) << (n - 1);
+    sv_status st = launch_norm2_group(g, half, half << 1, dtype, s);
+    if (st != SV_OK) return st;
+    Ptrs pp;
+    std::memset(&pp, 0, sizeof(pp));
+    for (int i = 0; i < g.count; ++i) {
+        pp.a[i] = reinterpret_cast<unsigned long long>(g.psi[i]);
+        pp.b[i] = reinterpret_cast<unsigned long long>(g.out[i]);
+    }
+    const int D = 1 << ns;
+    const dim3 grid((D + 255) / 256, (unsigned)g.count);
+    if (dtype == SV_C128)
+        hipLaunchKernelGGL((k_copy_block<double>), grid, dim3(256), 0, s, pp, half, D);
+    else
+        hipLaunchKernelGGL((k_copy_block<float>), grid, dim3(256), 0, s, pp, half, D);
+    HIPCK(hipGetLastError());
+    return SV_OK;
 }
 
 sv_status launch_gather(const void *psi, const uint64_t *dev_idx, size_t count,

@@ -14,7 +14,7 @@ namespace hhlsv {
 // Grouped launches: one launch applies the same op to up to kMaxGroup states
 // of the same size, each with its own table (blockIdx.y selects the member).
 // A member's arithmetic does not depend on the group it runs in.
-constexpr int kMaxGroup = 16;
+constexpr int kMaxGroup = 64;
 struct Ptrs {
     unsigned long long a[kMaxGroup];   // per member: the state (or primary buffer)
     unsigned long long b[kMaxGroup];   // per member: the op's table (or secondary buffer)
@@ -140,6 +140,10 @@ sv_status launch_norm2_range(const void *psi, uint64_t lo, uint64_t hi, sv_dtype
 // member into its out[] through its partials[].
 sv_status launch_init_zero_group(const Group &g, int n, sv_dtype dtype, hipStream_t s);
 sv_status launch_norm2_group(const Group &g, uint64_t lo, uint64_t hi, sv_dtype dtype, hipStream_t s);
+// Postselection of every member (Sec. III-A step 3): out[i] is the member's
+// block [P(ancilla = 1), 0, y_0.re, y_0.im, ...] with y_s = psi[2^{n-1} + s]
+// for s < 2^ns, in double; partials[i] is its reduction scratch.
+sv_status launch_postselect_group(const Group &g, int n, int ns, sv_dtype dtype, hipStream_t s);
 sv_status launch_gather(const void *psi, const uint64_t *dev_idx, size_t count,
                         void *dev_out, sv_dtype dtype, hipStream_t s);
 

@@ -60,21 +60,6 @@ __global__ __launch_bounds__(256) void k_gather_outputs(const BInst *__restrict_
     }
 }
 
-// Postselected block of a large request: out = [P(anc=1) (already there), 0,
-// y_0.re, y_0.im, ...] with y_s = psi[2^{n-1} + s], widened to double.
-template <typename R>
-__global__ __launch_bounds__(256) void k_copy_y(Ptrs pp, uint64_t half, int D)
-{
-    const typename V2<R>::type *__restrict__ psi = member_ptr<const typename V2<R>::type>(pp.a);
-    double *__restrict__ out = member_ptr<double>(pp.b);
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < D; i += gridDim.x * blockDim.x) {
-        const auto y = psi[half + i];
-        out[2 + 2 * i] = (double)y.x;
-        out[3 + 2 * i] = (double)y.y;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) out[1] = 0.0;
-}
-
 // How a request runs: in a batched launch with its state in LDS, in a
 // batched launch with its state in HBM (one workgroup per request), or alone
 // through the whole-GPU sweep kernels.
@@ -504,11 +489,12 @@ bool same_ops(const std::vector<DevOp> &a, const std::vector<DevOp> &b)
 }
 
 constexpr size_t kOutMax = 2 + 2 * 4096;   // [p1, 0, y] doubles for up to 12 system qubits
+constexpr int kServeGroup = 16;             // requests per launcher group
 
 // One group of larger requests in flight on a launcher's stream.
 struct Flight {
     hipEvent_t done = nullptr;
-    double *h_out = nullptr;   // pinned, kMaxGroup * kOutMax doubles
+    double *h_out = nullptr;   // pinned, kServeGroup * kOutMax doubles
     std::vector<std::shared_ptr<Req>> reqs;
     bool busy = false;
 };
@@ -521,16 +507,12 @@ sv_status launch_group(svs *s, Flight &f, hipStream_t st)
     const Req &r0 = *f.reqs[0];
     Group g;
     g.count = (int)f.reqs.size();
-    Ptrs py;
-    std::memset(&py, 0, sizeof(py));
     for (int i = 0; i < g.count; ++i) {
         const Req &r = *f.reqs[i];
         g.psi[i] = r.state;
         g.dbuf[i] = static_cast<const unsigned char *>(r.prog.dbuf);
         g.partials[i] = r.partials;
         g.out[i] = r.out;
-        py.a[i] = reinterpret_cast<unsigned long long>(r.state);
-        py.b[i] = reinterpret_cast<unsigned long long>(r.out);
     }
     for (int i = 0; i < g.count; ++i)
         if (hipStreamWaitEvent(st, f.reqs[i]->uploaded, 0) != hipSuccess)
@@ -540,16 +522,9 @@ sv_status launch_group(svs *s, Flight &f, hipStream_t st)
         if (rc != SV_OK) return rc;
         rc = launch_op_group(op, g, r0.n, s->dtype, st);
     }
-    const uint64_t half = uint64_t(1) << (r0.n - 1);
-    if (rc == SV_OK) rc = launch_norm2_group(g, half, half << 1, s->dtype, st);
+    if (rc == SV_OK) rc = launch_postselect_group(g, r0.n, r0.ns, s->dtype, st);
     if (rc != SV_OK) return rc;
-    const int D = 1 << r0.ns;
-    const dim3 grid((D + 255) / 256, (unsigned)g.count);
-    if (s->dtype == SV_C128)
-        hipLaunchKernelGGL((k_copy_y<double>), grid, dim3(256), 0, st, py, half, D);
-    else
-        hipLaunchKernelGGL((k_copy_y<float>), grid, dim3(256), 0, st, py, half, D);
-    hipError_t e = hipGetLastError();
+    hipError_t e = hipSuccess;
     const size_t len = 2 + (2u << r0.ns);
     for (int i = 0; i < g.count && e == hipSuccess; ++i)
         e = hipMemcpyAsync(f.h_out + (size_t)i * kOutMax, f.reqs[i]->out, len * sizeof(double),
@@ -568,7 +543,7 @@ void launcher_main(svs *s)
     hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
     for (Flight &f : fl) {
         if (e == hipSuccess) e = hipEventCreateWithFlags(&f.done, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipHostMalloc((void **)&f.h_out, kMaxGroup * kOutMax * sizeof(double));
+        if (e == hipSuccess) e = hipHostMalloc((void **)&f.h_out, kServeGroup * kOutMax * sizeof(double));
     }
     const std::string setup_err = e == hipSuccess ? "" : std::string("svs: launcher setup: ") + hipGetErrorString(e);
     Dead dead;
@@ -618,12 +593,12 @@ void launcher_main(svs *s)
                 const Req &L = *s->alone_q[i];
                 if (std::find(collecting.begin(), collecting.end(), L.sig) != collecting.end()) continue;
                 mates.clear();
-                for (size_t j = i + 1; j < s->alone_q.size() && j <= i + 512 && (int)mates.size() + 1 < kMaxGroup;
+                for (size_t j = i + 1; j < s->alone_q.size() && j <= i + 512 && (int)mates.size() + 1 < kServeGroup;
                      ++j) {
                     const Req &r = *s->alone_q[j];
                     if (r.sig == L.sig && r.n == L.n && same_ops(r.ops, L.ops)) mates.push_back(j);
                 }
-                if (s->group_window > 0 && (int)mates.size() + 1 < kMaxGroup && !s->stopping) {
+                if (s->group_window > 0 && (int)mates.size() + 1 < kServeGroup && !s->stopping) {
                     const double left = L.t_ready + s->group_window - now_s();
                     if (left > 0) {
                         wake = std::min(wake, left);

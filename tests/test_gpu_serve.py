@@ -13,7 +13,7 @@ import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-# (ns, m): n = 7..19.  n <= 13 (complex128) runs batched with the state in
+# (ns, m): n = 7..19.  n <= 12 (complex128) runs batched with the state in
 # LDS, 14..17 batched with the state in HBM, 18 and 19 alone.
 MIX = [(2, 4), (3, 6), (6, 10), (4, 8), (2, 6), (5, 8), (3, 10), (6, 7), (4, 5), (5, 10), (3, 3), (6, 6),
        (7, 10), (8, 10)]
@@ -76,7 +76,7 @@ def test_serving_matches_oracle(dtype, hbm_batch):
     prof = srv.profile()
     _say(f"serve {dtype}: {st} {prof}")
     assert st["done"] == len(systems) and st["failed"] == 0 and st["p50_s"] <= st["p99_s"]
-    lds_limit = 13 if dtype == "c128" else 14
+    lds_limit = 12 if dtype == "c128" else 13    # states of up to 64 KiB run in LDS
     n_alone = sum(ns + m + 1 > (17 if hbm_batch else lds_limit) for ns, m in MIX)
     assert prof["alone"] == n_alone and prof["batched"] == len(systems) - n_alone
     srv.stop()
