@@ -47,6 +47,12 @@ class HHLInfo(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class PFInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int),
+                ("n_unknowns", ctypes.c_int), ("mismatch", ctypes.c_double),
+                ("history", ctypes.c_double * 64)]
+
+
 _lib = None
 
 
@@ -83,6 +89,13 @@ def lib():
                                         ctypes.POINTER(HHLInfo)]
         L.orc_hhl_system.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, dp,
                                      dp, ip]
+        L.orc_pf_eval.argtypes = [ctypes.c_int, ctypes.c_int, ip, ip, dp, dp, dp,
+                                  ip, dp, dp, dp, dp, dp, dp, dp, dp]
+        L.orc_pf_newton.argtypes = [ctypes.c_int, ctypes.c_int, ip, ip, dp, dp,
+                                    dp, ip, dp, dp, dp, ctypes.c_int,
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_double, dp, dp,
+                                    ctypes.POINTER(PFInfo)]
         _lib = L
     return _lib
 
@@ -208,3 +221,45 @@ def hhl_solve(A, b, m: int, t: float = 0.0, want_state: bool = True,
                                   _dp(x_hhl), _dp(x_hat), ctypes.byref(info)),
            "hhl_solve")
     return psi, x_hhl, x_hat, info.as_dict()
+
+
+def _pf_arrays(case):
+    i32 = lambda a: np.ascontiguousarray(a, dtype=np.int32)
+    f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+    return (i32(case["from"]), i32(case["to"]), f64(case["r"]), f64(case["x"]),
+            f64(case["bsh"]), i32(case["type"]), f64(case["p"]), f64(case["q"]),
+            f64(case["vset"]))
+
+
+def pf_eval(case, vm, va):
+    """(P, Q, F, J) of the power-flow model at magnitudes vm, angles va."""
+    fr, to, r, x, b, ty, p, q, vs = _pf_arrays(case)
+    nb, nbr = ty.size, fr.size
+    vm = np.ascontiguousarray(vm, dtype=np.float64)
+    va = np.ascontiguousarray(va, dtype=np.float64)
+    P, Q = np.zeros(nb), np.zeros(nb)
+    null = ctypes.POINTER(ctypes.c_double)()
+    N = _check(lib().orc_pf_eval(nb, nbr, _ip(fr), _ip(to), _dp(r), _dp(x), _dp(b), _ip(ty),
+                                 _dp(p), _dp(q), _dp(vm), _dp(va), _dp(P), _dp(Q), null, null),
+               "pf_eval")
+    F, J = np.zeros(N), np.zeros((N, N))
+    _check(lib().orc_pf_eval(nb, nbr, _ip(fr), _ip(to), _dp(r), _dp(x), _dp(b), _ip(ty),
+                             _dp(p), _dp(q), _dp(vm), _dp(va), _dp(P), _dp(Q), _dp(F), _dp(J)),
+           "pf_eval")
+    return P, Q, F, J
+
+
+def pf_newton(case, solver="ge", m=10, flags=HHL_DILATE, max_iter=30, tol=1e-10):
+    """Newton-Raphson power flow; solver "ge" (exact) or "hhl".
+    Returns (vm, va, info dict)."""
+    fr, to, r, x, b, ty, p, q, vs = _pf_arrays(case)
+    nb = ty.size
+    vm, va = np.zeros(nb), np.zeros(nb)
+    info = PFInfo()
+    _check(lib().orc_pf_newton(nb, fr.size, _ip(fr), _ip(to), _dp(r), _dp(x), _dp(b), _ip(ty),
+                               _dp(p), _dp(q), _dp(vs), 0 if solver == "ge" else 1, m, flags,
+                               max_iter, tol, _dp(vm), _dp(va), ctypes.byref(info)), "pf_newton")
+    d = {"iterations": info.iterations, "converged": bool(info.converged),
+         "n_unknowns": info.n_unknowns, "mismatch": info.mismatch,
+         "history": list(info.history[:min(info.iterations + 1, 64)])}
+    return vm, va, d

@@ -844,3 +844,230 @@ int orc_hhl_solve(const double *A, const double *b, int N, int m, double t,
 {
     return orc_hhl_solve_ex(A, b, N, m, t, 0, psi_out, x_hhl, x_hat, info);
 }
+
+/* ------------------------------------------------------------------------
+ * Newton-Raphson AC power flow (Sec. III), the application the paper's HHL
+ * serves: each iteration solves J dx = F for the Jacobian J of the power
+ * injections, either exactly (Gaussian elimination) or with HHL.
+ *
+ * Model: branch (f, t) with series impedance r + jx and total line charging
+ * b contributes y = 1 / (r + jx) to Y_ft = Y_tf -= y and y + jb/2 to Y_ff
+ * and Y_tt.  Bus i injects P_i = V_i sum_k V_k (G_ik cos d_ik + B_ik sin d_ik)
+ * and Q_i = V_i sum_k V_k (G_ik sin d_ik - B_ik cos d_ik), d_ik = a_i - a_k.
+ * Unknowns: the angle of every non-slack bus, then the magnitude of every
+ * PQ bus (bus order).  F = [P_spec - P; Q_spec - Q] over the same buses, and
+ * J = d[P; Q] / d[angles; magnitudes], so the update is x += J^{-1} F.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int nb;
+    double *G, *B;    /* nb x nb admittance (real, imaginary)            */
+    int *ang, *mag;   /* unknown index of bus i's angle / magnitude or -1 */
+    int N;            /* number of unknowns                              */
+} pf_model;
+
+static void pf_free(pf_model *md)
+{
+    free(md->G); free(md->B); free(md->ang); free(md->mag);
+}
+
+static int pf_build(int nb, int nbr, const int *from, const int *to,
+                    const double *r, const double *x, const double *bsh,
+                    const int *type, pf_model *md)
+{
+    memset(md, 0, sizeof(*md));
+    if (nb < 2 || nbr < 1)
+        return ORC_EINVAL;
+    md->nb = nb;
+    md->G = (double *)calloc((size_t)nb * nb, sizeof(double));
+    md->B = (double *)calloc((size_t)nb * nb, sizeof(double));
+    md->ang = (int *)malloc(sizeof(int) * nb);
+    md->mag = (int *)malloc(sizeof(int) * nb);
+    if (!md->G || !md->B || !md->ang || !md->mag) {
+        pf_free(md);
+        return ORC_ENOMEM;
+    }
+    int nslack = 0;
+    for (int i = 0; i < nb; ++i) {
+        if (type[i] < 0 || type[i] > 2) {
+            pf_free(md);
+            return ORC_EINVAL;
+        }
+        nslack += type[i] == 0;
+    }
+    if (nslack != 1) {
+        pf_free(md);
+        return ORC_EINVAL;
+    }
+    for (int e = 0; e < nbr; ++e) {
+        const int f = from[e], t = to[e];
+        const double den = r[e] * r[e] + x[e] * x[e];
+        if (f < 0 || t < 0 || f >= nb || t >= nb || f == t || !(den > 0.0)) {
+            pf_free(md);
+            return ORC_EINVAL;
+        }
+        const double g = r[e] / den, bs = -x[e] / den;   /* 1 / (r + jx) */
+        md->G[f * nb + t] -= g;  md->B[f * nb + t] -= bs;
+        md->G[t * nb + f] -= g;  md->B[t * nb + f] -= bs;
+        md->G[f * nb + f] += g;  md->B[f * nb + f] += bs + 0.5 * bsh[e];
+        md->G[t * nb + t] += g;  md->B[t * nb + t] += bs + 0.5 * bsh[e];
+    }
+    int N = 0;
+    for (int i = 0; i < nb; ++i)
+        md->ang[i] = type[i] != 0 ? N++ : -1;
+    for (int i = 0; i < nb; ++i)
+        md->mag[i] = type[i] == 2 ? N++ : -1;
+    md->N = N;
+    return ORC_OK;
+}
+
+/* Injections P, Q at every bus for magnitudes vm and angles va. */
+static void pf_injections(const pf_model *md, const double *vm,
+                          const double *va, double *P, double *Q)
+{
+    const int nb = md->nb;
+    for (int i = 0; i < nb; ++i) {
+        double p = 0.0, q = 0.0;
+        for (int k = 0; k < nb; ++k) {
+            const double g = md->G[i * nb + k], b = md->B[i * nb + k];
+            if (g == 0.0 && b == 0.0)
+                continue;
+            const double d = va[i] - va[k];
+            p += vm[k] * (g * cos(d) + b * sin(d));
+            q += vm[k] * (g * sin(d) - b * cos(d));
+        }
+        P[i] = vm[i] * p;
+        Q[i] = vm[i] * q;
+    }
+}
+
+/* F (N) and, if J != NULL, the Jacobian (N x N, row-major). */
+static void pf_eval(const pf_model *md, const double *vm, const double *va,
+                    const double *pspec, const double *qspec, double *P,
+                    double *Q, double *F, double *J)
+{
+    const int nb = md->nb, N = md->N;
+    pf_injections(md, vm, va, P, Q);
+    for (int i = 0; i < nb; ++i) {
+        if (md->ang[i] >= 0)
+            F[md->ang[i]] = pspec[i] - P[i];
+        if (md->mag[i] >= 0)
+            F[md->mag[i]] = qspec[i] - Q[i];
+    }
+    if (!J)
+        return;
+    memset(J, 0, sizeof(double) * (size_t)N * N);
+    for (int i = 0; i < nb; ++i) {
+        const int rp = md->ang[i], rq = md->mag[i];
+        if (rp < 0 && rq < 0)
+            continue;
+        for (int k = 0; k < nb; ++k) {
+            const double g = md->G[i * nb + k], b = md->B[i * nb + k];
+            const int ca = md->ang[k], cm = md->mag[k];
+            double dPa, dPm, dQa, dQm;   /* d/d angle_k, d/d magnitude_k */
+            if (k == i) {
+                dPa = -Q[i] - b * vm[i] * vm[i];
+                dPm = P[i] / vm[i] + g * vm[i];
+                dQa = P[i] - g * vm[i] * vm[i];
+                dQm = Q[i] / vm[i] - b * vm[i];
+            } else {
+                if (g == 0.0 && b == 0.0)
+                    continue;
+                const double d = va[i] - va[k];
+                const double c = cos(d), s = sin(d);
+                dPa = vm[i] * vm[k] * (g * s - b * c);
+                dPm = vm[i] * (g * c + b * s);
+                dQa = -vm[i] * vm[k] * (g * c + b * s);
+                dQm = vm[i] * (g * s - b * c);
+            }
+            if (rp >= 0 && ca >= 0) J[rp * N + ca] = dPa;
+            if (rp >= 0 && cm >= 0) J[rp * N + cm] = dPm;
+            if (rq >= 0 && ca >= 0) J[rq * N + ca] = dQa;
+            if (rq >= 0 && cm >= 0) J[rq * N + cm] = dQm;
+        }
+    }
+}
+
+int orc_pf_eval(int nb, int nbr, const int *from, const int *to,
+                const double *r, const double *x, const double *bsh,
+                const int *type, const double *pspec, const double *qspec,
+                const double *vm, const double *va, double *P, double *Q,
+                double *F, double *J)
+{
+    pf_model md;
+    int rc = pf_build(nb, nbr, from, to, r, x, bsh, type, &md);
+    if (rc < 0)
+        return rc;
+    double *Fl = F ? F : (double *)malloc(sizeof(double) * (size_t)(md.N + 1));
+    pf_eval(&md, vm, va, pspec, qspec, P, Q, Fl, J);
+    if (!F)
+        free(Fl);
+    rc = md.N;
+    pf_free(&md);
+    return rc;
+}
+
+int orc_pf_newton(int nb, int nbr, const int *from, const int *to,
+                  const double *r, const double *x, const double *bsh,
+                  const int *type, const double *pspec, const double *qspec,
+                  const double *vset, int solver, int m, int flags,
+                  int max_iter, double tol, double *vm, double *va,
+                  orc_pf_info *info)
+{
+    pf_model md;
+    int rc = pf_build(nb, nbr, from, to, r, x, bsh, type, &md);
+    if (rc < 0)
+        return rc;
+    const int N = md.N;
+    double *P = (double *)malloc(sizeof(double) * nb);
+    double *Q = (double *)malloc(sizeof(double) * nb);
+    double *F = (double *)malloc(sizeof(double) * N);
+    double *J = (double *)malloc(sizeof(double) * (size_t)N * N);
+    double *dx = (double *)malloc(sizeof(double) * N);
+    if (!P || !Q || !F || !J || !dx) {
+        free(P); free(Q); free(F); free(J); free(dx); pf_free(&md);
+        return ORC_ENOMEM;
+    }
+    /* flat start: set-point magnitudes at slack and PV buses, 1 elsewhere */
+    for (int i = 0; i < nb; ++i) {
+        vm[i] = type[i] == 2 ? 1.0 : vset[i];
+        va[i] = 0.0;
+    }
+    if (info)
+        memset(info, 0, sizeof(*info));
+    int it = 0, conv = 0;
+    double worst = 0.0;
+    for (;; ++it) {
+        pf_eval(&md, vm, va, pspec, qspec, P, Q, F, J);
+        worst = 0.0;
+        for (int i = 0; i < N; ++i)
+            worst = fmax(worst, fabs(F[i]));
+        if (info && it < ORC_PF_HISTORY)
+            info->history[it] = worst;
+        if (worst < tol) {
+            conv = 1;
+            break;
+        }
+        if (it >= max_iter)
+            break;
+        if (solver == 0)
+            rc = orc_ge_solve(J, F, N, dx);
+        else
+            rc = orc_hhl_solve_ex(J, F, N, m, 0.0, flags, NULL, dx, NULL, NULL);
+        if (rc < 0)
+            break;
+        for (int i = 0; i < nb; ++i) {
+            if (md.ang[i] >= 0)
+                va[i] += dx[md.ang[i]];
+            if (md.mag[i] >= 0)
+                vm[i] += dx[md.mag[i]];
+        }
+    }
+    if (info) {
+        info->iterations = it;
+        info->converged = conv;
+        info->mismatch = worst;
+        info->n_unknowns = N;
+    }
+    free(P); free(Q); free(F); free(J); free(dx); pf_free(&md);
+    return rc < 0 ? rc : ORC_OK;
+}

@@ -134,6 +134,41 @@ int orc_hhl_params_ex(const double *A, const double *b, int N, int m,
 int orc_hhl_system(const double *A, const double *b, int N, int flags,
                    double *H, double *b_hat, int *x_off);
 
+/* Newton-Raphson AC power flow (Sec. III).  Buses 0..nb-1 with type 0
+ * (slack, exactly one), 1 (PV) or 2 (PQ); branch e joins from[e] and to[e]
+ * with series impedance r[e] + j x[e] and total line charging bsh[e] (p.u.).
+ * pspec / qspec: net injected power (generation minus load); vset: the
+ * magnitude held at slack and PV buses.  Unknowns: angles of non-slack
+ * buses, then magnitudes of PQ buses, in bus order.
+ *
+ * orc_pf_eval: injections P, Q (nb each), the mismatch F (N, may be NULL) and
+ * the Jacobian dF/dx of the injections (N x N row-major, may be NULL) at
+ * (vm, va); returns N.
+ * orc_pf_newton: flat start, then x += J^{-1} F until max |F| < tol or
+ * max_iter iterations; solver 0 solves exactly (Gaussian elimination),
+ * solver 1 with orc_hhl_solve_ex(J, F, m clock qubits, automatic t, flags)
+ * (flags must include ORC_HHL_DILATE or ORC_HHL_GS: J is not symmetric). */
+#define ORC_PF_HISTORY 64
+typedef struct {
+    int iterations;     /* updates applied                               */
+    int converged;      /* max |F| < tol reached                          */
+    int n_unknowns;
+    double mismatch;    /* final max |F|                                  */
+    double history[ORC_PF_HISTORY];   /* max |F| before each update       */
+} orc_pf_info;
+
+int orc_pf_eval(int nb, int nbr, const int *from, const int *to,
+                const double *r, const double *x, const double *bsh,
+                const int *type, const double *pspec, const double *qspec,
+                const double *vm, const double *va, double *P, double *Q,
+                double *F, double *J);
+int orc_pf_newton(int nb, int nbr, const int *from, const int *to,
+                  const double *r, const double *x, const double *bsh,
+                  const int *type, const double *pspec, const double *qspec,
+                  const double *vset, int solver, int m, int flags,
+                  int max_iter, double tol, double *vm, double *va,
+                  orc_pf_info *info);
+
 #ifdef __cplusplus
 }
 #endif

@@ -480,3 +480,139 @@ def test_gauss_seidel_rejects_zero_diagonal():
     A = np.array([[0.0, 1.0], [1.0, 2.0]])
     with pytest.raises(RuntimeError):
         oracle.hhl_solve(A, np.ones(2), 5, flags=oracle.HHL_GS)
+
+
+# --------------------------------------------- Newton-Raphson power flow ---
+def _two_bus(P, Q, x):
+    return {"from": np.array([0], np.int32), "to": np.array([1], np.int32),
+            "r": np.array([0.0]), "x": np.array([x]), "bsh": np.array([0.0]),
+            "type": np.array([0, 2], np.int32), "p": np.array([0.0, -P]),
+            "q": np.array([0.0, -Q]), "vset": np.array([1.0, 1.0])}
+
+
+@pytest.mark.parametrize("P,Q,x", [(0.5, 0.2, 0.1), (1.2, 0.4, 0.2), (0.3, -0.1, 0.3)])
+def test_pf_two_bus_closed_form(P, Q, x):
+    """A load P + jQ fed over a lossless line jx from a 1.0 p.u. slack has
+    V^4 + (2Qx - 1) V^2 + x^2 (P^2 + Q^2) = 0 (high-voltage root) and
+    sin(-angle) = P x / V."""
+    vm, va, info = oracle.pf_newton(_two_bus(P, Q, x), "ge")
+    a = 1 - 2 * Q * x
+    v2 = math.sqrt((a + math.sqrt(a * a - 4 * x * x * (P * P + Q * Q))) / 2)
+    assert info["converged"]
+    assert abs(vm[1] - v2) < 1e-10 and vm[0] == 1.0
+    assert abs(va[1] + math.asin(P * x / v2)) < 1e-10
+
+
+@pytest.mark.parametrize("nb,seed", [(5, 0), (14, 1), (30, 2)])
+def test_pf_injections_are_complex_power(nb, seed):
+    """P + jQ from the oracle's polar formulas equals V * conj(Y V) with Y
+    assembled in complex numpy from the branch list."""
+    c = W.ac_powerflow_case(nb, seed)
+    rng = np.random.default_rng(seed)
+    vm = rng.uniform(0.9, 1.1, nb)
+    va = rng.uniform(-0.3, 0.3, nb)
+    P, Q, F, J = oracle.pf_eval(c, vm, va)
+    Y = np.zeros((nb, nb), dtype=complex)
+    for f, t, r, x, b in zip(c["from"], c["to"], c["r"], c["x"], c["bsh"]):
+        y = 1 / complex(r, x)
+        Y[f, f] += y + 0.5j * b
+        Y[t, t] += y + 0.5j * b
+        Y[f, t] -= y
+        Y[t, f] -= y
+    V = vm * np.exp(1j * va)
+    S = V * np.conj(Y @ V)
+    assert np.abs(P - S.real).max() < 1e-12
+    assert np.abs(Q - S.imag).max() < 1e-12
+
+
+@pytest.mark.parametrize("nb,seed", [(5, 3), (14, 4)])
+def test_pf_jacobian_is_derivative(nb, seed):
+    """The Jacobian equals central finite differences of the mismatch."""
+    c = W.ac_powerflow_case(nb, seed)
+    rng = np.random.default_rng(seed)
+    vm = rng.uniform(0.95, 1.05, nb)
+    va = rng.uniform(-0.2, 0.2, nb)
+    _, _, F0, J = oracle.pf_eval(c, vm, va)
+    ty = c["type"]
+    cols = [("a", i) for i in range(nb) if ty[i] != 0] + [("m", i) for i in range(nb) if ty[i] == 2]
+    h = 1e-6
+    for j, (kind, i) in enumerate(cols):
+        vp, vq, ap, aq = vm.copy(), vm.copy(), va.copy(), va.copy()
+        if kind == "a":
+            ap[i] += h
+            aq[i] -= h
+        else:
+            vp[i] += h
+            vq[i] -= h
+        Fp = oracle.pf_eval(c, vp, ap)[2]
+        Fq = oracle.pf_eval(c, vq, aq)[2]
+        # F = spec - injections, so dF/dx = -J
+        fd = -(Fp - Fq) / (2 * h)
+        assert np.abs(fd - J[:, j]).max() < 1e-7 * max(1.0, np.abs(J).max())
+
+
+@pytest.mark.parametrize("nb,seed", [(14, 0), (30, 1)])
+def test_pf_newton_quadratic_with_exact_solves(nb, seed):
+    c = W.ac_powerflow_case(nb, seed)
+    vm, va, info = oracle.pf_newton(c, "ge")
+    h = info["history"]
+    assert info["converged"] and info["mismatch"] < 1e-10
+    # quadratic: once close, each mismatch is at most C times the square of the last
+    tail = [(h[i], h[i + 1]) for i in range(len(h) - 1) if h[i] < 1e-2]
+    assert tail and all(b <= 50 * a * a + 1e-13 for a, b in tail)
+
+
+def test_pf_lossless_network_conserves_power():
+    """With no resistance and no line charging, the injections sum to zero."""
+    c = W.ac_powerflow_case(14, 5)
+    c["r"] = np.zeros_like(c["r"])
+    c["bsh"] = np.zeros_like(c["bsh"])
+    vm, va, info = oracle.pf_newton(c, "ge")
+    P, Q, F, J = oracle.pf_eval(c, vm, va)
+    assert info["converged"] and abs(P.sum()) < 1e-10
+
+
+@pytest.mark.parametrize("flags", [oracle.HHL_DILATE, oracle.HHL_GS])
+def test_pf_newton_with_hhl_reaches_the_exact_solution(flags):
+    """HHL as the inner solver (an inexact Newton step) converges to the
+    same operating point as exact solves."""
+    c = W.ac_powerflow_case(5, 0)
+    v0, a0, _ = oracle.pf_newton(c, "ge")
+    vm, va, info = oracle.pf_newton(c, "hhl", m=9, flags=flags, max_iter=30, tol=1e-9)
+    assert info["converged"]
+    assert np.abs(vm - v0).max() < 1e-8 and np.abs(va - a0).max() < 1e-8
+
+
+def test_pf_rejects_bad_cases():
+    c = _two_bus(0.5, 0.2, 0.1)
+    c2 = dict(c, type=np.array([0, 0], np.int32))
+    with pytest.raises(RuntimeError):
+        oracle.pf_newton(c2, "ge")
+    c3 = dict(c, x=np.array([0.0]))
+    with pytest.raises(RuntimeError):
+        oracle.pf_newton(c3, "ge")
+
+
+@pytest.mark.parametrize("nb,seed", [(14, 6), (30, 7)])
+def test_pf_solution_meets_the_specification(nb, seed):
+    """At the converged point, checked with complex numpy arithmetic: |V| is
+    the set point at slack and PV buses, P matches at every non-slack bus and
+    Q at every PQ bus."""
+    c = W.ac_powerflow_case(nb, seed, pv_frac=0.4)
+    vm, va, info = oracle.pf_newton(c, "ge")
+    assert info["converged"]
+    Y = np.zeros((nb, nb), dtype=complex)
+    for f, t, r, x, b in zip(c["from"], c["to"], c["r"], c["x"], c["bsh"]):
+        y = 1 / complex(r, x)
+        Y[f, f] += y + 0.5j * b
+        Y[t, t] += y + 0.5j * b
+        Y[f, t] -= y
+        Y[t, f] -= y
+    V = vm * np.exp(1j * va)
+    S = V * np.conj(Y @ V)
+    ty = c["type"]
+    assert (ty == 1).any()
+    assert np.abs(vm[ty != 2] - c["vset"][ty != 2]).max() < 1e-15
+    assert abs(va[ty == 0][0]) < 1e-15
+    assert np.abs(S.real[ty != 0] - c["p"][ty != 0]).max() < 1e-9
+    assert np.abs(S.imag[ty == 2] - c["q"][ty == 2]).max() < 1e-9

@@ -38,7 +38,7 @@ __all__ = [
     "random_state", "random_circuit", "wide_gate_circuit", "batch_specs",
     "serve_specs", "exact_spectrum_system", "split_register_circuit",
     "flatten_circuit", "TWO_PI", "signed_spectrum_system",
-    "nonsymmetric_exact_system", "general_system",
+    "nonsymmetric_exact_system", "general_system", "ac_powerflow_case",
 ]
 
 TWO_PI = 2.0 * math.pi
@@ -120,6 +120,57 @@ def exact_spectrum_system(ns: int, m: int, seed: int, k_lo: int | None = None,
     b = rng.standard_normal(dim)
     t = TWO_PI / ((1 << m) * delta)
     return A, b, t, k
+
+
+def ac_powerflow_case(n_bus: int, seed: int, extra_frac: float = 0.3,
+                      pv_frac: float = 0.2):
+    """Seeded synthetic AC power-flow case (stands in for the IEEE cases).
+
+    Network: a random spanning tree plus ``round(extra_frac * (n_bus - 1))``
+    extra branches, as in ``dc_powerflow``.  Branch reactance x ~ U[0.05,
+    0.25] p.u., resistance r = x * U[0.1, 0.3], total line charging
+    b ~ U[0, 0.04].  Bus 0 is the slack (|V| = 1.02); about ``pv_frac`` of
+    the others are PV buses (|V| ~ U[0.99, 1.04], generation ~ U[0.1, 0.4]);
+    every non-slack bus carries a load P ~ U[0.02, 0.12], Q ~ U[0.01, 0.05].
+    Returns a dict of arrays: from, to, r, x, bsh, type (0 slack, 1 PV,
+    2 PQ), p, q (net injections), vset.
+    """
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(n_bus)
+    edges = set()
+    for i in range(1, n_bus):
+        j = int(rng.integers(0, i))
+        a, b = int(perm[i]), int(perm[j])
+        edges.add((min(a, b), max(a, b)))
+    n_extra = int(round(extra_frac * (n_bus - 1)))
+    tries = 0
+    while n_extra > 0 and tries < 100 * n_bus:
+        tries += 1
+        a, b = (int(v) for v in rng.integers(0, n_bus, size=2))
+        if a == b or (min(a, b), max(a, b)) in edges:
+            continue
+        edges.add((min(a, b), max(a, b)))
+        n_extra -= 1
+    edges = sorted(edges)
+    fr = np.array([e[0] for e in edges], dtype=np.int32)
+    to = np.array([e[1] for e in edges], dtype=np.int32)
+    x = rng.uniform(0.05, 0.25, size=len(edges))
+    r = x * rng.uniform(0.1, 0.3, size=len(edges))
+    bsh = rng.uniform(0.0, 0.04, size=len(edges))
+    typ = np.full(n_bus, 2, dtype=np.int32)
+    typ[0] = 0
+    vset = np.ones(n_bus)
+    vset[0] = 1.02
+    pv = rng.uniform(size=n_bus) < pv_frac
+    pv[0] = False
+    typ[pv] = 1
+    vset[pv] = rng.uniform(0.99, 1.04, size=int(pv.sum()))
+    p = -rng.uniform(0.02, 0.12, size=n_bus)
+    q = -rng.uniform(0.01, 0.05, size=n_bus)
+    p[pv] += rng.uniform(0.1, 0.4, size=int(pv.sum()))
+    p[0] = q[0] = 0.0
+    return {"from": fr, "to": to, "r": r, "x": x, "bsh": bsh, "type": typ,
+            "p": p, "q": q, "vset": vset}
 
 
 def _orthogonal(dim: int, rng: np.random.Generator) -> np.ndarray:
