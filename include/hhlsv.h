@@ -392,6 +392,58 @@ const char *sv_last_error(void);
 sv_status sv_qubit_estimate(int dim, double kappa, int has_negative,
                             int *n_data, int *n_qpe, int *n_total);
 
+/* ---- Newton-Raphson AC power flow ------------------------------------- */
+/* The power-flow use case of Sec. III: Newton-Raphson on the polar AC
+ * power-flow equations with HHL as the linear solver of every iteration.
+ *
+ * Case (all arrays caller-owned, read only): buses 0..n_bus-1 with
+ * bus_type 0 (slack, exactly one), 1 (PV) or 2 (PQ); branch e joins from[e]
+ * and to[e] with series impedance r[e] + j x[e] and total line charging
+ * b_charging[e] (per unit); p_spec / q_spec: net injected power (generation
+ * minus load); v_set: the voltage magnitude held at slack and PV buses.
+ * Unknowns: the angles of the non-slack buses, then the magnitudes of the
+ * PQ buses, in bus order (n_unknowns of them).
+ *
+ * pf_mismatch_jacobian (host only): at magnitudes vm and angles va (n_bus
+ * each), the injections P, Q (n_bus), the mismatch F = [p_spec - P;
+ * q_spec - Q] over the unknowns' buses (n_unknowns) and the Jacobian
+ * d[P; Q]/d[angles; magnitudes] (n_unknowns^2, row-major); any output may be
+ * NULL.  SV_ERR_INVALID on a malformed case.
+ *
+ * pf_newton_hhl: flat start, then for at most max_iter iterations builds the
+ * HHL circuit of J dx = F (circuit_build_hhl_ex with clock_bits, automatic t
+ * and hhl_flags: SV_HHL_DILATE, SV_HHL_GAUSS_SEIDEL or SV_HHL_AUTO, plus
+ * optionally SV_HHL_DEVICE_EVOLUTIONS; with none of the first three,
+ * SV_HHL_DILATE), fuses it to k_max (0: unfused), runs it on the GPU at
+ * dtype, takes dx = info.scale * x_hat from sv_postselect_solution and
+ * updates; stops when max |F| < tol.  vm, va (n_bus) receive the operating
+ * point; *info (may be NULL) the iteration record.  Errors from the HHL
+ * calls are returned as they are. */
+#define PF_HISTORY 64
+typedef struct {
+    int iterations;     /* updates applied                                */
+    int converged;      /* max |F| < tol reached                           */
+    int n_unknowns;
+    double mismatch;    /* final max |F|                                   */
+    double hhl_seconds; /* host wall time spent in the HHL solves          */
+    double history[PF_HISTORY];   /* max |F| before each update            */
+} pf_info;
+
+sv_status pf_mismatch_jacobian(int n_bus, int n_branch, const int *from,
+                               const int *to, const double *r,
+                               const double *x, const double *b_charging,
+                               const int *bus_type, const double *p_spec,
+                               const double *q_spec, const double *vm,
+                               const double *va, double *P, double *Q,
+                               double *F, double *J, int *n_unknowns);
+sv_status pf_newton_hhl(int n_bus, int n_branch, const int *from,
+                        const int *to, const double *r, const double *x,
+                        const double *b_charging, const int *bus_type,
+                        const double *p_spec, const double *q_spec,
+                        const double *v_set, int clock_bits, int hhl_flags,
+                        sv_dtype dtype, int k_max, int max_iter, double tol,
+                        double *vm, double *va, pf_info *info);
+
 #ifdef __cplusplus
 }
 #endif

@@ -61,6 +61,12 @@ class HHLInfo(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class PFInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int),
+                ("n_unknowns", ctypes.c_int), ("mismatch", ctypes.c_double),
+                ("hhl_seconds", ctypes.c_double), ("history", ctypes.c_double * 64)]
+
+
 class SolutionInfo(ctypes.Structure):
     _fields_ = [("scale", ctypes.c_double), ("p_anc1", ctypes.c_double),
                 ("p_anc1_clock0", ctypes.c_double), ("max_imag", ctypes.c_double),
@@ -108,6 +114,10 @@ _proto("sv_synchronize", _vp)
 _proto("sv_postselect_solution", _vp, _vp, _dp, ctypes.c_int, ctypes.POINTER(SolutionInfo))
 _proto("circuit_destroy", _vp)
 _proto("sv_qubit_estimate", ctypes.c_int, ctypes.c_double, ctypes.c_int, _ip, _ip, _ip)
+_proto("pf_mismatch_jacobian", ctypes.c_int, ctypes.c_int, _ip, _ip, _dp, _dp, _dp, _ip, _dp, _dp, _dp, _dp,
+       _dp, _dp, _dp, _dp, _ip)
+_proto("pf_newton_hhl", ctypes.c_int, ctypes.c_int, _ip, _ip, _dp, _dp, _dp, _ip, _dp, _dp, _dp, ctypes.c_int,
+       ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, ctypes.POINTER(PFInfo))
 _proto("svb_create", ctypes.c_int, ctypes.c_int, _vp, ctypes.POINTER(_vp))
 _proto("svb_add", _vp, _vp, _ip)
 _proto("svb_run", _vp)
@@ -510,3 +520,51 @@ class Server:
 
     def __del__(self):
         self.stop()
+
+
+# ---------------------------------------------------------------- power flow
+def _pf_arrays(case):
+    i32 = lambda a: np.ascontiguousarray(a, dtype=np.int32)
+    f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+    return (i32(case["from"]), i32(case["to"]), f64(case["r"]), f64(case["x"]), f64(case["bsh"]),
+            i32(case["type"]), f64(case["p"]), f64(case["q"]), f64(case["vset"]))
+
+
+def _iptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def pf_mismatch_jacobian(case, vm, va):
+    """(P, Q, F, J) of the AC power-flow model at magnitudes vm, angles va."""
+    fr, to, r, x, b, ty, p, q, vs = _pf_arrays(case)
+    nb = ty.size
+    vm = np.ascontiguousarray(vm, dtype=np.float64)
+    va = np.ascontiguousarray(va, dtype=np.float64)
+    nu = ctypes.c_int()
+    _check(_lib.pf_mismatch_jacobian(nb, fr.size, _iptr(fr), _iptr(to), _dptr(r), _dptr(x), _dptr(b),
+                                     _iptr(ty), None, None, None, None, None, None, None, None,
+                                     ctypes.byref(nu)), "pf_mismatch_jacobian")
+    N = nu.value
+    P, Q, F, J = np.zeros(nb), np.zeros(nb), np.zeros(N), np.zeros((N, N))
+    _check(_lib.pf_mismatch_jacobian(nb, fr.size, _iptr(fr), _iptr(to), _dptr(r), _dptr(x), _dptr(b),
+                                     _iptr(ty), _dptr(p), _dptr(q), _dptr(vm), _dptr(va), _dptr(P), _dptr(Q),
+                                     _dptr(F), _dptr(J), None), "pf_mismatch_jacobian")
+    return P, Q, F, J
+
+
+def pf_newton(case, clock_bits: int, mode: str = "dilate", dtype="c128", k_max: int = 3,
+              max_iter: int = 30, tol: float = 1e-9, device_evolutions: bool = False):
+    """Newton-Raphson AC power flow with HHL inner solves on the GPU.
+    mode: "dilate", "gauss_seidel" or "auto".  Returns (vm, va, info dict)."""
+    fr, to, r, x, b, ty, p, q, vs = _pf_arrays(case)
+    nb = ty.size
+    vm, va = np.zeros(nb), np.zeros(nb)
+    flags = _hhl_flags(mode) | (SV_HHL_DEVICE_EVOLUTIONS if device_evolutions else 0)
+    info = PFInfo()
+    _check(_lib.pf_newton_hhl(nb, fr.size, _iptr(fr), _iptr(to), _dptr(r), _dptr(x), _dptr(b), _iptr(ty),
+                              _dptr(p), _dptr(q), _dptr(vs), clock_bits, flags, DTYPES[dtype], k_max, max_iter,
+                              float(tol), _dptr(vm), _dptr(va), ctypes.byref(info)), "pf_newton_hhl")
+    d = {"iterations": info.iterations, "converged": bool(info.converged), "n_unknowns": info.n_unknowns,
+         "mismatch": info.mismatch, "hhl_seconds": info.hhl_seconds,
+         "history": list(info.history[:min(info.iterations + 1, 64)])}
+    return vm, va, d

@@ -15,7 +15,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhhlsv.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-CXX_SOURCES = ["circuit.cpp", "hhl_build.cpp"]
+CXX_SOURCES = ["circuit.cpp", "hhl_build.cpp", "powerflow.cpp"]
 HIP_SOURCES = ["kernels.hip", "state.hip", "batch.hip", "serve.hip"]
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -384,3 +384,33 @@ def test_signed_dilated_errors():
     Ac = np.ascontiguousarray(A)
     rc = hs._lib.circuit_build_hhl_ex(hs._dptr(Ac), hs._dptr(b), b.size, 5, 0.0, 64, hs.ctypes.byref(h))
     assert rc == -1
+
+
+# ------------------------------------------------- Newton-Raphson power flow ---
+@pytest.mark.parametrize("nb,seed", [(5, 0), (14, 1), (30, 2)])
+def test_pf_model_matches_oracle(nb, seed):
+    """The library's complex-form injections, mismatch and Jacobian equal the
+    oracle's polar-form ones at a random operating point."""
+    c = W.ac_powerflow_case(nb, seed, pv_frac=0.3)
+    rng = np.random.default_rng(seed)
+    vm = rng.uniform(0.9, 1.1, nb)
+    va = rng.uniform(-0.3, 0.3, nb)
+    P, Q, F, J = hs.pf_mismatch_jacobian(c, vm, va)
+    Po, Qo, Fo, Jo = oracle.pf_eval(c, vm, va)
+    scale = max(1.0, np.abs(Jo).max())
+    assert np.abs(P - Po).max() < 1e-12 * scale and np.abs(Q - Qo).max() < 1e-12 * scale
+    assert np.abs(F - Fo).max() < 1e-12 * scale
+    assert J.shape == Jo.shape and np.abs(J - Jo).max() < 1e-12 * scale
+
+
+def test_pf_validation():
+    c = W.ac_powerflow_case(5, 0)
+    bad = dict(c, type=np.zeros(5, np.int32))
+    with pytest.raises(hs.HHLSVError, match="INVALID"):
+        hs.pf_mismatch_jacobian(bad, np.ones(5), np.zeros(5))
+    bad = dict(c, x=np.zeros_like(c["x"]), r=np.zeros_like(c["r"]))
+    with pytest.raises(hs.HHLSVError, match="INVALID"):
+        hs.pf_mismatch_jacobian(bad, np.ones(5), np.zeros(5))
+    bad = dict(c, to=np.array(c["from"]))
+    with pytest.raises(hs.HHLSVError, match="INVALID"):
+        hs.pf_mismatch_jacobian(bad, np.ones(5), np.zeros(5))
