@@ -223,6 +223,26 @@ def hhl_serve(hs, W, seconds, rate=2000.0, pool_per_size=48):
     return out
 
 
+def pf_newton_leg(hs, W):
+    """Newton-Raphson AC power flow with HHL inner solves on synthetic 14- and
+    30-bus cases (dilated Jacobian systems, 9 clock qubits)."""
+    import numpy as np
+
+    out = {}
+    for nb, seed in ((14, 0), (30, 3)):
+        case = W.ac_powerflow_case(nb, seed)
+        t0 = time.perf_counter()
+        vm, va, info = hs.pf_newton(case, 9, mode="dilate", k_max=3, max_iter=40, tol=1e-9,
+                                    device_evolutions=True)
+        wall = time.perf_counter() - t0
+        out[f"{nb}_bus"] = {"unknowns": info["n_unknowns"], "iterations": info["iterations"],
+                            "converged": info["converged"], "final_mismatch": info["mismatch"],
+                            "wall_s": round(wall, 4), "hhl_s": round(info["hhl_seconds"], 4),
+                            "min_voltage": round(float(np.min(vm)), 6)}
+        log(f"[bench] power flow {nb}-bus: {out[f'{nb}_bus']}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -237,7 +257,7 @@ def main():
                     help="skip the per-sweep rates at the other fusion widths")
     ap.add_argument("--k-sweep-layers", type=int, default=10,
                     help="layers of the circuit used for the per-k sweep rates")
-    ap.add_argument("--part", choices=["all", "single", "batch", "serve"], default="all",
+    ap.add_argument("--part", choices=["all", "single", "batch", "serve", "powerflow"], default="all",
                     help="run one HHL leg alone (for profiling); prints that leg's JSON, not the bench line")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the Poisson arrival window (the full schedule is 60 s)")
@@ -254,7 +274,8 @@ def main():
 
     if args.part != "all":
         leg = {"single": lambda: hhl_single(hs, W), "batch": lambda: hhl_batch(hs, W),
-               "serve": lambda: hhl_serve(hs, W, args.serve_seconds)}[args.part]
+               "serve": lambda: hhl_serve(hs, W, args.serve_seconds),
+               "powerflow": lambda: pf_newton_leg(hs, W)}[args.part]
         print(json.dumps({"part": args.part, "result": leg()}), flush=True)
         return
 
@@ -367,6 +388,8 @@ def main():
         hhl["batch_8192"] = hhl_batch(hs, W)
         log(f"[bench] HHL: serving, {args.serve_seconds:.0f} s of arrivals at 2000/s")
         hhl["serve"] = hhl_serve(hs, W, args.serve_seconds)
+        log("[bench] HHL: Newton-Raphson AC power flow")
+        hhl["power_flow_newton"] = pf_newton_leg(hs, W)
         out["hhl"] = hhl
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host (bounded sample)")
