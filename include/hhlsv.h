@@ -245,8 +245,11 @@ sv_status sv_apply(sv_state *s, const sv_circuit *c);
 
 /* Kernel families reported by sv_apply_timed. */
 typedef enum {
-    SV_KERNEL_DENSE_DIRECT = 0, /* dense k <= 5, all targets >= 6: in registers */
-    SV_KERNEL_DENSE_LDS = 1,    /* dense k <= 5, some target < 6: LDS regroup  */
+    SV_KERNEL_DENSE_DIRECT = 0, /* dense k <= 5, no target inside a 128-byte
+                                   line (all >= 3 at c128, >= 4 at c64):
+                                   groups held in registers              */
+    SV_KERNEL_DENSE_LDS = 1,    /* dense k <= 5, some target inside a line:
+                                   LDS regroup                           */
     SV_KERNEL_DENSE_SMALL = 2,  /* dense k <= 5 on a state of < 6 + k qubits   */
     SV_KERNEL_DIAG = 3,         /* diagonal gate                                */
     SV_KERNEL_WIDE = 4,         /* dense gate on 6..12 targets, optional control */

@@ -28,16 +28,20 @@ namespace {
 // ---------------------------------------------------------------------------
 // Dense k-qubit gate, tiled for 64-lane waves (n >= 6 + k).
 //
-// A wave owns a tile of 64 * 2^k amplitudes: the six lowest index bits vary
-// across lanes (so every load instruction reads 64 consecutive amplitudes)
-// and k "register bits" vary across each lane's 2^k registers.
-//  - direct path (no target below bit 6): the register bits are the targets,
-//    so each lane already holds one whole group and multiplies it in
-//    registers;
-//  - LDS path (some targets below bit 6): the register bits are the high
-//    targets plus as many extra non-target bits as there are low targets.
-//    The tile goes through LDS once to regroup it so that each lane holds one
-//    group, then back.  Reads and writes to HBM stay fully coalesced.
+// A wave owns a tile of 64 * 2^k amplitudes: six index bits vary across
+// lanes and k "register bits" vary across each lane's 2^k registers.
+//  - direct path (no target inside a 128-byte cache line, i.e. no target
+//    below bit 3 at complex128, bit 4 at complex64): the register bits are
+//    the targets and the lane bits are the six lowest non-target bits, so
+//    each lane already holds one whole group and multiplies it in registers.
+//    With every target >= 6 a load instruction reads 64 consecutive
+//    amplitudes; a target in bits 3..5 splits it into runs of whole cache
+//    lines, so HBM sees the same full-line traffic;
+//  - LDS path (some target inside a cache line): the lanes take the six
+//    lowest index bits and the register bits are the targets >= 6 plus as
+//    many extra non-target bits as there are targets < 6.  The tile goes
+//    through LDS once to regroup it so that each lane holds one group, then
+//    back.  Reads and writes to HBM stay fully coalesced.
 // The matrix is uniform across the wave and is read through scalar loads.
 // ---------------------------------------------------------------------------
 struct TileArgs {
@@ -55,17 +59,37 @@ __device__ __forceinline__ uint64_t tile_base(uint64_t w, const int *rpos, int k
     return b;
 }
 
+// The tiles one wave visits: w, w + step, ... below end.  Workgroups go to
+// the eight XCDs round robin (workgroup i to XCD i mod 8).  When both counts
+// allow it, the workgroups of one XCD walk one contiguous eighth of the tiles,
+// so each XCD's L2 and the HBM pages it opens serve one region of the state;
+// this measured 1-3% faster than a grid-wide stride on whole-HBM sweeps.
+struct WaveRange {
+    uint64_t w, end, step;
+};
+__device__ __forceinline__ WaveRange wave_range(uint64_t ntiles, unsigned waves_per_block)
+{
+    const uint64_t wib = threadIdx.x >> 6;
+    if ((gridDim.x & 7) == 0 && (ntiles & 7) == 0) {
+        const uint64_t per = ntiles >> 3, xcd = blockIdx.x & 7;
+        return {xcd * per + (uint64_t)(blockIdx.x >> 3) * waves_per_block + wib, (xcd + 1) * per,
+                (uint64_t)(gridDim.x >> 3) * waves_per_block};
+    }
+    return {(uint64_t)blockIdx.x * waves_per_block + wib, ntiles, (uint64_t)gridDim.x * waves_per_block};
+}
+
 template <typename R, int K>
 __device__ __forceinline__ void k_dense_direct_body(typename V2<R>::type *__restrict__ psi,
                                                  const typename V2<R>::type *__restrict__ mat, const TileArgs &a)
 {
     typedef typename V2<R>::type C;
     constexpr int NR = 1 << K;
-    const int lane = threadIdx.x & 63;
-    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
-    for (uint64_t w = wave; w < a.ntiles; w += nwaves) {
-        const uint64_t base = tile_base(w, a.rpos, K) + lane;
+    // lane bits: the six lowest non-target index bits
+    uint64_t loff = threadIdx.x & 63;
+    for (int j = 0; j < K; ++j) loff = insert_zero(loff, a.rpos[j]);
+    const WaveRange wr = wave_range(a.ntiles, 4);
+    for (uint64_t w = wr.w; w < wr.end; w += wr.step) {
+        const uint64_t base = tile_base(w, a.rpos, K) + loff;
         const C *m = opaque(mat);
         C v[NR];
 #pragma unroll
@@ -109,7 +133,8 @@ __device__ __forceinline__ void k_dense_lds_body(typename V2<R>::type *__restric
     __shared__ C tile[NR * 65];
     const int lane = threadIdx.x;
     const int sg = a.slot_g[lane];
-    for (uint64_t w = blockIdx.x; w < a.ntiles; w += gridDim.x) {
+    const WaveRange wr = wave_range(a.ntiles, 1);
+    for (uint64_t w = wr.w; w < wr.end; w += wr.step) {
         const uint64_t base = tile_base(w, a.rpos, K) + lane;
         C v[NR];
 #pragma unroll
@@ -632,12 +657,18 @@ sv_status launch_dense_t(const DevOp &op, const Group &g, int n, hipStream_t st,
         TileArgs a;
         std::memset(&a, 0, sizeof(a));
         a.ntiles = uint64_t(1) << (n - 6 - k);
-        int nlo = 0;
-        for (int j = 0; j < k; ++j) nlo += op.q[j] < 6;
-        // register bits: high targets plus nlo extra non-target bits >= 6
+        // a target below this bit lies inside a 128-byte cache line
+        constexpr int line_bits = sizeof(R) == 8 ? 3 : 4;
+        int nlo = 0, nsub = 0;
+        for (int j = 0; j < k; ++j) {
+            nlo += op.q[j] < 6;
+            nsub += op.q[j] < line_bits;
+        }
+        if (nsub == 0) nlo = 0;  // direct path: the register bits are the targets
+        // register bits: targets kept in registers plus nlo extra non-target bits >= 6
         std::vector<int> rp;
         for (int j = 0; j < k; ++j)
-            if (op.q[j] >= 6) rp.push_back(op.q[j]);
+            if (nlo == 0 || op.q[j] >= 6) rp.push_back(op.q[j]);
         std::vector<int> extra;
         for (int b = 6; (int)extra.size() < nlo && b < n; ++b)
             if (std::find(op.q, op.q + k, b) == op.q + k) extra.push_back(b);
@@ -653,7 +684,7 @@ sv_status launch_dense_t(const DevOp &op, const Group &g, int n, hipStream_t st,
         auto regbit = [&](int pos) { return (int)(std::find(rp.begin(), rp.end(), pos) - rp.begin()); };
         if (nlo == 0) {
             *family = SV_KERNEL_DENSE_DIRECT;
-            const unsigned grid = grid_for(a.ntiles, 4, 8192);
+            const unsigned grid = grid_for(a.ntiles, 4, 32768);
             switch (k) {
             case 1: launch2(&k_dense_direct<R, 1>, &k_dense_direct_g<R, 1>, grid, 256, 0, st, pp, cnt, a); break;
             case 2: launch2(&k_dense_direct<R, 2>, &k_dense_direct_g<R, 2>, grid, 256, 0, st, pp, cnt, a); break;

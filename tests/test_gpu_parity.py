@@ -63,6 +63,11 @@ def _targets(pattern, k, n, rng):
         return list(range(q0, q0 + k))
     if pattern == "spread":
         return sorted(set(np.linspace(0, n - 1, k).astype(int).tolist()))
+    if pattern == "midline":
+        # targets in bits 3..5 (inside a lane run, outside a cache line)
+        lo = rng.choice(np.arange(3, 6), size=min(3, max(1, k // 2)), replace=False).tolist()
+        hi = rng.choice(np.arange(6, n), size=k - len(lo), replace=False).tolist()
+        return sorted(lo + hi)
     # mixed: at least one low and one high
     lo = rng.choice(6, size=max(1, k // 2), replace=False).tolist()
     hi = rng.choice(np.arange(6, n), size=k - len(lo), replace=False).tolist()
@@ -70,7 +75,7 @@ def _targets(pattern, k, n, rng):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("pattern", ["low", "high", "mixed", "adjacent", "spread"])
+@pytest.mark.parametrize("pattern", ["low", "high", "mixed", "adjacent", "spread", "midline"])
 @pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("n", [12, 15])
 def test_dense_gate_target_patterns(n, k, pattern, dtype):
@@ -88,6 +93,38 @@ def test_dense_gate_target_patterns(n, k, pattern, dtype):
     psi0 = W.random_state(n, int(rng.integers(1 << 30)))
     want = oracle.apply_circuit(psi0, n, [g])
     got = run_gpu(n, [g], psi0, dtype)
+    assert np.max(np.abs(got - want)) <= TOL[dtype]
+
+
+# (targets, family at complex128, family at complex64): the register path
+# takes every gate with no target inside a 128-byte cache line (bits < 3 at
+# complex128, < 4 at complex64), the LDS regroup the rest.
+FAMILY_CASES = [((8, 11), "dense_direct", "dense_direct"),
+                ((3, 9, 14), "dense_direct", "dense_lds"),
+                ((4, 5, 7, 13), "dense_direct", "dense_direct"),
+                ((2, 6), "dense_lds", "dense_lds"),
+                ((0, 1, 2, 3, 4), "dense_lds", "dense_lds")]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("case", range(len(FAMILY_CASES)))
+def test_dense_family_choice(case, dtype):
+    hs = _hs()
+    qs, fam128, fam64 = FAMILY_CASES[case]
+    n = 15
+    rng = np.random.default_rng(77 + case)
+    U = W.random_unitary(1 << len(qs), rng)
+    g = W.Gate("dense", tuple(qs), np.ascontiguousarray(U).view(np.float64).ravel())
+    _say(f"family n={n} targets={qs} dtype={dtype}")
+    c = hs.circuit_from_gates(n, [g])
+    psi0 = W.random_state(n, 5 + case)
+    s = hs.sv_create(n, dtype)
+    s.set(psi0)
+    _, fam = s.apply_timed(c)
+    got = s.get()
+    s.close()
+    assert hs.KERNEL_FAMILY[int(fam[0])] == (fam128 if dtype == "c128" else fam64)
+    want = oracle.apply_circuit(psi0, n, [g])
     assert np.max(np.abs(got - want)) <= TOL[dtype]
 
 
