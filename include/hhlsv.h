@@ -348,15 +348,22 @@ enum {
                                   allocation fails as out of memory (0 = off)  */
     SVS_OPT_BATCH_MAX_QUBITS = 7, /* also batch requests of up to this many
                                   qubits with the state in HBM (default 0:
-                                  batch only states that fit in LDS)          */
+                                  none)                                       */
     SVS_OPT_HHL_FLAGS = 8,     /* SV_HHL_SIGNED | _DILATE | _AUTO |
                                   _GAUSS_SEIDEL for every request's circuit
                                   (default 0)                                 */
     SVS_OPT_LAUNCHERS = 9,     /* threads (each with its own stream) that
                                   launch the requests not batched (default 4) */
-    SVS_OPT_GROUP_WINDOW_US = 10 /* microseconds a request not batched may
+    SVS_OPT_GROUP_WINDOW_US = 10, /* microseconds a request not batched may
                                   wait for others of its shape to share its
                                   launches (default 0: launch at once)        */
+    SVS_OPT_LDS_MAX_QUBITS = 11 /* batch a request with its state in LDS only
+                                  up to this many qubits, if its state fits
+                                  (-1: every state that fits, n <= 12 at
+                                  complex128, n <= 13 at complex64; default 0:
+                                  none, every request runs on the grouped
+                                  whole-GPU sweeps, which gave the lower
+                                  latency under load)                         */
 };
 sv_status svs_start(size_t hbm_budget_bytes, int max_slots, sv_dtype dtype,
                     svs **out);

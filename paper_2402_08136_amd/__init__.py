@@ -449,7 +449,7 @@ def svb_autotune(dtype, sample: Circuit, copies: int = 64):
 # ------------------------------------------------------------------- serving
 SVS_OPT = {"prep_threads": 1, "k_max": 2, "max_batch": 3, "streams": 4, "queue_limit": 5,
            "fail_alloc_at": 6, "batch_max_qubits": 7, "hhl_flags": 8, "launchers": 9,
-           "group_window_us": 10}
+           "group_window_us": 10, "lds_max_qubits": 11}
 
 
 class Server:

@@ -16,14 +16,19 @@ __device__ __forceinline__ T ld_nt(const T *p) { return __builtin_nontemporal_lo
 template <typename T>
 __device__ __forceinline__ void st_nt(T v, T *p) { __builtin_nontemporal_store(v, p); }
 
+// Fused multiply-add in the operands' own precision (__builtin_fma is the
+// double one: on float operands it would widen every product to FP64).
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // acc += m * v (complex), as four fused multiply-adds.
 template <typename C>
 __device__ __forceinline__ void cmac(C &acc, const C m, const C v)
 {
-    acc.x = __builtin_fma(m.x, v.x, acc.x);
-    acc.x = __builtin_fma(-m.y, v.y, acc.x);
-    acc.y = __builtin_fma(m.x, v.y, acc.y);
-    acc.y = __builtin_fma(m.y, v.x, acc.y);
+    acc.x = fmadd(m.x, v.x, acc.x);
+    acc.x = fmadd(-m.y, v.y, acc.x);
+    acc.y = fmadd(m.x, v.y, acc.y);
+    acc.y = fmadd(m.y, v.x, acc.y);
 }
 
 template <typename C>

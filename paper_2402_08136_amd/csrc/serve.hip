@@ -6,14 +6,15 @@
 // eigen-decompose; the controlled e^{iAt 2^j} are built later on the device),
 // fuses it, waits until the request's device footprint fits the HBM budget
 // and a slot is free (admission), then uploads its program so that it is
-// resident on the device.  A scheduler thread keeps up to `streams`
-// micro-batches in flight: resident requests of up to batch_max_qubits go
-// together through the batched persistent kernel (one workgroup per request,
-// the state in LDS when it fits, else in HBM).  Larger requests go to a few
-// launcher threads, each with its own stream, which run them through the
-// whole-GPU sweep kernels; requests of the same shape (same size and fused op
-// list) waiting together are launched as one group, each op applied to every
+// resident on the device.  By default every request goes to a few launcher
+// threads, each with its own stream, which run it through the whole-GPU
+// sweep kernels; requests of the same shape (same size and fused op list)
+// waiting together are launched as one group, each op applied to every
 // member's state with that member's own matrices in a single launch.
+// Optionally (lds_max_qubits, batch_max_qubits) small requests instead go
+// together through the batched persistent kernel (one workgroup per request,
+// the state in LDS when it fits, else in HBM), with a scheduler thread
+// keeping up to `streams` such micro-batches in flight.
 // New requests are admitted and launched while earlier ones are still on the
 // GPU.  When a micro-batch finishes its postselected outputs are copied back,
 // x is recovered (step 4), latency is recorded and the memory and slots are
@@ -122,7 +123,14 @@ struct svs {
     int k_max = 0;
     int max_batch = 256;
     int nstreams = 8;
-    int batch_max_qubits = 0;    // 0: batch only LDS-resident requests; larger run alone
+    int batch_max_qubits = 0;    // also batch requests up to this many qubits in HBM (0: none)
+    // LDS batching only up to this many qubits (-1: all that fit; 0: none).
+    // A batched micro-batch returns when its slowest workgroup has run a
+    // whole circuit; the grouped whole-GPU sweeps return sooner.  Measured
+    // at 2000 requests/s (n = 10..21): p50 / p99 20 / 47 ms with none
+    // batched against 26-35 / 73-150 ms with the LDS-resident ones batched
+    // (complex64), 17-25 / 42-54 ms against 26-27 / 59-63 ms (complex128).
+    int lds_max_qubits = 0;
     int nlaunchers = 4;          // threads (and streams) launching the larger requests
     double group_window = 0;     // seconds a larger request may wait for same-shape company
     int hhl_flags = 0;           // SV_HHL_SIGNED / _DILATE / _AUTO / _GAUSS_SEIDEL per request
@@ -307,6 +315,7 @@ bool prepare(svs *s, Req &r, hipStream_t up, StagingRing &ring, sv_status &st, s
     r.ns = r.h.ns;
     bool resident = false;
     batch_lds_bytes(r.n, s->dtype, &resident);
+    if (s->lds_max_qubits >= 0 && r.n > s->lds_max_qubits) resident = false;
     r.kind = resident ? kBatchLds : (r.n <= s->batch_max_qubits ? kBatchHbm : kAlone);
     // fusion width: the configured one, else the tuned one for batched
     // shapes; requests run through the sweep kernels are launch-bound at
@@ -976,6 +985,11 @@ extern "C" sv_status svs_configure(svs *s, int option, double value)
     case SVS_OPT_BATCH_MAX_QUBITS:
         if (value < 0 || value > 24) return fail(SV_ERR_INVALID, "svs_configure: batch qubit limit in [0, 24]");
         s->batch_max_qubits = (int)value;
+        return SV_OK;
+    case SVS_OPT_LDS_MAX_QUBITS:
+        if (value < -1 || value > 24 || value != (int)value)
+            return fail(SV_ERR_INVALID, "svs_configure: LDS qubit limit in [-1, 24]");
+        s->lds_max_qubits = (int)value;
         return SV_OK;
     case SVS_OPT_GROUP_WINDOW_US:
         if (value < 0 || value > 1e7) return fail(SV_ERR_INVALID, "svs_configure: group window in [0, 1e7] us");

@@ -13,8 +13,9 @@ import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-# (ns, m): n = 7..19.  n <= 12 (complex128) runs batched with the state in
-# LDS, 14..17 batched with the state in HBM, 18 and 19 alone.
+# (ns, m): n = 7..19.  By default every request runs alone on the grouped
+# sweeps; with LDS batching on, n <= 12 (complex128) runs batched with the
+# state in LDS, and with HBM batching up to 17, 14..17 batched in HBM.
 MIX = [(2, 4), (3, 6), (6, 10), (4, 8), (2, 6), (5, 8), (3, 10), (6, 7), (4, 5), (5, 10), (3, 3), (6, 6),
        (7, 10), (8, 10)]
 
@@ -57,11 +58,13 @@ def _wait_all(srv, tickets, timeout=120.0):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("hbm_batch", [False, True])
-def test_serving_matches_oracle(dtype, hbm_batch):
+@pytest.mark.parametrize("route", ["sweeps", "lds", "lds+hbm"])
+def test_serving_matches_oracle(dtype, route):
     hs = _hs()
     systems = _systems(MIX)
-    srv = hs.Server(dtype, k_max=3, batch_max_qubits=17 if hbm_batch else 0)
+    opts = {"sweeps": {}, "lds": {"lds_max_qubits": -1},
+            "lds+hbm": {"lds_max_qubits": -1, "batch_max_qubits": 17}}[route]
+    srv = hs.Server(dtype, k_max=3, **opts)
     tickets = [srv.submit(A, b, m) for A, b, m in systems]
     res = _wait_all(srv, tickets)
     tol = 1e-10 if dtype == "c128" else 2e-5
@@ -77,7 +80,8 @@ def test_serving_matches_oracle(dtype, hbm_batch):
     _say(f"serve {dtype}: {st} {prof}")
     assert st["done"] == len(systems) and st["failed"] == 0 and st["p50_s"] <= st["p99_s"]
     lds_limit = 12 if dtype == "c128" else 13    # states of up to 64 KiB run in LDS
-    n_alone = sum(ns + m + 1 > (17 if hbm_batch else lds_limit) for ns, m in MIX)
+    limit = {"sweeps": 0, "lds": lds_limit, "lds+hbm": 17}[route]
+    n_alone = sum(ns + m + 1 > limit for ns, m in MIX)
     assert prof["alone"] == n_alone and prof["batched"] == len(systems) - n_alone
     srv.stop()
 
@@ -86,7 +90,7 @@ def test_serving_matches_oracle(dtype, hbm_batch):
 def test_serving_alone_equals_mix_bitwise(dtype):
     hs = _hs()
     systems = _systems(MIX, seed0=700)
-    srv = hs.Server(dtype, k_max=3, streams=4, max_batch=5, batch_max_qubits=15)
+    srv = hs.Server(dtype, k_max=3, streams=4, max_batch=5, lds_max_qubits=-1, batch_max_qubits=15)
     # the mix: everything at once, twice over
     tickets = [srv.submit(A, b, m) for A, b, m in systems + systems]
     mix = _wait_all(srv, tickets)

@@ -142,7 +142,8 @@ def _wait_all(srv, tickets, timeout=120.0):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_serving_auto_mode_matches_oracle(dtype):
+@pytest.mark.parametrize("lds", [0, -1])
+def test_serving_auto_mode_matches_oracle(dtype, lds):
     """A server in auto mode: SPD, indefinite and non-symmetric requests
     each get the variant the builder picks, and match the oracle's run of it."""
     hs = _hs()
@@ -154,7 +155,7 @@ def test_serving_auto_mode_matches_oracle(dtype):
         reqs.append((oracle.HHL_SIGNED, S, bs, 7))
         G, bg = W.general_system(3 + 3 * i, 60 + i, kappa=10.0)
         reqs.append((oracle.HHL_DILATE, G, bg, 7))
-    srv = hs.Server(dtype, k_max=3, mode="auto")
+    srv = hs.Server(dtype, k_max=3, mode="auto", lds_max_qubits=lds)
     tickets = [srv.submit(A, b, m) for _, A, b, m in reqs]
     res = _wait_all(srv, tickets)
     tol = 1e-10 if dtype == "c128" else 2e-5
