@@ -69,8 +69,10 @@ def measured_traffic(label):
     return float(vals[key]) if key in vals else None
 
 
-def kernel_label(family, k, real="double"):
+def kernel_label(family, k, real="double", n=33):
     """Name of the kernel template instance a launch used (as rocprofv3 shows it)."""
+    if family == "dense_direct" and real == "float" and n >= 7 + k:
+        return f"k_dense_pair<{k}>"     # complex64: two amplitudes per lane access
     name = {"dense_direct": "k_dense_direct", "dense_lds": "k_dense_lds",
             "dense_small": "k_dense_generic", "diag": "k_diag", "wide": "k_wide",
             "ucry": "k_ucry"}[family]
@@ -243,6 +245,54 @@ def pf_newton_leg(hs, W):
     return out
 
 
+def c64_sweep(hs, circ, n, k, warmup, steps, probe_idx, ref_amps):
+    """The same circuit on a complex64 state (half the bytes per sweep), with
+    as many applications as the complex128 run, and the largest difference
+    from the complex128 state over a seeded sample of amplitudes."""
+    import numpy as np
+
+    log(f"[bench] complex64: allocating {8 * 2 ** n / 2 ** 30:.0f} GiB state")
+    s = hs.sv_create(n, "c64")
+    bps = 2 * (1 << n) * 8
+    for _ in range(warmup):
+        s.apply(hs.fuse(circ, k))
+    s.synchronize()
+    t0 = time.perf_counter()
+    ms_l, fam_l, widths = [], [], []
+    for _ in range(steps):
+        fused = hs.fuse(circ, k)
+        ms, fam = s.apply_timed(fused)
+        ms_l.append(ms)
+        fam_l.append(fam)
+        widths += [len(g[1]) for g in fused.gates()]
+    s.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_all, fam_all = np.concatenate(ms_l), np.concatenate(fam_l)
+    rate = bps / (ms_all * 1e-3) / 1e9
+    labels = np.array([kernel_label(hs.KERNEL_FAMILY[int(f)], int(w), "float", n) for f, w in zip(fam_all, widths)])
+    fams = {}
+    for lab in np.unique(labels):
+        sel = labels == lab
+        fams[str(lab)] = {"total_ms": round(float(ms_all[sel].sum()), 2), "launches": int(sel.sum()),
+                          "mean_ms": round(float(ms_all[sel].mean()), 3),
+                          "GBps": round(bps / (float(ms_all[sel].mean()) * 1e-3) / 1e9, 1)}
+    dom = max(fams, key=lambda f: fams[f]["total_ms"])
+    diff = float(np.max(np.abs(s.get_at(probe_idx).astype(np.complex128) - ref_amps)))
+    out = {"value_GBps": round(len(ms_all) * bps / elapsed / 1e9, 2), "bytes_per_sweep": bps,
+           "sweeps": len(ms_all),
+           "per_sweep_GBps": {"min": round(float(rate.min()), 1), "median": round(float(np.median(rate)), 1),
+                              "max": round(float(rate.max()), 1)},
+           "kernel_families": fams,
+           "dominant": {"kernel": dom, "GBps": fams[dom]["GBps"],
+                        "frac_of_hbm_peak": round(fams[dom]["GBps"] / HBM_PEAK_GBS, 4)},
+           "max_abs_diff_vs_complex128": diff, "sampled_amplitudes": int(probe_idx.size),
+           "max_abs_amplitude_sampled": float(np.max(np.abs(ref_amps))),
+           "final_norm2": s.norm2()}
+    s.close()
+    log(f"[bench] complex64: {out['value_GBps']:.0f} GB/s, max |c64 - c128| {diff:.2e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,6 +305,8 @@ def main():
     ap.add_argument("--no-hhl", action="store_true", help="skip the HHL solves/s part")
     ap.add_argument("--no-k-sweep", action="store_true",
                     help="skip the per-sweep rates at the other fusion widths")
+    ap.add_argument("--no-c64", action="store_true",
+                    help="skip the complex64 run of the same circuit")
     ap.add_argument("--k-sweep-layers", type=int, default=10,
                     help="layers of the circuit used for the per-k sweep rates")
     ap.add_argument("--part", choices=["all", "single", "batch", "serve", "powerflow"], default="all",
@@ -306,6 +358,9 @@ def main():
     state.synchronize()
     elapsed = time.perf_counter() - t0
     norm = state.norm2()
+    # seeded sample of amplitudes, for the complex64 run of the same circuit
+    probe_idx = np.random.default_rng(2402).integers(0, 1 << n, size=65536, dtype=np.uint64)
+    ref_amps = state.get_at(probe_idx)
 
     ms_all = np.concatenate(launch_ms)
     fam_all = np.concatenate(families)
@@ -313,7 +368,7 @@ def main():
     value = n_sweeps * bytes_per_sweep / elapsed / 1e9
     per_sweep = bytes_per_sweep / (ms_all * 1e-3) / 1e9
     by_fam = {}
-    labels = np.array([kernel_label(hs.KERNEL_FAMILY[int(f)], int(w)) for f, w in zip(fam_all, width)])
+    labels = np.array([kernel_label(hs.KERNEL_FAMILY[int(f)], int(w), "double", n) for f, w in zip(fam_all, width)])
     for lab in np.unique(labels):
         sel = labels == lab
         by_fam[str(lab)] = (float(ms_all[sel].sum()), int(sel.sum()), float(ms_all[sel].mean()))
@@ -381,6 +436,8 @@ def main():
             log(f"[bench] k={kk}: {fk.n_gates} sweeps, median {np.median(rate):.0f} GB/s")
         out["config"]["per_sweep_GBps_by_k"] = dict(sorted(by_k.items()))
     state.close()
+    if not args.no_c64:
+        out["complex64_sweep"] = c64_sweep(hs, circ, n, k, args.warmup, args.steps, probe_idx, ref_amps)
     if not args.no_hhl:
         log("[bench] HHL: one-circuit-at-a-time path")
         hhl = {"single_64bus_m10": hhl_single(hs, W)}

@@ -122,6 +122,58 @@ __global__ __launch_bounds__(256) void k_dense_direct_g(Ptrs pp, TileArgs a)
     k_dense_direct_body<R, K>(member_ptr<C>(pp.a), member_ptr<const C>(pp.b), a);
 }
 
+// complex64 on the direct path: each lane moves two neighbouring amplitudes
+// in one 16-byte access, so a load instruction carries 1 KiB as at
+// complex128.  The state is seen as 2^(n-1) pairs; index bit 0 is never a
+// target on this path (it lies inside a cache line), so the gate acts on both
+// amplitudes of a pair alike.  Tile arguments are in pair units (targets
+// shifted down by one).
+typedef float F4 __attribute__((ext_vector_type(4)));
+
+template <int K>
+__device__ __forceinline__ void k_dense_pair_body(F4 *__restrict__ psi, const V2<float>::type *__restrict__ mat,
+                                                  const TileArgs &a)
+{
+    typedef V2<float>::type C;
+    constexpr int NR = 1 << K;
+    uint64_t loff = threadIdx.x & 63;
+    for (int j = 0; j < K; ++j) loff = insert_zero(loff, a.rpos[j]);
+    const WaveRange wr = wave_range(a.ntiles, 4);
+    for (uint64_t w = wr.w; w < wr.end; w += wr.step) {
+        const uint64_t base = tile_base(w, a.rpos, K) + loff;
+        const C *m = opaque(mat);
+        F4 v[NR];
+#pragma unroll
+        for (int i = 0; i < NR; ++i) v[i] = ld_nt(psi + base + a.reg_off[i]);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            C lo = {0, 0}, hi = {0, 0};
+#pragma unroll
+            for (int c = 0; c < NR; ++c) {
+                const C mc = m[r * NR + c];
+                cmac(lo, mc, v[c].xy);
+                cmac(hi, mc, v[c].zw);
+                if (NR > 16 && (c & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+            }
+            st_nt(F4{lo.x, lo.y, hi.x, hi.y}, psi + base + a.reg_off[r]);
+        }
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_dense_pair(V2<float>::type *__restrict__ psi,
+                                                    const V2<float>::type *__restrict__ mat, TileArgs a)
+{
+    k_dense_pair_body<K>(reinterpret_cast<F4 *>(psi), mat, a);
+}
+
+// Grouped form: member blockIdx.y of up to kMaxGroup states.
+template <int K>
+__global__ __launch_bounds__(256) void k_dense_pair_g(Ptrs pp, TileArgs a)
+{
+    k_dense_pair_body<K>(member_ptr<F4>(pp.a), member_ptr<const V2<float>::type>(pp.b), a);
+}
+
 __device__ __forceinline__ int lds_phys(int s) { return s + (s >> 6); }
 
 template <typename R, int K>
@@ -682,7 +734,23 @@ sv_status launch_dense_t(const DevOp &op, const Group &g, int n, hipStream_t st,
             a.reg_off[i] = o;
         }
         auto regbit = [&](int pos) { return (int)(std::find(rp.begin(), rp.end(), pos) - rp.begin()); };
-        if (nlo == 0) {
+        if (nlo == 0 && sizeof(R) == 4 && n >= 7 + k) {
+            // complex64: two amplitudes per lane access (pair units)
+            *family = SV_KERNEL_DENSE_DIRECT;
+            a.ntiles >>= 1;
+            for (int j = 0; j < k; ++j) a.rpos[j] = op.q[j] - 1;
+            for (int i = 0; i < (1 << k); ++i) a.reg_off[i] >>= 1;
+            const unsigned grid = grid_for(a.ntiles, 4, 32768);
+            typedef V2<float>::type CF;
+            switch (k) {
+            case 1: launch2<CF>(&k_dense_pair<1>, &k_dense_pair_g<1>, grid, 256, 0, st, pp, cnt, a); break;
+            case 2: launch2<CF>(&k_dense_pair<2>, &k_dense_pair_g<2>, grid, 256, 0, st, pp, cnt, a); break;
+            case 3: launch2<CF>(&k_dense_pair<3>, &k_dense_pair_g<3>, grid, 256, 0, st, pp, cnt, a); break;
+            case 4: launch2<CF>(&k_dense_pair<4>, &k_dense_pair_g<4>, grid, 256, 0, st, pp, cnt, a); break;
+            case 5: launch2<CF>(&k_dense_pair<5>, &k_dense_pair_g<5>, grid, 256, 0, st, pp, cnt, a); break;
+            default: return fail(SV_ERR_INVALID, "dense op wider than 5 qubits");
+            }
+        } else if (nlo == 0) {
             *family = SV_KERNEL_DENSE_DIRECT;
             const unsigned grid = grid_for(a.ntiles, 4, 32768);
             switch (k) {

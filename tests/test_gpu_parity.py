@@ -96,6 +96,24 @@ def test_dense_gate_target_patterns(n, k, pattern, dtype):
     assert np.max(np.abs(got - want)) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("extra", [0, 1, 2])
+def test_dense_register_path_smallest_states(k, extra, dtype):
+    """The register path at n = 6 + k (one tile row), n = 7 + k (the first
+    size where complex64 moves amplitude pairs) and n = 8 + k."""
+    n = 6 + k + extra
+    rng = np.random.default_rng(31 * k + extra)
+    qs = sorted(rng.choice(np.arange(4, n), size=k, replace=False).tolist())
+    U = W.random_unitary(1 << k, rng)
+    g = W.Gate("dense", tuple(qs), np.ascontiguousarray(U).view(np.float64).ravel())
+    _say(f"register path n={n} targets={qs} dtype={dtype}")
+    psi0 = W.random_state(n, 90 + 7 * k + extra)
+    want = oracle.apply_circuit(psi0, n, [g])
+    got = run_gpu(n, [g], psi0, dtype)
+    assert np.max(np.abs(got - want)) <= TOL[dtype]
+
+
 # (targets, family at complex128, family at complex64): the register path
 # takes every gate with no target inside a 128-byte cache line (bits < 3 at
 # complex128, < 4 at complex64), the LDS regroup the rest.
