@@ -69,10 +69,14 @@ def measured_traffic(label):
     return float(vals[key]) if key in vals else None
 
 
-def kernel_label(family, k, real="double", n=33):
-    """Name of the kernel template instance a launch used (as rocprofv3 shows it)."""
+def kernel_label(family, qubits, real="double", n=33):
+    """Name of the kernel template instance a launch used (as rocprofv3 shows
+    it), from its family and target qubits."""
+    k = len(qubits)
     if family == "dense_direct" and real == "float" and n >= 7 + k:
         return f"k_dense_pair<{k}>"     # complex64: two amplitudes per lane access
+    if family == "dense_bfly":          # targets inside a 128-byte line: bits 0..2
+        return f"k_dense_bfly<{k}, {sum(q < 3 for q in qubits)}>"
     name = {"dense_direct": "k_dense_direct", "dense_lds": "k_dense_lds",
             "dense_small": "k_dense_generic", "diag": "k_diag", "wide": "k_wide",
             "ucry": "k_ucry"}[family]
@@ -258,18 +262,18 @@ def c64_sweep(hs, circ, n, k, warmup, steps, probe_idx, ref_amps):
         s.apply(hs.fuse(circ, k))
     s.synchronize()
     t0 = time.perf_counter()
-    ms_l, fam_l, widths = [], [], []
+    ms_l, fam_l, qsets = [], [], []
     for _ in range(steps):
         fused = hs.fuse(circ, k)
         ms, fam = s.apply_timed(fused)
         ms_l.append(ms)
         fam_l.append(fam)
-        widths += [len(g[1]) for g in fused.gates()]
+        qsets += [tuple(g[1]) for g in fused.gates()]
     s.synchronize()
     elapsed = time.perf_counter() - t0
     ms_all, fam_all = np.concatenate(ms_l), np.concatenate(fam_l)
     rate = bps / (ms_all * 1e-3) / 1e9
-    labels = np.array([kernel_label(hs.KERNEL_FAMILY[int(f)], int(w), "float", n) for f, w in zip(fam_all, widths)])
+    labels = np.array([kernel_label(hs.KERNEL_FAMILY[int(f)], q, "float", n) for f, q in zip(fam_all, qsets)])
     fams = {}
     for lab in np.unique(labels):
         sel = labels == lab
@@ -364,11 +368,11 @@ def main():
 
     ms_all = np.concatenate(launch_ms)
     fam_all = np.concatenate(families)
-    width = np.array([len(g[1]) for g in fused.gates()] * args.steps)
+    qsets = [tuple(g[1]) for g in fused.gates()] * args.steps
     value = n_sweeps * bytes_per_sweep / elapsed / 1e9
     per_sweep = bytes_per_sweep / (ms_all * 1e-3) / 1e9
     by_fam = {}
-    labels = np.array([kernel_label(hs.KERNEL_FAMILY[int(f)], int(w), "double", n) for f, w in zip(fam_all, width)])
+    labels = np.array([kernel_label(hs.KERNEL_FAMILY[int(f)], q, "double", n) for f, q in zip(fam_all, qsets)])
     for lab in np.unique(labels):
         sel = labels == lab
         by_fam[str(lab)] = (float(ms_all[sel].sum()), int(sel.sum()), float(ms_all[sel].mean()))

@@ -248,12 +248,16 @@ typedef enum {
     SV_KERNEL_DENSE_DIRECT = 0, /* dense k <= 5, no target inside a 128-byte
                                    line (all >= 3 at c128, >= 4 at c64):
                                    groups held in registers              */
-    SV_KERNEL_DENSE_LDS = 1,    /* dense k <= 5, some target inside a line:
+    SV_KERNEL_DENSE_LDS = 1,    /* dense k <= 5, some target inside a line
+                                   (at c128: three or more, or k = 5):
                                    LDS regroup                           */
     SV_KERNEL_DENSE_SMALL = 2,  /* dense k <= 5 on a state of < 6 + k qubits   */
     SV_KERNEL_DIAG = 3,         /* diagonal gate                                */
     SV_KERNEL_WIDE = 4,         /* dense gate on 6..12 targets, optional control */
-    SV_KERNEL_UCRY = 5          /* uniformly controlled RY                      */
+    SV_KERNEL_UCRY = 5,         /* uniformly controlled RY                      */
+    SV_KERNEL_DENSE_BFLY = 6    /* dense k <= 4 at c128 with one or two targets
+                                   inside a line: cross-lane butterfly, groups
+                                   held in registers                     */
 } sv_kernel_family;
 
 /* As sv_apply, and record the device time of each gate's launch with HIP

@@ -33,7 +33,7 @@ KIND = {"h": 0, "x": 1, "ry": 2, "rz": 3, "p": 4, "u3": 5, "cx": 6, "cp": 7,
         "swap": 8, "dense": 9, "cdense": 10, "ucry": 11, "diag": 12}
 KIND_NAME = {v: k for k, v in KIND.items()}
 KERNEL_FAMILY = {0: "dense_direct", 1: "dense_lds", 2: "dense_small", 3: "diag",
-                 4: "wide", 5: "ucry"}
+                 4: "wide", 5: "ucry", 6: "dense_bfly"}
 STATUS = {0: "SV_OK", 1: "SV_PENDING", -1: "SV_ERR_INVALID", -2: "SV_ERR_OOM",
           -3: "SV_ERR_HIP", -4: "SV_ERR_NOT_SYMMETRIC", -5: "SV_ERR_NOT_POSDEF",
           -6: "SV_ERR_SHAPE", -7: "SV_ERR_BUSY", -8: "SV_ERR_SINGULAR"}

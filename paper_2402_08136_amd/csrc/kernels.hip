@@ -50,6 +50,7 @@ struct TileArgs {
     int rpos[5];            // register-bit positions, ascending, all >= 6
     uint16_t slot_r[32];    // LDS slot contribution of matrix index r
     uint16_t slot_g[64];    // LDS slot contribution of lane (group) g
+    int qsub[2];            // butterfly path: lane bits of the targets inside a line
 };
 
 __device__ __forceinline__ uint64_t tile_base(uint64_t w, const int *rpos, int k)
@@ -172,6 +173,121 @@ template <int K>
 __global__ __launch_bounds__(256) void k_dense_pair_g(Ptrs pp, TileArgs a)
 {
     k_dense_pair_body<K>(member_ptr<F4>(pp.a), member_ptr<const V2<float>::type>(pp.b), a);
+}
+
+// ---------------------------------------------------------------------------
+// Dense gate with one or two targets inside a cache line (complex128): the
+// lanes take the six lowest index bits other than the targets >= 3, so the
+// targets inside the line are lane bits.  Each of them is paired with one
+// spare non-target index bit, held as the register bit of its matrix index.
+// A butterfly across lanes (ds_bpermute, no LDS allocation) swaps the two:
+// afterwards every lane holds one whole group in matrix order, so the matrix
+// is still a uniform scalar operand.  Rows are produced in blocks of
+// 2^nsub, swapped back the same way and stored.  The choices between a
+// lane's own and its partner's value are bitwise blends, so every register
+// index stays a compile-time constant.
+// ---------------------------------------------------------------------------
+typedef unsigned long long U2 __attribute__((ext_vector_type(2)));
+// widest gate on this path: at k = 5 the group registers leave no room for
+// the exchange, and the LDS regroup is used instead
+constexpr int kBflyMaxK = 4;
+
+// m all ones: a, else b.
+__device__ __forceinline__ V2<double>::type blend(unsigned long long m, V2<double>::type a, V2<double>::type b)
+{
+    const U2 ua = __builtin_bit_cast(U2, a), ub = __builtin_bit_cast(U2, b);
+    return __builtin_bit_cast(V2<double>::type, (ua & m) | (ub & ~m));
+}
+
+// The value of the lane whose byte address (lane * 4) is addr.
+__device__ __forceinline__ V2<double>::type lane_fetch(V2<double>::type x, int addr)
+{
+    typedef int I4 __attribute__((ext_vector_type(4)));
+    const I4 u = __builtin_bit_cast(I4, x);
+    I4 o;
+    o.x = __builtin_amdgcn_ds_bpermute(addr, u.x);
+    o.y = __builtin_amdgcn_ds_bpermute(addr, u.y);
+    o.z = __builtin_amdgcn_ds_bpermute(addr, u.z);
+    o.w = __builtin_amdgcn_ds_bpermute(addr, u.w);
+    return __builtin_bit_cast(V2<double>::type, o);
+}
+
+// Swap one lane bit (partner address, and hi = all ones where the lane bit
+// is 1) with bit J of the index into arr[N].
+template <int J, int N>
+__device__ __forceinline__ void butterfly(V2<double>::type *arr, int addr, unsigned long long hi)
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        if (i & (1 << J)) continue;
+        const int p = i | (1 << J);
+        const V2<double>::type got = lane_fetch(blend(hi, arr[i], arr[p]), addr);
+        const V2<double>::type ni = blend(hi, got, arr[i]);
+        const V2<double>::type np = blend(hi, arr[p], got);
+        arr[i] = ni;
+        arr[p] = np;
+    }
+}
+
+template <int K, int NSUB>
+__device__ __forceinline__ void k_dense_bfly_body(V2<double>::type *__restrict__ psi,
+                                                  const V2<double>::type *__restrict__ mat, const TileArgs &a)
+{
+    typedef V2<double>::type C;
+    constexpr int NR = 1 << K, B = 1 << NSUB;
+    const int lane = threadIdx.x & 63;
+    uint64_t loff = lane;
+    for (int j = 0; j < K; ++j) loff = insert_zero(loff, a.rpos[j]);
+    int addr[NSUB];
+    unsigned long long hi[NSUB];
+#pragma unroll
+    for (int j = 0; j < NSUB; ++j) {
+        addr[j] = (lane ^ (1 << a.qsub[j])) << 2;
+        hi[j] = ((lane >> a.qsub[j]) & 1) ? ~0ull : 0ull;
+    }
+    const WaveRange wr = wave_range(a.ntiles, 4);
+    for (uint64_t w = wr.w; w < wr.end; w += wr.step) {
+        const uint64_t base = tile_base(w, a.rpos, K) + loff;
+        C v[NR];
+#pragma unroll
+        for (int i = 0; i < NR; ++i) v[i] = ld_nt(psi + base + a.reg_off[i]);
+        butterfly<0, NR>(v, addr[0], hi[0]);
+        if constexpr (NSUB > 1) butterfly<1, NR>(v, addr[1], hi[1]);
+        const C *m = opaque(mat);
+#pragma unroll
+        for (int b = 0; b < NR / B; ++b) {
+            C out[B];
+#pragma unroll
+            for (int t = 0; t < B; ++t) {
+                C acc = {0, 0};
+#pragma unroll
+                for (int c = 0; c < NR; ++c) {
+                    cmac(acc, m[(b * B + t) * NR + c], v[c]);
+                    if (NR > 16 && (c & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+                }
+                out[t] = acc;
+            }
+            butterfly<0, B>(out, addr[0], hi[0]);
+            if constexpr (NSUB > 1) butterfly<1, B>(out, addr[1], hi[1]);
+#pragma unroll
+            for (int t = 0; t < B; ++t) st_nt(out[t], psi + base + a.reg_off[b * B + t]);
+        }
+    }
+}
+
+template <int K, int NSUB>
+__global__ __launch_bounds__(256) void k_dense_bfly(V2<double>::type *__restrict__ psi,
+                                                    const V2<double>::type *__restrict__ mat, TileArgs a)
+{
+    k_dense_bfly_body<K, NSUB>(psi, mat, a);
+}
+
+// Grouped form: member blockIdx.y of up to kMaxGroup states.
+template <int K, int NSUB>
+__global__ __launch_bounds__(256) void k_dense_bfly_g(Ptrs pp, TileArgs a)
+{
+    typedef V2<double>::type C;
+    k_dense_bfly_body<K, NSUB>(member_ptr<C>(pp.a), member_ptr<const C>(pp.b), a);
 }
 
 __device__ __forceinline__ int lds_phys(int s) { return s + (s >> 6); }
@@ -715,6 +831,46 @@ sv_status launch_dense_t(const DevOp &op, const Group &g, int n, hipStream_t st,
         for (int j = 0; j < k; ++j) {
             nlo += op.q[j] < 6;
             nsub += op.q[j] < line_bits;
+        }
+        if (sizeof(R) == 8 && nsub >= 1 && nsub <= 2 && k <= kBflyMaxK) {
+            // butterfly path: lanes are the six lowest bits other than the
+            // targets >= line_bits; each target inside the line (matrix bits
+            // 0..nsub-1, the targets being sorted) pairs with a spare bit
+            std::vector<int> lanes, spare;
+            for (int b = 0; (int)lanes.size() < 6; ++b)
+                if (std::find(op.q + nsub, op.q + k, b) == op.q + k) lanes.push_back(b);
+            for (int b = 0; (int)spare.size() < nsub && b < n; ++b)
+                if (std::find(lanes.begin(), lanes.end(), b) == lanes.end() &&
+                    std::find(op.q, op.q + k, b) == op.q + k)
+                    spare.push_back(b);
+            int pos[kMaxDenseQubits];
+            for (int j = 0; j < k; ++j) pos[j] = j < nsub ? spare[j] : op.q[j];
+            std::vector<int> sp(pos, pos + k);
+            std::sort(sp.begin(), sp.end());
+            for (int j = 0; j < k; ++j) a.rpos[j] = sp[j];
+            for (int i = 0; i < (1 << k); ++i) {
+                uint64_t o = 0;
+                for (int j = 0; j < k; ++j)
+                    if ((i >> j) & 1) o |= uint64_t(1) << pos[j];
+                a.reg_off[i] = o;
+            }
+            for (int j = 0; j < nsub; ++j) a.qsub[j] = op.q[j];
+            *family = SV_KERNEL_DENSE_BFLY;
+            const unsigned grid = grid_for(a.ntiles, 4, 32768);
+            typedef V2<double>::type CD;
+#define BFLY_GO(KK)                                                                                      \
+    (nsub == 1 ? launch2<CD>(&k_dense_bfly<KK, 1>, &k_dense_bfly_g<KK, 1>, grid, 256, 0, st, pp, cnt, a) \
+               : launch2<CD>(&k_dense_bfly<KK, 2>, &k_dense_bfly_g<KK, 2>, grid, 256, 0, st, pp, cnt, a))
+            switch (k) {
+            case 1: launch2<CD>(&k_dense_bfly<1, 1>, &k_dense_bfly_g<1, 1>, grid, 256, 0, st, pp, cnt, a); break;
+            case 2: BFLY_GO(2); break;
+            case 3: BFLY_GO(3); break;
+            case 4: BFLY_GO(4); break;
+            default: return fail(SV_ERR_INVALID, "butterfly path: dense op wider than supported");
+            }
+#undef BFLY_GO
+            HIPCK(hipGetLastError());
+            return SV_OK;
         }
         if (nsub == 0) nlo = 0;  // direct path: the register bits are the targets
         // register bits: targets kept in registers plus nlo extra non-target bits >= 6

@@ -116,11 +116,16 @@ def test_dense_register_path_smallest_states(k, extra, dtype):
 
 # (targets, family at complex128, family at complex64): the register path
 # takes every gate with no target inside a 128-byte cache line (bits < 3 at
-# complex128, < 4 at complex64), the LDS regroup the rest.
+# complex128, < 4 at complex64); at complex128 one or two targets inside the
+# line (k <= 4) take the cross-lane butterfly; the LDS regroup the rest.
 FAMILY_CASES = [((8, 11), "dense_direct", "dense_direct"),
                 ((3, 9, 14), "dense_direct", "dense_lds"),
                 ((4, 5, 7, 13), "dense_direct", "dense_direct"),
-                ((2, 6), "dense_lds", "dense_lds"),
+                ((2, 6), "dense_bfly", "dense_lds"),
+                ((0, 2, 9), "dense_bfly", "dense_lds"),
+                ((1, 4, 5, 12), "dense_bfly", "dense_lds"),
+                ((0, 1, 3, 14), "dense_bfly", "dense_lds"),
+                ((1, 6, 8, 10, 12), "dense_lds", "dense_lds"),
                 ((0, 1, 2, 3, 4), "dense_lds", "dense_lds")]
 
 
