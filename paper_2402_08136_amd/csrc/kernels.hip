@@ -607,6 +607,150 @@ __global__ __launch_bounds__(256) void k_wide_gemm_g(Ptrs pp, WideGemmArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// Wide dense gate on the matrix cores, for 2^k = D in {8, 16, 32, 64}.
+// With x the interleaved real view of a row (x[2c] = Re in[c], x[2c+1] =
+// Im in[c]), the row update out[j] = sum_c U[j][c] in[c] is one real product
+// y = x B with the 2D x 2D real matrix
+//   B[2c][2j] = Re U[j][c]     B[2c][2j+1] = Im U[j][c]
+//   B[2c+1][2j] = -Im U[j][c]  B[2c+1][2j+1] = Re U[j][c],
+// so rows are read and written in their natural (re, im) layout.  A wave
+// owns 16 RT rows and all 2D real output columns, as RT x D/8 tiles of
+// 16x16x4 MFMA accumulators (FP64 at complex128, FP32 at complex64).  A
+// fragments are gathered from the rows, B fragments are formed from the
+// stored U^T (small, L2-resident).  All loads of a wave's rows come before
+// its stores and no other wave touches those rows, so the in-place update
+// needs no barrier.
+// ---------------------------------------------------------------------------
+template <typename R> struct Mfma;
+template <> struct Mfma<double> {
+    typedef double V4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ V4 mac(double x, double y, V4 acc)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc, 0, 0, 0);
+    }
+    // accumulator item v of lane l: row 4 v + l / 16 (column l % 16)
+    static __device__ __forceinline__ int row(int l, int v) { return 4 * v + (l >> 4); }
+};
+template <> struct Mfma<float> {
+    typedef float V4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ V4 mac(float x, float y, V4 acc)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, acc, 0, 0, 0);
+    }
+    // accumulator item v of lane l: row 4 (l / 16) + v (column l % 16)
+    static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+
+// Offset of column c (target bits) and base of row g (control set, zeros at
+// the targets) of a wide gate.
+__device__ __forceinline__ uint64_t wide_col(const WideGemmArgs &a, uint64_t c)
+{
+    if (a.contiguous) return c << a.q[0];
+    uint64_t o = 0;
+    for (int j = 0; j < a.k; ++j) o |= ((c >> j) & 1) << a.q[j];
+    return o;
+}
+__device__ __forceinline__ uint64_t wide_row(const WideGemmArgs &a, uint64_t g)
+{
+    uint64_t b = g;
+    bool placed = a.control < 0;
+    for (int j = 0; j < a.k; ++j) {
+        if (!placed && a.control < a.q[j]) {
+            b = insert_zero(b, a.control) | (uint64_t(1) << a.control);
+            placed = true;
+        }
+        b = insert_zero(b, a.q[j]);
+    }
+    if (!placed) b = insert_zero(b, a.control) | (uint64_t(1) << a.control);
+    return b;
+}
+
+template <int D>
+struct WideMfmaShape {
+    static constexpr int CTN = D / 8;   // 16-column tiles of the 2D real outputs
+    // most 16-row tiles per wave (accumulators: RT * CTN tiles of 16x16)
+    static constexpr int RT_MAX = 16 / CTN > 8 ? 8 : 16 / CTN;
+};
+
+template <typename R, int D, int RT>
+__device__ __forceinline__ void k_wide_mfma_body(typename V2<R>::type *__restrict__ psi,
+                                                 const typename V2<R>::type *__restrict__ UT, const WideGemmArgs &a)
+{
+    typedef typename V2<R>::type C;
+    typedef typename Mfma<R>::V4 V4;
+    constexpr int CTN = WideMfmaShape<D>::CTN;
+    const int l = threadIdx.x & 63;
+    const int li = l & 15, lk = l >> 4;
+    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    constexpr uint64_t rows_per_wave = 16 * RT;
+    R *outr = reinterpret_cast<R *>(psi);
+    for (uint64_t rb = wave * rows_per_wave; rb < a.ngroups; rb += nwaves * rows_per_wave) {
+        uint64_t ga[RT];
+        bool oka[RT];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const uint64_t g = rb + 16 * rt + li;
+            oka[rt] = g < a.ngroups;
+            ga[rt] = oka[rt] ? wide_row(a, g) : 0;
+        }
+        V4 acc[RT][CTN];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < CTN; ++ct) acc[rt][ct] = V4{0, 0, 0, 0};
+#pragma unroll 2
+        for (int kk = 0; kk < 2 * D; kk += 4) {
+            const int k = kk + lk;   // this lane's real input index
+            const int c = k >> 1, s = k & 1;
+            const uint64_t oc = wide_col(a, c);
+            R xv[RT];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                const C x = oka[rt] ? psi[ga[rt] | oc] : C{0, 0};
+                xv[rt] = s ? x.y : x.x;
+            }
+#pragma unroll
+            for (int ct = 0; ct < CTN; ++ct) {
+                const int jj = 16 * ct + li, j = jj >> 1, t = jj & 1;
+                const C u = UT[(size_t)c * D + j];   // U[j][c]
+                const R bv = s ? (t ? u.x : -u.y) : (t ? u.y : u.x);
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = Mfma<R>::mac(xv[rt], bv, acc[rt][ct]);
+            }
+        }
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const uint64_t g = rb + 16 * rt + Mfma<R>::row(l, v);
+                if (g >= a.ngroups) continue;
+                const uint64_t gb = wide_row(a, g);
+#pragma unroll
+                for (int ct = 0; ct < CTN; ++ct) {
+                    const int jj = 16 * ct + li;
+                    outr[2 * (gb | wide_col(a, jj >> 1)) + (jj & 1)] = acc[rt][ct][v];
+                }
+            }
+    }
+}
+
+template <typename R, int D, int RT>
+__global__ __launch_bounds__(256) void k_wide_mfma(typename V2<R>::type *__restrict__ psi,
+                                                   const typename V2<R>::type *__restrict__ mat, WideGemmArgs a)
+{
+    k_wide_mfma_body<R, D, RT>(psi, mat, a);
+}
+
+// Grouped form: member blockIdx.y of up to kMaxGroup states.
+template <typename R, int D, int RT>
+__global__ __launch_bounds__(256) void k_wide_mfma_g(Ptrs pp, WideGemmArgs a)
+{
+    typedef typename V2<R>::type C;
+    k_wide_mfma_body<R, D, RT>(member_ptr<C>(pp.a), member_ptr<const C>(pp.b), a);
+}
+
+// ---------------------------------------------------------------------------
 // Evolution tables on the device: U[a][b] = sum_k V[a][k] V[b][k] e^{+-i phi_k}
 // with phi_k = fmod(w_k t 2^j, 2 pi), accumulated in FP64 and stored in the
 // program dtype.  U is symmetric, so the stored U is also U^T (the OP_WIDE
@@ -1005,6 +1149,38 @@ sv_status launch_op_t(const DevOp &op, const Group &g, int n, hipStream_t st, in
             for (int j = 1; j < op.k; ++j)
                 if (op.q[j] != op.q[0] + j) a.contiguous = 0;
             const int D = 1 << op.k;
+            // matrix-core form when the launch has rows enough for >= 1024
+            // waves of one 16-row tile: below that (a single state of up to
+            // ~17 qubits) the vector kernel below spreads the rows over more
+            // waves and finishes sooner (measured: a 64-bus, 10-clock solve
+            // took 0.75 ms through the matrix cores, 0.48 ms without)
+            if (D >= 8 && D <= 64 && (uint64_t)cnt * ngroups >= 16384) {
+                // 16-row tiles per wave as many as keep >= ~1024 waves busy
+                // over the whole group, up to the most the accumulators allow
+                // (a row's arithmetic does not depend on it)
+                auto waves_of = [&](int rt) { return (ngroups + 16 * (uint64_t)rt - 1) / (16 * (uint64_t)rt); };
+                const int rt_max = D == 8 ? 8 : D == 16 ? 8 : D == 32 ? 4 : 2;
+                int rt = rt_max;
+                while (rt > 1 && cnt * waves_of(rt) < 1024) rt >>= 1;
+                const unsigned grid = grid_for(waves_of(rt), 4, 8192);
+#define MFMA_GO(DD, RTV) launch2(&k_wide_mfma<R, DD, RTV>, &k_wide_mfma_g<R, DD, RTV>, grid, 256, 0, st, pp, cnt, a)
+#define MFMA_RT(DD)                            \
+    switch (rt) {                              \
+    case 8: MFMA_GO(DD, WideMfmaShape<DD>::RT_MAX >= 8 ? 8 : 1); break; \
+    case 4: MFMA_GO(DD, WideMfmaShape<DD>::RT_MAX >= 4 ? 4 : 1); break; \
+    case 2: MFMA_GO(DD, 2); break;             \
+    default: MFMA_GO(DD, 1); break;            \
+    }
+                switch (D) {
+                case 8: MFMA_RT(8) break;
+                case 16: MFMA_RT(16) break;
+                case 32: MFMA_RT(32) break;
+                default: MFMA_RT(64) break;
+                }
+#undef MFMA_RT
+#undef MFMA_GO
+                break;
+            }
             const int rps = D < 64 ? 64 / D : 1;
             // rows per wave: as many as keep >= ~1024 waves busy over the
             // whole group (reuse of each loaded U column across rows vs

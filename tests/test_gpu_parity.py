@@ -303,6 +303,28 @@ def test_wide_gate_widths(k, control, dtype):
     assert np.max(np.abs(got2 - want2)) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("k,control", [(3, True), (4, True), (5, True), (6, True), (6, False), (4, False)])
+def test_wide_gate_matrix_cores(k, control, dtype):
+    """Wide gates of 8..64 columns on states with >= 16384 rows per launch,
+    which run on the matrix cores: scattered and contiguous targets."""
+    n = k + 15 + (1 if control else 0)
+    rng = np.random.default_rng(70 + k + (100 if control else 0))
+    qs = rng.choice(n, size=k + (1 if control else 0), replace=False).tolist()
+    U = W.random_unitary(1 << k, rng)
+    g = W.Gate("cdense" if control else "dense", tuple(qs), np.ascontiguousarray(U).view(np.float64).ravel())
+    _say(f"wide on matrix cores n={n} qubits={qs} dtype={dtype}")
+    psi0 = W.random_state(n, 7 * k)
+    want = oracle.apply_circuit(psi0, n, [g])
+    got = run_gpu(n, [g], psi0, dtype)
+    assert np.max(np.abs(got - want)) <= TOL[dtype]
+    qs2 = [n - 1] + list(range(k)) if control else list(range(2, 2 + k))
+    g2 = W.Gate(g.kind, tuple(qs2), g.params)
+    want2 = oracle.apply_circuit(psi0, n, [g2])
+    got2 = run_gpu(n, [g2], psi0, dtype)
+    assert np.max(np.abs(got2 - want2)) <= TOL[dtype]
+
+
 # ---------------------------------------------------- hipGraph replays ---
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_graph_replay_matches_eager(dtype):
