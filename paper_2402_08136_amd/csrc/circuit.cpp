@@ -235,6 +235,45 @@ std::vector<int> unite(const std::vector<int> &a, const std::vector<int> &b)
     return u;
 }
 
+// Blocks examined, most recent first, for a merge with a disjoint block.
+constexpr int kDisjointLookback = 32;
+
+// Second pass over the fused blocks: a block that shares no qubit with a
+// later block, and that no block in between touches, commutes up to it; the
+// two become one block on the union of their qubits while that stays within
+// k_max (a layer of one-qubit gates on distinct qubits becomes one sweep).
+// Done after the overlap merges so that it never takes a gate away from a
+// block that shares its qubits.
+void merge_disjoint(std::vector<Block> &blocks, int n, int k_max)
+{
+    std::vector<int> last(n, -1);
+    for (int j = 0; j < (int)blocks.size(); ++j) {
+        Block &bj = blocks[j];
+        if (!bj.alive) continue;
+        if (bj.open) {
+            int seen = 0;
+            for (int i = j - 1; i >= 0 && seen < kDisjointLookback && (int)bj.qubits.size() < k_max; --i) {
+                Block &bi = blocks[i];
+                if (!bi.alive) continue;
+                ++seen;
+                if (!bi.open || (int)(bi.qubits.size() + bj.qubits.size()) > k_max) continue;
+                bool ok = true;
+                for (int q : bi.qubits)
+                    ok = ok && last[q] == i && !std::binary_search(bj.qubits.begin(), bj.qubits.end(), q);
+                if (!ok) continue;
+                const std::vector<int> U = unite(bi.qubits, bj.qubits);
+                const size_t D = (size_t)1 << U.size();
+                bj.M = matmul(embed(bj.M, bj.qubits, U), embed(bi.M, bi.qubits, U), D);
+                bj.diag = bj.diag && bi.diag;
+                bj.qubits = U;
+                bi.alive = false;
+                for (int q : bi.qubits) last[q] = j;
+            }
+        }
+        for (int q : bj.qubits) last[q] = j;
+    }
+}
+
 int fused_width(const Gate &g)
 {
     return (int)g.qubits.size();
@@ -432,6 +471,8 @@ extern "C" sv_status fuse(const sv_circuit *in, int k_max, sv_circuit **out)
         blocks.push_back(std::move(nb));
         for (int q : blocks.back().qubits) last[q] = (int)blocks.size() - 1;
     }
+
+    merge_disjoint(blocks, n, k_max);
 
     auto *oc = new (std::nothrow) sv_circuit;
     if (!oc) return fail(SV_ERR_OOM, "fuse: out of host memory");

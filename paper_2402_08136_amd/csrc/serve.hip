@@ -65,7 +65,12 @@ __global__ __launch_bounds__(256) void k_gather_outputs(const BInst *__restrict_
 // batched launch with its state in HBM (one workgroup per request), or alone
 // through the whole-GPU sweep kernels.
 enum { kBatchLds = 0, kBatchHbm = 1, kAlone = 2 };
-constexpr int kAloneK = 4;   // fusion width for kAlone requests when k_max is automatic
+// Fusion width for kAlone requests when k_max is automatic.  Below 20 qubits
+// a launch has few tiles and the wider gate's arithmetic is not hidden: over
+// a sample of the serving mix, k = 3 took 0.28 ms of kernel time per 10-qubit
+// request against 0.54 ms at k = 4, and stayed ahead up to 19 qubits; from
+// 20 qubits k = 4 is ahead (3.58 against 3.80 ms at 21 qubits).
+inline int alone_k(int n) { return n >= 20 ? 4 : 3; }
 
 struct Req {
     uint64_t ticket = 0;
@@ -321,7 +326,7 @@ bool prepare(svs *s, Req &r, hipStream_t up, StagingRing &ring, sv_status &st, s
     // shapes; requests run through the sweep kernels are launch-bound at
     // these sizes, so they fuse wider (fewer launches)
     int k = s->k_max;
-    if (k == 0) k = r.kind == kAlone ? kAloneK : batch_tuned_k(s->dtype, r.ns, r.m);
+    if (k == 0) k = r.kind == kAlone ? alone_k(r.n) : batch_tuned_k(s->dtype, r.ns, r.m);
     if (k == 0) k = kDefaultBatchK;
     st = fuse(c, k, &f);
     circuit_destroy(c);

@@ -207,6 +207,39 @@ def test_fusion_k2_is_the_papers_four_strategies():
     assert sorted(len(qs) for _, qs, _ in f.gates()) == [1, 2]
 
 
+@pytest.mark.parametrize("k,want", [(1, 6), (2, 3), (3, 2), (4, 2), (5, 2)])
+def test_disjoint_gates_share_a_sweep(k, want):
+    """A layer of one-qubit gates on distinct qubits fuses into blocks of up
+    to k_max qubits (they commute)."""
+    n = 6
+    gates = [W.Gate("h", (q,), np.array([])) for q in range(n)]
+    c = hs.circuit_from_gates(n, gates)
+    f = hs.fuse(c, k)
+    assert f.n_gates == want
+    psi = W.random_state(n, 3)
+    assert max_abs_diff(np_run(f, psi), np_run(c, psi)) < 1e-13
+
+
+def test_disjoint_merge_respects_order():
+    """A block moves forward to a disjoint later block only when nothing in
+    between touches its qubits; the overlap merges come first."""
+    gates = [W.Gate("h", (0,), np.array([])), W.Gate("h", (1,), np.array([])),
+             W.Gate("cx", (1, 2), np.array([])), W.Gate("h", (3,), np.array([])),
+             W.Gate("ry", (0,), np.array([0.4])), W.Gate("h", (0,), np.array([]))]
+    c = hs.circuit_from_gates(4, gates)
+    f = hs.fuse(c, 2)
+    # {h1, cx12}, then h0 h3 ry0 h0 as one two-qubit block {0, 3}
+    assert sorted(tuple(qs) for _, qs, _ in f.gates()) == [(0, 3), (1, 2)]
+    psi = W.random_state(4, 9)
+    assert max_abs_diff(np_run(f, psi), np_run(c, psi)) < 1e-13
+    # a gate between that touches qubit 3 keeps h3 where it is
+    gates2 = gates[:4] + [W.Gate("cx", (3, 2), np.array([]))] + gates[4:]
+    c2 = hs.circuit_from_gates(4, gates2)
+    f2 = hs.fuse(c2, 2)
+    psi2 = W.random_state(4, 10)
+    assert max_abs_diff(np_run(f2, psi2), np_run(c2, psi2)) < 1e-13
+
+
 def test_diagonal_runs_stay_diagonal():
     gates = [W.Gate("rz", (0,), np.array([0.3])), W.Gate("cp", (0, 1), np.array([0.5])),
              W.Gate("p", (1,), np.array([0.9]))]
