@@ -192,15 +192,20 @@ typedef unsigned long long U2 __attribute__((ext_vector_type(2)));
 // the exchange, and the LDS regroup is used instead
 constexpr int kBflyMaxK = 4;
 
+// Exchanged elements are 16 bytes: one complex128 amplitude, or a pair of
+// complex64 amplitudes.
 // m all ones: a, else b.
-__device__ __forceinline__ V2<double>::type blend(unsigned long long m, V2<double>::type a, V2<double>::type b)
+template <typename E>
+__device__ __forceinline__ E blend(unsigned long long m, E a, E b)
 {
+    static_assert(sizeof(E) == 16, "16-byte elements");
     const U2 ua = __builtin_bit_cast(U2, a), ub = __builtin_bit_cast(U2, b);
-    return __builtin_bit_cast(V2<double>::type, (ua & m) | (ub & ~m));
+    return __builtin_bit_cast(E, (ua & m) | (ub & ~m));
 }
 
 // The value of the lane whose byte address (lane * 4) is addr.
-__device__ __forceinline__ V2<double>::type lane_fetch(V2<double>::type x, int addr)
+template <typename E>
+__device__ __forceinline__ E lane_fetch(E x, int addr)
 {
     typedef int I4 __attribute__((ext_vector_type(4)));
     const I4 u = __builtin_bit_cast(I4, x);
@@ -209,21 +214,21 @@ __device__ __forceinline__ V2<double>::type lane_fetch(V2<double>::type x, int a
     o.y = __builtin_amdgcn_ds_bpermute(addr, u.y);
     o.z = __builtin_amdgcn_ds_bpermute(addr, u.z);
     o.w = __builtin_amdgcn_ds_bpermute(addr, u.w);
-    return __builtin_bit_cast(V2<double>::type, o);
+    return __builtin_bit_cast(E, o);
 }
 
 // Swap one lane bit (partner address, and hi = all ones where the lane bit
 // is 1) with bit J of the index into arr[N].
-template <int J, int N>
-__device__ __forceinline__ void butterfly(V2<double>::type *arr, int addr, unsigned long long hi)
+template <int J, int N, typename E>
+__device__ __forceinline__ void butterfly(E *arr, int addr, unsigned long long hi)
 {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         if (i & (1 << J)) continue;
         const int p = i | (1 << J);
-        const V2<double>::type got = lane_fetch(blend(hi, arr[i], arr[p]), addr);
-        const V2<double>::type ni = blend(hi, got, arr[i]);
-        const V2<double>::type np = blend(hi, arr[p], got);
+        const E got = lane_fetch(blend(hi, arr[i], arr[p]), addr);
+        const E ni = blend(hi, got, arr[i]);
+        const E np = blend(hi, arr[p], got);
         arr[i] = ni;
         arr[p] = np;
     }
@@ -273,6 +278,71 @@ __device__ __forceinline__ void k_dense_bfly_body(V2<double>::type *__restrict__
             for (int t = 0; t < B; ++t) st_nt(out[t], psi + base + a.reg_off[b * B + t]);
         }
     }
+}
+
+// complex64: the same layout on the pair view of the state (two neighbouring
+// amplitudes per 16-byte element, tile arguments in pair units); each lane
+// then holds two groups, which take the same matrix.  Used when index bit 0
+// is not a target.
+template <int K, int NSUB>
+__device__ __forceinline__ void k_dense_bfly_pair_body(F4 *__restrict__ psi, const V2<float>::type *__restrict__ mat,
+                                                       const TileArgs &a)
+{
+    typedef V2<float>::type C;
+    constexpr int NR = 1 << K, B = 1 << NSUB;
+    const int lane = threadIdx.x & 63;
+    uint64_t loff = lane;
+    for (int j = 0; j < K; ++j) loff = insert_zero(loff, a.rpos[j]);
+    int addr[NSUB];
+    unsigned long long hi[NSUB];
+#pragma unroll
+    for (int j = 0; j < NSUB; ++j) {
+        addr[j] = (lane ^ (1 << a.qsub[j])) << 2;
+        hi[j] = ((lane >> a.qsub[j]) & 1) ? ~0ull : 0ull;
+    }
+    const WaveRange wr = wave_range(a.ntiles, 4);
+    for (uint64_t w = wr.w; w < wr.end; w += wr.step) {
+        const uint64_t base = tile_base(w, a.rpos, K) + loff;
+        F4 v[NR];
+#pragma unroll
+        for (int i = 0; i < NR; ++i) v[i] = ld_nt(psi + base + a.reg_off[i]);
+        butterfly<0, NR>(v, addr[0], hi[0]);
+        if constexpr (NSUB > 1) butterfly<1, NR>(v, addr[1], hi[1]);
+        const C *m = opaque(mat);
+#pragma unroll
+        for (int b = 0; b < NR / B; ++b) {
+            F4 out[B];
+#pragma unroll
+            for (int t = 0; t < B; ++t) {
+                C lo = {0, 0}, hi2 = {0, 0};
+#pragma unroll
+                for (int c = 0; c < NR; ++c) {
+                    const C mc = m[(b * B + t) * NR + c];
+                    cmac(lo, mc, v[c].xy);
+                    cmac(hi2, mc, v[c].zw);
+                }
+                out[t] = F4{lo.x, lo.y, hi2.x, hi2.y};
+            }
+            butterfly<0, B>(out, addr[0], hi[0]);
+            if constexpr (NSUB > 1) butterfly<1, B>(out, addr[1], hi[1]);
+#pragma unroll
+            for (int t = 0; t < B; ++t) st_nt(out[t], psi + base + a.reg_off[b * B + t]);
+        }
+    }
+}
+
+template <int K, int NSUB>
+__global__ __launch_bounds__(256) void k_dense_bfly_pair(V2<float>::type *__restrict__ psi,
+                                                         const V2<float>::type *__restrict__ mat, TileArgs a)
+{
+    k_dense_bfly_pair_body<K, NSUB>(reinterpret_cast<F4 *>(psi), mat, a);
+}
+
+// Grouped form: member blockIdx.y of up to kMaxGroup states.
+template <int K, int NSUB>
+__global__ __launch_bounds__(256) void k_dense_bfly_pair_g(Ptrs pp, TileArgs a)
+{
+    k_dense_bfly_pair_body<K, NSUB>(member_ptr<F4>(pp.a), member_ptr<const V2<float>::type>(pp.b), a);
 }
 
 template <int K, int NSUB>
@@ -676,7 +746,6 @@ template <typename R, int D, int RT>
 __device__ __forceinline__ void k_wide_mfma_body(typename V2<R>::type *__restrict__ psi,
                                                  const typename V2<R>::type *__restrict__ UT, const WideGemmArgs &a)
 {
-    typedef typename V2<R>::type C;
     typedef typename Mfma<R>::V4 V4;
     constexpr int CTN = WideMfmaShape<D>::CTN;
     const int l = threadIdx.x & 63;
@@ -685,6 +754,13 @@ __device__ __forceinline__ void k_wide_mfma_body(typename V2<R>::type *__restric
     const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
     constexpr uint64_t rows_per_wave = 16 * RT;
     R *outr = reinterpret_cast<R *>(psi);
+    const R *inr = reinterpret_cast<const R *>(psi);
+    const R *ur = reinterpret_cast<const R *>(UT);
+    // this lane's real input index k = kk + lk has part s = lk & 1 of
+    // in[k / 2]; its real output column 16 ct + li has part t = li & 1, so
+    // its B entry is part s ^ t of U[j][c], negated when s = 1, t = 0
+    const int s_in = lk & 1, part = s_in ^ (li & 1);
+    const R sgn = (s_in && !(li & 1)) ? R(-1) : R(1);
     for (uint64_t rb = wave * rows_per_wave; rb < a.ngroups; rb += nwaves * rows_per_wave) {
         uint64_t ga[RT];
         bool oka[RT];
@@ -701,20 +777,15 @@ __device__ __forceinline__ void k_wide_mfma_body(typename V2<R>::type *__restric
             for (int ct = 0; ct < CTN; ++ct) acc[rt][ct] = V4{0, 0, 0, 0};
 #pragma unroll 2
         for (int kk = 0; kk < 2 * D; kk += 4) {
-            const int k = kk + lk;   // this lane's real input index
-            const int c = k >> 1, s = k & 1;
+            const int c = (kk + lk) >> 1;   // complex input column of this lane
             const uint64_t oc = wide_col(a, c);
             R xv[RT];
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt) {
-                const C x = oka[rt] ? psi[ga[rt] | oc] : C{0, 0};
-                xv[rt] = s ? x.y : x.x;
-            }
+            for (int rt = 0; rt < RT; ++rt) xv[rt] = oka[rt] ? inr[2 * (ga[rt] | oc) + s_in] : R(0);
 #pragma unroll
             for (int ct = 0; ct < CTN; ++ct) {
-                const int jj = 16 * ct + li, j = jj >> 1, t = jj & 1;
-                const C u = UT[(size_t)c * D + j];   // U[j][c]
-                const R bv = s ? (t ? u.x : -u.y) : (t ? u.y : u.x);
+                const int j = (16 * ct + li) >> 1;
+                const R bv = sgn * ur[2 * ((size_t)c * D + j) + part];   // from U[j][c]
 #pragma unroll
                 for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = Mfma<R>::mac(xv[rt], bv, acc[rt][ct]);
             }
@@ -976,21 +1047,33 @@ sv_status launch_dense_t(const DevOp &op, const Group &g, int n, hipStream_t st,
             nlo += op.q[j] < 6;
             nsub += op.q[j] < line_bits;
         }
-        if (sizeof(R) == 8 && nsub >= 1 && nsub <= 2 && k <= kBflyMaxK) {
-            // butterfly path: lanes are the six lowest bits other than the
-            // targets >= line_bits; each target inside the line (matrix bits
-            // 0..nsub-1, the targets being sorted) pairs with a spare bit
+        // butterfly path (see k_dense_bfly_body); complex64 runs it on the
+        // pair view (targets shifted down by one) when bit 0 is not a target
+        const bool pairs = sizeof(R) == 4;
+        const int sh = pairs ? 1 : 0;
+        const int nb_sub = nsub;   // targets inside the line (bits 0..2 in pair units at complex64)
+        // (complex64: one such target only; with two the pair form, which
+        // does two groups of FP32 work per element, measured below the LDS
+        // regroup: 5.50 against 5.84 TB/s at k = 4)
+        if (nb_sub >= 1 && nb_sub <= (pairs ? 1 : 2) && k <= kBflyMaxK &&
+            !(pairs && (op.q[0] == 0 || n < 7 + k))) {
+            // lanes are the six lowest (pair) bits other than the targets
+            // at or above the line; each target inside the line (matrix
+            // bits 0..nsub-1, the targets being sorted) pairs with a spare
+            int q[kMaxDenseQubits];
+            for (int j = 0; j < k; ++j) q[j] = op.q[j] - sh;
+            const int nn = n - sh;
             std::vector<int> lanes, spare;
             for (int b = 0; (int)lanes.size() < 6; ++b)
-                if (std::find(op.q + nsub, op.q + k, b) == op.q + k) lanes.push_back(b);
-            for (int b = 0; (int)spare.size() < nsub && b < n; ++b)
-                if (std::find(lanes.begin(), lanes.end(), b) == lanes.end() &&
-                    std::find(op.q, op.q + k, b) == op.q + k)
+                if (std::find(q + nb_sub, q + k, b) == q + k) lanes.push_back(b);
+            for (int b = 0; (int)spare.size() < nb_sub && b < nn; ++b)
+                if (std::find(lanes.begin(), lanes.end(), b) == lanes.end() && std::find(q, q + k, b) == q + k)
                     spare.push_back(b);
             int pos[kMaxDenseQubits];
-            for (int j = 0; j < k; ++j) pos[j] = j < nsub ? spare[j] : op.q[j];
+            for (int j = 0; j < k; ++j) pos[j] = j < nb_sub ? spare[j] : q[j];
             std::vector<int> sp(pos, pos + k);
             std::sort(sp.begin(), sp.end());
+            a.ntiles = uint64_t(1) << (nn - 6 - k);
             for (int j = 0; j < k; ++j) a.rpos[j] = sp[j];
             for (int i = 0; i < (1 << k); ++i) {
                 uint64_t o = 0;
@@ -998,21 +1081,39 @@ sv_status launch_dense_t(const DevOp &op, const Group &g, int n, hipStream_t st,
                     if ((i >> j) & 1) o |= uint64_t(1) << pos[j];
                 a.reg_off[i] = o;
             }
-            for (int j = 0; j < nsub; ++j) a.qsub[j] = op.q[j];
+            for (int j = 0; j < nb_sub; ++j) a.qsub[j] = q[j];
             *family = SV_KERNEL_DENSE_BFLY;
             const unsigned grid = grid_for(a.ntiles, 4, 32768);
-            typedef V2<double>::type CD;
+            if constexpr (sizeof(R) == 8) {
+                typedef V2<double>::type CD;
 #define BFLY_GO(KK)                                                                                      \
-    (nsub == 1 ? launch2<CD>(&k_dense_bfly<KK, 1>, &k_dense_bfly_g<KK, 1>, grid, 256, 0, st, pp, cnt, a) \
-               : launch2<CD>(&k_dense_bfly<KK, 2>, &k_dense_bfly_g<KK, 2>, grid, 256, 0, st, pp, cnt, a))
-            switch (k) {
-            case 1: launch2<CD>(&k_dense_bfly<1, 1>, &k_dense_bfly_g<1, 1>, grid, 256, 0, st, pp, cnt, a); break;
-            case 2: BFLY_GO(2); break;
-            case 3: BFLY_GO(3); break;
-            case 4: BFLY_GO(4); break;
-            default: return fail(SV_ERR_INVALID, "butterfly path: dense op wider than supported");
-            }
+    (nb_sub == 1 ? launch2<CD>(&k_dense_bfly<KK, 1>, &k_dense_bfly_g<KK, 1>, grid, 256, 0, st, pp, cnt, a) \
+                 : launch2<CD>(&k_dense_bfly<KK, 2>, &k_dense_bfly_g<KK, 2>, grid, 256, 0, st, pp, cnt, a))
+                switch (k) {
+                case 1: launch2<CD>(&k_dense_bfly<1, 1>, &k_dense_bfly_g<1, 1>, grid, 256, 0, st, pp, cnt, a); break;
+                case 2: BFLY_GO(2); break;
+                case 3: BFLY_GO(3); break;
+                case 4: BFLY_GO(4); break;
+                default: return fail(SV_ERR_INVALID, "butterfly path: dense op wider than supported");
+                }
 #undef BFLY_GO
+            } else {
+                typedef V2<float>::type CF;
+#define BFLY_GO(KK)                                                                                        \
+    (nb_sub == 1                                                                                           \
+         ? launch2<CF>(&k_dense_bfly_pair<KK, 1>, &k_dense_bfly_pair_g<KK, 1>, grid, 256, 0, st, pp, cnt, a) \
+         : launch2<CF>(&k_dense_bfly_pair<KK, 2>, &k_dense_bfly_pair_g<KK, 2>, grid, 256, 0, st, pp, cnt, a))
+                switch (k) {
+                case 1:
+                    launch2<CF>(&k_dense_bfly_pair<1, 1>, &k_dense_bfly_pair_g<1, 1>, grid, 256, 0, st, pp, cnt, a);
+                    break;
+                case 2: BFLY_GO(2); break;
+                case 3: BFLY_GO(3); break;
+                case 4: BFLY_GO(4); break;
+                default: return fail(SV_ERR_INVALID, "butterfly path: dense op wider than supported");
+                }
+#undef BFLY_GO
+            }
             HIPCK(hipGetLastError());
             return SV_OK;
         }

@@ -99,12 +99,19 @@ def test_dense_gate_target_patterns(n, k, pattern, dtype):
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("extra", [0, 1, 2])
-def test_dense_register_path_smallest_states(k, extra, dtype):
-    """The register path at n = 6 + k (one tile row), n = 7 + k (the first
-    size where complex64 moves amplitude pairs) and n = 8 + k."""
+@pytest.mark.parametrize("in_line", [False, True])
+def test_dense_register_path_smallest_states(k, extra, in_line, dtype):
+    """The register and butterfly paths at n = 6 + k (one tile row), n = 7 + k
+    (the first size where complex64 moves amplitude pairs) and n = 8 + k;
+    in_line puts one target in bit 1 or 2 (inside a cache line)."""
     n = 6 + k + extra
-    rng = np.random.default_rng(31 * k + extra)
-    qs = sorted(rng.choice(np.arange(4, n), size=k, replace=False).tolist())
+    rng = np.random.default_rng(31 * k + extra + (500 if in_line else 0))
+    if in_line:
+        first = int(rng.integers(1, 3))
+        rest = rng.choice(np.arange(4, n), size=k - 1, replace=False).tolist()
+        qs = sorted([first] + rest)
+    else:
+        qs = sorted(rng.choice(np.arange(4, n), size=k, replace=False).tolist())
     U = W.random_unitary(1 << k, rng)
     g = W.Gate("dense", tuple(qs), np.ascontiguousarray(U).view(np.float64).ravel())
     _say(f"register path n={n} targets={qs} dtype={dtype}")
@@ -116,15 +123,18 @@ def test_dense_register_path_smallest_states(k, extra, dtype):
 
 # (targets, family at complex128, family at complex64): the register path
 # takes every gate with no target inside a 128-byte cache line (bits < 3 at
-# complex128, < 4 at complex64); at complex128 one or two targets inside the
-# line (k <= 4) take the cross-lane butterfly; the LDS regroup the rest.
+# complex128, < 4 at complex64); targets inside the line (k <= 4) take the
+# cross-lane butterfly: one or two at complex128, one at complex64 (on
+# amplitude pairs, so not bit 0); the LDS regroup the rest.
 FAMILY_CASES = [((8, 11), "dense_direct", "dense_direct"),
-                ((3, 9, 14), "dense_direct", "dense_lds"),
+                ((3, 9, 14), "dense_direct", "dense_bfly"),
                 ((4, 5, 7, 13), "dense_direct", "dense_direct"),
-                ((2, 6), "dense_bfly", "dense_lds"),
+                ((2, 6), "dense_bfly", "dense_bfly"),
                 ((0, 2, 9), "dense_bfly", "dense_lds"),
-                ((1, 4, 5, 12), "dense_bfly", "dense_lds"),
+                ((1, 4, 5, 12), "dense_bfly", "dense_bfly"),
                 ((0, 1, 3, 14), "dense_bfly", "dense_lds"),
+                ((1, 2, 9), "dense_bfly", "dense_lds"),
+                ((1, 2, 3), "dense_bfly", "dense_lds"),
                 ((1, 6, 8, 10, 12), "dense_lds", "dense_lds"),
                 ((0, 1, 2, 3, 4), "dense_lds", "dense_lds")]
 
