@@ -714,6 +714,7 @@ sv_status capture(svb *b)
         const hipStream_t st = b->side[(b->classes.size() + gi) % nside];
         Group g;
         g.count = (int)sw.members.size();
+        g.batch = true;
         for (int i = 0; i < g.count; ++i) {
             const svb::Meta &in = b->insts[sw.members[i]];
             g.psi[i] = b->d_states + in.state_off;

@@ -821,6 +821,107 @@ __global__ __launch_bounds__(256) void k_wide_mfma_g(Ptrs pp, WideGemmArgs a)
     k_wide_mfma_body<R, D, RT>(member_ptr<C>(pp.a), member_ptr<const C>(pp.b), a);
 }
 
+// Wider gates (D = 128, 256) on launches with few rows (a single large
+// state): the accumulators of all 2D real columns do not fit one wave, so
+// the 16 waves of a workgroup share 16 RT rows and take 1/16 of the D/8
+// column tiles each.  The rows are first copied into LDS (real layout, row
+// stride padded by two reals against bank conflicts), so each wave reads its
+// A fragments there instead of from L2.  A barrier after the copy and one
+// after the last read of the rows bound the in-place update; the row loop
+// is bounded by the workgroup's first row, so all waves meet the same
+// barriers.
+constexpr int kStageWaves = 16;
+
+template <int D, int RT>
+struct WideStageShape {
+    static constexpr int STRIDE = 2 * D + 2;           // reals per staged row
+    static constexpr int CW = D / 8 / kStageWaves;     // column tiles per wave
+};
+
+template <typename R, int D, int RT>
+__device__ __forceinline__ void k_wide_mfma_stage_body(typename V2<R>::type *__restrict__ psi,
+                                                       const typename V2<R>::type *__restrict__ UT,
+                                                       const WideGemmArgs &a, R *rows_lds)
+{
+    typedef typename V2<R>::type C;
+    typedef typename Mfma<R>::V4 V4;
+    constexpr int STRIDE = WideStageShape<D, RT>::STRIDE, CW = WideStageShape<D, RT>::CW;
+    static_assert(CW >= 1, "at least one column tile per wave");
+    constexpr int NT = 64 * kStageWaves;
+    const int l = threadIdx.x & 63;
+    const int li = l & 15, lk = l >> 4;
+    const int ct0 = (threadIdx.x >> 6) * CW;
+    const int s_in = lk & 1, part = s_in ^ (li & 1);   // as in k_wide_mfma_body
+    const R sgn = (s_in && !(li & 1)) ? R(-1) : R(1);
+    const R *ur = reinterpret_cast<const R *>(UT);
+    R *outr = reinterpret_cast<R *>(psi);
+    constexpr uint64_t rows = 16 * RT;
+    for (uint64_t rb = (uint64_t)blockIdx.x * rows; rb < a.ngroups; rb += (uint64_t)gridDim.x * rows) {
+        // stage: element e = (row r, column c), consecutive threads on
+        // consecutive columns of a row
+        for (int e = threadIdx.x; e < (int)rows * D; e += NT) {
+            const int r = e / D, c = e % D;
+            const uint64_t g = rb + r;
+            const C x = g < a.ngroups ? psi[wide_row(a, g) | wide_col(a, c)] : C{0, 0};
+            rows_lds[r * STRIDE + 2 * c] = x.x;
+            rows_lds[r * STRIDE + 2 * c + 1] = x.y;
+        }
+        __syncthreads();
+        V4 acc[RT][CW];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < CW; ++ct) acc[rt][ct] = V4{0, 0, 0, 0};
+#pragma unroll 2
+        for (int kk = 0; kk < 2 * D; kk += 4) {
+            const int k = kk + lk, c = k >> 1;
+            R xv[RT];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) xv[rt] = rows_lds[(16 * rt + li) * STRIDE + k];
+#pragma unroll
+            for (int ct = 0; ct < CW; ++ct) {
+                const int j = (16 * (ct0 + ct) + li) >> 1;
+                const R bv = sgn * ur[2 * ((size_t)c * D + j) + part];   // from U[j][c]
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = Mfma<R>::mac(xv[rt], bv, acc[rt][ct]);
+            }
+        }
+        __syncthreads();   // the staged rows are read; the next copy may start after the stores
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const uint64_t g = rb + 16 * rt + Mfma<R>::row(l, v);
+                if (g >= a.ngroups) continue;
+                const uint64_t gb = wide_row(a, g);
+#pragma unroll
+                for (int ct = 0; ct < CW; ++ct) {
+                    const int jj = 16 * (ct0 + ct) + li;
+                    outr[2 * (gb | wide_col(a, jj >> 1)) + (jj & 1)] = acc[rt][ct][v];
+                }
+            }
+    }
+}
+
+template <typename R, int D, int RT>
+__global__ __launch_bounds__(64 * kStageWaves) void k_wide_mfma_stage(typename V2<R>::type *__restrict__ psi,
+                                                                      const typename V2<R>::type *__restrict__ mat,
+                                                                      WideGemmArgs a)
+{
+    extern __shared__ unsigned char smem_raw[];
+    k_wide_mfma_stage_body<R, D, RT>(psi, mat, a, reinterpret_cast<R *>(smem_raw));
+}
+
+// Grouped form: member blockIdx.y of up to kMaxGroup states.
+template <typename R, int D, int RT>
+__global__ __launch_bounds__(64 * kStageWaves) void k_wide_mfma_stage_g(Ptrs pp, WideGemmArgs a)
+{
+    typedef typename V2<R>::type C;
+    extern __shared__ unsigned char smem_raw[];
+    k_wide_mfma_stage_body<R, D, RT>(member_ptr<C>(pp.a), member_ptr<const C>(pp.b), a,
+                                     reinterpret_cast<R *>(smem_raw));
+}
+
 // ---------------------------------------------------------------------------
 // Evolution tables on the device: U[a][b] = sum_k V[a][k] V[b][k] e^{+-i phi_k}
 // with phi_k = fmod(w_k t 2^j, 2 pi), accumulated in FP64 and stored in the
@@ -1250,12 +1351,14 @@ sv_status launch_op_t(const DevOp &op, const Group &g, int n, hipStream_t st, in
             for (int j = 1; j < op.k; ++j)
                 if (op.q[j] != op.q[0] + j) a.contiguous = 0;
             const int D = 1 << op.k;
-            // matrix-core form when the launch has rows enough for >= 1024
-            // waves of one 16-row tile: below that (a single state of up to
-            // ~17 qubits) the vector kernel below spreads the rows over more
-            // waves and finishes sooner (measured: a 64-bus, 10-clock solve
-            // took 0.75 ms through the matrix cores, 0.48 ms without)
-            if (D >= 8 && D <= 64 && (uint64_t)cnt * ngroups >= 16384) {
+            // matrix-core form for batch instances (launched in groups of up
+            // to 64), and for states with rows enough for >= 1024 waves of
+            // one 16-row tile: below that a single state (up to ~17 qubits)
+            // finishes sooner on the vector kernel, which spreads the rows
+            // over more waves (a 64-bus, 10-clock solve took 0.75 ms through
+            // the matrix cores, 0.48 ms without).  The choice depends on
+            // each member's own shape only (see Group::batch).
+            if (D >= 8 && D <= 64 && (g.batch || ngroups >= 16384)) {
                 // 16-row tiles per wave as many as keep >= ~1024 waves busy
                 // over the whole group, up to the most the accumulators allow
                 // (a row's arithmetic does not depend on it)
@@ -1280,6 +1383,41 @@ sv_status launch_op_t(const DevOp &op, const Group &g, int n, hipStream_t st, in
                 }
 #undef MFMA_RT
 #undef MFMA_GO
+                break;
+            }
+            // 128 and 256 columns with >= 2048 rows per state: staged
+            // matrix-core form (a workgroup of 16 rows takes about the same
+            // time however many run: 22 us at 128 columns, 59 us at 256; the
+            // vector kernel took 26 and 74 us at 2048 rows, 46 and 99 us at
+            // 4096)
+            if ((D == 128 || D == 256) && ngroups >= 2048) {
+                constexpr int RTS = 1;
+                const uint64_t blocks = (ngroups + 16 * RTS - 1) / (16 * RTS);
+                const unsigned grid = (unsigned)std::min<uint64_t>(blocks, 65536);
+                const size_t smem = sizeof(R) * 16 * RTS * (2 * (size_t)D + 2);
+                if (D == 128) {
+                    launch2(&k_wide_mfma_stage<R, 128, RTS>, &k_wide_mfma_stage_g<R, 128, RTS>, grid,
+                            64 * kStageWaves, smem, st, pp, cnt, a);
+                } else {
+                    // above the default 64 KiB of dynamic LDS at complex128:
+                    // opt the two kernels in once (gfx950 has 160 KiB per CU)
+                    static std::once_flag once;
+                    static hipError_t attr_err = hipSuccess;
+                    std::call_once(once, [&] {
+                        const int bytes = (int)(sizeof(R) * 16 * RTS * (2 * 256 + 2));
+                        attr_err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wide_mfma_stage<R, 256, RTS>),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+                        if (attr_err == hipSuccess)
+                            attr_err = hipFuncSetAttribute(
+                                reinterpret_cast<const void *>(&k_wide_mfma_stage_g<R, 256, RTS>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+                    });
+                    if (attr_err != hipSuccess)
+                        return fail(SV_ERR_HIP, std::string("wide gate: LDS size attribute: ") +
+                                                    hipGetErrorString(attr_err));
+                    launch2(&k_wide_mfma_stage<R, 256, RTS>, &k_wide_mfma_stage_g<R, 256, RTS>, grid,
+                            64 * kStageWaves, smem, st, pp, cnt, a);
+                }
                 break;
             }
             const int rps = D < 64 ? 64 / D : 1;

@@ -37,6 +37,11 @@ struct Group {
     const unsigned char *dbuf[kMaxGroup] = {};   // program image of each member
     double *partials[kMaxGroup] = {};            // kReducePartials doubles each
     double *out[kMaxGroup] = {};                 // one double each (norm result)
+    // Members are instances of a batch: wide gates of 8..64 columns always
+    // take the matrix cores, whatever the row count.  Elsewhere the kernel
+    // follows each member's own row count.  The choice never depends on the
+    // group size, so a member's bits are the same alone or grouped.
+    bool batch = false;
 };
 
 // One device operation, lowered from a circuit gate.

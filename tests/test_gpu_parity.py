@@ -314,11 +314,13 @@ def test_wide_gate_widths(k, control, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("k,control", [(3, True), (4, True), (5, True), (6, True), (6, False), (4, False)])
+@pytest.mark.parametrize("k,control", [(3, True), (4, True), (5, True), (6, True), (6, False), (4, False),
+                                       (7, True), (8, True), (8, False)])
 def test_wide_gate_matrix_cores(k, control, dtype):
-    """Wide gates of 8..64 columns on states with >= 16384 rows per launch,
-    which run on the matrix cores: scattered and contiguous targets."""
-    n = k + 15 + (1 if control else 0)
+    """Wide gates that run on the matrix cores: 8..64 columns on states with
+    >= 16384 rows per launch, 128 and 256 columns (rows staged in LDS) with
+    >= 2048 rows; scattered and contiguous targets."""
+    n = k + (15 if k <= 6 else 12) + (1 if control else 0)
     rng = np.random.default_rng(70 + k + (100 if control else 0))
     qs = rng.choice(n, size=k + (1 if control else 0), replace=False).tolist()
     U = W.random_unitary(1 << k, rng)
