@@ -753,6 +753,8 @@ extern "C" sv_status svb_create(sv_dtype dtype, int k_max, void *hip_stream, svb
     *out = nullptr;
     if (dtype != SV_C128 && dtype != SV_C64) return fail(SV_ERR_INVALID, "svb_create: bad dtype");
     if (k_max < 0 || k_max > 5) return fail(SV_ERR_INVALID, "svb_create: k_max must be 0 (autotuned) or 1..5");
+    const sv_status ps = prepare_kernels();
+    if (ps != SV_OK) return ps;
     auto *b = new (std::nothrow) svb;
     if (!b) return fail(SV_ERR_OOM, "svb_create: out of host memory");
     b->dtype = dtype;

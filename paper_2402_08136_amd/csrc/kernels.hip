@@ -1119,6 +1119,25 @@ void launch2(void (*direct)(T *, const T *, A), void (*grouped)(Ptrs, A), unsign
         hipLaunchKernelGGL(grouped, dim3(gx, cnt), dim3(block), smem, st, pp, args);
 }
 
+// Kernels that need more than the default 64 KiB of dynamic LDS are opted
+// in once (prepare_kernels below).
+sv_status prepare_kernels_once()
+{
+    static std::once_flag once;
+    static hipError_t err = hipSuccess;
+    std::call_once(once, [] {
+        const int bytes = (int)(sizeof(double) * 16 * (2 * 256 + 2));   // 256 columns, complex128
+        err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wide_mfma_stage<double, 256, 1>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (err == hipSuccess)
+            err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wide_mfma_stage_g<double, 256, 1>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    });
+    if (err != hipSuccess)
+        return fail(SV_ERR_HIP, std::string("kernel LDS size attribute: ") + hipGetErrorString(err));
+    return SV_OK;
+}
+
 // Per-member (state, op table) pointers of a grouped launch.
 Ptrs op_ptrs(const DevOp &op, const Group &g)
 {
@@ -1399,22 +1418,11 @@ sv_status launch_op_t(const DevOp &op, const Group &g, int n, hipStream_t st, in
                     launch2(&k_wide_mfma_stage<R, 128, RTS>, &k_wide_mfma_stage_g<R, 128, RTS>, grid,
                             64 * kStageWaves, smem, st, pp, cnt, a);
                 } else {
-                    // above the default 64 KiB of dynamic LDS at complex128:
-                    // opt the two kernels in once (gfx950 has 160 KiB per CU)
-                    static std::once_flag once;
-                    static hipError_t attr_err = hipSuccess;
-                    std::call_once(once, [&] {
-                        const int bytes = (int)(sizeof(R) * 16 * RTS * (2 * 256 + 2));
-                        attr_err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wide_mfma_stage<R, 256, RTS>),
-                                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-                        if (attr_err == hipSuccess)
-                            attr_err = hipFuncSetAttribute(
-                                reinterpret_cast<const void *>(&k_wide_mfma_stage_g<R, 256, RTS>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-                    });
-                    if (attr_err != hipSuccess)
-                        return fail(SV_ERR_HIP, std::string("wide gate: LDS size attribute: ") +
-                                                    hipGetErrorString(attr_err));
+                    // above the default 64 KiB of dynamic LDS at complex128;
+                    // the opt-in is made by prepare_kernels (already done
+                    // here: every state, batch and server calls it first)
+                    const sv_status ps = prepare_kernels();
+                    if (ps != SV_OK) return ps;
                     launch2(&k_wide_mfma_stage<R, 256, RTS>, &k_wide_mfma_stage_g<R, 256, RTS>, grid,
                             64 * kStageWaves, smem, st, pp, cnt, a);
                 }
@@ -1520,6 +1528,10 @@ std::vector<cd> to_sorted(const std::vector<cd> &M, const std::vector<int> &gq, 
 }
 
 }  // namespace
+
+// Called from sv_create, svb_create and svs_start, which never run inside a
+// stream capture, so no launch that a capture records makes the call itself.
+sv_status prepare_kernels() { return prepare_kernels_once(); }
 
 LoweredOp lower_gate_op(const Gate &g0, const HHLParams &h)
 {

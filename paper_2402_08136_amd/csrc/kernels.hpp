@@ -149,6 +149,9 @@ sv_status launch_norm2_group(const Group &g, uint64_t lo, uint64_t hi, sv_dtype 
 // block [P(ancilla = 1), 0, y_0.re, y_0.im, ...] with y_s = psi[2^{n-1} + s]
 // for s < 2^ns, in double; partials[i] is its reduction scratch.
 sv_status launch_postselect_group(const Group &g, int n, int ns, sv_dtype dtype, hipStream_t s);
+
+// One-time kernel attributes (LDS opt-ins); call before any launch or capture.
+sv_status prepare_kernels();
 sv_status launch_gather(const void *psi, const uint64_t *dev_idx, size_t count,
                         void *dev_out, sv_dtype dtype, hipStream_t s);
 

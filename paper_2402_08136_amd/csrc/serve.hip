@@ -930,6 +930,8 @@ extern "C" sv_status svs_start(size_t hbm_budget_bytes, int max_slots, sv_dtype 
     *out = nullptr;
     if (dtype != SV_C128 && dtype != SV_C64) return fail(SV_ERR_INVALID, "svs_start: bad dtype");
     if (max_slots < 1) return fail(SV_ERR_INVALID, "svs_start: max_slots must be >= 1");
+    const sv_status ps = prepare_kernels();
+    if (ps != SV_OK) return ps;
     auto *s = new (std::nothrow) svs;
     if (!s) return fail(SV_ERR_OOM, "svs_start: out of host memory");
     s->dtype = dtype;

@@ -41,6 +41,8 @@ sv_status make_state(int n, sv_dtype dtype, void *buf, size_t bytes, sv_state **
     if (dtype != SV_C128 && dtype != SV_C64) return fail(SV_ERR_INVALID, "sv_create: bad dtype");
     const size_t need = amp_bytes(dtype) << n;
     if (buf && bytes < need) return fail(SV_ERR_INVALID, "sv_create_from_buffer: buffer smaller than 2^n amplitudes");
+    const sv_status ps = prepare_kernels();
+    if (ps != SV_OK) return ps;
     auto *s = new (std::nothrow) sv_state;
     if (!s) return fail(SV_ERR_OOM, "sv_create: out of host memory");
     s->n = n;
