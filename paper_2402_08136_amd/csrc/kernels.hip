@@ -36,18 +36,24 @@ namespace {
 //    each lane already holds one whole group and multiplies it in registers.
 //    With every target >= 6 a load instruction reads 64 consecutive
 //    amplitudes; a target in bits 3..5 splits it into runs of whole cache
-//    lines, so HBM sees the same full-line traffic;
-//  - LDS path (some target inside a cache line): the lanes take the six
-//    lowest index bits and the register bits are the targets >= 6 plus as
-//    many extra non-target bits as there are targets < 6.  The tile goes
-//    through LDS once to regroup it so that each lane holds one group, then
-//    back.  Reads and writes to HBM stay fully coalesced.
+//    lines, so HBM sees the same full-line traffic.  At complex64 each lane
+//    moves two neighbouring amplitudes per access (k_dense_pair);
+//  - butterfly path (one or two targets inside the line at complex128, one
+//    at complex64 with bit 0 not a target, k <= 4): those targets stay lane
+//    bits and are swapped with spare register bits across lanes
+//    (k_dense_bfly, k_dense_bfly_pair);
+//  - LDS path (the other gates with a target inside a cache line): the
+//    lanes take the six lowest index bits and the register bits are the
+//    targets >= 6 plus as many extra non-target bits as there are targets
+//    < 6.  The tile goes through LDS once to regroup it so that each lane
+//    holds one group, then back.  Reads and writes to HBM stay fully
+//    coalesced.
 // The matrix is uniform across the wave and is read through scalar loads.
 // ---------------------------------------------------------------------------
 struct TileArgs {
     uint64_t ntiles;
     uint64_t reg_off[32];   // amplitude offset of register i
-    int rpos[5];            // register-bit positions, ascending, all >= 6
+    int rpos[5];            // register-bit positions, ascending
     uint16_t slot_r[32];    // LDS slot contribution of matrix index r
     uint16_t slot_g[64];    // LDS slot contribution of lane (group) g
     int qsub[2];            // butterfly path: lane bits of the targets inside a line
