@@ -278,6 +278,12 @@ sv_status sv_postselect_solution(sv_state *s, const sv_circuit *hhl,
                                  double *x_hat, int dim,
                                  sv_solution_info *info);
 
+/* Step 4b of Sec. III-A: x = info->scale * x_hat, elementwise over dim
+ * entries, into the caller's x (dim doubles).  SV_ERR_INVALID on a NULL
+ * pointer or dim < 1.  Host only. */
+sv_status sv_solution_x(const double *x_hat, int dim,
+                        const sv_solution_info *info, double *x);
+
 sv_status circuit_destroy(sv_circuit *c);
 
 /* ---- batched solves --------------------------------------------------- */
@@ -303,6 +309,13 @@ sv_status svb_add(svb *bt, const sv_circuit *hhl, int *index_out);
 sv_status svb_run(svb *bt);
 sv_status svb_solution(svb *bt, int index, double *x_hat, int dim,
                        sv_solution_info *info);
+/* svb_postselected: the raw postselected block of instance `index` (Sec.
+ * III-A step 3): y_s = psi[2^{n-1} + s] for s < count (count <= 2^ns), as
+ * 2*count doubles (re, im) widened from the instance's dtype, and
+ * P(ancilla = 1) into *p_anc1 (may be NULL).  SV_ERR_INVALID before the
+ * first svb_run or for a bad index, SV_ERR_SHAPE if count > 2^ns. */
+sv_status svb_postselected(svb *bt, int index, double *y, int count,
+                           double *p_anc1);
 sv_status svb_last_run_ms(const svb *bt, double *ms);
 sv_status svb_size(const svb *bt, int *count);
 sv_status svb_destroy(svb *bt);
@@ -377,6 +390,14 @@ sv_status svs_submit(svs *srv, const double *A, const double *b, int dim,
                      int clock_bits, double t, uint64_t *ticket);
 sv_status svs_poll(svs *srv, uint64_t ticket, double *x_hat, int dim,
                    sv_solution_info *info);
+/* As svs_poll; when the request is done also copies its raw postselected
+ * block y_s = psi[2^{n-1} + s], s < y_count (y_count <= 2^ns; y may be NULL)
+ * as 2*y_count doubles (re, im), and P(ancilla = 1) into *p_anc1 (may be
+ * NULL).  SV_ERR_SHAPE if y_count > 2^ns; the ticket is consumed as by
+ * svs_poll. */
+sv_status svs_poll_ex(svs *srv, uint64_t ticket, double *x_hat, int dim,
+                      sv_solution_info *info, double *y, int y_count,
+                      double *p_anc1);
 sv_status svs_cancel(svs *srv, uint64_t ticket);
 sv_status svs_drain(svs *srv, double timeout_s);
 sv_status svs_stats(svs *srv, double *p50_s, double *p99_s,
@@ -400,6 +421,15 @@ sv_status svb_autotune(sv_dtype dtype, const sv_circuit *sample, int copies,
                        int *best_k, double *ms_per_k);
 
 const char *sv_last_error(void);
+
+/* Test hook: bound the workgroups of every kernel launch made after the call
+ * by max_workgroups (0 = no bound, the default).  Every kernel walks its
+ * tiles or rows with a grid-wide (or per-XCD) loop, so the bound changes
+ * which wave takes which tile, not the arithmetic of any output element; it
+ * lets small states drive the multi-tile loops that large states take.
+ * Graphs captured earlier keep their launch shapes.  Process-wide; not for
+ * use while other threads launch.  SV_ERR_INVALID if negative. */
+sv_status sv_debug_set_grid_cap(int max_workgroups);
 
 /* Sec. III-B qubit estimate, in the reading that reproduces Table I:
  * n_data = ceil(log2 dim), n_qpe = max(n_data + 1, ceil(log2(kappa + 1)))

@@ -113,6 +113,8 @@ _proto("sv_apply_timed", _vp, _vp, _dp, _ip, ctypes.c_int)
 _proto("sv_synchronize", _vp)
 _proto("sv_postselect_solution", _vp, _vp, _dp, ctypes.c_int, ctypes.POINTER(SolutionInfo))
 _proto("circuit_destroy", _vp)
+_proto("sv_solution_x", _dp, ctypes.c_int, ctypes.POINTER(SolutionInfo), _dp)
+_proto("sv_debug_set_grid_cap", ctypes.c_int)
 _proto("sv_qubit_estimate", ctypes.c_int, ctypes.c_double, ctypes.c_int, _ip, _ip, _ip)
 _proto("pf_mismatch_jacobian", ctypes.c_int, ctypes.c_int, _ip, _ip, _dp, _dp, _dp, _ip, _dp, _dp, _dp, _dp,
        _dp, _dp, _dp, _dp, _ip)
@@ -123,6 +125,7 @@ _proto("svb_add", _vp, _vp, _ip)
 _proto("svb_run", _vp)
 _proto("svb_solution", _vp, ctypes.c_int, _dp, ctypes.c_int, ctypes.POINTER(SolutionInfo))
 _proto("svb_last_run_ms", _vp, _dp)
+_proto("svb_postselected", _vp, ctypes.c_int, _dp, ctypes.c_int, _dp)
 _proto("svb_size", _vp, _ip)
 _proto("svb_destroy", _vp)
 _proto("svb_autotune", ctypes.c_int, _vp, ctypes.c_int, _ip, _dp)
@@ -131,6 +134,7 @@ _proto("svs_start", _sz, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp))
 _proto("svs_configure", _vp, ctypes.c_int, ctypes.c_double)
 _proto("svs_submit", _vp, _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.POINTER(_u64))
 _proto("svs_poll", _vp, _u64, _dp, ctypes.c_int, ctypes.POINTER(SolutionInfo))
+_proto("svs_poll_ex", _vp, _u64, _dp, ctypes.c_int, ctypes.POINTER(SolutionInfo), _dp, ctypes.c_int, _dp)
 _proto("svs_cancel", _vp, _u64)
 _proto("svs_drain", _vp, ctypes.c_double)
 _proto("svs_stats", _vp, _dp, _dp, _dp, ctypes.POINTER(_u64))
@@ -388,7 +392,21 @@ def solve(A, b, clock_bits: int, dtype="c128", k_max: int | None = None, t: floa
     s = sv_create(c.n_qubits, dtype)
     s.apply(run)
     x_hat, info = s.postselect_solution(c, len(b))
-    return info["scale"] * x_hat, x_hat, info, c.info()
+    return sv_solution_x(x_hat, info), x_hat, info, c.info()
+
+
+def sv_solution_x(x_hat, info: dict) -> np.ndarray:
+    """Step 4b, in the library: x = scale * x_hat."""
+    x_hat = np.ascontiguousarray(x_hat, dtype=np.float64)
+    si = SolutionInfo(**{k: float(info[k]) for k, _ in SolutionInfo._fields_})
+    x = np.zeros(x_hat.size)
+    _check(_lib.sv_solution_x(_dptr(x_hat), x_hat.size, ctypes.byref(si), _dptr(x)), "sv_solution_x")
+    return x
+
+
+def sv_debug_set_grid_cap(max_workgroups: int):
+    """Test hook: bound every launch's workgroup count (0 = no bound)."""
+    _check(_lib.sv_debug_set_grid_cap(int(max_workgroups)), "sv_debug_set_grid_cap")
 
 
 # ------------------------------------------------------------------- batches
@@ -402,6 +420,7 @@ class Batch:
                "svb_create")
         self.handle = h
         self.dims = []
+        self.ns = []
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -415,7 +434,9 @@ class Batch:
     def add(self, hhl: Circuit) -> int:
         idx = ctypes.c_int()
         _check(_lib.svb_add(self.handle, hhl.handle, ctypes.byref(idx)), "svb_add")
-        self.dims.append(hhl.info()["dim"])
+        inf = hhl.info()
+        self.dims.append(inf["dim"])
+        self.ns.append(inf["n_sys"])
         return idx.value
 
     def __len__(self):
@@ -435,6 +456,18 @@ class Batch:
         _check(_lib.svb_solution(self.handle, index, _dptr(x), dim, ctypes.byref(info)),
                "svb_solution")
         return x, info.as_dict()
+
+
+    def postselected(self, index: int, count: int | None = None):
+        """Raw postselected block y (complex, count <= 2^ns entries) and
+        P(ancilla = 1) of one instance."""
+        ns = self.ns[index]
+        count = (1 << ns) if count is None else count
+        y = np.zeros(2 * count)
+        p1 = ctypes.c_double()
+        _check(_lib.svb_postselected(self.handle, index, _dptr(y), count, ctypes.byref(p1)),
+               "svb_postselected")
+        return y.view(np.complex128), p1.value
 
 
 def svb_autotune(dtype, sample: Circuit, copies: int = 64):
@@ -486,6 +519,23 @@ class Server:
         self.dims.pop(ticket, None)
         _check(rc, "svs_poll")
         return x, info.as_dict()
+
+    def poll_ex(self, ticket: int, y_count: int):
+        """As poll, plus the raw postselected block y (y_count complex
+        entries) and P(ancilla = 1): None while pending, else
+        (x_hat, info, y, p_anc1)."""
+        dim = self.dims[ticket]
+        x = np.zeros(dim)
+        y = np.zeros(2 * y_count)
+        p1 = ctypes.c_double()
+        info = SolutionInfo()
+        rc = _lib.svs_poll_ex(self.handle, ticket, _dptr(x), dim, ctypes.byref(info), _dptr(y), y_count,
+                              ctypes.byref(p1))
+        if rc == 1:
+            return None
+        self.dims.pop(ticket, None)
+        _check(rc, "svs_poll_ex")
+        return x, info.as_dict(), y.view(np.complex128), p1.value
 
     def cancel(self, ticket: int):
         _check(_lib.svs_cancel(self.handle, ticket), "svs_cancel")

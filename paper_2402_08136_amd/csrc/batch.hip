@@ -85,18 +85,25 @@ __device__ void b_diag(C *psi, int n, const BOp &op, const C *d)
     }
 }
 
-// Wide dense gate (e.g. e^{iAt 2^j} on the system register controlled by a
-// clock qubit).  The table holds U^T so that a wave reads row c of U^T
-// (column c of U) coalesced.  Thread (i, s) produces output i of R groups
-// per pass, with the group amplitudes read from the state by broadcast.
+// Wide dense gate with 2^k = D > 256 columns (e.g. e^{iAt 2^j} on a system
+// register of 9 or more qubits, controlled by a clock qubit).  The table
+// holds U^T, so that thread i reads row c of U^T (column c of U) coalesced.
+// The update is in place and every output of a group depends on all D of its
+// inputs, so the block takes one group at a time: thread i accumulates
+// outputs i, i + blockDim, ... (D / blockDim <= kWideGenericOuts of them) in
+// registers, reads every input of the group, and writes only after a barrier
+// that all threads reach; a second barrier keeps the next group's reads
+// behind these writes.
+constexpr int kWideGenericOuts = 16;   // 4096 columns over 256 threads
+static_assert((1 << kMaxDenseQubits) / kThreads <= kWideGenericOuts, "outputs per thread of the widest gate");
+
 template <typename C>
 __device__ void b_wide_generic(C *psi, int n, const BOp &op, const C *UT)
 {
-    constexpr int R = 4;
     const int k = op.k;
     const uint32_t D = 1u << k;
     const uint32_t ngroups = 1u << (n - k - (op.control >= 0 ? 1 : 0));
-    const uint32_t slots = blockDim.x >= D ? blockDim.x / D : 1;
+    const uint32_t nout = D / blockDim.x;   // D > blockDim, both powers of two
     auto off = [&](uint32_t c) -> uint32_t {
         if (op.contiguous) return c << op.q[0];
         uint32_t o = 0;
@@ -116,37 +123,23 @@ __device__ void b_wide_generic(C *psi, int n, const BOp &op, const C *UT)
         if (!placed) b = insert_zero32(b, op.control) | (1u << op.control);
         return b;
     };
-    // outputs handled by this thread: i = tid % D (+ multiples of blockDim
-    // when D > blockDim), group slot s = tid / D
-    const uint32_t s = D <= blockDim.x ? threadIdx.x / D : 0;
-    for (uint32_t chunk = 0; chunk < ngroups; chunk += slots * R) {
-        for (uint32_t i = (D <= blockDim.x ? threadIdx.x % D : threadIdx.x); i < D; i += blockDim.x) {
-            C acc[R];
-            uint32_t gb[R];
+    for (uint32_t g = 0; g < ngroups; ++g) {
+        const uint32_t gb = gbase(g);
+        C acc[kWideGenericOuts];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                acc[r] = C{0, 0};
-                const uint32_t g = chunk + s + slots * r;
-                gb[r] = g < ngroups ? gbase(g) : 0xffffffffu;
-            }
-            if (threadIdx.x < slots * D || D > blockDim.x) {
-                for (uint32_t c = 0; c < D; ++c) {
-                    const C u = UT[(size_t)c * D + i];
-                    const uint32_t oc = off(c);
+        for (int p = 0; p < kWideGenericOuts; ++p) acc[p] = C{0, 0};
+        for (uint32_t c = 0; c < D; ++c) {
+            const C x = psi[gb | off(c)];
+            const C *u = UT + (size_t)c * D + threadIdx.x;
 #pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        if (gb[r] != 0xffffffffu) cmac(acc[r], u, psi[gb[r] | oc]);
-                }
-            }
-            __syncthreads();
-            if (threadIdx.x < slots * D || D > blockDim.x) {
-                const uint32_t oi = off(i);
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-                    if (gb[r] != 0xffffffffu) psi[gb[r] | oi] = acc[r];
-            }
-            __syncthreads();
+            for (int p = 0; p < kWideGenericOuts; ++p)
+                if ((uint32_t)p < nout) cmac(acc[p], u[(size_t)p * blockDim.x], x);
         }
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < kWideGenericOuts; ++p)
+            if ((uint32_t)p < nout) psi[gb | off(threadIdx.x + (uint32_t)p * blockDim.x)] = acc[p];
+        __syncthreads();
     }
 }
 
@@ -920,6 +913,20 @@ extern "C" sv_status svb_solution(svb *b, int index, double *x_hat, int dim, sv_
     const HHLParams &h = b->params[index];
     if (dim != h.dim) return fail(SV_ERR_SHAPE, "svb_solution: dim differs from the instance's");
     return recover_solution(h, b->h_out + b->insts[index].out_off, x_hat, dim, info);
+}
+
+extern "C" sv_status svb_postselected(svb *b, int index, double *y, int count, double *p_anc1)
+{
+    if (!b || !y) return fail(SV_ERR_INVALID, "svb_postselected: NULL argument");
+    if (index < 0 || index >= (int)b->insts.size())
+        return fail(SV_ERR_INVALID, "svb_postselected: index out of range");
+    if (!b->have_result) return fail(SV_ERR_INVALID, "svb_postselected: batch has not run");
+    const HHLParams &h = b->params[index];
+    if (count < 0 || count > (1 << h.ns)) return fail(SV_ERR_SHAPE, "svb_postselected: count exceeds 2^ns");
+    const double *o = b->h_out + b->insts[index].out_off;
+    std::memcpy(y, o + 2, sizeof(double) * 2 * (size_t)count);
+    if (p_anc1) *p_anc1 = o[0];
+    return SV_OK;
 }
 
 extern "C" sv_status svb_destroy(svb *b)

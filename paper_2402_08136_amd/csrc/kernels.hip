@@ -7,6 +7,7 @@
 // of the index.  A k-qubit gate on sorted targets q_0 < ... < q_{k-1} maps
 // each group of 2^k amplitudes {base + sum_j bit_j(r) 2^{q_j}} by its matrix.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -1102,10 +1103,19 @@ __global__ __launch_bounds__(256) void k_gather(const typename V2<R>::type *__re
         out[i] = psi[idx[i]];
 }
 
+// Upper bound on the workgroups of every launch (0 = none).  Every kernel
+// here walks its work with a grid-wide (or XCD-sliced) loop, so a smaller
+// grid changes only which wave handles which tile, never an output element's
+// arithmetic.  Tests lower it so that small states drive the multi-tile
+// loops that large states take.
+std::atomic<unsigned> g_grid_cap{0};
+
 inline unsigned grid_for(uint64_t work, unsigned per_block, unsigned cap)
 {
     uint64_t g = (work + per_block - 1) / per_block;
     if (g < 1) g = 1;
+    const unsigned tc = g_grid_cap.load(std::memory_order_relaxed);
+    if (tc != 0 && tc < cap) cap = tc;
     return (unsigned)std::min<uint64_t>(g, cap);
 }
 
@@ -1417,8 +1427,7 @@ sv_status launch_op_t(const DevOp &op, const Group &g, int n, hipStream_t st, in
             // 4096)
             if ((D == 128 || D == 256) && ngroups >= 2048) {
                 constexpr int RTS = 1;
-                const uint64_t blocks = (ngroups + 16 * RTS - 1) / (16 * RTS);
-                const unsigned grid = (unsigned)std::min<uint64_t>(blocks, 65536);
+                const unsigned grid = grid_for(ngroups, 16 * RTS, 65536);
                 const size_t smem = sizeof(R) * 16 * RTS * (2 * (size_t)D + 2);
                 if (D == 128) {
                     launch2(&k_wide_mfma_stage<R, 128, RTS>, &k_wide_mfma_stage_g<R, 128, RTS>, grid,
@@ -1954,3 +1963,10 @@ sv_status launch_gather(const void *psi, const uint64_t *dev_idx, size_t count,
 }
 
 }  // namespace hhlsv
+
+extern "C" sv_status sv_debug_set_grid_cap(int max_workgroups)
+{
+    if (max_workgroups < 0) return hhlsv::fail(SV_ERR_INVALID, "sv_debug_set_grid_cap: negative cap");
+    hhlsv::g_grid_cap.store((unsigned)max_workgroups, std::memory_order_relaxed);
+    return SV_OK;
+}

@@ -1056,6 +1056,12 @@ extern "C" sv_status svs_submit(svs *s, const double *A, const double *b, int di
 
 extern "C" sv_status svs_poll(svs *s, uint64_t ticket, double *x_hat, int dim, sv_solution_info *info)
 {
+    return svs_poll_ex(s, ticket, x_hat, dim, info, nullptr, 0, nullptr);
+}
+
+extern "C" sv_status svs_poll_ex(svs *s, uint64_t ticket, double *x_hat, int dim, sv_solution_info *info,
+                                 double *y, int y_count, double *p_anc1)
+{
     if (!s) return fail(SV_ERR_INVALID, "svs_poll: NULL server");
     std::shared_ptr<Req> r;
     {
@@ -1069,6 +1075,11 @@ extern "C" sv_status svs_poll(svs *s, uint64_t ticket, double *x_hat, int dim, s
     if (r->status != SV_OK) return fail(r->status, r->err);
     if (!x_hat) return fail(SV_ERR_INVALID, "svs_poll: x_hat is NULL");
     if (dim != r->h.dim) return fail(SV_ERR_SHAPE, "svs_poll: dim differs from the request's");
+    if (y) {
+        if (y_count < 0 || y_count > (1 << r->h.ns)) return fail(SV_ERR_SHAPE, "svs_poll_ex: y_count exceeds 2^ns");
+        std::memcpy(y, r->result.data() + 2, sizeof(double) * 2 * (size_t)y_count);
+    }
+    if (p_anc1) *p_anc1 = r->result[0];
     return recover_solution(r->h, r->result.data(), x_hat, dim, info);
 }
 

@@ -280,5 +280,11 @@ extern "C" sv_status sv_postselect_solution(sv_state *s, const sv_circuit *hhl, 
     }
     if (st != SV_OK) return st;
     return recover_solution(h, buf.data(), x_hat, dim, info);
+}
+
+extern "C" sv_status sv_solution_x(const double *x_hat, int dim, const sv_solution_info *info, double *x)
+{
+    if (!x_hat || !info || !x || dim < 1) return fail(SV_ERR_INVALID, "sv_solution_x: NULL argument or dim < 1");
+    for (int i = 0; i < dim; ++i) x[i] = info->scale * x_hat[i];
     return SV_OK;
 }

@@ -81,5 +81,34 @@ def inverse_gates(gates):
     return out
 
 
+def oracle_postselected(A, b, m, flags=0, t=0.0):
+    """The oracle's solve of (A, b) with m clock qubits: (x_hat, info, y)
+    with y_s = psi[2^{n-1} + s], s < 2^ns, the postselected block of Sec.
+    III-A step 3."""
+    import oracle
+    psi, _, xh, info = oracle.hhl_solve(A, b, m, t, flags=flags)
+    half = 1 << (info["n"] - 1)
+    return xh, info, psi[half:half + (1 << info["ns"])].copy()
+
+
+AMP_TOL = {"c128": 1e-12, "c64": 2e-5}
+
+
+def check_postselected(y, p1, x_hat, ref, dtype, what=""):
+    """A batched or served result against the oracle: the raw block y and
+    P(ancilla = 1) at the amplitude bar; x_hat = Re(y)/||Re y|| (over the
+    x entries) through the bound an amplitude error e gives it,
+    |d x_hat| ||Re y|| <= e (1 + sqrt(2^ns)).  Returns max |d y|."""
+    xh_ref, info_ref, y_ref = ref
+    tol = AMP_TOL[dtype]
+    err_y = float(np.max(np.abs(np.asarray(y) - y_ref)))
+    assert err_y <= tol, (what, err_y)
+    assert abs(p1 - info_ref["p1"]) <= tol, what
+    xo = int(info_ref["x_off"])
+    rn = float(np.linalg.norm(y_ref.real[xo:xo + np.size(xh_ref)]))
+    assert np.max(np.abs(np.asarray(x_hat) - xh_ref)) * rn <= tol * (1 + np.sqrt(y_ref.size)), what
+    return err_y
+
+
 def max_abs_diff(a, b) -> float:
     return float(np.max(np.abs(np.asarray(a) - np.asarray(b)))) if np.size(a) else 0.0

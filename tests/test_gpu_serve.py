@@ -10,6 +10,7 @@ import pytest
 
 import oracle
 import workloads as W
+from _ref import check_postselected, oracle_postselected
 
 pytestmark = pytest.mark.gpu
 
@@ -38,7 +39,10 @@ def _systems(shapes, seed0=500):
     return out
 
 
-def _wait_all(srv, tickets, timeout=120.0):
+def _wait_all(srv, tickets, timeout=120.0, y_counts=None):
+    """Poll until every ticket is done: {ticket: (x_hat, info) or the
+    error}; with y_counts ({ticket: 2^ns}) the results are (x_hat, info, y,
+    p_anc1) with the raw postselected block."""
     res = {}
     t0 = time.time()
     while len(res) < len(tickets):
@@ -46,7 +50,7 @@ def _wait_all(srv, tickets, timeout=120.0):
             if t in res:
                 continue
             try:
-                r = srv.poll(t)
+                r = srv.poll_ex(t, y_counts[t]) if y_counts else srv.poll(t)
             except Exception as e:     # noqa: BLE001 - failures are results here
                 res[t] = e
                 continue
@@ -66,15 +70,15 @@ def test_serving_matches_oracle(dtype, route):
             "lds+hbm": {"lds_max_qubits": -1, "batch_max_qubits": 17}}[route]
     srv = hs.Server(dtype, k_max=3, **opts)
     tickets = [srv.submit(A, b, m) for A, b, m in systems]
-    res = _wait_all(srv, tickets)
-    tol = 1e-10 if dtype == "c128" else 2e-5
+    res = _wait_all(srv, tickets, y_counts={t: 1 << ns for t, (ns, _) in zip(tickets, MIX)})
+    worst = 0.0
     for t, (A, b, m) in zip(tickets, systems):
-        _, _, xh, info_ref = oracle.hhl_solve(A, b, m, want_state=False)
-        x_hat, info = res[t]
-        scale = np.sqrt(max(info_ref["p10"], 1e-30))
-        assert np.max(np.abs(x_hat - xh)) * scale <= tol
-        assert abs(info["p_anc1"] - info_ref["p1"]) <= tol
-        assert float(np.dot(x_hat, xh) ** 2) >= 0.999
+        ref = oracle_postselected(A, b, m)
+        x_hat, info, y, p1 = res[t]
+        assert p1 == info["p_anc1"]
+        worst = max(worst, check_postselected(y, p1, x_hat, ref, dtype, (t, route)))
+        assert float(np.dot(x_hat, ref[0]) ** 2) >= 0.999
+    _say(f"serve {dtype} {route}: max|dy| vs oracle {worst:.3e}")
     st = srv.stats()
     prof = srv.profile()
     _say(f"serve {dtype}: {st} {prof}")
@@ -114,23 +118,19 @@ def test_grouped_launches_equal_single_launches_bitwise(dtype):
     systems = _systems(shapes, seed0=900)
     grouped = hs.Server(dtype, k_max=3, launchers=1, group_window_us=300000)
     tickets = [grouped.submit(A, b, m) for A, b, m in systems]
-    res_g = _wait_all(grouped, tickets)
+    res_g = _wait_all(grouped, tickets, y_counts={t: 1 << ns for t, (ns, _) in zip(tickets, shapes)})
     prof = grouped.profile()
     grouped.stop()
     _say(f"grouped {dtype}: {prof}")
     assert prof["groups"] >= 2 and prof["grouped"] >= 6
     single = hs.Server(dtype, k_max=3, launchers=1)
-    tol = 1e-10 if dtype == "c128" else 2e-5
-    for t, (A, b, m) in zip(tickets, systems):
+    for t, (A, b, m), (ns, _) in zip(tickets, systems, shapes):
         t1 = single.submit(A, b, m)
-        x1, info1 = _wait_all(single, [t1])[t1]
-        xg, info_g = res_g[t]
-        assert np.array_equal(x1, xg)
+        x1, info1, y1, _ = _wait_all(single, [t1], y_counts={t1: 1 << ns})[t1]
+        xg, info_g, yg, p1g = res_g[t]
+        assert np.array_equal(x1, xg) and np.array_equal(y1, yg)
         assert info1 == info_g
-        _, _, xh, info_ref = oracle.hhl_solve(A, b, m, want_state=False)
-        scale = np.sqrt(max(info_ref["p10"], 1e-30))
-        assert np.max(np.abs(xg - xh)) * scale <= tol
-        assert abs(info_g["p_anc1"] - info_ref["p1"]) <= tol
+        check_postselected(yg, p1g, xg, oracle_postselected(A, b, m), dtype, t)
     assert single.profile()["groups"] == 0
     single.stop()
 
@@ -194,3 +194,39 @@ def test_queue_limit_and_cancel():
     assert n_cancel == cancelled
     assert all(not isinstance(r, Exception) or "cancelled" in str(r) for r in res.values())
     srv.stop()
+
+
+_NS9 = {}
+
+
+def _ns9_system():
+    """A 512-bus system (511 reduced + 1 pad = 2^9: 9 system qubits) with 2
+    clock qubits: n = 12, which fits in LDS at both precisions, so the
+    controlled evolutions (512 columns) run through the batched kernel's
+    wide gate for more columns than a workgroup has threads."""
+    if not _NS9:
+        A, b = W.dc_powerflow(512, 5)
+        _NS9["sys"] = (A, b, 2)
+        _NS9["ref"] = oracle_postselected(A, b, 2)
+    return _NS9["sys"], _NS9["ref"]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_nine_system_qubits_batched_and_served(dtype):
+    hs = _hs()
+    (A, b, m), ref = _ns9_system()
+    bt = hs.Batch(dtype, 3)
+    c = hs.circuit_build_hhl(A, b, m)
+    assert c.n_qubits == 12 and c.info()["n_sys"] == 9
+    bt.add(c)
+    bt.run()
+    x_hat, info = bt.solution(0)
+    y, p1 = bt.postselected(0)
+    err_b = check_postselected(y, p1, x_hat, ref, dtype, "batch")
+    srv = hs.Server(dtype, k_max=3, lds_max_qubits=-1)
+    t = srv.submit(A, b, m)
+    xs, infos, ys, p1s = _wait_all(srv, [t], y_counts={t: 512})[t]
+    assert srv.profile()["batched"] == 1
+    srv.stop()
+    err_s = check_postselected(ys, p1s, xs, ref, dtype, "served")
+    _say(f"ns=9 m=2 {dtype}: max|dy| batch {err_b:.3e}, served {err_s:.3e}")

@@ -15,6 +15,7 @@ import pytest
 
 import oracle
 import workloads as W
+from _ref import AMP_TOL, check_postselected, oracle_postselected
 
 pytestmark = pytest.mark.gpu
 
@@ -114,25 +115,24 @@ def test_signed_dilated_batch_matches_oracle(dtype):
         bt.add(c)
     ms = bt.run()
     _say(f"signed/dilated batch {dtype}: {len(bt)} instances in {ms:.3f} ms")
-    tol = 1e-10 if dtype == "c128" else 2e-5
+    tol = AMP_TOL[dtype]
     for i, (mode, A, b, m, t) in enumerate(items):
-        _, _, xh_ref, info_ref = oracle.hhl_solve(A, b, m, t, want_state=False,
-                                                  flags=OFLAGS.get(mode, 0))
+        ref = oracle_postselected(A, b, m, OFLAGS.get(mode, 0), t)
+        info_ref = ref[1]
         x_hat, info = bt.solution(i)
-        scale = np.sqrt(max(info_ref["p10"], 1e-30))
-        assert np.max(np.abs(x_hat - xh_ref)) * scale <= tol, (i, mode)
-        assert abs(info["p_anc1"] - info_ref["p1"]) <= tol
-        assert abs(info["p_anc1_clock0"] - info_ref["p10"]) <= tol
-        assert abs(info["pad_leak"] - info_ref["pad_leak"]) <= tol
+        y, p1 = bt.postselected(i)
+        check_postselected(y, p1, x_hat, ref, dtype, (i, mode))
+        assert abs(info["p_anc1_clock0"] - info_ref["p10"]) <= 2 * tol * np.sqrt(y.size)
+        assert abs(info["pad_leak"] - info_ref["pad_leak"]) <= 2 * tol * np.sqrt(y.size)
 
 
-def _wait_all(srv, tickets, timeout=120.0):
+def _wait_all(srv, tickets, timeout=120.0, y_counts=None):
     res = {}
     t0 = time.time()
     while len(res) < len(tickets):
         for t in tickets:
             if t not in res:
-                r = srv.poll(t)
+                r = srv.poll_ex(t, y_counts[t]) if y_counts else srv.poll(t)
                 if r is not None:
                     res[t] = r
         if time.time() - t0 > timeout:
@@ -157,14 +157,11 @@ def test_serving_auto_mode_matches_oracle(dtype, lds):
         reqs.append((oracle.HHL_DILATE, G, bg, 7))
     srv = hs.Server(dtype, k_max=3, mode="auto", lds_max_qubits=lds)
     tickets = [srv.submit(A, b, m) for _, A, b, m in reqs]
-    res = _wait_all(srv, tickets)
-    tol = 1e-10 if dtype == "c128" else 2e-5
-    for t, (fl, A, b, m) in zip(tickets, reqs):
-        _, _, xh, info_ref = oracle.hhl_solve(A, b, m, want_state=False, flags=fl)
-        x_hat, info = res[t]
-        scale = np.sqrt(max(info_ref["p10"], 1e-30))
-        assert np.max(np.abs(x_hat - xh)) * scale <= tol
-        assert abs(info["p_anc1"] - info_ref["p1"]) <= tol
+    refs = {t: oracle_postselected(A, b, m, fl) for t, (fl, A, b, m) in zip(tickets, reqs)}
+    res = _wait_all(srv, tickets, y_counts={t: 1 << refs[t][1]["ns"] for t in tickets})
+    for t in tickets:
+        x_hat, info, y, p1 = res[t]
+        check_postselected(y, p1, x_hat, refs[t], dtype, t)
     st = srv.stats()
     _say(f"serve auto {dtype}: {st}")
     assert st["done"] == len(reqs) and st["failed"] == 0
