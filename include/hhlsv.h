@@ -125,13 +125,23 @@ sv_status sv_create(int n_qubits, sv_dtype dtype, sv_state **out);
 
 /* Wrap caller-owned device memory (e.g. a torch tensor) of at least
  * 2^n * amplitude-size bytes; the contents are left as they are.  The
- * memory must outlive the state. */
+ * memory must outlive the state.  The library links the system HIP runtime;
+ * a torch build that bundles its own runtime must initialise it (first
+ * torch.cuda call) before the library's first device call in the process. */
 sv_status sv_create_from_buffer(void *dev_ptr, size_t bytes, int n_qubits,
                                 sv_dtype dtype, sv_state **out);
 
 /* Order the state's device work on a caller stream (hipStream_t, e.g.
  * torch.cuda.current_stream().cuda_stream); NULL restores the state's own. */
 sv_status sv_set_stream(sv_state *s, void *hip_stream);
+
+/* The state's device memory and stream, for callers that work on the
+ * amplitudes themselves: *dev_ptr the device address of the 2^n amplitudes,
+ * *bytes (may be NULL) their size, *hip_stream (may be NULL) the stream its
+ * work is ordered on.  The state keeps ownership; the address is valid until
+ * sv_destroy.  Host only. */
+sv_status sv_device_buffer(const sv_state *s, void **dev_ptr, size_t *bytes,
+                           void **hip_stream);
 
 /* Free the state (and its memory unless adopted). */
 sv_status sv_destroy(sv_state *s);
@@ -283,6 +293,25 @@ sv_status sv_postselect_solution(sv_state *s, const sv_circuit *hhl,
  * pointer or dim < 1.  Host only. */
 sv_status sv_solution_x(const double *x_hat, int dim,
                         const sv_solution_info *info, double *x);
+
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * readout of sv_postselect_solution, with the same results, on a state the
+ * caller owns.  dev_psi: device pointer to the 2^n_qubits amplitudes of
+ * dtype (bytes = its size, at least 2^n_qubits amplitudes); hip_stream: the
+ * stream the work is ordered on (NULL = the null stream); hhl, x_hat, dim
+ * and info as in sv_postselect_solution.  Allocates nothing: the reduction
+ * partials and the postselected block go to a fixed device array of
+ * 1024 + 2 + 2*1024 doubles per GPU (about 24 KiB, held until the process
+ * ends), so the circuit may have at most 10 system qubits (SV_ERR_SHAPE
+ * beyond).  Calls that overlap on one GPU share that array and race.
+ * Synchronises hip_stream. */
+sv_status sv_postselect_solution_noalloc(const void *dev_psi, size_t bytes,
+                                         int n_qubits, sv_dtype dtype,
+                                         void *hip_stream,
+                                         const sv_circuit *hhl,
+                                         double *x_hat, int dim,
+                                         sv_solution_info *info);
 
 sv_status circuit_destroy(sv_circuit *c);
 

@@ -93,6 +93,7 @@ _lib.sv_last_error.restype = ctypes.c_char_p
 _proto("sv_create", ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp))
 _proto("sv_create_from_buffer", _vp, _sz, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp))
 _proto("sv_set_stream", _vp, _vp)
+_proto("sv_device_buffer", _vp, ctypes.POINTER(_vp), ctypes.POINTER(_sz), ctypes.POINTER(_vp))
 _proto("sv_destroy", _vp)
 _proto("sv_reset", _vp)
 _proto("sv_get_amplitudes", _vp, _sz, _sz, _vp)
@@ -112,6 +113,8 @@ _proto("sv_apply", _vp, _vp)
 _proto("sv_apply_timed", _vp, _vp, _dp, _ip, ctypes.c_int)
 _proto("sv_synchronize", _vp)
 _proto("sv_postselect_solution", _vp, _vp, _dp, ctypes.c_int, ctypes.POINTER(SolutionInfo))
+_proto("sv_postselect_solution_noalloc", _vp, _sz, ctypes.c_int, ctypes.c_int, _vp, _vp, _dp, ctypes.c_int,
+       ctypes.POINTER(SolutionInfo))
 _proto("circuit_destroy", _vp)
 _proto("sv_solution_x", _dp, ctypes.c_int, ctypes.POINTER(SolutionInfo), _dp)
 _proto("sv_debug_set_grid_cap", ctypes.c_int)
@@ -319,6 +322,13 @@ class State:
     def reset(self):
         _check(_lib.sv_reset(self.handle), "sv_reset")
 
+    def device_buffer(self):
+        """(device address, bytes, hipStream_t) of the state's amplitudes."""
+        p, nb, st = _vp(), _sz(), _vp()
+        _check(_lib.sv_device_buffer(self.handle, ctypes.byref(p), ctypes.byref(nb), ctypes.byref(st)),
+               "sv_device_buffer")
+        return p.value, nb.value, st.value
+
     def get(self, offset: int = 0, count: int | None = None) -> np.ndarray:
         if count is None:
             count = (1 << self.n) - offset
@@ -380,6 +390,20 @@ def sv_apply(s: State, c: Circuit):
 
 def sv_postselect_solution(s: State, hhl: Circuit, dim: int):
     return s.postselect_solution(hhl, dim)
+
+
+def sv_postselect_solution_noalloc(dev_ptr: int, nbytes: int, n_qubits: int, dtype, stream,
+                                   hhl: Circuit, dim: int):
+    """The readout of sv_postselect_solution on caller-owned device memory
+    (a raw device address of 2^n_qubits amplitudes), with no allocation in
+    the library.  stream: a torch stream or a raw hipStream_t integer."""
+    ptr = getattr(stream, "cuda_stream", stream)
+    x = np.zeros(dim)
+    info = SolutionInfo()
+    _check(_lib.sv_postselect_solution_noalloc(_vp(dev_ptr), nbytes, n_qubits, DTYPES[dtype],
+                                               _vp(ptr) if ptr else None, hhl.handle, _dptr(x), dim,
+                                               ctypes.byref(info)), "sv_postselect_solution_noalloc")
+    return x, info.as_dict()
 
 
 def solve(A, b, clock_bits: int, dtype="c128", k_max: int | None = None, t: float = 0.0,

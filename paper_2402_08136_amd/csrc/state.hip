@@ -101,6 +101,15 @@ extern "C" sv_status sv_create_from_buffer(void *dev_ptr, size_t bytes, int n_qu
     return make_state(n_qubits, dtype, dev_ptr, bytes, out);
 }
 
+extern "C" sv_status sv_device_buffer(const sv_state *s, void **dev_ptr, size_t *bytes, void **hip_stream)
+{
+    if (!s || !dev_ptr) return fail(SV_ERR_INVALID, "sv_device_buffer: NULL argument");
+    *dev_ptr = s->psi;
+    if (bytes) *bytes = amp_bytes(s->dtype) << s->n;
+    if (hip_stream) *hip_stream = s->stream;
+    return SV_OK;
+}
+
 extern "C" sv_status sv_set_stream(sv_state *s, void *hip_stream)
 {
     if (!s) return fail(SV_ERR_INVALID, "sv_set_stream: NULL state");
@@ -287,4 +296,82 @@ extern "C" sv_status sv_solution_x(const double *x_hat, int dim, const sv_soluti
     if (!x_hat || !info || !x || dim < 1) return fail(SV_ERR_INVALID, "sv_solution_x: NULL argument or dim < 1");
     for (int i = 0; i < dim; ++i) x[i] = info->scale * x_hat[i];
     return SV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Postselected readout that allocates nothing (for callers that cannot
+// allocate device memory: code under stream capture, tight serving loops).
+// The reduction partials and the widened y block live in one file-scope
+// device array per GPU; its device address is looked up once per device.
+// Every call on a GPU shares that GPU's array, so calls that overlap on one
+// GPU race; each call overwrites every element it later reads.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kNoAllocMaxSys = 10;   // y block of at most 2^10 amplitudes
+constexpr size_t kNoAllocBlock = 2 + 2 * (size_t(1) << kNoAllocMaxSys);
+constexpr size_t kNoAllocDoubles = kReducePartials + kNoAllocBlock;
+constexpr int kNoAllocMaxDevices = 64;
+
+std::once_flag g_scratch_once[kNoAllocMaxDevices];
+double *g_scratch_ptr[kNoAllocMaxDevices];
+hipError_t g_scratch_err[kNoAllocMaxDevices];
+}  // namespace
+
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+// Device address of this device's copy of `scratch` (the device must be
+// current).  Host code uses only this address, never the array's name.
+static sv_status noalloc_scratch(int dev, double **out)
+{
+    if (dev < 0 || dev >= kNoAllocMaxDevices)
+        return fail(SV_ERR_INVALID, "sv_postselect_solution_noalloc: device index beyond 63");
+    std::call_once(g_scratch_once[dev], [dev] {
+        void *p = nullptr;
+        g_scratch_err[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    });
+    if (g_scratch_err[dev] != hipSuccess || !g_scratch_ptr[dev])
+        return fail(SV_ERR_HIP, std::string("sv_postselect_solution_noalloc: scratch address: ") +
+                                    hipGetErrorString(g_scratch_err[dev]));
+    *out = g_scratch_ptr[dev];
+    return SV_OK;
+}
+
+extern "C" sv_status sv_postselect_solution_noalloc(const void *dev_psi, size_t bytes, int n_qubits,
+                                                    sv_dtype dtype, void *hip_stream, const sv_circuit *hhl,
+                                                    double *x_hat, int dim, sv_solution_info *info)
+{
+    if (!dev_psi || !hhl || !x_hat) return fail(SV_ERR_INVALID, "sv_postselect_solution_noalloc: NULL argument");
+    if (dtype != SV_C128 && dtype != SV_C64) return fail(SV_ERR_INVALID, "sv_postselect_solution_noalloc: bad dtype");
+    if (n_qubits < 2 || n_qubits > kMaxQubits)
+        return fail(SV_ERR_INVALID, "sv_postselect_solution_noalloc: n_qubits must be in [2, 34]");
+    if (bytes < (amp_bytes(dtype) << n_qubits))
+        return fail(SV_ERR_INVALID, "sv_postselect_solution_noalloc: buffer smaller than 2^n amplitudes");
+    const HHLParams &h = hhl->c.hhl;
+    if (!h.is_hhl) return fail(SV_ERR_INVALID, "sv_postselect_solution_noalloc: not an HHL circuit");
+    if (hhl->c.n != n_qubits) return fail(SV_ERR_SHAPE, "sv_postselect_solution_noalloc: circuit and state differ in size");
+    if (dim != h.dim) return fail(SV_ERR_SHAPE, "sv_postselect_solution_noalloc: dim differs from the circuit's");
+    if (h.ns > kNoAllocMaxSys)
+        return fail(SV_ERR_SHAPE, "sv_postselect_solution_noalloc: more than 10 system qubits (the scratch holds a "
+                                  "postselected block of at most 1024 amplitudes)");
+    int dev = 0;
+    HIPCK(hipGetDevice(&dev));
+    double *scr = nullptr;
+    sv_status st = noalloc_scratch(dev, &scr);
+    if (st != SV_OK) return st;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    // [partials | P(anc = 1), 0, y_0.re, y_0.im, ...]: every element read
+    // below is written by this call's kernels first
+    Group g;
+    g.count = 1;
+    g.psi[0] = const_cast<void *>(dev_psi);
+    g.partials[0] = scr;
+    g.out[0] = scr + kReducePartials;
+    st = launch_postselect_group(g, n_qubits, h.ns, dtype, stream);
+    if (st != SV_OK) return st;
+    const size_t D = size_t(1) << h.ns;
+    double block[kNoAllocBlock];
+    HIPCK(hipMemcpyAsync(block, scr + kReducePartials, sizeof(double) * (2 + 2 * D), hipMemcpyDeviceToHost, stream));
+    HIPCK(hipStreamSynchronize(stream));
+    return recover_solution(h, block, x_hat, dim, info);
 }
