@@ -265,9 +265,12 @@ typedef enum {
     SV_KERNEL_DIAG = 3,         /* diagonal gate                                */
     SV_KERNEL_WIDE = 4,         /* dense gate on 6..12 targets, optional control */
     SV_KERNEL_UCRY = 5,         /* uniformly controlled RY                      */
-    SV_KERNEL_DENSE_BFLY = 6    /* dense k <= 4 at c128 with one or two targets
+    SV_KERNEL_DENSE_BFLY = 6,   /* dense k <= 4 at c128 with one or two targets
                                    inside a line: cross-lane butterfly, groups
                                    held in registers                     */
+    SV_KERNEL_DENSE_MFMA = 7    /* dense k = 5 on >= 9 qubits, every target
+                                   inside a line among the two lowest:
+                                   16x16x4 matrix-core products          */
 } sv_kernel_family;
 
 /* As sv_apply, and record the device time of each gate's launch with HIP
@@ -459,6 +462,14 @@ const char *sv_last_error(void);
  * Graphs captured earlier keep their launch shapes.  Process-wide; not for
  * use while other threads launch.  SV_ERR_INVALID if negative. */
 sv_status sv_debug_set_grid_cap(int max_workgroups);
+
+/* Select the form of 5-qubit dense gates for launches made after the call:
+ * enable != 0 (the default) the matrix-core kernel where it applies, 0 the
+ * vector kernels everywhere.  Both compute the same gate (Sec. II-C fused
+ * gates); the switch exists to compare and test them.  Process-wide; not for
+ * use while other threads launch; graphs captured earlier keep their
+ * kernels. */
+sv_status sv_debug_set_dense_mfma(int enable);
 
 /* Sec. III-B qubit estimate, in the reading that reproduces Table I:
  * n_data = ceil(log2 dim), n_qpe = max(n_data + 1, ceil(log2(kappa + 1)))

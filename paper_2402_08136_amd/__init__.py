@@ -33,7 +33,7 @@ KIND = {"h": 0, "x": 1, "ry": 2, "rz": 3, "p": 4, "u3": 5, "cx": 6, "cp": 7,
         "swap": 8, "dense": 9, "cdense": 10, "ucry": 11, "diag": 12}
 KIND_NAME = {v: k for k, v in KIND.items()}
 KERNEL_FAMILY = {0: "dense_direct", 1: "dense_lds", 2: "dense_small", 3: "diag",
-                 4: "wide", 5: "ucry", 6: "dense_bfly"}
+                 4: "wide", 5: "ucry", 6: "dense_bfly", 7: "dense_mfma"}
 STATUS = {0: "SV_OK", 1: "SV_PENDING", -1: "SV_ERR_INVALID", -2: "SV_ERR_OOM",
           -3: "SV_ERR_HIP", -4: "SV_ERR_NOT_SYMMETRIC", -5: "SV_ERR_NOT_POSDEF",
           -6: "SV_ERR_SHAPE", -7: "SV_ERR_BUSY", -8: "SV_ERR_SINGULAR"}
@@ -118,6 +118,7 @@ _proto("sv_postselect_solution_noalloc", _vp, _sz, ctypes.c_int, ctypes.c_int, _
 _proto("circuit_destroy", _vp)
 _proto("sv_solution_x", _dp, ctypes.c_int, ctypes.POINTER(SolutionInfo), _dp)
 _proto("sv_debug_set_grid_cap", ctypes.c_int)
+_proto("sv_debug_set_dense_mfma", ctypes.c_int)
 _proto("sv_qubit_estimate", ctypes.c_int, ctypes.c_double, ctypes.c_int, _ip, _ip, _ip)
 _proto("pf_mismatch_jacobian", ctypes.c_int, ctypes.c_int, _ip, _ip, _dp, _dp, _dp, _ip, _dp, _dp, _dp, _dp,
        _dp, _dp, _dp, _dp, _ip)
@@ -431,6 +432,11 @@ def sv_solution_x(x_hat, info: dict) -> np.ndarray:
 def sv_debug_set_grid_cap(max_workgroups: int):
     """Test hook: bound every launch's workgroup count (0 = no bound)."""
     _check(_lib.sv_debug_set_grid_cap(int(max_workgroups)), "sv_debug_set_grid_cap")
+
+
+def sv_debug_set_dense_mfma(enable: bool):
+    """Matrix-core (True, default) or vector (False) form of 5-qubit dense gates."""
+    _check(_lib.sv_debug_set_dense_mfma(int(bool(enable))), "sv_debug_set_dense_mfma")
 
 
 # ------------------------------------------------------------------- batches

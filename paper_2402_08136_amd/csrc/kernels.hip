@@ -718,6 +718,98 @@ template <> struct Mfma<float> {
     static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
 };
 
+// ---------------------------------------------------------------------------
+// Dense 5-qubit gate on the matrix cores.  At k = 5 the dense product costs
+// 8 * 32 flops per amplitude, near the FP64 ridge of the chip, so the
+// vector form spends the VALU on arithmetic that the matrix cores can take.
+//
+// A wave owns 16 groups (lane bits 0..3: the four lowest non-target index
+// bits) of 32 amplitudes.  With the targets sorted q_0 < ... < q_4 and the
+// matrix index c = sum_l bit(q_l) 2^l, lane bits 4..5 hold c bits 0..1
+// (q_0, q_1) and each lane's 8 registers hold c bits 2..4 (q_2..q_4): lane
+// (j, kq) holds x_j[4 s + kq] in register s.  That is exactly the B operand
+// of a 16x16x4 MFMA over the 4-wide slice c = 4s .. 4s+3 (B[k][j] in lane
+// j + 16 k), so Y^T = M X^T runs as 2 row tiles x 8 k-steps, each split
+// into four real products (Re M Re x, -Im M Im x, Re M Im x, Im M Re x).
+// The FP64 accumulator puts row 4 v + kq of a tile in item v of lane j + 16
+// kq: output row 16 t + 4 v + kq, the same matrix index the lane loaded
+// into register 4 t + v, so every lane stores to the addresses it read.
+// The FP32 accumulator puts row 4 kq + v there instead; loading the A rows
+// with the two 2-bit halves of the tile row swapped makes its item v of
+// lane j + 16 kq again output row 16 t + 4 v + kq.  Each load and store is
+// one amplitude per lane; with q_2 above the 128-byte line (every target
+// inside a line is q_0 or q_1) each instruction touches whole lines.
+// The matrix, as A fragments (Re and Im of 2 x 8 entries per lane), stays
+// in registers for the wave's whole loop.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void k_dense_mfma5_body(typename V2<R>::type *__restrict__ psi,
+                                                   const typename V2<R>::type *__restrict__ mat, const TileArgs &a)
+{
+    typedef typename V2<R>::type C;
+    typedef typename Mfma<R>::V4 V4;
+    const int l = threadIdx.x & 63;
+    const int i = l & 15, kq = l >> 4;
+    const int ri = sizeof(R) == 8 ? i : (((i & 3) << 2) | (i >> 2));
+    R are[2][8], aim[2][8];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const C m = mat[(16 * t + ri) * 32 + 4 * s + kq];
+            are[t][s] = m.x;
+            aim[t][s] = m.y;
+        }
+    uint64_t loff = (uint64_t)i;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) loff = insert_zero(loff, a.rpos[j]);
+    loff |= (uint64_t(kq & 1) << a.rpos[0]) | (uint64_t(kq >> 1) << a.rpos[1]);
+    const WaveRange wr = wave_range(a.ntiles, 4);
+    for (uint64_t w = wr.w; w < wr.end; w += wr.step) {
+        uint64_t b = w << 4;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) b = insert_zero(b, a.rpos[j]);
+        C *p = psi + b + loff;
+        C x[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) x[s] = ld_nt(p + a.reg_off[s]);
+        V4 yr[2], yi[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) yr[t] = yi[t] = V4{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const R nxi = -x[s].y;
+#pragma unroll
+            for (int t = 0; t < 2; ++t) yr[t] = Mfma<R>::mac(are[t][s], x[s].x, yr[t]);
+#pragma unroll
+            for (int t = 0; t < 2; ++t) yi[t] = Mfma<R>::mac(are[t][s], x[s].y, yi[t]);
+#pragma unroll
+            for (int t = 0; t < 2; ++t) yr[t] = Mfma<R>::mac(aim[t][s], nxi, yr[t]);
+#pragma unroll
+            for (int t = 0; t < 2; ++t) yi[t] = Mfma<R>::mac(aim[t][s], x[s].x, yi[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) st_nt(C{yr[t][v], yi[t][v]}, p + a.reg_off[4 * t + v]);
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_dense_mfma5(typename V2<R>::type *__restrict__ psi,
+                                                     const typename V2<R>::type *__restrict__ mat, TileArgs a)
+{
+    k_dense_mfma5_body<R>(psi, mat, a);
+}
+
+// Grouped form: member blockIdx.y of up to kMaxGroup states.
+template <typename R>
+__global__ __launch_bounds__(256) void k_dense_mfma5_g(Ptrs pp, TileArgs a)
+{
+    typedef typename V2<R>::type C;
+    k_dense_mfma5_body<R>(member_ptr<C>(pp.a), member_ptr<const C>(pp.b), a);
+}
+
 // Offset of column c (target bits) and base of row g (control set, zeros at
 // the targets) of a wide gate.
 __device__ __forceinline__ uint64_t wide_col(const WideGemmArgs &a, uint64_t c)
@@ -1109,6 +1201,9 @@ __global__ __launch_bounds__(256) void k_gather(const typename V2<R>::type *__re
 // arithmetic.  Tests lower it so that small states drive the multi-tile
 // loops that large states take.
 std::atomic<unsigned> g_grid_cap{0};
+// 5-qubit dense gates on the matrix cores (k_dense_mfma5); off selects the
+// vector forms, for comparison.
+std::atomic<bool> g_dense_mfma{true};
 
 inline unsigned grid_for(uint64_t work, unsigned per_block, unsigned cap)
 {
@@ -1172,6 +1267,23 @@ sv_status launch_dense_t(const DevOp &op, const Group &g, int n, hipStream_t st,
     const Ptrs pp = op_ptrs(op, g);
     const unsigned cnt = (unsigned)g.count;
     const int k = op.k;
+    // 5-qubit gates on the matrix cores (k_dense_mfma5_body) when every
+    // target inside a 128-byte cache line is q_0 or q_1
+    constexpr int kLineBits = sizeof(R) == 8 ? 3 : 4;
+    if (k == 5 && n >= 9 && op.q[2] >= kLineBits && g_dense_mfma.load(std::memory_order_relaxed)) {
+        TileArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.ntiles = uint64_t(1) << (n - 9);
+        for (int j = 0; j < 5; ++j) a.rpos[j] = op.q[j];
+        for (int s = 0; s < 8; ++s)
+            a.reg_off[s] = (uint64_t(s & 1) << op.q[2]) | (uint64_t((s >> 1) & 1) << op.q[3]) |
+                           (uint64_t(s >> 2) << op.q[4]);
+        *family = SV_KERNEL_DENSE_MFMA;
+        const unsigned grid = grid_for(a.ntiles, 4, 32768);
+        launch2(&k_dense_mfma5<R>, &k_dense_mfma5_g<R>, grid, 256, 0, st, pp, cnt, a);
+        HIPCK(hipGetLastError());
+        return SV_OK;
+    }
     if (n >= 6 + k) {
         TileArgs a;
         std::memset(&a, 0, sizeof(a));
@@ -1968,5 +2080,11 @@ extern "C" sv_status sv_debug_set_grid_cap(int max_workgroups)
 {
     if (max_workgroups < 0) return hhlsv::fail(SV_ERR_INVALID, "sv_debug_set_grid_cap: negative cap");
     hhlsv::g_grid_cap.store((unsigned)max_workgroups, std::memory_order_relaxed);
+    return SV_OK;
+}
+
+extern "C" sv_status sv_debug_set_dense_mfma(int enable)
+{
+    hhlsv::g_dense_mfma.store(enable != 0, std::memory_order_relaxed);
     return SV_OK;
 }

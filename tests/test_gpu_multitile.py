@@ -68,8 +68,9 @@ def _run(n, gates, psi0, dtype, k=None):
 # (name, targets for k = 1..5, families expected at complex128 / complex64).
 # Every dense sweep family: registers (direct, complex64 pairs), the
 # cross-lane butterfly (one or two targets inside a cache line; complex64 on
-# pairs), and the LDS regroup (three targets inside a line, k = 5 with a low
-# target, complex64 with bit 0 or two targets inside the line).
+# pairs), the matrix cores (k = 5 with no target inside a line above the two
+# lowest) and the LDS regroup (three targets inside a line, complex64 with
+# bit 0 or two targets inside the line, k = 5 otherwise).
 PATTERNS = {
     "high": [(9,), (7, 12), (6, 10, 15), (6, 8, 11, 17), (6, 7, 9, 13, 16)],
     "midline": [(4,), (3, 11), (5, 8, 14), (3, 4, 9, 16), (4, 5, 7, 12, 17)],
@@ -96,7 +97,32 @@ def test_dense_multitile(k, pattern, dtype, grid_cap):
     want = oracle.apply_circuit(psi0, n, [g])
     got, fams = _run(n, [g], psi0, dtype)
     _say(f"  families {sorted(fams)}")
-    assert fams and fams <= {"dense_direct", "dense_bfly", "dense_lds"}
+    assert fams and fams <= {"dense_direct", "dense_bfly", "dense_lds", "dense_mfma"}
+    assert np.max(np.abs(got - want)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("grid_cap", CAPS, indirect=True)
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("pattern", list(PATTERNS))
+def test_dense5_vector_form_multitile(pattern, dtype, grid_cap):
+    """The vector kernels of 5-qubit gates (the matrix-core form switched
+    off), over several tiles per wave."""
+    hs = _hs()
+    n = 18
+    qs = list(PATTERNS[pattern][4])
+    rng = np.random.default_rng(7100 + len(pattern) + (7 if dtype == "c64" else 0))
+    U = W.random_unitary(32, rng)
+    g = W.Gate("dense", tuple(qs), np.ascontiguousarray(U).view(np.float64).ravel())
+    _say(f"multitile dense5 vector form n={n} targets={qs} dtype={dtype} cap={grid_cap}")
+    psi0 = W.random_state(n, int(rng.integers(1 << 30)))
+    want = oracle.apply_circuit(psi0, n, [g])
+    hs.sv_debug_set_dense_mfma(False)
+    try:
+        got, fams = _run(n, [g], psi0, dtype)
+    finally:
+        hs.sv_debug_set_dense_mfma(True)
+    _say(f"  families {sorted(fams)}")
+    assert fams and fams <= {"dense_direct", "dense_lds"}
     assert np.max(np.abs(got - want)) <= TOL[dtype]
 
 

@@ -122,10 +122,12 @@ def test_dense_register_path_smallest_states(k, extra, in_line, dtype):
 
 
 # (targets, family at complex128, family at complex64): the register path
-# takes every gate with no target inside a 128-byte cache line (bits < 3 at
-# complex128, < 4 at complex64); targets inside the line (k <= 4) take the
-# cross-lane butterfly: one or two at complex128, one at complex64 (on
-# amplitude pairs, so not bit 0); the LDS regroup the rest.
+# takes every gate of k <= 4 with no target inside a 128-byte cache line
+# (bits < 3 at complex128, < 4 at complex64); targets inside the line
+# (k <= 4) take the cross-lane butterfly: one or two at complex128, one at
+# complex64 (on amplitude pairs, so not bit 0); 5-qubit gates take the
+# matrix cores when every target inside a line is one of the two lowest;
+# the LDS regroup the rest.
 FAMILY_CASES = [((8, 11), "dense_direct", "dense_direct"),
                 ((3, 9, 14), "dense_direct", "dense_bfly"),
                 ((4, 5, 7, 13), "dense_direct", "dense_direct"),
@@ -135,7 +137,9 @@ FAMILY_CASES = [((8, 11), "dense_direct", "dense_direct"),
                 ((0, 1, 3, 14), "dense_bfly", "dense_lds"),
                 ((1, 2, 9), "dense_bfly", "dense_lds"),
                 ((1, 2, 3), "dense_bfly", "dense_lds"),
-                ((1, 6, 8, 10, 12), "dense_lds", "dense_lds"),
+                ((1, 6, 8, 10, 12), "dense_mfma", "dense_mfma"),
+                ((0, 3, 4, 9, 12), "dense_mfma", "dense_mfma"),
+                ((0, 1, 3, 7, 10), "dense_mfma", "dense_lds"),
                 ((0, 1, 2, 3, 4), "dense_lds", "dense_lds")]
 
 
@@ -157,6 +161,51 @@ def test_dense_family_choice(case, dtype):
     got = s.get()
     s.close()
     assert hs.KERNEL_FAMILY[int(fam[0])] == (fam128 if dtype == "c128" else fam64)
+    want = oracle.apply_circuit(psi0, n, [g])
+    assert np.max(np.abs(got - want)) <= TOL[dtype]
+
+
+# 5-qubit target patterns for both forms of the gate: the matrix-core kernel
+# (two lowest targets as lane bits, the other three as register bits) and the
+# vector kernels (registers or the LDS regroup)
+DENSE5 = [(5, 6, 7, 8, 9), (0, 1, 5, 7, 9), (0, 4, 5, 6, 8), (2, 3, 4, 6, 8), (1, 3, 4, 5, 8),
+          (3, 4, 5, 6, 7), (0, 1, 2, 3, 4), (4, 5, 6, 7, 8)]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("form", ["mfma", "vector"])
+@pytest.mark.parametrize("n", [9, 10, 13])
+@pytest.mark.parametrize("case", range(len(DENSE5)))
+def test_dense5_forms(case, n, form, dtype):
+    hs = _hs()
+    qs = [q for q in DENSE5[case]]
+    if max(qs) >= n:
+        pytest.skip("targets beyond the state")
+    rng = np.random.default_rng(900 + 11 * case + n)
+    U = W.random_unitary(32, rng)
+    perm = rng.permutation(5)
+    qs_list = [qs[i] for i in perm]
+    g = W.Gate("dense", tuple(qs_list), np.ascontiguousarray(U).view(np.float64).ravel())
+    _say(f"dense5 n={n} targets={qs_list} form={form} dtype={dtype}")
+    psi0 = W.random_state(n, 70 + case + n)
+    c = hs.circuit_from_gates(n, [g])
+    hs.sv_debug_set_dense_mfma(form == "mfma")
+    try:
+        s = hs.sv_create(n, dtype)
+        s.set(psi0)
+        _, fam = s.apply_timed(c)
+        got = s.get()
+        s.close()
+    finally:
+        hs.sv_debug_set_dense_mfma(True)
+    line_bits = 3 if dtype == "c128" else 4
+    mfma_applies = sorted(qs)[2] >= line_bits
+    want_fam = "dense_mfma" if form == "mfma" and mfma_applies else None
+    got_fam = hs.KERNEL_FAMILY[int(fam[0])]
+    if want_fam:
+        assert got_fam == want_fam
+    else:
+        assert got_fam in ("dense_direct", "dense_lds", "dense_small")
     want = oracle.apply_circuit(psi0, n, [g])
     assert np.max(np.abs(got - want)) <= TOL[dtype]
 
