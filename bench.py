@@ -116,21 +116,129 @@ def cpu_baseline(budget_s=15.0, n=26):
             break
     dt = time.perf_counter() - t0
     gbs = done * 2 * (1 << n) * 16 / dt / 1e9
-    return {"value": round(gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+    return {"value": round(gbs, 3), "unit": "GB/s", "cores": 1, "host_cpu_count": os.cpu_count(),
+            "kind": "oracle",
             "sample": f"first {done} unfused gates of the layered-circuit generator "
                       f"(seed 2402) at n={n} (1 GiB state), one thread, {dt:.1f} s; "
                       f"GB/s = gates * 2 * 2^n * 16 B / time"}
 
 
-def hhl_single(hs, W, reps=40):
-    """Plain one-circuit-at-a-time path on the 64-bus, 10-clock-qubit system:
-    reset + apply (cached hipGraph) + postselect per solve."""
-    A, b = W.dc_powerflow(64, 0)
-    c = hs.circuit_build_hhl(A, b, 10)
+# ------------------------------------------------------------- HHL legs ---
+# Host threads for the oracle pools: the machine's CPU share for one GPU is 16
+# cores, whatever os.cpu_count() reports there.
+HOST_THREADS = max(1, min(16, os.cpu_count() or 1))
+AMP_BAR = {"c128": 1e-12, "c64": 2e-5}
+
+
+def oracle_pool(jobs, budget_s=None, threads=HOST_THREADS):
+    """FP64 oracle HHL solves of jobs [(key, A, b, m)] on a pool of host
+    threads (the C oracle runs outside the GIL), one solve per thread at a
+    time.  With budget_s no job starts after that much wall time.  Returns
+    ({key: (x_hat, info, y, psi)}, wall seconds)."""
+    import concurrent.futures as cf
+
+    import oracle
+
+    def solve(A, b, m):
+        psi, _, xh, info = oracle.hhl_solve(A, b, m)
+        half = 1 << (info["n"] - 1)
+        return xh, info, psi[half:half + (1 << info["ns"])].copy(), psi
+
     out = {}
+    t0 = time.perf_counter()
+    it = iter(jobs)
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        running = {}
+
+        def start_next():
+            if budget_s is not None and time.perf_counter() - t0 > budget_s:
+                return False
+            job = next(it, None)
+            if job is None:
+                return False
+            key, A, b, m = job
+            running[ex.submit(solve, A, b, m)] = key
+            return True
+
+        for _ in range(threads):
+            if not start_next():
+                break
+        while running:
+            done, _ = cf.wait(list(running), return_when=cf.FIRST_COMPLETED)
+            for f in done:
+                out[running.pop(f)] = f.result()
+                start_next()
+    return out, time.perf_counter() - t0
+
+
+def result_errors(pairs, dtype):
+    """Errors of library results against the FP64 oracle: pairs of
+    ((y, p1, x_hat), (x_hat_ref, info_ref, y_ref, psi_ref)).  y is the
+    postselected block (ancilla 1, clock 0), p1 = P(ancilla = 1)."""
+    dy, dp1, fid = 0.0, 0.0, 1.0
+    for (y, p1, xh), (xh_ref, info_ref, y_ref, _) in pairs:
+        dy = max(dy, float(np.max(np.abs(np.asarray(y) - y_ref))))
+        dp1 = max(dp1, abs(p1 - info_ref["p1"]))
+        fid = min(fid, float(np.dot(xh, xh_ref)) ** 2)
+    return {"checked": len(pairs), "max_abs_dy": dy, "max_abs_dp_anc1": dp1,
+            "min_fidelity_vs_oracle": fid, "bar": AMP_BAR[dtype],
+            "within_bar": bool(dy <= AMP_BAR[dtype] and dp1 <= AMP_BAR[dtype])}
+
+
+def cpu_solves(n_done, wall, sample):
+    return {"value": round(n_done / wall, 2) if wall > 0 else None, "unit": "solves/s",
+            "cores": HOST_THREADS, "host_cpu_count": os.cpu_count(), "kind": "oracle",
+            "sample": f"{n_done} FP64 oracle HHL solves ({sample}), one solve per host thread, "
+                      f"{wall:.1f} s wall"}
+
+
+def _y_of(s, c, ns, dtype):
+    """Postselected block of a state: psi[2^{n-1} + s] for s < 2^ns."""
+    return s.get(1 << (c.n_qubits - 1), 1 << ns).astype(np.complex128)
+
+
+def hhl_plain_4bus(hs, W, seeds=100):
+    """The 4-bus, 4-clock-qubit solve (7 qubits, unfused) on the plain
+    one-circuit-at-a-time path, complex128 and complex64, over seeded
+    systems; every full state against the oracle's."""
+    systems = [W.dc_powerflow(4, sd) for sd in range(seeds)]
+    refs, wall = oracle_pool([(i, A, b, 4) for i, (A, b) in enumerate(systems)])
+    out = {"systems": seeds, "cpu_baseline": cpu_solves(len(refs), wall, f"4-bus, m=4, seeds 0..{seeds - 1}")}
     for dtype in ("c128", "c64"):
-        best = None
-        for k in (2, 3, 4):
+        circs = [hs.circuit_build_hhl(A, b, 4) for A, b in systems]
+        dpsi, pairs = 0.0, []
+        t0 = time.perf_counter()
+        for i, (c, (A, b)) in enumerate(zip(circs, systems)):
+            s = hs.sv_create(c.n_qubits, dtype)
+            s.apply(c)
+            x_hat, info = s.postselect_solution(c, b.size)
+            psi = s.get().astype(np.complex128)
+            s.close()
+            dpsi = max(dpsi, float(np.max(np.abs(psi - refs[i][3]))))
+            half = 1 << (c.n_qubits - 1)
+            pairs.append(((psi[half:half + 4], info["p_anc1"], x_hat), refs[i]))
+        dt = time.perf_counter() - t0
+        err = result_errors(pairs, dtype)
+        err["max_abs_dpsi_full_state"] = dpsi
+        out[dtype] = {"solves_per_s": round(seeds / dt, 1), "error_vs_oracle": err}
+    return out
+
+
+def hhl_single(hs, W, reps=40):
+    """Plain one-circuit-at-a-time path on the 64-bus, 10-clock-qubit system
+    (17 qubits): reset + apply (cached hipGraph) + postselect per solve, at
+    every fusion width k = 1..5, complex128 and complex64; each result's full
+    state against the FP64 oracle's.  Seeds 1..9 add error checks at k = 4."""
+    seeds = list(range(10))
+    systems = {sd: W.dc_powerflow(64, sd) for sd in seeds}
+    refs, wall = oracle_pool([(sd, A, b, 10) for sd, (A, b) in systems.items()])
+    A, b = systems[0]
+    c = hs.circuit_build_hhl(A, b, 10)
+    xs = np.linalg.solve(A, b)
+    out = {"cpu_baseline": cpu_solves(len(refs), wall, "64-bus, m=10, seeds 0..9")}
+    for dtype in ("c128", "c64"):
+        by_k, best = {}, None
+        for k in (1, 2, 3, 4, 5):
             run = hs.fuse(c, k)
             s = hs.sv_create(c.n_qubits, dtype)
             s.apply(run)
@@ -142,30 +250,57 @@ def hhl_single(hs, W, reps=40):
                 s.postselect_solution(c, 63)
             dt = (time.perf_counter() - t0) / reps
             x_hat, info = s.postselect_solution(c, 63)
+            psi = s.get().astype(np.complex128)
             s.close()
+            half = 1 << (c.n_qubits - 1)
+            err = result_errors([((psi[half:half + 64], info["p_anc1"], x_hat), refs[0])], dtype)
+            err["max_abs_dpsi_full_state"] = float(np.max(np.abs(psi - refs[0][3])))
+            by_k[str(k)] = {"solves_per_s": round(1.0 / dt, 1), "ms_per_solve": round(dt * 1e3, 4),
+                            "fused_ops": run.n_gates, "error_vs_oracle": err}
             if best is None or dt < best[1]:
                 best = (k, dt, x_hat, info)
-        xs = np.linalg.solve(A, b)
         k, dt, x_hat, info = best
-        x = info["scale"] * x_hat
-        out[dtype] = {"solves_per_s": round(1.0 / dt, 1), "ms_per_solve": round(dt * 1e3, 4),
-                      "k_max": k,
+        x = hs.sv_solution_x(x_hat, info)
+        # the other seeds at k = 4
+        pairs = []
+        for sd in seeds[1:]:
+            As, bs = systems[sd]
+            cs = hs.circuit_build_hhl(As, bs, 10)
+            s = hs.sv_create(cs.n_qubits, dtype)
+            s.apply(hs.fuse(cs, 4))
+            xh, inf = s.postselect_solution(cs, 63)
+            y = _y_of(s, cs, 6, dtype)
+            s.close()
+            pairs.append(((y, inf["p_anc1"], xh), refs[sd]))
+        out[dtype] = {"solves_per_s": round(1.0 / dt, 1), "ms_per_solve": round(dt * 1e3, 4), "k_max": k,
                       "fidelity_vs_Ainv_b": float(np.dot(x_hat, xs / np.linalg.norm(xs)) ** 2),
-                      "rel_err_vs_Ainv_b": float(np.linalg.norm(x - xs) / np.linalg.norm(xs))}
+                      "rel_err_vs_Ainv_b": float(np.linalg.norm(x - xs) / np.linalg.norm(xs)),
+                      "by_k": by_k, "seeds_1_9_k4_error_vs_oracle": result_errors(pairs, dtype)}
     return out
 
 
 def hhl_batch(hs, W, count=8192):
     """Batched persistent path on the 8192-instance mix (seed 8136); one
-    autotuned k_max per (ns, m) shape; device time of the replayed graph."""
+    autotuned k_max per (ns, m) shape; device time of the replayed graph.
+    The first instance of every (ns, m) shape (a stratified sample: shapes
+    are drawn uniformly) is checked against the FP64 oracle."""
     specs = W.batch_specs(count, 8136)
     t0 = time.perf_counter()
-    circs = []
+    circs, systems = [], []
     for ns, m, gseed in specs:
         A, b = W.dc_powerflow(1 << ns, gseed)
+        systems.append((A, b, m))
         circs.append(hs.circuit_build_hhl(A, b, m, device_evolutions=True))
     build_s = time.perf_counter() - t0
-    out = {"instances": count, "host_build_s": round(build_s, 2)}
+    first = {}
+    for i, (ns, m, _) in enumerate(specs):
+        first.setdefault((ns, m), i)
+    refs, wall = oracle_pool([(i, *systems[i]) for i in sorted(first.values())])
+    out = {"instances": count, "host_build_s": round(build_s, 2),
+           "cpu_baseline": cpu_solves(len(refs), wall, "the first instance of each of the "
+                                      f"{len(first)} (ns, m) shapes of the mix")}
+    flop = sum(m * 2 ** (ns + m + 1 + 3 + ns) for ns, m, _ in specs)
+    out["controlled_evolution_flop_per_batch"] = flop
     for dtype in ("c128", "c64"):
         shapes = {}
         for (ns, m, _), c in zip(specs, circs):
@@ -179,46 +314,100 @@ def hhl_batch(hs, W, count=8192):
         for c in circs:
             bt.add(c)
         t0 = time.perf_counter()
-        first_ms = bt.run()      # upload, device evolution tables, capture, run
+        bt.run()      # upload, device evolution tables, capture, run
         setup_s = time.perf_counter() - t0
         runs = [bt.run() for _ in range(5)]
         ms = float(np.median(runs))
+        pairs = []
+        for i in sorted(first.values()):
+            y, p1 = bt.postselected(i)
+            xh, _ = bt.solution(i)
+            pairs.append(((y, p1, xh), refs[i]))
         out[dtype] = {"solves_per_s": round(count / (ms * 1e-3), 1), "device_ms": round(ms, 3),
+                      "controlled_evolution_TFLOPs": round(flop / (ms * 1e-3) / 1e12, 2),
                       "first_run_s": round(setup_s, 3), "autotune_s": round(tune_s, 2),
-                      "k_by_shape": tuned}
+                      "k_by_shape": tuned, "error_vs_oracle": result_errors(pairs, dtype)}
         bt.close()
     return out
 
 
-def hhl_serve(hs, W, seconds, rate=2000.0, pool_per_size=48):
+def _serve_run(hs, sched, pool, pool_per_size, dtype, budget_bytes=0, sample_every=0):
+    """Submit the schedule open loop; drain; stats; the results of every
+    sample_every-th request (polled after the drain)."""
+    srv = hs.Server(dtype, hbm_budget_bytes=budget_bytes)
+    t_start = time.perf_counter()
+    rejected = 0
+    tickets = [None] * len(sched)
+    for i, (ta, ns, m, _) in enumerate(sched):
+        delay = t_start + ta - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        A, b = pool[ns][i % pool_per_size]
+        try:
+            tickets[i] = srv.submit(A, b, m)
+        except hs.HHLSVError:
+            rejected += 1
+    srv.drain()
+    st = srv.stats()
+    res = {}
+    if sample_every:
+        for i in range(0, len(sched), sample_every):
+            if tickets[i] is not None:
+                ns = sched[i][1]
+                xh, info, y, p1 = srv.poll_ex(tickets[i], 1 << ns)
+                res[i] = (y, p1, xh)
+    srv.stop()
+    return {"p50_ms": round(st["p50_s"] * 1e3, 3), "p99_ms": round(st["p99_s"] * 1e3, 3),
+            "solves_per_s": round(st["solves_per_s"], 1), "done": st["done"],
+            "failed": st["failed"], "rejected": st["rejected"] + rejected}, res
+
+
+def hhl_serve(hs, W, seconds, rate=2000.0, pool_per_size=48, constrained_seconds=10.0,
+              oracle_budget_s=20.0, max_check_qubits=19):
     """Serving loop under open-loop Poisson arrivals (seed 2000 for arrivals,
     2001 for sizes); request systems come from a pool of seeded systems per
-    size.  Latency = submit to finish inside the server."""
+    size.  Latency = submit to finish inside the server.  1% of the requests
+    (every 100th) are polled for their postselected block; a time-boxed
+    subset of those, taken round robin over the system sizes, is checked
+    against the FP64 oracle.  A shorter run with a 256 MiB HBM budget forces
+    admission waits."""
     sched = W.serve_specs(rate, seconds, 2000, 2001)
     pool = {}
     for ns in range(3, 9):
         pool[ns] = [W.dc_powerflow(1 << ns, 50000 + 100 * ns + i) for i in range(pool_per_size)]
     out = {"offered_rate_per_s": rate, "duration_s": seconds, "requests": len(sched)}
+    results = {}
     for dtype in ("c128", "c64"):
-        srv = hs.Server(dtype)
-        t_start = time.perf_counter()
-        rejected = 0
-        for i, (ta, ns, m, _) in enumerate(sched):
-            delay = t_start + ta - time.perf_counter()
-            if delay > 0:
-                time.sleep(delay)
-            A, b = pool[ns][i % pool_per_size]
-            try:
-                srv.submit(A, b, m)
-            except hs.HHLSVError:
-                rejected += 1
-        srv.drain()
-        st = srv.stats()
-        srv.stop()
-        out[dtype] = {"p50_ms": round(st["p50_s"] * 1e3, 3), "p99_ms": round(st["p99_s"] * 1e3, 3),
-                      "solves_per_s": round(st["solves_per_s"], 1), "done": st["done"],
-                      "failed": st["failed"], "rejected": st["rejected"] + rejected}
+        out[dtype], results[dtype] = _serve_run(hs, sched, pool, pool_per_size, dtype, sample_every=100)
         log(f"[bench] serve {dtype}: {out[dtype]}")
+    # oracle check: round robin over ns strata of the 1% sample
+    strata = {}
+    for i in sorted(results["c128"]):
+        ta, ns, m, _ = sched[i]
+        if ns + m + 1 <= max_check_qubits and i in results["c64"]:
+            strata.setdefault(ns, []).append(i)
+    order = []
+    while any(strata.values()):
+        for ns in sorted(strata):
+            if strata[ns]:
+                order.append(strata[ns].pop(0))
+    jobs = [(i, *pool[sched[i][1]][i % pool_per_size], sched[i][2]) for i in order]
+    refs, wall = oracle_pool(jobs, budget_s=oracle_budget_s)
+    checked = sorted(refs)
+    for dtype in ("c128", "c64"):
+        out[dtype]["error_vs_oracle"] = result_errors([(results[dtype][i], refs[i]) for i in checked], dtype)
+        out[dtype]["error_vs_oracle"]["sample"] = (
+            f"{len(checked)} of the {len(results[dtype])} polled requests (every 100th), round robin over "
+            f"ns = {sorted({sched[i][1] for i in checked})}, states of <= {max_check_qubits} qubits")
+    out["cpu_baseline"] = cpu_solves(len(refs), wall, f"served requests of <= {max_check_qubits} qubits, "
+                                     "round robin over the system sizes")
+    # constrained HBM budget: admission waits for memory
+    sched_c = W.serve_specs(rate, constrained_seconds, 2000, 2001)
+    out["constrained_256MiB"] = {"duration_s": constrained_seconds, "requests": len(sched_c)}
+    for dtype in ("c128", "c64"):
+        out["constrained_256MiB"][dtype], _ = _serve_run(hs, sched_c, pool, pool_per_size, dtype,
+                                                         budget_bytes=256 << 20)
+        log(f"[bench] serve {dtype}, 256 MiB budget: {out['constrained_256MiB'][dtype]}")
     # the plain one-circuit-at-a-time FP64 path on a sample of the same requests
     sample = sched[:: max(1, len(sched) // 200)]
     t0 = time.perf_counter()
@@ -254,9 +443,10 @@ def pf_newton_leg(hs, W):
 
 
 def c64_sweep(hs, circ, n, k, warmup, steps, probe_idx, ref_amps):
-    """The same circuit on a complex64 state (half the bytes per sweep), with
-    as many applications as the complex128 run, and the largest difference
-    from the complex128 state over a seeded sample of amplitudes."""
+    """The same circuit on a complex64 state (half the bytes per sweep): one
+    warm-up application and `steps` timed ones, then the largest difference
+    from the complex128 state after as many applications (ref_amps, None if
+    that state was not sampled) over a seeded sample of amplitudes."""
     import numpy as np
 
     log(f"[bench] complex64: allocating {8 * 2 ** n / 2 ** 30:.0f} GiB state")
@@ -285,7 +475,8 @@ def c64_sweep(hs, circ, n, k, warmup, steps, probe_idx, ref_amps):
                           "mean_ms": round(float(ms_all[sel].mean()), 3),
                           "GBps": round(bps / (float(ms_all[sel].mean()) * 1e-3) / 1e9, 1)}
     dom = max(fams, key=lambda f: fams[f]["total_ms"])
-    diff = float(np.max(np.abs(s.get_at(probe_idx).astype(np.complex128) - ref_amps)))
+    diff = (float(np.max(np.abs(s.get_at(probe_idx).astype(np.complex128) - ref_amps)))
+            if ref_amps is not None else None)
     out = {"value_GBps": round(len(ms_all) * bps / elapsed / 1e9, 2), "bytes_per_sweep": bps,
            "sweeps": len(ms_all),
            "per_sweep_GBps": {"min": round(float(rate.min()), 1), "median": round(float(np.median(rate)), 1),
@@ -294,10 +485,11 @@ def c64_sweep(hs, circ, n, k, warmup, steps, probe_idx, ref_amps):
            "dominant": {"kernel": dom, "GBps": fams[dom]["GBps"],
                         "frac_of_hbm_peak": round(fams[dom]["GBps"] / HBM_PEAK_GBS, 4)},
            "max_abs_diff_vs_complex128": diff, "sampled_amplitudes": int(probe_idx.size),
-           "max_abs_amplitude_sampled": float(np.max(np.abs(ref_amps))),
+           "max_abs_amplitude_sampled": float(np.max(np.abs(ref_amps))) if ref_amps is not None else None,
+           "applications_compared": warmup + steps,
            "final_norm2": s.norm2()}
     s.close()
-    log(f"[bench] complex64: {out['value_GBps']:.0f} GB/s, max |c64 - c128| {diff:.2e}")
+    log(f"[bench] complex64: {out['value_GBps']:.0f} GB/s, max |c64 - c128| {diff}")
     return out
 
 
@@ -319,8 +511,12 @@ def main():
                     help="layers of the circuit used for the per-k sweep rates")
     ap.add_argument("--part", choices=["all", "single", "batch", "serve", "powerflow"], default="all",
                     help="run one HHL leg alone (for profiling); prints that leg's JSON, not the bench line")
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
-                    help="length of the Poisson arrival window (the full schedule is 60 s)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="length of the Poisson arrival window")
+    ap.add_argument("--serve-constrained-seconds", type=float, default=10.0,
+                    help="length of the arrival window of the 256 MiB HBM-budget run")
+    ap.add_argument("--c64-steps", type=int, default=2,
+                    help="timed steps of the complex64 run of the same circuit (after one warm-up step)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the library has no multi-GPU path "
@@ -333,8 +529,10 @@ def main():
     import workloads as W
 
     if args.part != "all":
-        leg = {"single": lambda: hhl_single(hs, W), "batch": lambda: hhl_batch(hs, W),
-               "serve": lambda: hhl_serve(hs, W, args.serve_seconds),
+        leg = {"single": lambda: {"plain_4bus_m4": hhl_plain_4bus(hs, W), "single_64bus_m10": hhl_single(hs, W)},
+               "batch": lambda: hhl_batch(hs, W),
+               "serve": lambda: hhl_serve(hs, W, args.serve_seconds,
+                                          constrained_seconds=args.serve_constrained_seconds),
                "powerflow": lambda: pf_newton_leg(hs, W)}[args.part]
         print(json.dumps({"part": args.part, "result": leg()}), flush=True)
         return
@@ -346,11 +544,19 @@ def main():
     state = hs.sv_create(n, "c128")
     bytes_per_sweep = 2 * (1 << n) * 16
 
+    # seeded sample of amplitudes, for the complex64 run of the same circuit:
+    # taken after as many applications as that run makes (one warm-up plus
+    # its timed steps), outside the timed region
+    probe_idx = np.random.default_rng(2402).integers(0, 1 << n, size=65536, dtype=np.uint64)
+    c64_apps = 1 + args.c64_steps
+    ref_amps = None
     for w in range(args.warmup):
         t = time.perf_counter()
         state.apply(hs.fuse(circ, k))
         state.synchronize()
         log(f"[bench] warmup {w}: {time.perf_counter() - t:.2f} s")
+        if w + 1 == c64_apps:
+            ref_amps = state.get_at(probe_idx)
 
     state.synchronize()
     t0 = time.perf_counter()
@@ -366,9 +572,12 @@ def main():
     state.synchronize()
     elapsed = time.perf_counter() - t0
     norm = state.norm2()
-    # seeded sample of amplitudes, for the complex64 run of the same circuit
-    probe_idx = np.random.default_rng(2402).integers(0, 1 << n, size=65536, dtype=np.uint64)
-    ref_amps = state.get_at(probe_idx)
+    if ref_amps is None and args.warmup + args.steps == c64_apps:
+        ref_amps = state.get_at(probe_idx)
+    # achievable bandwidth: in-place read and write-back with the sweeps'
+    # access shape, on the same state (left unchanged)
+    probe_ms = float(np.median(state.stream_probe(5)))
+    achievable = bytes_per_sweep / (probe_ms * 1e-3) / 1e9
 
     ms_all = np.concatenate(launch_ms)
     fam_all = np.concatenate(families)
@@ -422,6 +631,10 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
+            "achievable": round(achievable, 1),
+            "frac_of_achievable": round(achieved / achievable, 4),
+            "achievable_probe": "median of 5 launches of sv_stream_probe (in-place read and write-back "
+                                "of the same state with the dense sweeps' access shape, grid and XCD slices)",
         },
     }
     if not args.no_k_sweep:
@@ -445,14 +658,14 @@ def main():
         out["config"]["per_sweep_GBps_by_k"] = dict(sorted(by_k.items()))
     state.close()
     if not args.no_c64:
-        out["complex64_sweep"] = c64_sweep(hs, circ, n, k, args.warmup, args.steps, probe_idx, ref_amps)
+        out["complex64_sweep"] = c64_sweep(hs, circ, n, k, 1, args.c64_steps, probe_idx, ref_amps)
     if not args.no_hhl:
         log("[bench] HHL: one-circuit-at-a-time path")
-        hhl = {"single_64bus_m10": hhl_single(hs, W)}
+        hhl = {"plain_4bus_m4": hhl_plain_4bus(hs, W), "single_64bus_m10": hhl_single(hs, W)}
         log("[bench] HHL: batched 8192 instances")
         hhl["batch_8192"] = hhl_batch(hs, W)
         log(f"[bench] HHL: serving, {args.serve_seconds:.0f} s of arrivals at 2000/s")
-        hhl["serve"] = hhl_serve(hs, W, args.serve_seconds)
+        hhl["serve"] = hhl_serve(hs, W, args.serve_seconds, constrained_seconds=args.serve_constrained_seconds)
         log("[bench] HHL: Newton-Raphson AC power flow")
         hhl["power_flow_newton"] = pf_newton_leg(hs, W)
         out["hhl"] = hhl

@@ -463,6 +463,15 @@ const char *sv_last_error(void);
  * use while other threads launch.  SV_ERR_INVALID if negative. */
 sv_status sv_debug_set_grid_cap(int max_workgroups);
 
+/* Achievable-bandwidth probe: reps launches, each reading every amplitude of
+ * a complex128 state of >= 10 qubits and writing it back unchanged, with the
+ * access shape, grid and per-XCD tile slices of the dense sweep kernels;
+ * launch_ms[r] (reps entries) receives each launch's device time (HIP
+ * events on the state's stream).  Algorithmic bytes per launch: 2 * 16 *
+ * 2^n.  The state is unchanged.  Synchronises.  SV_ERR_SHAPE for another
+ * dtype or fewer qubits. */
+sv_status sv_stream_probe(sv_state *s, int reps, double *launch_ms);
+
 /* Select the form of 5-qubit dense gates for launches made after the call:
  * enable != 0 (the default) the matrix-core kernel where it applies, 0 the
  * vector kernels everywhere.  Both compute the same gate (Sec. II-C fused

@@ -119,6 +119,7 @@ _proto("circuit_destroy", _vp)
 _proto("sv_solution_x", _dp, ctypes.c_int, ctypes.POINTER(SolutionInfo), _dp)
 _proto("sv_debug_set_grid_cap", ctypes.c_int)
 _proto("sv_debug_set_dense_mfma", ctypes.c_int)
+_proto("sv_stream_probe", _vp, ctypes.c_int, _dp)
 _proto("sv_qubit_estimate", ctypes.c_int, ctypes.c_double, ctypes.c_int, _ip, _ip, _ip)
 _proto("pf_mismatch_jacobian", ctypes.c_int, ctypes.c_int, _ip, _ip, _dp, _dp, _dp, _ip, _dp, _dp, _dp, _dp,
        _dp, _dp, _dp, _dp, _ip)
@@ -370,6 +371,13 @@ class State:
 
     def synchronize(self):
         _check(_lib.sv_synchronize(self.handle), "sv_synchronize")
+
+    def stream_probe(self, reps: int = 5) -> np.ndarray:
+        """Device ms of each of ``reps`` in-place read/write-back launches
+        with the dense sweeps' access shape (complex128, n >= 10)."""
+        ms = np.zeros(reps)
+        _check(_lib.sv_stream_probe(self.handle, reps, _dptr(ms)), "sv_stream_probe")
+        return ms
 
     def postselect_solution(self, hhl: Circuit, dim: int):
         x = np.zeros(dim)

@@ -1185,6 +1185,30 @@ __global__ __launch_bounds__(256) void k_copy_block(Ptrs pp, uint64_t half, int 
     if (blockIdx.x == 0 && threadIdx.x == 0) out[1] = 0.0;
 }
 
+// Bandwidth probe with the dense sweeps' access shape: a wave tile is 16
+// runs of 64 consecutive amplitudes (as a 4-qubit gate on bits 6..9), read
+// with non-temporal 16-byte loads and written back unchanged, over the same
+// XCD-sliced tile range and grid as k_dense_direct.
+__global__ __launch_bounds__(256) void k_stream_probe(V2<double>::type *__restrict__ psi, uint64_t ntiles)
+{
+    typedef V2<double>::type C;
+    const WaveRange wr = wave_range(ntiles, 4);
+    const uint64_t lane = threadIdx.x & 63;
+    for (uint64_t w = wr.w; w < wr.end; w += wr.step) {
+        C *p = psi + (w << 10) + lane;
+        C v[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = ld_nt(p + 64 * i);
+        // an empty asm on each value hides that it is the one just loaded
+        // (else the store of a loaded value to its own address and the load
+        // are both removed)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) asm volatile("" : "+v"(v[i].x), "+v"(v[i].y));
+#pragma unroll
+        for (int i = 0; i < 16; ++i) st_nt(v[i], p + 64 * i);
+    }
+}
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_gather(const typename V2<R>::type *__restrict__ psi,
                                                 const uint64_t *__restrict__ idx, size_t count,
@@ -2070,6 +2094,15 @@ sv_status launch_gather(const void *psi, const uint64_t *dev_idx, size_t count,
         hipLaunchKernelGGL((k_gather<float>), dim3(grid), dim3(256), 0, s,
                            static_cast<const V2<float>::type *>(psi), dev_idx, count,
                            static_cast<V2<float>::type *>(dev_out));
+    HIPCK(hipGetLastError());
+    return SV_OK;
+}
+
+sv_status launch_stream_probe(void *psi, int n, hipStream_t s)
+{
+    const uint64_t ntiles = uint64_t(1) << (n - 10);
+    hipLaunchKernelGGL(k_stream_probe, dim3(grid_for(ntiles, 4, 32768)), dim3(256), 0, s,
+                       static_cast<V2<double>::type *>(psi), ntiles);
     HIPCK(hipGetLastError());
     return SV_OK;
 }

@@ -152,6 +152,9 @@ sv_status launch_postselect_group(const Group &g, int n, int ns, sv_dtype dtype,
 
 // One-time kernel attributes (LDS opt-ins); call before any launch or capture.
 sv_status prepare_kernels();
+// In-place read and write-back of a complex128 state of n >= 10 qubits with
+// the dense sweeps' access shape (the state is unchanged).
+sv_status launch_stream_probe(void *psi, int n, hipStream_t s);
 sv_status launch_gather(const void *psi, const uint64_t *dev_idx, size_t count,
                         void *dev_out, sv_dtype dtype, hipStream_t s);
 

@@ -257,6 +257,31 @@ extern "C" sv_status sv_apply_timed(sv_state *s, const sv_circuit *c, double *la
     return apply_impl(s, c, launch_ms, kernel_ids, cap);
 }
 
+extern "C" sv_status sv_stream_probe(sv_state *s, int reps, double *launch_ms)
+{
+    if (!s || !launch_ms || reps < 1) return fail(SV_ERR_INVALID, "sv_stream_probe: NULL argument or reps < 1");
+    if (s->dtype != SV_C128 || s->n < 10)
+        return fail(SV_ERR_SHAPE, "sv_stream_probe: needs a complex128 state of at least 10 qubits");
+    std::vector<hipEvent_t> ev(reps + 1);
+    for (auto &e : ev) HIPCK(hipEventCreate(&e));
+    sv_status st = SV_OK;
+    hipError_t e = hipEventRecord(ev[0], s->stream);
+    for (int r = 0; r < reps && st == SV_OK && e == hipSuccess; ++r) {
+        st = launch_stream_probe(s->psi, s->n, s->stream);
+        if (st == SV_OK) e = hipEventRecord(ev[r + 1], s->stream);
+    }
+    if (st == SV_OK && e == hipSuccess) e = hipEventSynchronize(ev[reps]);
+    for (int r = 0; r < reps && st == SV_OK && e == hipSuccess; ++r) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, ev[r], ev[r + 1]);
+        launch_ms[r] = ms;
+    }
+    for (auto &x : ev) (void)hipEventDestroy(x);
+    if (st != SV_OK) return st;
+    if (e != hipSuccess) return fail(SV_ERR_HIP, std::string("sv_stream_probe: ") + hipGetErrorString(e));
+    return SV_OK;
+}
+
 extern "C" sv_status sv_synchronize(sv_state *s)
 {
     if (!s) return fail(SV_ERR_INVALID, "sv_synchronize: NULL state");

@@ -423,3 +423,22 @@ def test_device_evolutions_match_oracle(nbus, m, k, dtype):
     _say(f"device evolutions nbus={nbus} m={m} k={k} {dtype}: max|d amp|={err:.3e}")
     assert err <= TOL[dtype]
     assert float(np.dot(x_hat, xh_ref) ** 2) >= 0.999
+
+
+def test_stream_probe_leaves_state_unchanged():
+    """The bandwidth probe reads and writes back every amplitude: the state
+    is bitwise the same afterwards, and each launch reports a positive time."""
+    hs = _hs()
+    n = 16
+    psi0 = W.random_state(n, 1616)
+    s = hs.sv_create(n, "c128")
+    s.set(psi0)
+    ms = s.stream_probe(3)
+    got = s.get()
+    s.close()
+    assert ms.shape == (3,) and np.all(ms > 0)
+    assert np.array_equal(got, psi0)
+    s64 = hs.sv_create(n, "c64")
+    with pytest.raises(hs.HHLSVError):
+        s64.stream_probe(1)
+    s64.close()
