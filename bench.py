@@ -73,6 +73,8 @@ def kernel_label(family, qubits, real="double", n=33):
     """Name of the kernel template instance a launch used (as rocprofv3 shows
     it), from its family and target qubits."""
     k = len(qubits)
+    if family == "dense_direct" and real == "float" and 0 in qubits:
+        return f"k_dense_pair0<{k}>"    # complex64, bit 0 a target: a pair holds two entries of a group
     if family == "dense_direct" and real == "float" and n >= 7 + k:
         return f"k_dense_pair<{k}>"     # complex64: two amplitudes per lane access
     if family == "dense_bfly" and real == "float":   # amplitude pairs, targets in bits 1..3

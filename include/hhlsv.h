@@ -256,7 +256,8 @@ sv_status sv_apply(sv_state *s, const sv_circuit *c);
 /* Kernel families reported by sv_apply_timed. */
 typedef enum {
     SV_KERNEL_DENSE_DIRECT = 0, /* dense k <= 5, no target inside a 128-byte
-                                   line (all >= 3 at c128, >= 4 at c64):
+                                   line (all >= 3 at c128, >= 4 at c64; at
+                                   c64 also bit 0 alone inside the line):
                                    groups held in registers              */
     SV_KERNEL_DENSE_LDS = 1,    /* dense k <= 5, some target inside a line
                                    (at c128: three or more, or k = 5):
@@ -349,6 +350,17 @@ sv_status svb_solution(svb *bt, int index, double *x_hat, int dim,
 sv_status svb_postselected(svb *bt, int index, double *y, int count,
                            double *p_anc1);
 sv_status svb_last_run_ms(const svb *bt, double *ms);
+/* svb_run_timed: the launches of svb_run without its graph, one work item
+ * after another on the batch's stream, each timed with HIP events, for a
+ * breakdown of the batch's device time.  An item is a size class of the
+ * batched kernel (kind 0) or a group of same-shape instances run through the
+ * whole-GPU sweep kernels (kind 1).  For item i < *items: n[i] qubits,
+ * count[i] instances, ops[i] fused ops per instance (the most in a class),
+ * ms[i] device time.  The arrays hold cap entries; SV_ERR_INVALID (with
+ * *items set) if cap is below the number of items.  Leaves the results as
+ * svb_run does; svb_last_run_ms then gives the sum of the items. */
+sv_status svb_run_timed(svb *bt, int cap, int *items, int *kind, int *n,
+                        int *count, int *ops, double *ms);
 sv_status svb_size(const svb *bt, int *count);
 sv_status svb_destroy(svb *bt);
 
@@ -479,6 +491,13 @@ sv_status sv_stream_probe(sv_state *s, int reps, double *launch_ms);
  * use while other threads launch; graphs captured earlier keep their
  * kernels. */
 sv_status sv_debug_set_dense_mfma(int enable);
+
+/* Select the kernel of complex64 dense gates whose only target inside a
+ * 128-byte line is bit 0, for launches made after the call: enable != 0 (the
+ * default) the register kernel that moves amplitude pairs (a pair holds two
+ * entries of one group), 0 the LDS regroup.  Same gate either way; for
+ * comparison and tests.  Process-wide, as sv_debug_set_dense_mfma. */
+sv_status sv_debug_set_pair0(int enable);
 
 /* Sec. III-B qubit estimate, in the reading that reproduces Table I:
  * n_data = ceil(log2 dim), n_qpe = max(n_data + 1, ceil(log2(kappa + 1)))

@@ -119,6 +119,7 @@ _proto("circuit_destroy", _vp)
 _proto("sv_solution_x", _dp, ctypes.c_int, ctypes.POINTER(SolutionInfo), _dp)
 _proto("sv_debug_set_grid_cap", ctypes.c_int)
 _proto("sv_debug_set_dense_mfma", ctypes.c_int)
+_proto("sv_debug_set_pair0", ctypes.c_int)
 _proto("sv_stream_probe", _vp, ctypes.c_int, _dp)
 _proto("sv_qubit_estimate", ctypes.c_int, ctypes.c_double, ctypes.c_int, _ip, _ip, _ip)
 _proto("pf_mismatch_jacobian", ctypes.c_int, ctypes.c_int, _ip, _ip, _dp, _dp, _dp, _ip, _dp, _dp, _dp, _dp,
@@ -130,6 +131,7 @@ _proto("svb_add", _vp, _vp, _ip)
 _proto("svb_run", _vp)
 _proto("svb_solution", _vp, ctypes.c_int, _dp, ctypes.c_int, ctypes.POINTER(SolutionInfo))
 _proto("svb_last_run_ms", _vp, _dp)
+_proto("svb_run_timed", _vp, ctypes.c_int, _ip, _ip, _ip, _ip, _ip, _dp)
 _proto("svb_postselected", _vp, ctypes.c_int, _dp, ctypes.c_int, _dp)
 _proto("svb_size", _vp, _ip)
 _proto("svb_destroy", _vp)
@@ -447,6 +449,12 @@ def sv_debug_set_dense_mfma(enable: bool):
     _check(_lib.sv_debug_set_dense_mfma(int(bool(enable))), "sv_debug_set_dense_mfma")
 
 
+def sv_debug_set_pair0(enable: bool):
+    """complex64 gates with bit 0 the only target inside a line: pair kernel
+    (True, default) or LDS regroup (False)."""
+    _check(_lib.sv_debug_set_pair0(int(bool(enable))), "sv_debug_set_pair0")
+
+
 # ------------------------------------------------------------------- batches
 class Batch:
     """Owning wrapper of an ``svb*``: many small HHL solves per launch."""
@@ -486,6 +494,18 @@ class Batch:
         ms = ctypes.c_double()
         _check(_lib.svb_last_run_ms(self.handle, ctypes.byref(ms)), "svb_last_run_ms")
         return ms.value
+
+    def run_timed(self, cap: int = 4096):
+        """Eager run, one work item after another, each timed: a list of
+        dicts (kind "batched" or "swept", n, count, ops, ms)."""
+        items = ctypes.c_int()
+        kind, n, count, ops = (np.zeros(cap, dtype=np.int32) for _ in range(4))
+        ms = np.zeros(cap)
+        _check(_lib.svb_run_timed(self.handle, cap, ctypes.byref(items), kind.ctypes.data_as(_ip),
+                                  n.ctypes.data_as(_ip), count.ctypes.data_as(_ip), ops.ctypes.data_as(_ip),
+                                  _dptr(ms)), "svb_run_timed")
+        return [{"kind": "swept" if kind[i] else "batched", "n": int(n[i]), "count": int(count[i]),
+                 "ops": int(ops[i]), "ms": float(ms[i])} for i in range(items.value)]
 
     def solution(self, index: int):
         dim = self.dims[index]

@@ -476,17 +476,18 @@ struct svb {
     double *h_out = nullptr;   // pinned
     std::vector<BatchClass> classes;
     // Instances whose state does not fit in LDS run through the whole-GPU
-    // sweep kernels instead, in groups of up to kMaxGroup instances of the
+    // sweep kernels instead, in groups of up to kMaxGroup (256) instances of the
     // same shape (same size and fused op list): one launch per op for the
     // whole group, each member with its own tables.
     struct Swept {
         int n = 0, ns = 0;
         std::vector<DevOp> ops;     // table offsets relative to a member's table base
         std::vector<int> members;   // instance indices
-        size_t part_first = 0;      // first reduction-scratch slot
+        size_t part_first = 0;      // first reduction-scratch slot (and first member-table entry)
     };
     std::vector<Swept> swept;
     double *d_partials = nullptr;
+    unsigned long long *d_members = nullptr;   // device member tables of the swept groups
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool have_result = false;
@@ -508,7 +509,9 @@ void release_device(svb *b)
     (void)hipFree(b->d_states);
     (void)hipFree(b->d_out);
     (void)hipFree(b->d_partials);
+    (void)hipFree(b->d_members);
     b->d_partials = nullptr;
+    b->d_members = nullptr;
     b->swept.clear();
     if (b->h_out) (void)hipHostFree(b->h_out);
     b->d_ops = nullptr;
@@ -550,6 +553,23 @@ bool same_ops(const std::vector<DevOp> &x, const std::vector<DevOp> &y)
             if (a.q[j] != c.q[j]) return false;
     }
     return true;
+}
+
+// The launch group of a swept group: each member's state, program image,
+// reduction scratch and output block (device addresses), and its device
+// member table.
+void swept_group(const svb *b, const svb::Swept &sw, Group *g)
+{
+    g->count = (int)sw.members.size();
+    g->batch = true;
+    for (int i = 0; i < g->count; ++i) {
+        const svb::Meta &in = b->insts[sw.members[i]];
+        g->psi[i] = b->d_states + in.state_off;
+        g->dbuf[i] = b->d_tables + in.tab_base;
+        g->partials[i] = b->d_partials + (sw.part_first + i) * (kReducePartials + 1);
+        g->out[i] = b->d_out + in.out_off;
+    }
+    g->d_members = b->d_members + sw.part_first * MF_COUNT;
 }
 
 sv_status upload(svb *b)
@@ -626,6 +646,7 @@ sv_status upload(svb *b)
     if ((st = alloc((void **)&b->d_states, arena)) != SV_OK) return st;
     if ((st = alloc((void **)&b->d_out, b->out_doubles * sizeof(double))) != SV_OK) return st;
     if ((st = alloc((void **)&b->d_partials, nparts * (kReducePartials + 1) * sizeof(double))) != SV_OK) return st;
+    if ((st = alloc((void **)&b->d_members, nparts * MF_COUNT * sizeof(unsigned long long))) != SV_OK) return st;
     HIPCK(hipHostMalloc((void **)&b->h_out, std::max<size_t>(b->out_doubles, 1) * sizeof(double)));
     std::vector<BInst> dev(b->insts.size());
     for (size_t i = 0; i < b->insts.size(); ++i) {
@@ -644,6 +665,15 @@ sv_status upload(svb *b)
     HIPCK(hipMemcpy(b->d_tables, b->tables.data(), b->tables.size(), hipMemcpyHostToDevice));
     HIPCK(hipMemcpy(b->d_insts, dev.data(), dev.size() * sizeof(BInst), hipMemcpyHostToDevice));
     HIPCK(hipMemcpy(b->d_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (nparts) {
+        std::vector<unsigned long long> mt(nparts * MF_COUNT);
+        for (const svb::Swept &sw : b->swept) {
+            Group g;
+            swept_group(b, sw, &g);
+            member_table(g, mt.data() + sw.part_first * MF_COUNT);
+        }
+        HIPCK(hipMemcpy(b->d_members, mt.data(), mt.size() * sizeof(unsigned long long), hipMemcpyHostToDevice));
+    }
     if (!b->evo_jobs.empty()) {
         // Spectral arena: each distinct eigen-decomposition once (Vt, then w).
         std::map<const Spectral *, std::pair<size_t, size_t>> where;
@@ -706,15 +736,7 @@ sv_status capture(svb *b)
         const svb::Swept &sw = b->swept[gi];
         const hipStream_t st = b->side[(b->classes.size() + gi) % nside];
         Group g;
-        g.count = (int)sw.members.size();
-        g.batch = true;
-        for (int i = 0; i < g.count; ++i) {
-            const svb::Meta &in = b->insts[sw.members[i]];
-            g.psi[i] = b->d_states + in.state_off;
-            g.dbuf[i] = b->d_tables + in.tab_base;
-            g.partials[i] = b->d_partials + (sw.part_first + i) * (kReducePartials + 1);
-            g.out[i] = b->d_out + in.out_off;
-        }
+        swept_group(b, sw, &g);
         sv_status ls = launch_init_zero_group(g, sw.n, b->dtype, st);
         for (size_t o = 0; o < sw.ops.size() && ls == SV_OK; ++o) ls = launch_op_group(sw.ops[o], g, sw.n, b->dtype, st);
         if (ls == SV_OK) ls = launch_postselect_group(g, sw.n, sw.ns, b->dtype, st);
@@ -856,6 +878,78 @@ extern "C" sv_status svb_run(svb *b)
     float ms = 0.f;
     HIPCK(hipEventElapsedTime(&ms, b->t0, b->t1));
     b->last_ms = ms;
+    b->have_result = true;
+    return SV_OK;
+}
+
+extern "C" sv_status svb_run_timed(svb *b, int cap, int *items, int *kind, int *n, int *count, int *ops,
+                                   double *ms)
+{
+    if (!b || !items || !kind || !n || !count || !ops || !ms || cap < 0)
+        return fail(SV_ERR_INVALID, "svb_run_timed: NULL argument or cap < 0");
+    if (b->insts.empty()) return fail(SV_ERR_INVALID, "svb_run_timed: empty batch");
+    sv_status st;
+    if (!b->uploaded) {
+        if ((st = upload(b)) != SV_OK) {
+            release_device(b);
+            return st;
+        }
+        if ((st = capture(b)) != SV_OK) {
+            release_device(b);
+            return st;
+        }
+    }
+    const int total = (int)(b->classes.size() + b->swept.size());
+    *items = total;
+    if (cap < total) return fail(SV_ERR_INVALID, "svb_run_timed: cap below the number of items");
+    std::vector<hipEvent_t> ev(total + 1, nullptr);
+    hipError_t e = hipSuccess;
+    for (auto &x : ev)
+        if (e == hipSuccess) e = hipEventCreate(&x);
+    if (e == hipSuccess) e = hipEventRecord(ev[0], b->stream);
+    int it = 0;
+    for (size_t c = 0; c < b->classes.size() && e == hipSuccess; ++c, ++it) {
+        const BatchClass &cl = b->classes[c];
+        kind[it] = 0;
+        n[it] = cl.n;
+        count[it] = cl.count;
+        ops[it] = 0;
+        for (const svb::Meta &m : b->insts)
+            if (m.n == cl.n) ops[it] = std::max(ops[it], m.op_count);
+        if (launch_batch_class(b->d_insts, b->d_order + cl.first, cl.count, cl.n, cl.kmax, b->dtype, b->stream) !=
+            SV_OK)
+            e = hipErrorLaunchFailure;
+        if (e == hipSuccess) e = hipEventRecord(ev[it + 1], b->stream);
+    }
+    for (size_t gi = 0; gi < b->swept.size() && e == hipSuccess; ++gi, ++it) {
+        const svb::Swept &sw = b->swept[gi];
+        kind[it] = 1;
+        n[it] = sw.n;
+        count[it] = (int)sw.members.size();
+        ops[it] = (int)sw.ops.size();
+        Group g;
+        swept_group(b, sw, &g);
+        sv_status ls = launch_init_zero_group(g, sw.n, b->dtype, b->stream);
+        for (size_t o = 0; o < sw.ops.size() && ls == SV_OK; ++o)
+            ls = launch_op_group(sw.ops[o], g, sw.n, b->dtype, b->stream);
+        if (ls == SV_OK) ls = launch_postselect_group(g, sw.n, sw.ns, b->dtype, b->stream);
+        if (ls != SV_OK) e = hipErrorLaunchFailure;
+        if (e == hipSuccess) e = hipEventRecord(ev[it + 1], b->stream);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->h_out, b->d_out, b->out_doubles * sizeof(double), hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    double sum = 0.0;
+    for (int i = 0; i < total && e == hipSuccess; ++i) {
+        float t = 0.f;
+        e = hipEventElapsedTime(&t, ev[i], ev[i + 1]);
+        ms[i] = t;
+        sum += t;
+    }
+    for (auto &x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (e != hipSuccess) return fail(SV_ERR_HIP, std::string("svb_run_timed: ") + hipGetErrorString(e));
+    b->last_ms = sum;
     b->have_result = true;
     return SV_OK;
 }

@@ -124,10 +124,10 @@ __global__ __launch_bounds__(256) void k_dense_direct(typename V2<R>::type *__re
 
 // Grouped form: member blockIdx.y of up to kMaxGroup states.
 template <typename R, int K>
-__global__ __launch_bounds__(256) void k_dense_direct_g(Ptrs pp, TileArgs a)
+__global__ __launch_bounds__(256) void k_dense_direct_g(Members mm, TileArgs a)
 {
     typedef typename V2<R>::type C;
-    k_dense_direct_body<R, K>(member_ptr<C>(pp.a), member_ptr<const C>(pp.b), a);
+    k_dense_direct_body<R, K>(member_ptr<C>(mm, MF_STATE), member_ptr<const C>(mm, MF_PROG), a);
 }
 
 // complex64 on the direct path: each lane moves two neighbouring amplitudes
@@ -177,9 +177,61 @@ __global__ __launch_bounds__(256) void k_dense_pair(V2<float>::type *__restrict_
 
 // Grouped form: member blockIdx.y of up to kMaxGroup states.
 template <int K>
-__global__ __launch_bounds__(256) void k_dense_pair_g(Ptrs pp, TileArgs a)
+__global__ __launch_bounds__(256) void k_dense_pair_g(Members mm, TileArgs a)
 {
-    k_dense_pair_body<K>(member_ptr<F4>(pp.a), member_ptr<const V2<float>::type>(pp.b), a);
+    k_dense_pair_body<K>(member_ptr<F4>(mm, MF_STATE), member_ptr<const V2<float>::type>(mm, MF_PROG), a);
+}
+
+// complex64 with bit 0 as the lowest target and every other target outside
+// the 128-byte line: a 16-byte pair holds amplitudes 2i and 2i + 1 of one
+// group, so each lane loads the 2^(K-1) pairs of one group (the other
+// targets are register bits, in pair units) and holds the whole group in
+// matrix order.  Loads and stores stay 16 bytes per lane, 1 KiB per
+// instruction, as on the pair path.
+template <int K>
+__device__ __forceinline__ void k_dense_pair0_body(F4 *__restrict__ psi, const V2<float>::type *__restrict__ mat,
+                                                   const TileArgs &a)
+{
+    typedef V2<float>::type C;
+    constexpr int NP = 1 << (K - 1);
+    constexpr int NR = 1 << K;
+    uint64_t loff = threadIdx.x & 63;
+    for (int j = 0; j < K - 1; ++j) loff = insert_zero(loff, a.rpos[j]);
+    const WaveRange wr = wave_range(a.ntiles, 4);
+    for (uint64_t w = wr.w; w < wr.end; w += wr.step) {
+        const uint64_t base = tile_base(w, a.rpos, K - 1) + loff;
+        const C *m = opaque(mat);
+        F4 v[NP];
+#pragma unroll
+        for (int i = 0; i < NP; ++i) v[i] = ld_nt(psi + base + a.reg_off[i]);
+#pragma unroll
+        for (int rp = 0; rp < NP; ++rp) {
+            C lo = {0, 0}, hi = {0, 0};   // rows 2 rp and 2 rp + 1
+#pragma unroll
+            for (int cp = 0; cp < NP; ++cp) {
+                cmac(lo, m[(2 * rp) * NR + 2 * cp], v[cp].xy);
+                cmac(lo, m[(2 * rp) * NR + 2 * cp + 1], v[cp].zw);
+                cmac(hi, m[(2 * rp + 1) * NR + 2 * cp], v[cp].xy);
+                cmac(hi, m[(2 * rp + 1) * NR + 2 * cp + 1], v[cp].zw);
+                if (NR > 16 && (cp & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+            }
+            st_nt(F4{lo.x, lo.y, hi.x, hi.y}, psi + base + a.reg_off[rp]);
+        }
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_dense_pair0(V2<float>::type *__restrict__ psi,
+                                                     const V2<float>::type *__restrict__ mat, TileArgs a)
+{
+    k_dense_pair0_body<K>(reinterpret_cast<F4 *>(psi), mat, a);
+}
+
+// Grouped form: member blockIdx.y of up to kMaxGroup states.
+template <int K>
+__global__ __launch_bounds__(256) void k_dense_pair0_g(Members mm, TileArgs a)
+{
+    k_dense_pair0_body<K>(member_ptr<F4>(mm, MF_STATE), member_ptr<const V2<float>::type>(mm, MF_PROG), a);
 }
 
 // ---------------------------------------------------------------------------
@@ -347,9 +399,9 @@ __global__ __launch_bounds__(256) void k_dense_bfly_pair(V2<float>::type *__rest
 
 // Grouped form: member blockIdx.y of up to kMaxGroup states.
 template <int K, int NSUB>
-__global__ __launch_bounds__(256) void k_dense_bfly_pair_g(Ptrs pp, TileArgs a)
+__global__ __launch_bounds__(256) void k_dense_bfly_pair_g(Members mm, TileArgs a)
 {
-    k_dense_bfly_pair_body<K, NSUB>(member_ptr<F4>(pp.a), member_ptr<const V2<float>::type>(pp.b), a);
+    k_dense_bfly_pair_body<K, NSUB>(member_ptr<F4>(mm, MF_STATE), member_ptr<const V2<float>::type>(mm, MF_PROG), a);
 }
 
 template <int K, int NSUB>
@@ -361,10 +413,10 @@ __global__ __launch_bounds__(256) void k_dense_bfly(V2<double>::type *__restrict
 
 // Grouped form: member blockIdx.y of up to kMaxGroup states.
 template <int K, int NSUB>
-__global__ __launch_bounds__(256) void k_dense_bfly_g(Ptrs pp, TileArgs a)
+__global__ __launch_bounds__(256) void k_dense_bfly_g(Members mm, TileArgs a)
 {
     typedef V2<double>::type C;
-    k_dense_bfly_body<K, NSUB>(member_ptr<C>(pp.a), member_ptr<const C>(pp.b), a);
+    k_dense_bfly_body<K, NSUB>(member_ptr<C>(mm, MF_STATE), member_ptr<const C>(mm, MF_PROG), a);
 }
 
 __device__ __forceinline__ int lds_phys(int s) { return s + (s >> 6); }
@@ -416,10 +468,10 @@ __global__ __launch_bounds__(64) void k_dense_lds(typename V2<R>::type *__restri
 
 // Grouped form: member blockIdx.y of up to kMaxGroup states.
 template <typename R, int K>
-__global__ __launch_bounds__(64) void k_dense_lds_g(Ptrs pp, TileArgs a)
+__global__ __launch_bounds__(64) void k_dense_lds_g(Members mm, TileArgs a)
 {
     typedef typename V2<R>::type C;
-    k_dense_lds_body<R, K>(member_ptr<C>(pp.a), member_ptr<const C>(pp.b), a);
+    k_dense_lds_body<R, K>(member_ptr<C>(mm, MF_STATE), member_ptr<const C>(mm, MF_PROG), a);
 }
 
 // Dense k-qubit gate, one thread per group (any n >= k; used for small states).
@@ -463,10 +515,10 @@ __global__ __launch_bounds__(256) void k_dense_generic(typename V2<R>::type *__r
 
 // Grouped form: member blockIdx.y of up to kMaxGroup states.
 template <typename R, int K>
-__global__ __launch_bounds__(256) void k_dense_generic_g(Ptrs pp, GenericArgs a)
+__global__ __launch_bounds__(256) void k_dense_generic_g(Members mm, GenericArgs a)
 {
     typedef typename V2<R>::type C;
-    k_dense_generic_body<R, K>(member_ptr<C>(pp.a), member_ptr<const C>(pp.b), a);
+    k_dense_generic_body<R, K>(member_ptr<C>(mm, MF_STATE), member_ptr<const C>(mm, MF_PROG), a);
 }
 
 // ---------------------------------------------------------------------------
@@ -506,10 +558,10 @@ __global__ __launch_bounds__(256) void k_diag(typename V2<R>::type *__restrict__
 
 // Grouped form: member blockIdx.y of up to kMaxGroup states.
 template <typename R>
-__global__ __launch_bounds__(256) void k_diag_g(Ptrs pp, DiagArgs a)
+__global__ __launch_bounds__(256) void k_diag_g(Members mm, DiagArgs a)
 {
     typedef typename V2<R>::type C;
-    k_diag_body<R>(member_ptr<C>(pp.a), member_ptr<const C>(pp.b), a);
+    k_diag_body<R>(member_ptr<C>(mm, MF_STATE), member_ptr<const C>(mm, MF_PROG), a);
 }
 
 // ---------------------------------------------------------------------------
@@ -572,10 +624,10 @@ __global__ __launch_bounds__(256) void k_wide(typename V2<R>::type *__restrict__
 
 // Grouped form: member blockIdx.y of up to kMaxGroup states.
 template <typename R>
-__global__ __launch_bounds__(256) void k_wide_g(Ptrs pp, WideArgs a)
+__global__ __launch_bounds__(256) void k_wide_g(Members mm, WideArgs a)
 {
     typedef typename V2<R>::type C;
-    k_wide_body<R>(member_ptr<C>(pp.a), member_ptr<const C>(pp.b), a);
+    k_wide_body<R>(member_ptr<C>(mm, MF_STATE), member_ptr<const C>(mm, MF_PROG), a);
 }
 
 // ---------------------------------------------------------------------------
@@ -677,10 +729,10 @@ __global__ __launch_bounds__(256) void k_wide_gemm(typename V2<R>::type *__restr
 
 // Grouped form: member blockIdx.y of up to kMaxGroup states.
 template <typename R, int CT, int RW>
-__global__ __launch_bounds__(256) void k_wide_gemm_g(Ptrs pp, WideGemmArgs a)
+__global__ __launch_bounds__(256) void k_wide_gemm_g(Members mm, WideGemmArgs a)
 {
     typedef typename V2<R>::type C;
-    k_wide_gemm_body<R, CT, RW>(member_ptr<C>(pp.a), member_ptr<const C>(pp.b), a);
+    k_wide_gemm_body<R, CT, RW>(member_ptr<C>(mm, MF_STATE), member_ptr<const C>(mm, MF_PROG), a);
 }
 
 // ---------------------------------------------------------------------------
@@ -804,10 +856,10 @@ __global__ __launch_bounds__(256) void k_dense_mfma5(typename V2<R>::type *__res
 
 // Grouped form: member blockIdx.y of up to kMaxGroup states.
 template <typename R>
-__global__ __launch_bounds__(256) void k_dense_mfma5_g(Ptrs pp, TileArgs a)
+__global__ __launch_bounds__(256) void k_dense_mfma5_g(Members mm, TileArgs a)
 {
     typedef typename V2<R>::type C;
-    k_dense_mfma5_body<R>(member_ptr<C>(pp.a), member_ptr<const C>(pp.b), a);
+    k_dense_mfma5_body<R>(member_ptr<C>(mm, MF_STATE), member_ptr<const C>(mm, MF_PROG), a);
 }
 
 // Offset of column c (target bits) and base of row g (control set, zeros at
@@ -914,10 +966,10 @@ __global__ __launch_bounds__(256) void k_wide_mfma(typename V2<R>::type *__restr
 
 // Grouped form: member blockIdx.y of up to kMaxGroup states.
 template <typename R, int D, int RT>
-__global__ __launch_bounds__(256) void k_wide_mfma_g(Ptrs pp, WideGemmArgs a)
+__global__ __launch_bounds__(256) void k_wide_mfma_g(Members mm, WideGemmArgs a)
 {
     typedef typename V2<R>::type C;
-    k_wide_mfma_body<R, D, RT>(member_ptr<C>(pp.a), member_ptr<const C>(pp.b), a);
+    k_wide_mfma_body<R, D, RT>(member_ptr<C>(mm, MF_STATE), member_ptr<const C>(mm, MF_PROG), a);
 }
 
 // Wider gates (D = 128, 256) on launches with few rows (a single large
@@ -1013,11 +1065,11 @@ __global__ __launch_bounds__(64 * kStageWaves) void k_wide_mfma_stage(typename V
 
 // Grouped form: member blockIdx.y of up to kMaxGroup states.
 template <typename R, int D, int RT>
-__global__ __launch_bounds__(64 * kStageWaves) void k_wide_mfma_stage_g(Ptrs pp, WideGemmArgs a)
+__global__ __launch_bounds__(64 * kStageWaves) void k_wide_mfma_stage_g(Members mm, WideGemmArgs a)
 {
     typedef typename V2<R>::type C;
     extern __shared__ unsigned char smem_raw[];
-    k_wide_mfma_stage_body<R, D, RT>(member_ptr<C>(pp.a), member_ptr<const C>(pp.b), a,
+    k_wide_mfma_stage_body<R, D, RT>(member_ptr<C>(mm, MF_STATE), member_ptr<const C>(mm, MF_PROG), a,
                                      reinterpret_cast<R *>(smem_raw));
 }
 
@@ -1111,20 +1163,20 @@ __global__ __launch_bounds__(256) void k_ucry(typename V2<R>::type *__restrict__
 
 // Grouped form: member blockIdx.y of up to kMaxGroup states.
 template <typename R>
-__global__ __launch_bounds__(256) void k_ucry_g(Ptrs pp, UcryArgs a)
+__global__ __launch_bounds__(256) void k_ucry_g(Members mm, UcryArgs a)
 {
     typedef typename V2<R>::type C;
-    k_ucry_body<R>(member_ptr<C>(pp.a), member_ptr<const C>(pp.b), a);
+    k_ucry_body<R>(member_ptr<C>(mm, MF_STATE), member_ptr<const C>(mm, MF_PROG), a);
 }
 
 // ---------------------------------------------------------------------------
 // Utility kernels.
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(256) void k_zero_state(Ptrs pp, uint64_t namps)
+__global__ __launch_bounds__(256) void k_zero_state(Members mm, uint64_t namps)
 {
     typedef typename V2<R>::type C;
-    C *__restrict__ psi = member_ptr<C>(pp.a);
+    C *__restrict__ psi = member_ptr<C>(mm, MF_STATE);
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < namps;
          i += (uint64_t)gridDim.x * blockDim.x) {
         C z = {(R)(i == 0 ? 1 : 0), (R)0};
@@ -1133,10 +1185,10 @@ __global__ __launch_bounds__(256) void k_zero_state(Ptrs pp, uint64_t namps)
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_norm2_partial(Ptrs pp, uint64_t lo, uint64_t hi)
+__global__ __launch_bounds__(256) void k_norm2_partial(Members mm, uint64_t lo, uint64_t hi)
 {
-    const typename V2<R>::type *__restrict__ psi = member_ptr<const typename V2<R>::type>(pp.a);
-    double *__restrict__ partials = member_ptr<double>(pp.b);
+    const typename V2<R>::type *__restrict__ psi = member_ptr<const typename V2<R>::type>(mm, MF_STATE);
+    double *__restrict__ partials = member_ptr<double>(mm, MF_PARTIALS);
     __shared__ double red[256];
     double s = 0.0;
     for (uint64_t i = lo + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi;
@@ -1153,10 +1205,10 @@ __global__ __launch_bounds__(256) void k_norm2_partial(Ptrs pp, uint64_t lo, uin
     if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
 }
 
-__global__ __launch_bounds__(256) void k_sum_partials(Ptrs pp, int n)
+__global__ __launch_bounds__(256) void k_sum_partials(Members mm, int n)
 {
-    const double *__restrict__ partials = member_ptr<const double>(pp.a);
-    double *__restrict__ out = member_ptr<double>(pp.b);
+    const double *__restrict__ partials = member_ptr<const double>(mm, MF_PARTIALS);
+    double *__restrict__ out = member_ptr<double>(mm, MF_OUT);
     __shared__ double red[256];
     double s = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) s += partials[i];
@@ -1173,10 +1225,10 @@ __global__ __launch_bounds__(256) void k_sum_partials(Ptrs pp, int n)
 // norm reduction), 0, y_0.re, y_0.im, ...] with y_s = psi[2^{n-1} + s],
 // widened to double.  Member pointers: a = state, b = its output block.
 template <typename R>
-__global__ __launch_bounds__(256) void k_copy_block(Ptrs pp, uint64_t half, int D)
+__global__ __launch_bounds__(256) void k_copy_block(Members mm, uint64_t half, int D)
 {
-    const typename V2<R>::type *__restrict__ psi = member_ptr<const typename V2<R>::type>(pp.a);
-    double *__restrict__ out = member_ptr<double>(pp.b);
+    const typename V2<R>::type *__restrict__ psi = member_ptr<const typename V2<R>::type>(mm, MF_STATE);
+    double *__restrict__ out = member_ptr<double>(mm, MF_OUT);
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < D; i += gridDim.x * blockDim.x) {
         const auto y = psi[half + i];
         out[2 + 2 * i] = (double)y.x;
@@ -1228,6 +1280,10 @@ std::atomic<unsigned> g_grid_cap{0};
 // 5-qubit dense gates on the matrix cores (k_dense_mfma5); off selects the
 // vector forms, for comparison.
 std::atomic<bool> g_dense_mfma{true};
+// complex64 gates with bit 0 as the only target inside a cache line on the
+// pair kernel (k_dense_pair0); off sends them to the LDS regroup, for
+// comparison.
+std::atomic<bool> g_pair0{true};
 
 inline unsigned grid_for(uint64_t work, unsigned per_block, unsigned cap)
 {
@@ -1244,14 +1300,14 @@ inline unsigned grid_for(uint64_t work, unsigned per_block, unsigned cap)
 // One op on a group: the plain kernel (pointer arguments) for a single
 // state, the grouped form (member pointers from the table) for several.
 template <typename T, typename A>
-void launch2(void (*direct)(T *, const T *, A), void (*grouped)(Ptrs, A), unsigned gx, unsigned block,
-             size_t smem, hipStream_t st, const Ptrs &pp, unsigned cnt, const A &args)
+void launch2(void (*direct)(T *, const T *, A), void (*grouped)(Members, A), unsigned gx, unsigned block,
+             size_t smem, hipStream_t st, const Members &mm, unsigned cnt, const A &args)
 {
     if (cnt == 1)
-        hipLaunchKernelGGL(direct, dim3(gx), dim3(block), smem, st, reinterpret_cast<T *>(pp.a[0]),
-                           reinterpret_cast<const T *>(pp.b[0]), args);
+        hipLaunchKernelGGL(direct, dim3(gx), dim3(block), smem, st, reinterpret_cast<T *>(mm.one[MF_STATE]),
+                           reinterpret_cast<const T *>(mm.one[MF_PROG] + mm.boff), args);
     else
-        hipLaunchKernelGGL(grouped, dim3(gx, cnt), dim3(block), smem, st, pp, args);
+        hipLaunchKernelGGL(grouped, dim3(gx, cnt), dim3(block), smem, st, mm, args);
 }
 
 // Kernels that need more than the default 64 KiB of dynamic LDS are opted
@@ -1273,22 +1329,31 @@ sv_status prepare_kernels_once()
     return SV_OK;
 }
 
-// Per-member (state, op table) pointers of a grouped launch.
-Ptrs op_ptrs(const DevOp &op, const Group &g)
+// Member addresses of a grouped launch, with boff added to each member's
+// program image; SV_ERR_INVALID for a bad group size or a group of several
+// members without its device table.
+sv_status group_members(const Group &g, unsigned long long boff, Members *mm)
 {
-    Ptrs pp;
-    std::memset(&pp, 0, sizeof(pp));
-    for (int i = 0; i < g.count; ++i) {
-        pp.a[i] = reinterpret_cast<unsigned long long>(g.psi[i]);
-        pp.b[i] = reinterpret_cast<unsigned long long>(g.dbuf[i] + op.off);
+    if (g.count < 1 || g.count > kMaxGroup) return fail(SV_ERR_INVALID, "launch: bad group size");
+    std::memset(mm, 0, sizeof(*mm));
+    mm->boff = boff;
+    if (g.count == 1) {
+        member_table(g, mm->one);
+        return SV_OK;
     }
-    return pp;
+    if (!g.d_members) return fail(SV_ERR_INVALID, "launch: a group of several members needs its device table");
+    mm->tab = g.d_members;
+    return SV_OK;
 }
 
 template <typename R>
 sv_status launch_dense_t(const DevOp &op, const Group &g, int n, hipStream_t st, int *family)
 {
-    const Ptrs pp = op_ptrs(op, g);
+    Members pp;
+    {
+        const sv_status ms = group_members(g, op.off, &pp);
+        if (ms != SV_OK) return ms;
+    }
     const unsigned cnt = (unsigned)g.count;
     const int k = op.k;
     // 5-qubit gates on the matrix cores (k_dense_mfma5_body) when every
@@ -1318,6 +1383,31 @@ sv_status launch_dense_t(const DevOp &op, const Group &g, int n, hipStream_t st,
         for (int j = 0; j < k; ++j) {
             nlo += op.q[j] < 6;
             nsub += op.q[j] < line_bits;
+        }
+        // complex64 with bit 0 the only target inside the line: pairs hold
+        // whole groups (k_dense_pair0_body)
+        if (sizeof(R) == 4 && op.q[0] == 0 && nsub == 1 && g_pair0.load(std::memory_order_relaxed)) {
+            a.ntiles = uint64_t(1) << (n - 6 - k);
+            for (int j = 1; j < k; ++j) a.rpos[j - 1] = op.q[j] - 1;
+            for (int i = 0; i < (1 << (k - 1)); ++i) {
+                uint64_t o = 0;
+                for (int j = 1; j < k; ++j)
+                    if ((i >> (j - 1)) & 1) o |= uint64_t(1) << (op.q[j] - 1);
+                a.reg_off[i] = o;
+            }
+            *family = SV_KERNEL_DENSE_DIRECT;
+            const unsigned grid = grid_for(a.ntiles, 4, 32768);
+            typedef V2<float>::type CF;
+            switch (k) {
+            case 1: launch2<CF>(&k_dense_pair0<1>, &k_dense_pair0_g<1>, grid, 256, 0, st, pp, cnt, a); break;
+            case 2: launch2<CF>(&k_dense_pair0<2>, &k_dense_pair0_g<2>, grid, 256, 0, st, pp, cnt, a); break;
+            case 3: launch2<CF>(&k_dense_pair0<3>, &k_dense_pair0_g<3>, grid, 256, 0, st, pp, cnt, a); break;
+            case 4: launch2<CF>(&k_dense_pair0<4>, &k_dense_pair0_g<4>, grid, 256, 0, st, pp, cnt, a); break;
+            case 5: launch2<CF>(&k_dense_pair0<5>, &k_dense_pair0_g<5>, grid, 256, 0, st, pp, cnt, a); break;
+            default: return fail(SV_ERR_INVALID, "dense op wider than 5 qubits");
+            }
+            HIPCK(hipGetLastError());
+            return SV_OK;
         }
         // butterfly path (see k_dense_bfly_body); complex64 runs it on the
         // pair view (targets shifted down by one) when bit 0 is not a target
@@ -1493,7 +1583,11 @@ template <typename R>
 sv_status launch_op_t(const DevOp &op, const Group &g, int n, hipStream_t st, int *family)
 {
     typedef typename V2<R>::type C;
-    const Ptrs pp = op_ptrs(op, g);
+    Members pp;
+    {
+        const sv_status ms = group_members(g, op.off, &pp);
+        if (ms != SV_OK) return ms;
+    }
     const unsigned cnt = (unsigned)g.count;
     switch (op.type) {
     case OP_DENSE:
@@ -2005,10 +2099,9 @@ sv_status launch_build_evolutions(const EvoJob *d_jobs, int njobs, int max_D, co
 
 sv_status launch_init_zero_group(const Group &g, int n, sv_dtype dtype, hipStream_t s)
 {
-    if (g.count < 1 || g.count > kMaxGroup) return fail(SV_ERR_INVALID, "launch: bad group size");
-    Ptrs pp;
-    std::memset(&pp, 0, sizeof(pp));
-    for (int i = 0; i < g.count; ++i) pp.a[i] = reinterpret_cast<unsigned long long>(g.psi[i]);
+    Members pp;
+    const sv_status ms = group_members(g, 0, &pp);
+    if (ms != SV_OK) return ms;
     const uint64_t namps = uint64_t(1) << n;
     const dim3 grid(grid_for(namps, 256, 16384), (unsigned)g.count);
     if (dtype == SV_C128)
@@ -2029,23 +2122,16 @@ sv_status launch_init_zero_state(void *psi, int n, sv_dtype dtype, hipStream_t s
 
 sv_status launch_norm2_group(const Group &g, uint64_t lo, uint64_t hi, sv_dtype dtype, hipStream_t s)
 {
-    if (g.count < 1 || g.count > kMaxGroup) return fail(SV_ERR_INVALID, "launch: bad group size");
-    Ptrs p1, p2;
-    std::memset(&p1, 0, sizeof(p1));
-    std::memset(&p2, 0, sizeof(p2));
-    for (int i = 0; i < g.count; ++i) {
-        p1.a[i] = reinterpret_cast<unsigned long long>(g.psi[i]);
-        p1.b[i] = reinterpret_cast<unsigned long long>(g.partials[i]);
-        p2.a[i] = p1.b[i];
-        p2.b[i] = reinterpret_cast<unsigned long long>(g.out[i]);
-    }
+    Members p1;
+    const sv_status ms = group_members(g, 0, &p1);
+    if (ms != SV_OK) return ms;
     const unsigned cnt = (unsigned)g.count;
     if (dtype == SV_C128)
         hipLaunchKernelGGL((k_norm2_partial<double>), dim3(kReducePartials, cnt), dim3(256), 0, s, p1, lo, hi);
     else
         hipLaunchKernelGGL((k_norm2_partial<float>), dim3(kReducePartials, cnt), dim3(256), 0, s, p1, lo, hi);
     HIPCK(hipGetLastError());
-    hipLaunchKernelGGL(k_sum_partials, dim3(1, cnt), dim3(256), 0, s, p2, kReducePartials);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1, cnt), dim3(256), 0, s, p1, kReducePartials);
     HIPCK(hipGetLastError());
     return SV_OK;
 }
@@ -2066,12 +2152,9 @@ sv_status launch_postselect_group(const Group &g, int n, int ns, sv_dtype dtype,
     const uint64_t half = uint64_t(1) << (n - 1);
     sv_status st = launch_norm2_group(g, half, half << 1, dtype, s);
     if (st != SV_OK) return st;
-    Ptrs pp;
-    std::memset(&pp, 0, sizeof(pp));
-    for (int i = 0; i < g.count; ++i) {
-        pp.a[i] = reinterpret_cast<unsigned long long>(g.psi[i]);
-        pp.b[i] = reinterpret_cast<unsigned long long>(g.out[i]);
-    }
+    Members pp;
+    st = group_members(g, 0, &pp);
+    if (st != SV_OK) return st;
     const int D = 1 << ns;
     const dim3 grid((D + 255) / 256, (unsigned)g.count);
     if (dtype == SV_C128)
@@ -2119,5 +2202,11 @@ extern "C" sv_status sv_debug_set_grid_cap(int max_workgroups)
 extern "C" sv_status sv_debug_set_dense_mfma(int enable)
 {
     hhlsv::g_dense_mfma.store(enable != 0, std::memory_order_relaxed);
+    return SV_OK;
+}
+
+extern "C" sv_status sv_debug_set_pair0(int enable)
+{
+    hhlsv::g_pair0.store(enable != 0, std::memory_order_relaxed);
     return SV_OK;
 }

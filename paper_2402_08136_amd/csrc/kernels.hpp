@@ -14,35 +14,60 @@ namespace hhlsv {
 // Grouped launches: one launch applies the same op to up to kMaxGroup states
 // of the same size, each with its own table (blockIdx.y selects the member).
 // A member's arithmetic does not depend on the group it runs in.
-constexpr int kMaxGroup = 64;
-struct Ptrs {
-    unsigned long long a[kMaxGroup];   // per member: the state (or primary buffer)
-    unsigned long long b[kMaxGroup];   // per member: the op's table (or secondary buffer)
+constexpr int kMaxGroup = 256;
+
+// Fields of a member: its state, its program image (an op's table is at a
+// byte offset in it), its reduction partials and its output block.
+enum MemberField : int { MF_STATE = 0, MF_PROG = 1, MF_PARTIALS = 2, MF_OUT = 3, MF_COUNT = 4 };
+
+// Member addresses of a grouped launch, passed by value (48 bytes): a
+// device table of MF_COUNT addresses per member, or, with a single member,
+// its addresses in `one`.  boff is added to MF_PROG (the op's table).
+struct Members {
+    const unsigned long long *tab;
+    unsigned long long one[MF_COUNT];
+    unsigned long long boff;
 };
 
 template <typename T>
-__device__ __forceinline__ T *member_ptr(const unsigned long long (&p)[kMaxGroup])
+__device__ __forceinline__ T *member_ptr(const Members &m, int field)
 {
+    unsigned long long v = m.tab ? m.tab[MF_COUNT * blockIdx.y + field] : m.one[field];
+    if (field == MF_PROG) v += m.boff;
     // the table holds device (global) addresses; saying so lets the accesses
     // compile to global rather than flat memory instructions
     typedef __attribute__((address_space(1))) T GT;
-    return (T *)reinterpret_cast<GT *>(p[blockIdx.y]);
+    return (T *)reinterpret_cast<GT *>(v);
 }
 
 // Host description of a group: members share n, dtype and the op list (same
-// table offsets in their program images).
+// table offsets in their program images).  With more than one member,
+// d_members holds their addresses on the device (MF_COUNT per member, the
+// same values as the host arrays) and stays valid until the launches end.
 struct Group {
     int count = 0;
     void *psi[kMaxGroup] = {};
     const unsigned char *dbuf[kMaxGroup] = {};   // program image of each member
     double *partials[kMaxGroup] = {};            // kReducePartials doubles each
     double *out[kMaxGroup] = {};                 // one double each (norm result)
+    const unsigned long long *d_members = nullptr;
     // Members are instances of a batch: wide gates of 8..64 columns always
     // take the matrix cores, whatever the row count.  Elsewhere the kernel
     // follows each member's own row count.  The choice never depends on the
     // group size, so a member's bits are the same alone or grouped.
     bool batch = false;
 };
+
+// The MF_COUNT device addresses of each member of g, in table order.
+inline void member_table(const Group &g, unsigned long long *out)
+{
+    for (int i = 0; i < g.count; ++i) {
+        out[MF_COUNT * i + MF_STATE] = reinterpret_cast<unsigned long long>(g.psi[i]);
+        out[MF_COUNT * i + MF_PROG] = reinterpret_cast<unsigned long long>(g.dbuf[i]);
+        out[MF_COUNT * i + MF_PARTIALS] = reinterpret_cast<unsigned long long>(g.partials[i]);
+        out[MF_COUNT * i + MF_OUT] = reinterpret_cast<unsigned long long>(g.out[i]);
+    }
+}
 
 // One device operation, lowered from a circuit gate.
 enum OpType : int {

@@ -509,6 +509,10 @@ constexpr int kServeGroup = 16;             // requests per launcher group
 struct Flight {
     hipEvent_t done = nullptr;
     double *h_out = nullptr;   // pinned, kServeGroup * kOutMax doubles
+    // member table of the group's launches: staged in pinned memory, copied
+    // to the device on the launch stream (reused once the flight is done)
+    unsigned long long *h_members = nullptr;
+    unsigned long long *d_members = nullptr;
     std::vector<std::shared_ptr<Req>> reqs;
     bool busy = false;
 };
@@ -531,6 +535,13 @@ sv_status launch_group(svs *s, Flight &f, hipStream_t st)
     for (int i = 0; i < g.count; ++i)
         if (hipStreamWaitEvent(st, f.reqs[i]->uploaded, 0) != hipSuccess)
             return fail(SV_ERR_HIP, "svs: wait for upload failed");
+    if (g.count > 1) {
+        member_table(g, f.h_members);
+        if (hipMemcpyAsync(f.d_members, f.h_members, sizeof(unsigned long long) * MF_COUNT * g.count,
+                           hipMemcpyHostToDevice, st) != hipSuccess)
+            return fail(SV_ERR_HIP, "svs: member table upload failed");
+        g.d_members = f.d_members;
+    }
     sv_status rc = launch_init_zero_group(g, r0.n, s->dtype, st);
     for (const DevOp &op : r0.ops) {
         if (rc != SV_OK) return rc;
@@ -558,6 +569,9 @@ void launcher_main(svs *s)
     for (Flight &f : fl) {
         if (e == hipSuccess) e = hipEventCreateWithFlags(&f.done, hipEventDisableTiming);
         if (e == hipSuccess) e = hipHostMalloc((void **)&f.h_out, kServeGroup * kOutMax * sizeof(double));
+        if (e == hipSuccess)
+            e = hipHostMalloc((void **)&f.h_members, kServeGroup * MF_COUNT * sizeof(unsigned long long));
+        if (e == hipSuccess) e = hipMalloc((void **)&f.d_members, kServeGroup * MF_COUNT * sizeof(unsigned long long));
     }
     const std::string setup_err = e == hipSuccess ? "" : std::string("svs: launcher setup: ") + hipGetErrorString(e);
     Dead dead;
@@ -681,6 +695,8 @@ void launcher_main(svs *s)
     for (Flight &f : fl) {
         if (f.done) (void)hipEventDestroy(f.done);
         if (f.h_out) (void)hipHostFree(f.h_out);
+        if (f.h_members) (void)hipHostFree(f.h_members);
+        if (f.d_members) (void)hipFree(f.d_members);
     }
     if (st) (void)hipStreamDestroy(st);
 }

@@ -77,6 +77,7 @@ PATTERNS = {
     "line1": [(1,), (2, 10), (1, 7, 13), (2, 6, 9, 15), (1, 6, 8, 12, 16)],
     "line2": [(0,), (0, 2), (1, 2, 11), (0, 2, 8, 14), (1, 2, 7, 10, 15)],
     "line3": [(2,), (0, 1), (0, 1, 2), (0, 1, 2, 9), (0, 1, 2, 6, 13)],
+    "bit0": [(0,), (0, 7), (0, 5, 11), (0, 4, 9, 15), (0, 4, 6, 10, 16)],
 }
 
 
@@ -124,6 +125,33 @@ def test_dense5_vector_form_multitile(pattern, dtype, grid_cap):
     _say(f"  families {sorted(fams)}")
     assert fams and fams <= {"dense_direct", "dense_lds"}
     assert np.max(np.abs(got - want)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("grid_cap", CAPS, indirect=True)
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
+def test_bit0_pair_and_lds_forms_multitile(k, grid_cap):
+    """complex64 gates with bit 0 the only target inside a line: the pair
+    kernel and the LDS regroup it replaces, over several tiles per wave."""
+    hs = _hs()
+    n = 18
+    qs = list(PATTERNS["bit0"][k - 1])
+    rng = np.random.default_rng(8300 + k)
+    U = W.random_unitary(1 << k, rng)
+    g = W.Gate("dense", tuple(qs), np.ascontiguousarray(U).view(np.float64).ravel())
+    psi0 = W.random_state(n, int(rng.integers(1 << 30)))
+    want = oracle.apply_circuit(psi0, n, [g])
+    for pair0 in (True, False):
+        _say(f"multitile bit-0 gate n={n} targets={qs} pair kernel={pair0} cap={grid_cap}")
+        hs.sv_debug_set_pair0(pair0)
+        hs.sv_debug_set_dense_mfma(False)
+        try:
+            got, fams = _run(n, [g], psi0, "c64")
+        finally:
+            hs.sv_debug_set_pair0(True)
+            hs.sv_debug_set_dense_mfma(True)
+        _say(f"  families {sorted(fams)}")
+        assert fams == ({"dense_direct"} if pair0 else {"dense_lds"})
+        assert np.max(np.abs(got - want)) <= TOL["c64"]
 
 
 @pytest.mark.parametrize("grid_cap", CAPS, indirect=True)

@@ -125,7 +125,9 @@ def test_dense_register_path_smallest_states(k, extra, in_line, dtype):
 # takes every gate of k <= 4 with no target inside a 128-byte cache line
 # (bits < 3 at complex128, < 4 at complex64); targets inside the line
 # (k <= 4) take the cross-lane butterfly: one or two at complex128, one at
-# complex64 (on amplitude pairs, so not bit 0); 5-qubit gates take the
+# complex64 (on amplitude pairs, so not bit 0); at complex64 bit 0 alone
+# inside the line takes the register path on pairs that hold two entries of
+# one group; 5-qubit gates take the
 # matrix cores when every target inside a line is one of the two lowest;
 # the LDS regroup the rest.
 FAMILY_CASES = [((8, 11), "dense_direct", "dense_direct"),
@@ -133,6 +135,9 @@ FAMILY_CASES = [((8, 11), "dense_direct", "dense_direct"),
                 ((4, 5, 7, 13), "dense_direct", "dense_direct"),
                 ((2, 6), "dense_bfly", "dense_bfly"),
                 ((0, 2, 9), "dense_bfly", "dense_lds"),
+                ((0, 5, 9), "dense_bfly", "dense_direct"),
+                ((0, 6, 8, 12), "dense_bfly", "dense_direct"),
+                ((0,), "dense_bfly", "dense_direct"),
                 ((1, 4, 5, 12), "dense_bfly", "dense_bfly"),
                 ((0, 1, 3, 14), "dense_bfly", "dense_lds"),
                 ((1, 2, 9), "dense_bfly", "dense_lds"),
