@@ -303,14 +303,19 @@ def hhl_batch(hs, W, count=8192):
                                       f"{len(first)} (ns, m) shapes of the mix")}
     flop = sum(m * 2 ** (ns + m + 1 + 3 + ns) for ns, m, _ in specs)
     out["controlled_evolution_flop_per_batch"] = flop
+    shapes, counts = {}, {}
+    for (ns, m, _), c in zip(specs, circs):
+        shapes.setdefault((ns, m), c)
+        counts[(ns, m)] = counts.get((ns, m), 0) + 1
     for dtype in ("c128", "c64"):
-        shapes = {}
-        for (ns, m, _), c in zip(specs, circs):
-            shapes.setdefault((ns, m), c)
+        # every launch choice per shape, tuned on as many copies of a sample
+        # instance as the batch holds of that shape
         t0 = time.perf_counter()
         tuned = {}
         for (ns, m), c in sorted(shapes.items()):
-            tuned[f"{ns},{m}"] = hs.svb_autotune(dtype, c, 16)[0]
+            t, _ = hs.svb_autotune_ex(dtype, c, counts[(ns, m)])
+            tuned[f"{ns},{m}"] = {"k": t["k_max"], "group_max": t["group_max"], "wave_target": t["wave_target"],
+                                  "resident_kib": t["resident_kib"], "ms": round(t["ms"], 4)}
         tune_s = time.perf_counter() - t0
         bt = hs.Batch(dtype, 0)
         for c in circs:
@@ -320,6 +325,18 @@ def hhl_batch(hs, W, count=8192):
         setup_s = time.perf_counter() - t0
         runs = [bt.run() for _ in range(5)]
         ms = float(np.median(runs))
+        # where the device time goes: the same launches one work item after
+        # another, each timed with HIP events (batched-kernel size classes
+        # and groups of same-shape instances run through the sweep kernels)
+        items = bt.run_timed()
+        breakdown = {}
+        for it in items:
+            key = f"{it['kind']} n={it['n']}"
+            e = breakdown.setdefault(key, {"items": 0, "instances": 0, "ms": 0.0, "ops_per_instance": 0})
+            e["items"] += 1
+            e["instances"] += it["count"]
+            e["ms"] = round(e["ms"] + it["ms"], 3)
+            e["ops_per_instance"] = max(e["ops_per_instance"], it["ops"])
         pairs = []
         for i in sorted(first.values()):
             y, p1 = bt.postselected(i)
@@ -328,7 +345,9 @@ def hhl_batch(hs, W, count=8192):
         out[dtype] = {"solves_per_s": round(count / (ms * 1e-3), 1), "device_ms": round(ms, 3),
                       "controlled_evolution_TFLOPs": round(flop / (ms * 1e-3) / 1e12, 2),
                       "first_run_s": round(setup_s, 3), "autotune_s": round(tune_s, 2),
-                      "k_by_shape": tuned, "error_vs_oracle": result_errors(pairs, dtype)}
+                      "tuned_by_shape": tuned, "error_vs_oracle": result_errors(pairs, dtype),
+                      "eager_item_breakdown": {"sum_ms": round(sum(it["ms"] for it in items), 3),
+                                               "by_kind_and_qubits": breakdown}}
         bt.close()
     return out
 
@@ -351,6 +370,7 @@ def _serve_run(hs, sched, pool, pool_per_size, dtype, budget_bytes=0, sample_eve
             rejected += 1
     srv.drain()
     st = srv.stats()
+    prof = srv.profile()
     res = {}
     if sample_every:
         for i in range(0, len(sched), sample_every):
@@ -361,7 +381,10 @@ def _serve_run(hs, sched, pool, pool_per_size, dtype, budget_bytes=0, sample_eve
     srv.stop()
     return {"p50_ms": round(st["p50_s"] * 1e3, 3), "p99_ms": round(st["p99_s"] * 1e3, 3),
             "solves_per_s": round(st["solves_per_s"], 1), "done": st["done"],
-            "failed": st["failed"], "rejected": st["rejected"] + rejected}, res
+            "failed": st["failed"], "rejected": st["rejected"] + rejected,
+            "mean_phase_ms": {k: round(prof[k] * 1e3, 4) for k in
+                              ("queue_s", "prep_s", "upload_s", "ready_wait_s", "gpu_s")},
+            "grouped_launches": int(prof["groups"]), "requests_in_groups": int(prof["grouped"])}, res
 
 
 def hhl_serve(hs, W, seconds, rate=2000.0, pool_per_size=48, constrained_seconds=10.0,

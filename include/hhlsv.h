@@ -457,12 +457,42 @@ sv_status svs_counts(svs *srv, uint64_t *done, uint64_t *failed,
 sv_status svs_profile(svs *srv, double *out, int cap);
 sv_status svs_stop(svs *srv);
 
-/* Autotuner: time a batch of `copies` copies of `sample` at k_max = 1..5,
- * record the fastest width for the sample's (dtype, ns, m) (used by batches
- * created with k_max = 0), and return it.  ms_per_k (5 entries, may be NULL)
- * receives the measured device times. */
+/* Launch choices of batch instances of one shape (dtype, ns, m). */
+typedef struct {
+    int k_max;         /* fusion width, 1..5                                  */
+    int group_max;     /* instances per grouped launch of states in HBM
+                          (at most 256)                                        */
+    int wave_target;   /* waves a grouped wide-gate launch aims to keep busy
+                          when it picks rows per wave                          */
+    int resident_kib;  /* largest state, in KiB, run with the state in LDS
+                          (64 or 128); larger ones run as grouped sweeps       */
+    int tuned;         /* 1: chosen by the autotuner, 0: the defaults         */
+    double ms;         /* device time of the choice on the tuning batch       */
+} svb_tune;
+
+/* Autotuner: time batches of `copies` copies of `sample` (for a batch, the
+ * number of its instances of that shape is representative) and record the
+ * fastest launch choices for the sample's (dtype, ns, m), used by batches
+ * created with k_max = 0.  Coordinate descent from the defaults (k 3, groups
+ * of 256, wave target 1024, LDS residency up to 64 KiB): k_max = 1..5 first
+ * (device times into ms_per_k, 5 entries, may be NULL); then, for a state of
+ * 64..128 KiB, residency in LDS; then, for a state that runs as grouped
+ * sweeps, groups of 64 and wave targets of 256 and 4096.  A trial's time is
+ * the sum of its launches run one work item after another (svb_run_timed),
+ * the cost the shape adds to a large batch.  k_max and
+ * residency change the arithmetic order (the results stay within the parity
+ * bars); the other choices do not.  *out (may be NULL) gets the choice. */
+sv_status svb_autotune_ex(sv_dtype dtype, const sv_circuit *sample, int copies,
+                          svb_tune *out, double *ms_per_k);
+/* As svb_autotune_ex; returns the chosen k_max only. */
 sv_status svb_autotune(sv_dtype dtype, const sv_circuit *sample, int copies,
                        int *best_k, double *ms_per_k);
+/* The recorded choices for a shape (the defaults, tuned = 0, if none). */
+sv_status svb_get_tune(sv_dtype dtype, int ns, int m, svb_tune *out);
+/* Record choices for a shape (e.g. a saved tuning table), as the autotuner
+ * would; t->tuned and t->ms are ignored.  SV_ERR_INVALID outside k_max 1..5,
+ * group_max 1..256, wave_target >= 1, resident_kib 64 or 128. */
+sv_status svb_set_tune(sv_dtype dtype, int ns, int m, const svb_tune *t);
 
 const char *sv_last_error(void);
 

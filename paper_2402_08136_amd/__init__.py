@@ -76,6 +76,14 @@ class SolutionInfo(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class SvbTune(ctypes.Structure):
+    _fields_ = [("k_max", ctypes.c_int), ("group_max", ctypes.c_int), ("wave_target", ctypes.c_int),
+                ("resident_kib", ctypes.c_int), ("tuned", ctypes.c_int), ("ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _vp = ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int)
@@ -136,6 +144,9 @@ _proto("svb_postselected", _vp, ctypes.c_int, _dp, ctypes.c_int, _dp)
 _proto("svb_size", _vp, _ip)
 _proto("svb_destroy", _vp)
 _proto("svb_autotune", ctypes.c_int, _vp, ctypes.c_int, _ip, _dp)
+_proto("svb_autotune_ex", ctypes.c_int, _vp, ctypes.c_int, ctypes.POINTER(SvbTune), _dp)
+_proto("svb_get_tune", ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(SvbTune))
+_proto("svb_set_tune", ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(SvbTune))
 _u64 = ctypes.c_uint64
 _proto("svs_start", _sz, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp))
 _proto("svs_configure", _vp, ctypes.c_int, ctypes.c_double)
@@ -526,6 +537,28 @@ class Batch:
         _check(_lib.svb_postselected(self.handle, index, _dptr(y), count, ctypes.byref(p1)),
                "svb_postselected")
         return y.view(np.complex128), p1.value
+
+
+def svb_autotune_ex(dtype, sample: Circuit, copies: int = 64):
+    """Tune every launch choice for the sample's shape (see svb_autotune_ex in
+    hhlsv.h); returns (choice dict, device ms per k = 1..5)."""
+    t = SvbTune()
+    ms = np.zeros(5)
+    _check(_lib.svb_autotune_ex(DTYPES[dtype], sample.handle, copies, ctypes.byref(t), _dptr(ms)),
+           "svb_autotune_ex")
+    return t.as_dict(), ms
+
+
+def svb_get_tune(dtype, ns: int, m: int) -> dict:
+    t = SvbTune()
+    _check(_lib.svb_get_tune(DTYPES[dtype], ns, m, ctypes.byref(t)), "svb_get_tune")
+    return t.as_dict()
+
+
+def svb_set_tune(dtype, ns: int, m: int, k_max: int = 3, group_max: int = 256, wave_target: int = 1024,
+                 resident_kib: int = 64):
+    t = SvbTune(k_max, group_max, wave_target, resident_kib, 0, 0.0)
+    _check(_lib.svb_set_tune(DTYPES[dtype], ns, m, ctypes.byref(t)), "svb_set_tune")
 
 
 def svb_autotune(dtype, sample: Circuit, copies: int = 64):

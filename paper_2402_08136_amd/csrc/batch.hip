@@ -401,10 +401,11 @@ void launch_k(bool resident, int grid, size_t lds, hipStream_t st, const BInst *
 }  // namespace
 
 sv_status launch_batch_class(const BInst *d_insts, const int *d_order, int count, int n, int kmax,
-                             sv_dtype dtype, hipStream_t st)
+                             bool resident, sv_dtype dtype, hipStream_t st)
 {
-    bool resident = false;
-    const size_t lds = batch_lds_bytes(n, dtype, &resident);
+    bool fits = false;
+    const size_t lds = batch_lds_bytes(n, dtype, &fits, resident ? kResidentStateLimit : 0);
+    if (resident != fits) return fail(SV_ERR_INVALID, "batch: state too large for LDS residency");
     const int per_cu = std::max(1, std::min(8, (int)(kBatchLdsLimit / lds)));
     const int grid = std::max(1, std::min(count, 256 * (resident ? per_cu : 2)));
     sv_status s = dtype == SV_C128 ? set_lds_attr<double>() : set_lds_attr<float>();
@@ -428,9 +429,9 @@ sv_status launch_batch_class(const BInst *d_insts, const int *d_order, int count
 namespace {
 size_t amp_size(sv_dtype d) { return d == SV_C128 ? 16 : 8; }
 
-// Process-wide autotune table: best k_max per (device arch, dtype, ns, m).
+// Process-wide autotune table: launch choices per (dtype, ns, m).
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int>, int> g_tune;
+std::map<std::tuple<int, int, int>, BatchTune> g_tune;
 
 }  // namespace
 
@@ -458,7 +459,11 @@ struct svb {
     struct Meta {
         int n, ns, op_begin, op_count, kmax;
         size_t state_off, out_off, tab_base;
+        BatchTune tune;
     };
+    // the autotuner's trial batches use these choices for every instance
+    bool forced = false;
+    BatchTune forced_tune;
     std::vector<Meta> insts;
     std::vector<HHLParams> params;
     // evolution tables built on the device at upload: (spec owner, job)
@@ -484,6 +489,7 @@ struct svb {
         std::vector<DevOp> ops;     // table offsets relative to a member's table base
         std::vector<int> members;   // instance indices
         size_t part_first = 0;      // first reduction-scratch slot (and first member-table entry)
+        int wave_target = 1024;     // the shape's tuned choice (BatchTune)
     };
     std::vector<Swept> swept;
     double *d_partials = nullptr;
@@ -570,6 +576,7 @@ void swept_group(const svb *b, const svb::Swept &sw, Group *g)
         g->out[i] = b->d_out + in.out_off;
     }
     g->d_members = b->d_members + sw.part_first * MF_COUNT;
+    g->wave_target = sw.wave_target;
 }
 
 sv_status upload(svb *b)
@@ -583,7 +590,7 @@ sv_status upload(svb *b)
     for (size_t i = 0; i < b->insts.size(); ++i) {
         svb::Meta &in = b->insts[i];
         bool resident = false;
-        batch_lds_bytes(in.n, b->dtype, &resident);
+        batch_lds_bytes(in.n, b->dtype, &resident, (size_t)in.tune.resident_kib << 10);
         in.state_off = 0;
         if (resident) {
             by_n[in.n].push_back((int)i);
@@ -595,7 +602,8 @@ sv_status upload(svb *b)
         svb::Swept *grp = nullptr;
         for (size_t gi : swept_by_n[in.n]) {
             svb::Swept &sw = b->swept[gi];
-            if ((int)sw.members.size() < kMaxGroup && same_ops(sw.ops, ops)) {
+            if ((int)sw.members.size() < std::min(kMaxGroup, std::max(1, in.tune.group_max)) &&
+                same_ops(sw.ops, ops)) {
                 grp = &sw;
                 break;
             }
@@ -606,6 +614,7 @@ sv_status upload(svb *b)
             grp = &b->swept.back();
             grp->n = in.n;
             grp->ns = in.ns;
+            grp->wave_target = in.tune.wave_target;
             grp->ops = std::move(ops);
         }
         grp->members.push_back((int)i);
@@ -727,7 +736,7 @@ sv_status capture(svb *b)
     for (int i = 0; i < nside && e == hipSuccess; ++i) e = hipStreamWaitEvent(b->side[i], b->ev[0], 0);
     for (size_t c = 0; c < b->classes.size() && e == hipSuccess; ++c) {
         const BatchClass &cl = b->classes[c];
-        if (launch_batch_class(b->d_insts, b->d_order + cl.first, cl.count, cl.n, cl.kmax, b->dtype,
+        if (launch_batch_class(b->d_insts, b->d_order + cl.first, cl.count, cl.n, cl.kmax, true, b->dtype,
                                b->side[c % nside]) != SV_OK)
             e = hipErrorLaunchFailure;
     }
@@ -793,18 +802,81 @@ extern "C" sv_status svb_create(sv_dtype dtype, int k_max, void *hip_stream, svb
     return SV_OK;
 }
 
-int hhlsv::batch_tuned_k(sv_dtype dtype, int ns, int m)
+bool hhlsv::batch_tuned(sv_dtype dtype, int ns, int m, BatchTune *out)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find({(int)dtype, ns, m});
-    return it == g_tune.end() ? 0 : it->second;
+    *out = it == g_tune.end() ? BatchTune() : it->second;
+    return it != g_tune.end();
 }
 
-void hhlsv::batch_set_tuned_k(sv_dtype dtype, int ns, int m, int k)
+int hhlsv::batch_tuned_k(sv_dtype dtype, int ns, int m)
+{
+    BatchTune t;
+    return batch_tuned(dtype, ns, m, &t) ? t.k : 0;
+}
+
+void hhlsv::batch_set_tuned(sv_dtype dtype, int ns, int m, const BatchTune &t)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[{(int)dtype, ns, m}] = k;
+    g_tune[{(int)dtype, ns, m}] = t;
 }
+
+namespace {
+
+// A fused HHL circuit lowered for the batch once, added to a batch as many
+// times as needed (the autotuner adds copies of one sample).
+struct LoweredInst {
+    std::vector<BOp> ops;
+    std::vector<unsigned char> tab;
+    std::vector<EvoJob> evo;
+    size_t dev_bytes = 0;
+    std::shared_ptr<const Spectral> spec;
+};
+
+sv_status lower_inst(svb *b, const sv_circuit *hhl, int k, LoweredInst *L)
+{
+    sv_circuit *f = nullptr;
+    const sv_status st = fuse(hhl, k, &f);
+    if (st != SV_OK) return st;
+    lower_for_batch(f->c, b->dtype, L->ops, L->tab, L->evo, &L->dev_bytes);
+    L->spec = f->c.hhl.spec;
+    circuit_destroy(f);
+    return SV_OK;
+}
+
+void add_lowered(svb *b, const LoweredInst &L, const HHLParams &h, int n, const BatchTune &tune, int *index_out)
+{
+    svb::Meta in = {};
+    in.n = n;
+    in.ns = h.ns;
+    in.tune = tune;
+    in.op_begin = (int)b->ops.size();
+    const size_t base = (b->tables.size() + 255) & ~size_t(255);
+    in.tab_base = base;
+    b->tables.resize(base + L.dev_bytes);
+    std::memcpy(b->tables.data() + base, L.tab.data(), L.tab.size());
+    for (BOp op : L.ops) {
+        op.off += base;
+        if (op.type == OP_DENSE) in.kmax = std::max(in.kmax, op.k);
+        b->ops.push_back(op);
+    }
+    for (EvoJob jb : L.evo) {
+        jb.out_off += base;
+        b->evo_jobs.emplace_back(L.spec, jb);
+    }
+    in.op_count = (int)b->ops.size() - in.op_begin;
+    in.out_off = b->out_doubles;
+    b->out_doubles += 2 + 2 * ((size_t)1 << h.ns);
+    b->insts.push_back(in);
+    b->params.push_back(h);
+    // the device copy and the captured graph no longer match
+    release_device(b);
+    b->have_result = false;
+    if (index_out) *index_out = (int)b->insts.size() - 1;
+}
+
+}  // namespace
 
 extern "C" sv_status svb_add(svb *b, const sv_circuit *hhl, int *index_out)
 {
@@ -812,47 +884,17 @@ extern "C" sv_status svb_add(svb *b, const sv_circuit *hhl, int *index_out)
     const HHLParams &h = hhl->c.hhl;
     if (!h.is_hhl) return fail(SV_ERR_INVALID, "svb_add: not an HHL circuit");
     if (hhl->c.n > kMaxBatchQubits) return fail(SV_ERR_INVALID, "svb_add: batch instances are limited to 24 qubits");
-    int k = b->k_max;
-    if (k == 0) k = batch_tuned_k(b->dtype, h.ns, h.m);
-    if (k == 0) k = kDefaultBatchK;
-    sv_circuit *f = nullptr;
-    sv_status st = fuse(hhl, k, &f);
+    BatchTune tune;
+    if (b->forced)
+        tune = b->forced_tune;
+    else if (b->k_max == 0)
+        batch_tuned(b->dtype, h.ns, h.m, &tune);
+    else
+        tune.k = b->k_max;
+    LoweredInst L;
+    const sv_status st = lower_inst(b, hhl, tune.k, &L);
     if (st != SV_OK) return st;
-    svb::Meta in;
-    std::memset(&in, 0, sizeof(in));
-    in.n = hhl->c.n;
-    in.ns = h.ns;
-    in.op_begin = (int)b->ops.size();
-    {
-        std::vector<BOp> ops;
-        std::vector<unsigned char> tab;
-        std::vector<EvoJob> evo;
-        size_t dev_bytes = 0;
-        lower_for_batch(f->c, b->dtype, ops, tab, evo, &dev_bytes);
-        const size_t base = (b->tables.size() + 255) & ~size_t(255);
-        in.tab_base = base;
-        b->tables.resize(base + dev_bytes);
-        std::memcpy(b->tables.data() + base, tab.data(), tab.size());
-        for (BOp &op : ops) {
-            op.off += base;
-            if (op.type == OP_DENSE) in.kmax = std::max(in.kmax, op.k);
-            b->ops.push_back(op);
-        }
-        for (EvoJob &jb : evo) {
-            jb.out_off += base;
-            b->evo_jobs.emplace_back(f->c.hhl.spec, jb);
-        }
-    }
-    in.op_count = (int)b->ops.size() - in.op_begin;
-    in.out_off = b->out_doubles;
-    b->out_doubles += 2 + 2 * ((size_t)1 << h.ns);
-    circuit_destroy(f);
-    b->insts.push_back(in);
-    b->params.push_back(h);
-    // the device copy and the captured graph no longer match
-    release_device(b);
-    b->have_result = false;
-    if (index_out) *index_out = (int)b->insts.size() - 1;
+    add_lowered(b, L, h, hhl->c.n, tune, index_out);
     return SV_OK;
 }
 
@@ -916,8 +958,8 @@ extern "C" sv_status svb_run_timed(svb *b, int cap, int *items, int *kind, int *
         ops[it] = 0;
         for (const svb::Meta &m : b->insts)
             if (m.n == cl.n) ops[it] = std::max(ops[it], m.op_count);
-        if (launch_batch_class(b->d_insts, b->d_order + cl.first, cl.count, cl.n, cl.kmax, b->dtype, b->stream) !=
-            SV_OK)
+        if (launch_batch_class(b->d_insts, b->d_order + cl.first, cl.count, cl.n, cl.kmax, true, b->dtype,
+                               b->stream) != SV_OK)
             e = hipErrorLaunchFailure;
         if (e == hipSuccess) e = hipEventRecord(ev[it + 1], b->stream);
     }
@@ -1039,31 +1081,147 @@ extern "C" sv_status svb_destroy(svb *b)
     return SV_OK;
 }
 
+namespace {
+
+// Device time of a batch of `copies` copies of `sample` with every instance
+// launched under `t`: the median of three runs of its launches one work item
+// after another (svb_run_timed's sum), which is what the shape costs inside
+// a large batch, whose graph runs its items in turn.
+sv_status tune_trial(sv_dtype dtype, const sv_circuit *sample, int copies, const BatchTune &t, double *ms)
+{
+    svb *b = nullptr;
+    sv_status st = svb_create(dtype, t.k, nullptr, &b);
+    if (st != SV_OK) return st;
+    b->forced = true;
+    b->forced_tune = t;
+    LoweredInst L;
+    st = lower_inst(b, sample, t.k, &L);
+    for (int i = 0; i < copies && st == SV_OK; ++i) add_lowered(b, L, sample->c.hhl, sample->c.n, t, nullptr);
+    const int cap = copies + 64;
+    std::vector<int> kind(cap), nq(cap), cnt(cap), nops(cap);
+    std::vector<double> item_ms(cap);
+    int items = 0;
+    double r[3] = {0, 0, 0};
+    if (st == SV_OK) st = svb_run(b);   // upload + capture + first run
+    for (int i = 0; i < 3 && st == SV_OK; ++i) {
+        st = svb_run_timed(b, cap, &items, kind.data(), nq.data(), cnt.data(), nops.data(), item_ms.data());
+        if (st == SV_OK) st = svb_last_run_ms(b, &r[i]);
+    }
+    svb_destroy(b);
+    if (st != SV_OK) return st;
+    std::sort(r, r + 3);
+    *ms = r[1];
+    return SV_OK;
+}
+
+void to_public(const BatchTune &t, double ms, int tuned, svb_tune *out)
+{
+    out->k_max = t.k;
+    out->group_max = t.group_max;
+    out->wave_target = t.wave_target;
+    out->resident_kib = t.resident_kib;
+    out->tuned = tuned;
+    out->ms = ms;
+}
+
+}  // namespace
+
+extern "C" sv_status svb_autotune_ex(sv_dtype dtype, const sv_circuit *sample, int copies, svb_tune *out,
+                                     double *ms_per_k)
+{
+    if (!sample || copies < 1) return fail(SV_ERR_INVALID, "svb_autotune: need a sample circuit and copies >= 1");
+    if (dtype != SV_C128 && dtype != SV_C64) return fail(SV_ERR_INVALID, "svb_autotune: bad dtype");
+    const HHLParams &h = sample->c.hhl;
+    if (!h.is_hhl) return fail(SV_ERR_INVALID, "svb_autotune: not an HHL circuit");
+    if (sample->c.n > kMaxBatchQubits) return fail(SV_ERR_INVALID, "svb_autotune: batch instances are limited to 24 qubits");
+    // coordinate descent from the defaults: the fusion width, then (for
+    // states that would otherwise run through the grouped sweeps) LDS
+    // residency up to 128 KiB, the group size and the wide gates' wave target
+    BatchTune best;
+    double best_ms = 0.0;
+    for (int k = 1; k <= 5; ++k) {
+        BatchTune t;
+        t.k = k;
+        double ms = 0.0;
+        const sv_status st = tune_trial(dtype, sample, copies, t, &ms);
+        if (st != SV_OK) return st;
+        if (ms_per_k) ms_per_k[k - 1] = ms;
+        if (k == 1 || ms < best_ms) {
+            best_ms = ms;
+            best = t;
+        }
+    }
+    auto consider = [&](const BatchTune &t) -> sv_status {
+        double ms = 0.0;
+        const sv_status st = tune_trial(dtype, sample, copies, t, &ms);
+        if (st == SV_OK && ms < best_ms) {
+            best_ms = ms;
+            best = t;
+        }
+        return st;
+    };
+    const size_t sb = amp_size(dtype) << sample->c.n;
+    sv_status st = SV_OK;
+    if (sb > kResidentStateMax && sb <= kResidentStateLimit) {
+        BatchTune t = best;
+        t.resident_kib = (int)(kResidentStateLimit >> 10);
+        st = consider(t);
+    }
+    bool resident = false;
+    batch_lds_bytes(sample->c.n, dtype, &resident, (size_t)best.resident_kib << 10);
+    if (!resident) {
+        const BatchTune base = best;
+        for (int gm : {64})
+            if (st == SV_OK && gm < copies) {
+                BatchTune t = base;
+                t.group_max = gm;
+                st = consider(t);
+            }
+        const BatchTune base2 = best;
+        for (int wt : {256, 4096})
+            if (st == SV_OK) {
+                BatchTune t = base2;
+                t.wave_target = wt;
+                st = consider(t);
+            }
+    }
+    if (st != SV_OK) return st;
+    batch_set_tuned(dtype, h.ns, h.m, best);
+    if (out) to_public(best, best_ms, 1, out);
+    return SV_OK;
+}
+
 extern "C" sv_status svb_autotune(sv_dtype dtype, const sv_circuit *sample, int copies, int *best_k,
                                   double *ms_per_k)
 {
-    if (!sample || copies < 1) return fail(SV_ERR_INVALID, "svb_autotune: need a sample circuit and copies >= 1");
-    const HHLParams &h = sample->c.hhl;
-    if (!h.is_hhl) return fail(SV_ERR_INVALID, "svb_autotune: not an HHL circuit");
-    double best = 0.0;
-    int bk = 0;
-    for (int k = 1; k <= 5; ++k) {
-        svb *b = nullptr;
-        sv_status st = svb_create(dtype, k, nullptr, &b);
-        for (int i = 0; i < copies && st == SV_OK; ++i) st = svb_add(b, sample, nullptr);
-        if (st == SV_OK) st = svb_run(b);   // upload + capture + first run
-        double ms = 0.0;
-        if (st == SV_OK) st = svb_run(b);
-        if (st == SV_OK) st = svb_last_run_ms(b, &ms);
-        svb_destroy(b);
-        if (st != SV_OK) return st;
-        if (ms_per_k) ms_per_k[k - 1] = ms;
-        if (bk == 0 || ms < best) {
-            best = ms;
-            bk = k;
-        }
-    }
-    batch_set_tuned_k(dtype, h.ns, h.m, bk);
-    if (best_k) *best_k = bk;
+    svb_tune t;
+    const sv_status st = svb_autotune_ex(dtype, sample, copies, &t, ms_per_k);
+    if (st == SV_OK && best_k) *best_k = t.k_max;
+    return st;
+}
+
+extern "C" sv_status svb_set_tune(sv_dtype dtype, int ns, int m, const svb_tune *t)
+{
+    if (!t) return fail(SV_ERR_INVALID, "svb_set_tune: NULL argument");
+    if (dtype != SV_C128 && dtype != SV_C64) return fail(SV_ERR_INVALID, "svb_set_tune: bad dtype");
+    if (t->k_max < 1 || t->k_max > 5 || t->group_max < 1 || t->group_max > kMaxGroup || t->wave_target < 1 ||
+        (t->resident_kib != 64 && t->resident_kib != 128))
+        return fail(SV_ERR_INVALID, "svb_set_tune: k_max 1..5, group_max 1..256, wave_target >= 1, "
+                                    "resident_kib 64 or 128");
+    BatchTune b;
+    b.k = t->k_max;
+    b.group_max = t->group_max;
+    b.wave_target = t->wave_target;
+    b.resident_kib = t->resident_kib;
+    batch_set_tuned(dtype, ns, m, b);
+    return SV_OK;
+}
+
+extern "C" sv_status svb_get_tune(sv_dtype dtype, int ns, int m, svb_tune *out)
+{
+    if (!out) return fail(SV_ERR_INVALID, "svb_get_tune: NULL argument");
+    BatchTune t;
+    const bool tuned = batch_tuned(dtype, ns, m, &t);
+    to_public(t, 0.0, tuned ? 1 : 0, out);
     return SV_OK;
 }

@@ -29,24 +29,27 @@ struct BInst {
 };
 
 // LDS budget of one batch workgroup and whether an n-qubit state runs in it.
-// States above kResidentStateMax would fit (up to 128 KiB) but leave one
-// workgroup per CU; they run faster through the grouped sweep kernels.
+// By default states above kResidentStateMax run through the grouped sweep
+// kernels: a state of up to 128 KiB would fit, but leave one workgroup per
+// CU.  The autotuner may raise the cut per shape (resident_max).
 constexpr int kBatchThreads = 256;
 constexpr int kBatchLdsLimit = 160 * 1024;
 constexpr size_t kResidentStateMax = 64 * 1024;
-inline size_t batch_lds_bytes(int n, sv_dtype d, bool *resident)
+constexpr size_t kResidentStateLimit = 128 * 1024;
+inline size_t batch_lds_bytes(int n, sv_dtype d, bool *resident, size_t resident_max = kResidentStateMax)
 {
     const size_t red = kBatchThreads * 8;
     const size_t sb = (d == SV_C128 ? size_t(16) : size_t(8)) << n;
-    *resident = sb <= kResidentStateMax && sb + red <= (size_t)kBatchLdsLimit;
+    *resident = sb <= resident_max && sb + red <= (size_t)kBatchLdsLimit;
     return red + (*resident ? sb : 0);
 }
 
 // Launch the batch kernel over count instances (insts[order[i]]) that all
-// have n qubits and whose dense ops are at most kmax qubits wide; grid
-// chosen from the LDS footprint, a leaner kernel when kmax <= 3.
+// have n qubits and whose dense ops are at most kmax qubits wide, with the
+// state in LDS (resident) or in its HBM buffer; grid chosen from the LDS
+// footprint, a leaner kernel when kmax <= 3.
 sv_status launch_batch_class(const BInst *d_insts, const int *d_order, int count, int n, int kmax,
-                             sv_dtype dtype, hipStream_t st);
+                             bool resident, sv_dtype dtype, hipStream_t st);
 
 // Lower a (fused) HHL circuit into batch ops and a table buffer of
 // *device_bytes.  tables holds the host-built tables (its first
@@ -60,9 +63,22 @@ void lower_for_batch(const Circuit &f, sv_dtype dtype, std::vector<BOp> &ops, st
 // and the autotuner has no entry for the instance's shape.
 constexpr int kDefaultBatchK = 3;
 
-// Autotuned k_max per (dtype, ns, m); 0 when unknown.
+// Launch choices of a batch instance's shape (dtype, ns, m), as the
+// autotuner picks them (defaults otherwise).  None changes an instance's
+// arithmetic except k (the fusion) and resident_kib (LDS-resident kernel or
+// grouped sweeps); both are parity-tested either way.
+struct BatchTune {
+    int k = kDefaultBatchK;       // fusion width
+    int group_max = 256;          // instances per grouped launch (states in HBM)
+    int wave_target = 1024;       // waves a grouped wide-gate launch aims to keep busy
+    int resident_kib = 64;        // largest state (KiB) run with the state in LDS
+};
+
+// The tuned choices for a shape; false (and defaults) when the autotuner has
+// no entry.  batch_tuned_k: the tuned k, 0 when unknown.
+bool batch_tuned(sv_dtype dtype, int ns, int m, BatchTune *out);
+void batch_set_tuned(sv_dtype dtype, int ns, int m, const BatchTune &t);
 int batch_tuned_k(sv_dtype dtype, int ns, int m);
-void batch_set_tuned_k(sv_dtype dtype, int ns, int m, int k);
 
 // Sec. III-A step 4 from [P(ancilla = 1), pad, y_0.re, y_0.im, ...]:
 // x_hat = Re(y) / ||Re(y)|| over the first dim entries, scale = ||b|| ||Re y|| / C.

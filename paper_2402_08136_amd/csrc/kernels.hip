@@ -1624,13 +1624,13 @@ sv_status launch_op_t(const DevOp &op, const Group &g, int n, hipStream_t st, in
             // the matrix cores, 0.48 ms without).  The choice depends on
             // each member's own shape only (see Group::batch).
             if (D >= 8 && D <= 64 && (g.batch || ngroups >= 16384)) {
-                // 16-row tiles per wave as many as keep >= ~1024 waves busy
-                // over the whole group, up to the most the accumulators allow
+                // 16-row tiles per wave as many as keep >= ~wave_target waves
+                // busy over the whole group, up to the most the accumulators allow
                 // (a row's arithmetic does not depend on it)
                 auto waves_of = [&](int rt) { return (ngroups + 16 * (uint64_t)rt - 1) / (16 * (uint64_t)rt); };
                 const int rt_max = D == 8 ? 8 : D == 16 ? 8 : D == 32 ? 4 : 2;
                 int rt = rt_max;
-                while (rt > 1 && cnt * waves_of(rt) < 1024) rt >>= 1;
+                while (rt > 1 && cnt * waves_of(rt) < (uint64_t)g.wave_target) rt >>= 1;
                 const unsigned grid = grid_for(waves_of(rt), 4, 8192);
 #define MFMA_GO(DD, RTV) launch2(&k_wide_mfma<R, DD, RTV>, &k_wide_mfma_g<R, DD, RTV>, grid, 256, 0, st, pp, cnt, a)
 #define MFMA_RT(DD)                            \
@@ -1674,12 +1674,12 @@ sv_status launch_op_t(const DevOp &op, const Group &g, int n, hipStream_t st, in
                 break;
             }
             const int rps = D < 64 ? 64 / D : 1;
-            // rows per wave: as many as keep >= ~1024 waves busy over the
-            // whole group (reuse of each loaded U column across rows vs
+            // rows per wave: as many as keep >= ~wave_target waves busy over
+            // the whole group (reuse of each loaded U column across rows vs
             // parallelism); a row's arithmetic does not depend on it
             auto waves_for = [&](int rw) { return (ngroups + (uint64_t)rw * rps - 1) / ((uint64_t)rw * rps); };
             int rw = 8;
-            while (rw > 1 && cnt * waves_for(rw) < 1024) rw >>= 1;
+            while (rw > 1 && cnt * waves_for(rw) < (uint64_t)g.wave_target) rw >>= 1;
             const unsigned grid = grid_for(waves_for(rw), 4, 8192);
 #define WIDE_GO(CT, RWV) launch2(&k_wide_gemm<R, CT, RWV>, &k_wide_gemm_g<R, CT, RWV>, grid, 256, 0, st, pp, cnt, a)
 #define WIDE_RW(CT)                          \

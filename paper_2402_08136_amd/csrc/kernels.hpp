@@ -56,6 +56,9 @@ struct Group {
     // follows each member's own row count.  The choice never depends on the
     // group size, so a member's bits are the same alone or grouped.
     bool batch = false;
+    // waves a wide-gate launch aims to keep busy over the whole group when
+    // it chooses rows per wave (no output's arithmetic depends on it)
+    int wave_target = 1024;
 };
 
 // The MF_COUNT device addresses of each member of g, in table order.

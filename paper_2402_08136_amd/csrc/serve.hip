@@ -789,8 +789,8 @@ sv_status launch_slot(svs *s, Slot &sl)
         const int n = sl.reqs[idx[first]]->n;
         int last = first, kmax = 0;
         while (last < cnt && sl.reqs[idx[last]]->n == n) kmax = std::max(kmax, sl.reqs[idx[last++]]->kmax);
-        sv_status st = launch_batch_class(sl.d_insts, sl.d_order + first, last - first, n, kmax, s->dtype,
-                                          sl.stream);
+        sv_status st = launch_batch_class(sl.d_insts, sl.d_order + first, last - first, n, kmax,
+                                          sl.reqs[idx[first]]->kind == kBatchLds, s->dtype, sl.stream);
         if (st != SV_OK) return st;
         first = last;
     }

@@ -144,6 +144,54 @@ def test_autotune_picks_a_width():
     check_instance(y, p1, x, _oracle_refs([(A, b, 5)])[0], "c128", "autotuned")
 
 
+def test_autotune_ex_records_every_choice():
+    hs = _hs()
+    A, b = W.dc_powerflow(32, 6)                 # 5 system + 8 clock qubits: n = 14
+    c = hs.circuit_build_hhl(A, b, 8, device_evolutions=True)
+    t, ms = hs.svb_autotune_ex("c64", c, copies=24)
+    _say(f"autotune_ex ns=5 m=8 c64: {t}, ms per k={np.round(ms, 4).tolist()}")
+    assert 1 <= t["k_max"] <= 5 and t["tuned"] == 1 and t["ms"] > 0 and np.all(ms > 0)
+    assert t["resident_kib"] in (64, 128) and 1 <= t["group_max"] <= 256 and t["wave_target"] >= 1
+    assert hs.svb_get_tune("c64", 5, 8) == dict(t, ms=0.0)
+
+
+# (ns, m, dtype): a state of 128 KiB (c128 n = 13) or 128 KiB (c64 n = 14)
+@pytest.mark.parametrize("ns,m,dtype", [(4, 8, "c128"), (5, 8, "c64")])
+@pytest.mark.parametrize("choice", ["resident128", "groups16_wave256", "wave4096"])
+def test_tuned_choices_match_oracle(ns, m, dtype, choice):
+    """Each launch choice the autotuner can make, set directly, against the
+    oracle: LDS residency up to 128 KiB, small groups, both wave targets."""
+    hs = _hs()
+    kw = {"resident128": dict(resident_kib=128), "groups16_wave256": dict(group_max=16, wave_target=256),
+          "wave4096": dict(wave_target=4096)}[choice]
+    systems = [W.dc_powerflow(1 << ns, 700 + i) + (m,) for i in range(20)]
+    refs = _oracle_refs(systems[:3])
+    try:
+        hs.svb_set_tune(dtype, ns, m, k_max=4, **kw)
+        bt = hs.Batch(dtype, 0)
+        for A, b, mm in systems:
+            bt.add(hs.circuit_build_hhl(A, b, mm, device_evolutions=True))
+        items = bt.run_timed()
+        kinds = {it["kind"] for it in items}
+        _say(f"tuned choice {choice} ns={ns} m={m} {dtype}: items {items}")
+        assert kinds == ({"batched"} if choice == "resident128" else {"swept"})
+        if choice == "groups16_wave256":
+            assert [it["count"] for it in items] == [16, 4]
+        for i, ref in enumerate(refs):
+            x_hat, _ = bt.solution(i)
+            y, p1 = bt.postselected(i)
+            check_instance(y, p1, x_hat, ref, dtype, (choice, i))
+        bt.run()
+        for i, ref in enumerate(refs):
+            x_hat, _ = bt.solution(i)
+            y, p1 = bt.postselected(i)
+            check_instance(y, p1, x_hat, ref, dtype, (choice, "graph", i))
+    finally:
+        hs.svb_set_tune(dtype, ns, m)
+    with pytest.raises(hs.HHLSVError, match="INVALID"):
+        hs.svb_set_tune(dtype, ns, m, resident_kib=96)
+
+
 def test_batch_errors():
     hs = _hs()
     with pytest.raises(hs.HHLSVError, match="INVALID"):
