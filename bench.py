@@ -79,8 +79,8 @@ def kernel_label(family, qubits, real="double", n=33):
         return f"k_dense_pair<{k}>"     # complex64: two amplitudes per lane access
     if family == "dense_bfly" and real == "float":   # amplitude pairs, targets in bits 1..3
         return f"k_dense_bfly_pair<{k}, {sum(q < 4 for q in qubits)}>"
-    if family == "dense_mfma":          # 5-qubit gates on the matrix cores
-        return f"k_dense_mfma5<{real}>"
+    if family == "dense_mfma":          # matrix cores: 5 qubits, or 4 with two targets inside a line
+        return f"k_dense_mfma<{real}, {k}>"
     if family == "dense_bfly":          # targets inside a 128-byte line: bits 0..2
         return f"k_dense_bfly<{k}, {sum(q < 3 for q in qubits)}>"
     name = {"dense_direct": "k_dense_direct", "dense_lds": "k_dense_lds",

@@ -269,9 +269,10 @@ typedef enum {
     SV_KERNEL_DENSE_BFLY = 6,   /* dense k <= 4 at c128 with one or two targets
                                    inside a line: cross-lane butterfly, groups
                                    held in registers                     */
-    SV_KERNEL_DENSE_MFMA = 7    /* dense k = 5 on >= 9 qubits, every target
-                                   inside a line among the two lowest:
-                                   16x16x4 matrix-core products          */
+    SV_KERNEL_DENSE_MFMA = 7    /* dense k = 5 on >= 9 qubits, or k = 4 with
+                                   two targets inside a line on >= 8; every
+                                   target inside a line among the two
+                                   lowest: 16x16x4 matrix-core products  */
 } sv_kernel_family;
 
 /* As sv_apply, and record the device time of each gate's launch with HIP
@@ -514,9 +515,10 @@ sv_status sv_debug_set_grid_cap(int max_workgroups);
  * dtype or fewer qubits. */
 sv_status sv_stream_probe(sv_state *s, int reps, double *launch_ms);
 
-/* Select the form of 5-qubit dense gates for launches made after the call:
- * enable != 0 (the default) the matrix-core kernel where it applies, 0 the
- * vector kernels everywhere.  Both compute the same gate (Sec. II-C fused
+/* Select the form of 5-qubit dense gates, and of 4-qubit gates with two
+ * targets inside a cache line, for launches made after the call: enable != 0
+ * (the default) the matrix-core kernel where it applies, 0 the vector
+ * kernels everywhere.  Both compute the same gate (Sec. II-C fused
  * gates); the switch exists to compare and test them.  Process-wide; not for
  * use while other threads launch; graphs captured earlier keep their
  * kernels. */

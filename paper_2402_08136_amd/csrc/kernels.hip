@@ -771,95 +771,101 @@ template <> struct Mfma<float> {
 };
 
 // ---------------------------------------------------------------------------
-// Dense 5-qubit gate on the matrix cores.  At k = 5 the dense product costs
-// 8 * 32 flops per amplitude, near the FP64 ridge of the chip, so the
-// vector form spends the VALU on arithmetic that the matrix cores can take.
+// Dense 5- and 4-qubit gates on the matrix cores.  At k = 5 the dense
+// product costs 8 * 32 flops per amplitude, near the FP64 ridge of the chip,
+// so the vector form spends the VALU on arithmetic that the matrix cores can
+// take; at k = 4 the same form serves gates with two targets inside a cache
+// line, where the vector forms need a two-level lane exchange.
 //
 // A wave owns 16 groups (lane bits 0..3: the four lowest non-target index
-// bits) of 32 amplitudes.  With the targets sorted q_0 < ... < q_4 and the
-// matrix index c = sum_l bit(q_l) 2^l, lane bits 4..5 hold c bits 0..1
-// (q_0, q_1) and each lane's 8 registers hold c bits 2..4 (q_2..q_4): lane
+// bits) of 2^K amplitudes.  With the targets sorted q_0 < ... < q_{K-1} and
+// the matrix index c = sum_l bit(q_l) 2^l, lane bits 4..5 hold c bits 0..1
+// (q_0, q_1) and each lane's 2^K / 4 registers hold the higher c bits: lane
 // (j, kq) holds x_j[4 s + kq] in register s.  That is exactly the B operand
 // of a 16x16x4 MFMA over the 4-wide slice c = 4s .. 4s+3 (B[k][j] in lane
-// j + 16 k), so Y^T = M X^T runs as 2 row tiles x 8 k-steps, each split
-// into four real products (Re M Re x, -Im M Im x, Re M Im x, Im M Re x).
-// The FP64 accumulator puts row 4 v + kq of a tile in item v of lane j + 16
-// kq: output row 16 t + 4 v + kq, the same matrix index the lane loaded
-// into register 4 t + v, so every lane stores to the addresses it read.
-// The FP32 accumulator puts row 4 kq + v there instead; loading the A rows
-// with the two 2-bit halves of the tile row swapped makes its item v of
-// lane j + 16 kq again output row 16 t + 4 v + kq.  Each load and store is
-// one amplitude per lane; with q_2 above the 128-byte line (every target
-// inside a line is q_0 or q_1) each instruction touches whole lines.
-// The matrix, as A fragments (Re and Im of 2 x 8 entries per lane), stays
-// in registers for the wave's whole loop.
+// j + 16 k), so Y^T = M X^T runs as 2^K / 16 row tiles x 2^K / 4 k-steps,
+// each split into four real products (Re M Re x, -Im M Im x, Re M Im x,
+// Im M Re x).  The FP64 accumulator puts row 4 v + kq of a tile in item v
+// of lane j + 16 kq: output row 16 t + 4 v + kq, the same matrix index the
+// lane loaded into register 4 t + v, so every lane stores to the addresses
+// it read.  The FP32 accumulator puts row 4 kq + v there instead; loading
+// the A rows with the two 2-bit halves of the tile row swapped makes its
+// item v of lane j + 16 kq again output row 16 t + 4 v + kq.  Each load and
+// store is one amplitude per lane; with q_2 above the 128-byte line (every
+// target inside a line is q_0 or q_1) each instruction touches whole lines.
+// The matrix, as A fragments (Re and Im of its 2^K x 2^K / 64 entries per
+// lane), stays in registers for the wave's whole loop.
 // ---------------------------------------------------------------------------
-template <typename R>
-__device__ __forceinline__ void k_dense_mfma5_body(typename V2<R>::type *__restrict__ psi,
-                                                   const typename V2<R>::type *__restrict__ mat, const TileArgs &a)
+template <typename R, int K>
+__device__ __forceinline__ void k_dense_mfma_body(typename V2<R>::type *__restrict__ psi,
+                                                  const typename V2<R>::type *__restrict__ mat, const TileArgs &a)
 {
     typedef typename V2<R>::type C;
     typedef typename Mfma<R>::V4 V4;
+    static_assert(K == 4 || K == 5, "matrix-core dense form: 4 or 5 targets");
+    constexpr int NR = 1 << K;        // matrix dimension
+    constexpr int NT = NR / 16;       // 16-row output tiles
+    constexpr int NS = NR / 4;        // 4-wide k-steps = registers per lane
     const int l = threadIdx.x & 63;
     const int i = l & 15, kq = l >> 4;
     const int ri = sizeof(R) == 8 ? i : (((i & 3) << 2) | (i >> 2));
-    R are[2][8], aim[2][8];
+    R are[NT][NS], aim[NT][NS];
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            const C m = mat[(16 * t + ri) * 32 + 4 * s + kq];
+        for (int s = 0; s < NS; ++s) {
+            const C m = mat[(16 * t + ri) * NR + 4 * s + kq];
             are[t][s] = m.x;
             aim[t][s] = m.y;
         }
     uint64_t loff = (uint64_t)i;
 #pragma unroll
-    for (int j = 0; j < 5; ++j) loff = insert_zero(loff, a.rpos[j]);
+    for (int j = 0; j < K; ++j) loff = insert_zero(loff, a.rpos[j]);
     loff |= (uint64_t(kq & 1) << a.rpos[0]) | (uint64_t(kq >> 1) << a.rpos[1]);
     const WaveRange wr = wave_range(a.ntiles, 4);
     for (uint64_t w = wr.w; w < wr.end; w += wr.step) {
         uint64_t b = w << 4;
 #pragma unroll
-        for (int j = 0; j < 5; ++j) b = insert_zero(b, a.rpos[j]);
+        for (int j = 0; j < K; ++j) b = insert_zero(b, a.rpos[j]);
         C *p = psi + b + loff;
-        C x[8];
+        C x[NS];
 #pragma unroll
-        for (int s = 0; s < 8; ++s) x[s] = ld_nt(p + a.reg_off[s]);
-        V4 yr[2], yi[2];
+        for (int s = 0; s < NS; ++s) x[s] = ld_nt(p + a.reg_off[s]);
+        V4 yr[NT], yi[NT];
 #pragma unroll
-        for (int t = 0; t < 2; ++t) yr[t] = yi[t] = V4{0, 0, 0, 0};
+        for (int t = 0; t < NT; ++t) yr[t] = yi[t] = V4{0, 0, 0, 0};
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
+        for (int s = 0; s < NS; ++s) {
             const R nxi = -x[s].y;
 #pragma unroll
-            for (int t = 0; t < 2; ++t) yr[t] = Mfma<R>::mac(are[t][s], x[s].x, yr[t]);
+            for (int t = 0; t < NT; ++t) yr[t] = Mfma<R>::mac(are[t][s], x[s].x, yr[t]);
 #pragma unroll
-            for (int t = 0; t < 2; ++t) yi[t] = Mfma<R>::mac(are[t][s], x[s].y, yi[t]);
+            for (int t = 0; t < NT; ++t) yi[t] = Mfma<R>::mac(are[t][s], x[s].y, yi[t]);
 #pragma unroll
-            for (int t = 0; t < 2; ++t) yr[t] = Mfma<R>::mac(aim[t][s], nxi, yr[t]);
+            for (int t = 0; t < NT; ++t) yr[t] = Mfma<R>::mac(aim[t][s], nxi, yr[t]);
 #pragma unroll
-            for (int t = 0; t < 2; ++t) yi[t] = Mfma<R>::mac(aim[t][s], x[s].x, yi[t]);
+            for (int t = 0; t < NT; ++t) yi[t] = Mfma<R>::mac(aim[t][s], x[s].x, yi[t]);
         }
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
+        for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int v = 0; v < 4; ++v) st_nt(C{yr[t][v], yi[t][v]}, p + a.reg_off[4 * t + v]);
     }
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_dense_mfma5(typename V2<R>::type *__restrict__ psi,
-                                                     const typename V2<R>::type *__restrict__ mat, TileArgs a)
+template <typename R, int K>
+__global__ __launch_bounds__(256) void k_dense_mfma(typename V2<R>::type *__restrict__ psi,
+                                                    const typename V2<R>::type *__restrict__ mat, TileArgs a)
 {
-    k_dense_mfma5_body<R>(psi, mat, a);
+    k_dense_mfma_body<R, K>(psi, mat, a);
 }
 
 // Grouped form: member blockIdx.y of up to kMaxGroup states.
-template <typename R>
-__global__ __launch_bounds__(256) void k_dense_mfma5_g(Members mm, TileArgs a)
+template <typename R, int K>
+__global__ __launch_bounds__(256) void k_dense_mfma_g(Members mm, TileArgs a)
 {
     typedef typename V2<R>::type C;
-    k_dense_mfma5_body<R>(member_ptr<C>(mm, MF_STATE), member_ptr<const C>(mm, MF_PROG), a);
+    k_dense_mfma_body<R, K>(member_ptr<C>(mm, MF_STATE), member_ptr<const C>(mm, MF_PROG), a);
 }
 
 // Offset of column c (target bits) and base of row g (control set, zeros at
@@ -1277,8 +1283,9 @@ __global__ __launch_bounds__(256) void k_gather(const typename V2<R>::type *__re
 // arithmetic.  Tests lower it so that small states drive the multi-tile
 // loops that large states take.
 std::atomic<unsigned> g_grid_cap{0};
-// 5-qubit dense gates on the matrix cores (k_dense_mfma5); off selects the
-// vector forms, for comparison.
+// dense gates on the matrix cores (k_dense_mfma: 5 qubits, and 4 qubits with
+// two targets inside a cache line); off selects the vector forms, for
+// comparison.
 std::atomic<bool> g_dense_mfma{true};
 // complex64 gates with bit 0 as the only target inside a cache line on the
 // pair kernel (k_dense_pair0); off sends them to the LDS regroup, for
@@ -1356,20 +1363,29 @@ sv_status launch_dense_t(const DevOp &op, const Group &g, int n, hipStream_t st,
     }
     const unsigned cnt = (unsigned)g.count;
     const int k = op.k;
-    // 5-qubit gates on the matrix cores (k_dense_mfma5_body) when every
-    // target inside a 128-byte cache line is q_0 or q_1
+    // matrix-core form (k_dense_mfma_body) when every target inside a
+    // 128-byte cache line is q_0 or q_1: every 5-qubit gate, and 4-qubit
+    // gates with two targets inside the line
     constexpr int kLineBits = sizeof(R) == 8 ? 3 : 4;
-    if (k == 5 && n >= 9 && op.q[2] >= kLineBits && g_dense_mfma.load(std::memory_order_relaxed)) {
+    const bool mfma5 = k == 5 && n >= 9 && op.q[2] >= kLineBits;
+    const bool mfma4 = k == 4 && n >= 8 && op.q[1] < kLineBits && op.q[2] >= kLineBits;
+    if ((mfma5 || mfma4) && g_dense_mfma.load(std::memory_order_relaxed)) {
         TileArgs a;
         std::memset(&a, 0, sizeof(a));
-        a.ntiles = uint64_t(1) << (n - 9);
-        for (int j = 0; j < 5; ++j) a.rpos[j] = op.q[j];
-        for (int s = 0; s < 8; ++s)
-            a.reg_off[s] = (uint64_t(s & 1) << op.q[2]) | (uint64_t((s >> 1) & 1) << op.q[3]) |
-                           (uint64_t(s >> 2) << op.q[4]);
+        a.ntiles = uint64_t(1) << (n - 4 - k);
+        for (int j = 0; j < k; ++j) a.rpos[j] = op.q[j];
+        for (int s = 0; s < (1 << (k - 2)); ++s) {
+            uint64_t o = 0;
+            for (int j = 2; j < k; ++j)
+                if ((s >> (j - 2)) & 1) o |= uint64_t(1) << op.q[j];
+            a.reg_off[s] = o;
+        }
         *family = SV_KERNEL_DENSE_MFMA;
         const unsigned grid = grid_for(a.ntiles, 4, 32768);
-        launch2(&k_dense_mfma5<R>, &k_dense_mfma5_g<R>, grid, 256, 0, st, pp, cnt, a);
+        if (k == 5)
+            launch2(&k_dense_mfma<R, 5>, &k_dense_mfma_g<R, 5>, grid, 256, 0, st, pp, cnt, a);
+        else
+            launch2(&k_dense_mfma<R, 4>, &k_dense_mfma_g<R, 4>, grid, 256, 0, st, pp, cnt, a);
         HIPCK(hipGetLastError());
         return SV_OK;
     }

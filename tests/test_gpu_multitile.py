@@ -105,16 +105,17 @@ def test_dense_multitile(k, pattern, dtype, grid_cap):
 @pytest.mark.parametrize("grid_cap", CAPS, indirect=True)
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("pattern", list(PATTERNS))
-def test_dense5_vector_form_multitile(pattern, dtype, grid_cap):
-    """The vector kernels of 5-qubit gates (the matrix-core form switched
-    off), over several tiles per wave."""
+@pytest.mark.parametrize("k", [4, 5])
+def test_dense45_vector_form_multitile(k, pattern, dtype, grid_cap):
+    """The vector kernels of 4- and 5-qubit gates (the matrix-core form
+    switched off), over several tiles per wave."""
     hs = _hs()
     n = 18
-    qs = list(PATTERNS[pattern][4])
+    qs = list(PATTERNS[pattern][k - 1])
     rng = np.random.default_rng(7100 + len(pattern) + (7 if dtype == "c64" else 0))
-    U = W.random_unitary(32, rng)
+    U = W.random_unitary(1 << k, rng)
     g = W.Gate("dense", tuple(qs), np.ascontiguousarray(U).view(np.float64).ravel())
-    _say(f"multitile dense5 vector form n={n} targets={qs} dtype={dtype} cap={grid_cap}")
+    _say(f"multitile dense k={k} vector form n={n} targets={qs} dtype={dtype} cap={grid_cap}")
     psi0 = W.random_state(n, int(rng.integers(1 << 30)))
     want = oracle.apply_circuit(psi0, n, [g])
     hs.sv_debug_set_dense_mfma(False)
@@ -123,7 +124,7 @@ def test_dense5_vector_form_multitile(pattern, dtype, grid_cap):
     finally:
         hs.sv_debug_set_dense_mfma(True)
     _say(f"  families {sorted(fams)}")
-    assert fams and fams <= {"dense_direct", "dense_lds"}
+    assert fams and fams <= {"dense_direct", "dense_bfly", "dense_lds"}
     assert np.max(np.abs(got - want)) <= TOL[dtype]
 
 

@@ -127,9 +127,9 @@ def test_dense_register_path_smallest_states(k, extra, in_line, dtype):
 # (k <= 4) take the cross-lane butterfly: one or two at complex128, one at
 # complex64 (on amplitude pairs, so not bit 0); at complex64 bit 0 alone
 # inside the line takes the register path on pairs that hold two entries of
-# one group; 5-qubit gates take the
-# matrix cores when every target inside a line is one of the two lowest;
-# the LDS regroup the rest.
+# one group; 5-qubit gates, and 4-qubit gates with two targets inside the
+# line, take the matrix cores when every target inside a line is one of the
+# two lowest; the LDS regroup the rest.
 FAMILY_CASES = [((8, 11), "dense_direct", "dense_direct"),
                 ((3, 9, 14), "dense_direct", "dense_bfly"),
                 ((4, 5, 7, 13), "dense_direct", "dense_direct"),
@@ -139,7 +139,9 @@ FAMILY_CASES = [((8, 11), "dense_direct", "dense_direct"),
                 ((0, 6, 8, 12), "dense_bfly", "dense_direct"),
                 ((0,), "dense_bfly", "dense_direct"),
                 ((1, 4, 5, 12), "dense_bfly", "dense_bfly"),
-                ((0, 1, 3, 14), "dense_bfly", "dense_lds"),
+                ((0, 1, 3, 14), "dense_mfma", "dense_lds"),
+                ((1, 2, 6, 11), "dense_mfma", "dense_mfma"),
+                ((0, 3, 5, 11), "dense_bfly", "dense_mfma"),
                 ((1, 2, 9), "dense_bfly", "dense_lds"),
                 ((1, 2, 3), "dense_bfly", "dense_lds"),
                 ((1, 6, 8, 10, 12), "dense_mfma", "dense_mfma"),
@@ -170,28 +172,40 @@ def test_dense_family_choice(case, dtype):
     assert np.max(np.abs(got - want)) <= TOL[dtype]
 
 
-# 5-qubit target patterns for both forms of the gate: the matrix-core kernel
-# (two lowest targets as lane bits, the other three as register bits) and the
-# vector kernels (registers or the LDS regroup)
+# 5- and 4-qubit target patterns for both forms of the gate: the matrix-core
+# kernel (two lowest targets as lane bits, the others as register bits) and
+# the vector kernels (registers, butterflies or the LDS regroup)
 DENSE5 = [(5, 6, 7, 8, 9), (0, 1, 5, 7, 9), (0, 4, 5, 6, 8), (2, 3, 4, 6, 8), (1, 3, 4, 5, 8),
-          (3, 4, 5, 6, 7), (0, 1, 2, 3, 4), (4, 5, 6, 7, 8)]
+          (3, 4, 5, 6, 7), (0, 1, 2, 3, 4), (4, 5, 6, 7, 8),
+          (0, 1, 5, 7), (1, 2, 6, 7), (0, 2, 3, 7), (2, 3, 4, 6), (0, 3, 5, 6), (0, 1, 2, 6)]
+
+
+def _mfma_applies(qs, dtype):
+    """The matrix-core form takes 5-qubit gates and 4-qubit gates with two
+    targets inside a cache line, when no third target is inside it."""
+    line_bits = 3 if dtype == "c128" else 4
+    q = sorted(qs)
+    if len(q) == 5:
+        return q[2] >= line_bits
+    return q[1] < line_bits <= q[2]
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("form", ["mfma", "vector"])
 @pytest.mark.parametrize("n", [9, 10, 13])
 @pytest.mark.parametrize("case", range(len(DENSE5)))
-def test_dense5_forms(case, n, form, dtype):
+def test_dense_mfma_forms(case, n, form, dtype):
     hs = _hs()
     qs = [q for q in DENSE5[case]]
+    k = len(qs)
     if max(qs) >= n:
         pytest.skip("targets beyond the state")
     rng = np.random.default_rng(900 + 11 * case + n)
-    U = W.random_unitary(32, rng)
-    perm = rng.permutation(5)
+    U = W.random_unitary(1 << k, rng)
+    perm = rng.permutation(k)
     qs_list = [qs[i] for i in perm]
     g = W.Gate("dense", tuple(qs_list), np.ascontiguousarray(U).view(np.float64).ravel())
-    _say(f"dense5 n={n} targets={qs_list} form={form} dtype={dtype}")
+    _say(f"dense k={k} n={n} targets={qs_list} form={form} dtype={dtype}")
     psi0 = W.random_state(n, 70 + case + n)
     c = hs.circuit_from_gates(n, [g])
     hs.sv_debug_set_dense_mfma(form == "mfma")
@@ -203,14 +217,12 @@ def test_dense5_forms(case, n, form, dtype):
         s.close()
     finally:
         hs.sv_debug_set_dense_mfma(True)
-    line_bits = 3 if dtype == "c128" else 4
-    mfma_applies = sorted(qs)[2] >= line_bits
-    want_fam = "dense_mfma" if form == "mfma" and mfma_applies else None
+    want_fam = "dense_mfma" if form == "mfma" and _mfma_applies(qs, dtype) and n >= k + 4 else None
     got_fam = hs.KERNEL_FAMILY[int(fam[0])]
     if want_fam:
         assert got_fam == want_fam
     else:
-        assert got_fam in ("dense_direct", "dense_lds", "dense_small")
+        assert got_fam in ("dense_direct", "dense_bfly", "dense_lds", "dense_small")
     want = oracle.apply_circuit(psi0, n, [g])
     assert np.max(np.abs(got - want)) <= TOL[dtype]
 
