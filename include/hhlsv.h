@@ -270,9 +270,10 @@ typedef enum {
                                    inside a line: cross-lane butterfly, groups
                                    held in registers                     */
     SV_KERNEL_DENSE_MFMA = 7    /* dense k = 5 on >= 9 qubits, or k = 4 with
-                                   two targets inside a line on >= 8; every
-                                   target inside a line among the two
-                                   lowest: 16x16x4 matrix-core products  */
+                                   two targets inside a line (at c64: one
+                                   or two) on >= 8; every target inside a
+                                   line among the two lowest: 16x16x4
+                                   matrix-core products                  */
 } sv_kernel_family;
 
 /* As sv_apply, and record the device time of each gate's launch with HIP
@@ -515,10 +516,12 @@ sv_status sv_debug_set_grid_cap(int max_workgroups);
  * dtype or fewer qubits. */
 sv_status sv_stream_probe(sv_state *s, int reps, double *launch_ms);
 
-/* Select the form of 5-qubit dense gates, and of 4-qubit gates with two
- * targets inside a cache line, for launches made after the call: enable != 0
+/* Select the form of 5-qubit dense gates, and of 4-qubit gates with targets
+ * inside a cache line, for launches made after the call: enable = 1
  * (the default) the matrix-core kernel where it applies, 0 the vector
- * kernels everywhere.  Both compute the same gate (Sec. II-C fused
+ * kernels everywhere, 2 the matrix-core kernel also for every other 4-qubit
+ * gate it can take (no third target inside a line).  SV_ERR_INVALID for
+ * other values.  Both compute the same gate (Sec. II-C fused
  * gates); the switch exists to compare and test them.  Process-wide; not for
  * use while other threads launch; graphs captured earlier keep their
  * kernels. */

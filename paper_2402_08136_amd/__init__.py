@@ -455,9 +455,10 @@ def sv_debug_set_grid_cap(max_workgroups: int):
     _check(_lib.sv_debug_set_grid_cap(int(max_workgroups)), "sv_debug_set_grid_cap")
 
 
-def sv_debug_set_dense_mfma(enable: bool):
-    """Matrix-core (True, default) or vector (False) form of 5-qubit dense gates."""
-    _check(_lib.sv_debug_set_dense_mfma(int(bool(enable))), "sv_debug_set_dense_mfma")
+def sv_debug_set_dense_mfma(enable):
+    """Matrix-core form of 4/5-qubit dense gates: True or 1 (default rules),
+    False or 0 (vector forms), 2 (also every other 4-qubit gate it can take)."""
+    _check(_lib.sv_debug_set_dense_mfma(int(enable)), "sv_debug_set_dense_mfma")
 
 
 def sv_debug_set_pair0(enable: bool):

@@ -1286,7 +1286,7 @@ std::atomic<unsigned> g_grid_cap{0};
 // dense gates on the matrix cores (k_dense_mfma: 5 qubits, and 4 qubits with
 // two targets inside a cache line); off selects the vector forms, for
 // comparison.
-std::atomic<bool> g_dense_mfma{true};
+std::atomic<int> g_dense_mfma{1};
 // complex64 gates with bit 0 as the only target inside a cache line on the
 // pair kernel (k_dense_pair0); off sends them to the LDS regroup, for
 // comparison.
@@ -1365,11 +1365,17 @@ sv_status launch_dense_t(const DevOp &op, const Group &g, int n, hipStream_t st,
     const int k = op.k;
     // matrix-core form (k_dense_mfma_body) when every target inside a
     // 128-byte cache line is q_0 or q_1: every 5-qubit gate, and 4-qubit
-    // gates with two targets inside the line
+    // gates with targets inside the line
     constexpr int kLineBits = sizeof(R) == 8 ? 3 : 4;
+    const int mfma_mode = g_dense_mfma.load(std::memory_order_relaxed);
     const bool mfma5 = k == 5 && n >= 9 && op.q[2] >= kLineBits;
-    const bool mfma4 = k == 4 && n >= 8 && op.q[1] < kLineBits && op.q[2] >= kLineBits;
-    if ((mfma5 || mfma4) && g_dense_mfma.load(std::memory_order_relaxed)) {
+    // (4 qubits: with two targets inside the line; at complex64 also with
+    // one, where it beats the pair butterfly, 6.15 against 6.03 TB/s at 33
+    // qubits; at complex128 the register and butterfly kernels stay ahead
+    // with none or one, 6.29 / 6.22 against 6.22 / 6.16 TB/s)
+    const bool line4 = op.q[1] < kLineBits || (sizeof(R) == 4 && op.q[0] < kLineBits);
+    const bool mfma4 = k == 4 && n >= 8 && (line4 || mfma_mode == 2) && op.q[2] >= kLineBits;
+    if ((mfma5 || mfma4) && mfma_mode != 0) {
         TileArgs a;
         std::memset(&a, 0, sizeof(a));
         a.ntiles = uint64_t(1) << (n - 4 - k);
@@ -2217,7 +2223,8 @@ extern "C" sv_status sv_debug_set_grid_cap(int max_workgroups)
 
 extern "C" sv_status sv_debug_set_dense_mfma(int enable)
 {
-    hhlsv::g_dense_mfma.store(enable != 0, std::memory_order_relaxed);
+    if (enable < 0 || enable > 2) return hhlsv::fail(SV_ERR_INVALID, "sv_debug_set_dense_mfma: enable must be 0, 1 or 2");
+    hhlsv::g_dense_mfma.store(enable, std::memory_order_relaxed);
     return SV_OK;
 }
 

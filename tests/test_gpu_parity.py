@@ -128,17 +128,18 @@ def test_dense_register_path_smallest_states(k, extra, in_line, dtype):
 # complex64 (on amplitude pairs, so not bit 0); at complex64 bit 0 alone
 # inside the line takes the register path on pairs that hold two entries of
 # one group; 5-qubit gates, and 4-qubit gates with two targets inside the
-# line, take the matrix cores when every target inside a line is one of the
-# two lowest; the LDS regroup the rest.
+# line (at complex64 one or two), take the matrix cores when every target
+# inside a line is one of the two lowest; the LDS regroup the rest.
 FAMILY_CASES = [((8, 11), "dense_direct", "dense_direct"),
                 ((3, 9, 14), "dense_direct", "dense_bfly"),
                 ((4, 5, 7, 13), "dense_direct", "dense_direct"),
                 ((2, 6), "dense_bfly", "dense_bfly"),
                 ((0, 2, 9), "dense_bfly", "dense_lds"),
                 ((0, 5, 9), "dense_bfly", "dense_direct"),
-                ((0, 6, 8, 12), "dense_bfly", "dense_direct"),
+                ((0, 6, 8, 12), "dense_bfly", "dense_mfma"),
+                ((0, 6, 8), "dense_bfly", "dense_direct"),
                 ((0,), "dense_bfly", "dense_direct"),
-                ((1, 4, 5, 12), "dense_bfly", "dense_bfly"),
+                ((1, 4, 5, 12), "dense_bfly", "dense_mfma"),
                 ((0, 1, 3, 14), "dense_mfma", "dense_lds"),
                 ((1, 2, 6, 11), "dense_mfma", "dense_mfma"),
                 ((0, 3, 5, 11), "dense_bfly", "dense_mfma"),
@@ -182,12 +183,14 @@ DENSE5 = [(5, 6, 7, 8, 9), (0, 1, 5, 7, 9), (0, 4, 5, 6, 8), (2, 3, 4, 6, 8), (1
 
 def _mfma_applies(qs, dtype):
     """The matrix-core form takes 5-qubit gates and 4-qubit gates with two
-    targets inside a cache line, when no third target is inside it."""
+    targets inside a cache line (at complex64 one or two), when no third
+    target is inside it."""
     line_bits = 3 if dtype == "c128" else 4
     q = sorted(qs)
     if len(q) == 5:
         return q[2] >= line_bits
-    return q[1] < line_bits <= q[2]
+    inside = q[0] if dtype == "c64" else q[1]
+    return inside < line_bits <= q[2]
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
