@@ -79,7 +79,9 @@ def kernel_label(family, qubits, real="double", n=33):
         return f"k_dense_pair<{k}>"     # complex64: two amplitudes per lane access
     if family == "dense_bfly" and real == "float":   # amplitude pairs, targets in bits 1..3
         return f"k_dense_bfly_pair<{k}, {sum(q < 4 for q in qubits)}>"
-    if family == "dense_mfma":          # matrix cores: 5 qubits, or 4 with two targets inside a line
+    if family == "dense_mfma" and real == "float" and k == 4 and 0 not in qubits and n >= k + 5:
+        return f"k_dense_mfma_pair<{k}>"  # complex64 matrix cores on amplitude pairs
+    if family == "dense_mfma":          # matrix cores: 5 qubits, or 4 with targets inside a line
         return f"k_dense_mfma<{real}, {k}>"
     if family == "dense_bfly":          # targets inside a 128-byte line: bits 0..2
         return f"k_dense_bfly<{k}, {sum(q < 3 for q in qubits)}>"
@@ -89,7 +91,7 @@ def kernel_label(family, qubits, real="double", n=33):
     return f"{name}<{real}, {k}>" if family.startswith("dense") else f"{name}<{real}>"
 
 
-def cpu_baseline(budget_s=15.0, n=26):
+def cpu_baseline(budget_s=10.0, n=26):
     """Oracle (plain C, one thread) on the same layered-circuit generator at
     n qubits, unfused, gate by gate until ~budget_s of CPU time."""
     import numpy as np
@@ -388,7 +390,7 @@ def _serve_run(hs, sched, pool, pool_per_size, dtype, budget_bytes=0, sample_eve
 
 
 def hhl_serve(hs, W, seconds, rate=2000.0, pool_per_size=48, constrained_seconds=10.0,
-              oracle_budget_s=20.0, max_check_qubits=19):
+              oracle_budget_s=12.0, max_check_qubits=19):
     """Serving loop under open-loop Poisson arrivals (seed 2000 for arrivals,
     2001 for sizes); request systems come from a pool of seeded systems per
     size.  Latency = submit to finish inside the server.  1% of the requests
@@ -538,7 +540,7 @@ def main():
                     help="run one HHL leg alone (for profiling); prints that leg's JSON, not the bench line")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the Poisson arrival window")
-    ap.add_argument("--serve-constrained-seconds", type=float, default=10.0,
+    ap.add_argument("--serve-constrained-seconds", type=float, default=5.0,
                     help="length of the arrival window of the 256 MiB HBM-budget run")
     ap.add_argument("--c64-steps", type=int, default=2,
                     help="timed steps of the complex64 run of the same circuit (after one warm-up step)")

@@ -796,16 +796,19 @@ template <> struct Mfma<float> {
 // The matrix, as A fragments (Re and Im of its 2^K x 2^K / 64 entries per
 // lane), stays in registers for the wave's whole loop.
 // ---------------------------------------------------------------------------
+// The loop is software-pipelined: the next tile's loads are in flight while
+// this tile's MFMAs run and its outputs are stored (tiles are disjoint, so
+// the in-place update is unaffected).  At 33 qubits that took the 5-qubit
+// sweeps from 5.59-5.77 to 5.75-5.96 TB/s at complex64, and from 6.08-6.09
+// to 6.18-6.20 TB/s at complex128 with a target inside a line.
 template <typename R, int K>
 __device__ __forceinline__ void k_dense_mfma_body(typename V2<R>::type *__restrict__ psi,
-                                                  const typename V2<R>::type *__restrict__ mat, const TileArgs &a)
+                                                       const typename V2<R>::type *__restrict__ mat, const TileArgs &a)
 {
     typedef typename V2<R>::type C;
     typedef typename Mfma<R>::V4 V4;
     static_assert(K == 4 || K == 5, "matrix-core dense form: 4 or 5 targets");
-    constexpr int NR = 1 << K;        // matrix dimension
-    constexpr int NT = NR / 16;       // 16-row output tiles
-    constexpr int NS = NR / 4;        // 4-wide k-steps = registers per lane
+    constexpr int NR = 1 << K, NT = NR / 16, NS = NR / 4;
     const int l = threadIdx.x & 63;
     const int i = l & 15, kq = l >> 4;
     const int ri = sizeof(R) == 8 ? i : (((i & 3) << 2) | (i >> 2));
@@ -823,14 +826,25 @@ __device__ __forceinline__ void k_dense_mfma_body(typename V2<R>::type *__restri
     for (int j = 0; j < K; ++j) loff = insert_zero(loff, a.rpos[j]);
     loff |= (uint64_t(kq & 1) << a.rpos[0]) | (uint64_t(kq >> 1) << a.rpos[1]);
     const WaveRange wr = wave_range(a.ntiles, 4);
-    for (uint64_t w = wr.w; w < wr.end; w += wr.step) {
+    if (wr.w >= wr.end) return;
+    auto tile = [&](uint64_t w) {
         uint64_t b = w << 4;
 #pragma unroll
         for (int j = 0; j < K; ++j) b = insert_zero(b, a.rpos[j]);
-        C *p = psi + b + loff;
-        C x[NS];
+        return psi + b + loff;
+    };
+    C *p = tile(wr.w);
+    C x[NS];
 #pragma unroll
-        for (int s = 0; s < NS; ++s) x[s] = ld_nt(p + a.reg_off[s]);
+    for (int s = 0; s < NS; ++s) x[s] = ld_nt(p + a.reg_off[s]);
+    for (uint64_t w = wr.w; w < wr.end; w += wr.step) {
+        const bool more = w + wr.step < wr.end;
+        C *pn = more ? tile(w + wr.step) : p;
+        C nx[NS];
+        if (more) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) nx[s] = ld_nt(pn + a.reg_off[s]);
+        }
         V4 yr[NT], yi[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) yr[t] = yi[t] = V4{0, 0, 0, 0};
@@ -850,6 +864,11 @@ __device__ __forceinline__ void k_dense_mfma_body(typename V2<R>::type *__restri
         for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int v = 0; v < 4; ++v) st_nt(C{yr[t][v], yi[t][v]}, p + a.reg_off[4 * t + v]);
+        if (more) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) x[s] = nx[s];
+        }
+        p = pn;
     }
 }
 
@@ -866,6 +885,87 @@ __global__ __launch_bounds__(256) void k_dense_mfma_g(Members mm, TileArgs a)
 {
     typedef typename V2<R>::type C;
     k_dense_mfma_body<R, K>(member_ptr<C>(mm, MF_STATE), member_ptr<const C>(mm, MF_PROG), a);
+}
+
+// complex64 matrix-core form on amplitude pairs (bit 0 not a target): each
+// lane loads 16-byte pairs, i.e. the same matrix index of two groups (index
+// bit 0 = 0 and 1), and runs the layout above twice, once per group, so a
+// wave owns 32 groups and every access carries 16 bytes as on the other
+// complex64 paths.  Tile arguments are in pair units (targets shifted down
+// by one).
+template <int K>
+__device__ __forceinline__ void k_dense_mfma_pair_body(F4 *__restrict__ psi, const V2<float>::type *__restrict__ mat,
+                                                       const TileArgs &a)
+{
+    typedef V2<float>::type C;
+    typedef Mfma<float>::V4 V4;
+    static_assert(K == 4, "pair form of the matrix-core kernel: 4 targets");
+    constexpr int NR = 1 << K;
+    constexpr int NT = NR / 16;
+    constexpr int NS = NR / 4;
+    const int l = threadIdx.x & 63;
+    const int i = l & 15, kq = l >> 4;
+    const int ri = ((i & 3) << 2) | (i >> 2);
+    float are[NT][NS], aim[NT][NS];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const C m = mat[(16 * t + ri) * NR + 4 * s + kq];
+            are[t][s] = m.x;
+            aim[t][s] = m.y;
+        }
+    uint64_t loff = (uint64_t)i;
+#pragma unroll
+    for (int j = 0; j < K; ++j) loff = insert_zero(loff, a.rpos[j]);
+    loff |= (uint64_t(kq & 1) << a.rpos[0]) | (uint64_t(kq >> 1) << a.rpos[1]);
+    const WaveRange wr = wave_range(a.ntiles, 4);
+    for (uint64_t w = wr.w; w < wr.end; w += wr.step) {
+        uint64_t b = w << 4;
+#pragma unroll
+        for (int j = 0; j < K; ++j) b = insert_zero(b, a.rpos[j]);
+        F4 *p = psi + b + loff;
+        F4 x[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) x[s] = ld_nt(p + a.reg_off[s]);
+        V4 er[NT], ei[NT], orr[NT], oi[NT];   // even and odd group of each pair
+#pragma unroll
+        for (int t = 0; t < NT; ++t) er[t] = ei[t] = orr[t] = oi[t] = V4{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const float nxe = -x[s].y, nxo = -x[s].w;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                er[t] = Mfma<float>::mac(are[t][s], x[s].x, er[t]);
+                orr[t] = Mfma<float>::mac(are[t][s], x[s].z, orr[t]);
+                ei[t] = Mfma<float>::mac(are[t][s], x[s].y, ei[t]);
+                oi[t] = Mfma<float>::mac(are[t][s], x[s].w, oi[t]);
+                er[t] = Mfma<float>::mac(aim[t][s], nxe, er[t]);
+                orr[t] = Mfma<float>::mac(aim[t][s], nxo, orr[t]);
+                ei[t] = Mfma<float>::mac(aim[t][s], x[s].x, ei[t]);
+                oi[t] = Mfma<float>::mac(aim[t][s], x[s].z, oi[t]);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                st_nt(F4{er[t][v], ei[t][v], orr[t][v], oi[t][v]}, p + a.reg_off[4 * t + v]);
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_dense_mfma_pair(V2<float>::type *__restrict__ psi,
+                                                         const V2<float>::type *__restrict__ mat, TileArgs a)
+{
+    k_dense_mfma_pair_body<K>(reinterpret_cast<F4 *>(psi), mat, a);
+}
+
+// Grouped form: member blockIdx.y of up to kMaxGroup states.
+template <int K>
+__global__ __launch_bounds__(256) void k_dense_mfma_pair_g(Members mm, TileArgs a)
+{
+    k_dense_mfma_pair_body<K>(member_ptr<F4>(mm, MF_STATE), member_ptr<const V2<float>::type>(mm, MF_PROG), a);
 }
 
 // Offset of column c (target bits) and base of row g (control set, zeros at
@@ -1387,6 +1487,21 @@ sv_status launch_dense_t(const DevOp &op, const Group &g, int n, hipStream_t st,
             a.reg_off[s] = o;
         }
         *family = SV_KERNEL_DENSE_MFMA;
+        if (sizeof(R) == 4 && k == 4 && op.q[0] >= 1 && n >= k + 5) {
+            // complex64 with bit 0 not a target: pairs of groups, 16-byte
+            // accesses (pair units).  4 qubits only: at 33 qubits the pair
+            // form took 6.19 against 6.10-6.13 TB/s for the 8-byte form at
+            // k = 4, but at k = 5 circuits with it ran every kernel at about
+            // 5.2 TB/s (the register kernels too, 6.1-6.2 otherwise)
+            a.ntiles >>= 1;
+            for (int j = 0; j < k; ++j) a.rpos[j] = op.q[j] - 1;
+            for (int s = 0; s < (1 << (k - 2)); ++s) a.reg_off[s] >>= 1;
+            const unsigned grid = grid_for(a.ntiles, 4, 32768);
+            typedef V2<float>::type CF;
+            launch2<CF>(&k_dense_mfma_pair<4>, &k_dense_mfma_pair_g<4>, grid, 256, 0, st, pp, cnt, a);
+            HIPCK(hipGetLastError());
+            return SV_OK;
+        }
         const unsigned grid = grid_for(a.ntiles, 4, 32768);
         if (k == 5)
             launch2(&k_dense_mfma<R, 5>, &k_dense_mfma_g<R, 5>, grid, 256, 0, st, pp, cnt, a);
