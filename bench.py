@@ -339,6 +339,29 @@ def hhl_batch(hs, W, count=8192):
             e["instances"] += it["count"]
             e["ms"] = round(e["ms"] + it["ms"], 3)
             e["ops_per_instance"] = max(e["ops_per_instance"], it["ops"])
+        # the grouped sweeps op by op, by kernel family: algorithmic bytes
+        # (each amplitude read and written once; a controlled wide gate only
+        # its control = 1 half) and the gate's complex multiply-adds
+        amp = 16 if dtype == "c128" else 8
+        by_family = {}
+        for op in bt.run_timed_ops():
+            it = items[op["item"]]
+            touched = it["count"] * 2 ** it["n"] * (0.5 if op["controlled"] else 1.0)
+            fam = op["family"]
+            key = f"{fam} k={op['k']}" + (" controlled" if op["controlled"] else "")
+            e = by_family.setdefault(key, {"launches": 0, "ms": 0.0, "bytes": 0.0, "flop": 0.0})
+            e["launches"] += 1
+            e["ms"] += op["ms"]
+            e["bytes"] += 2 * amp * touched
+            if fam.startswith("dense") or fam == "wide":
+                e["flop"] += 8 * 2 ** op["k"] * touched
+        bt.run()
+        for e in by_family.values():
+            sec = e["ms"] * 1e-3
+            e["GBps"] = round(e.pop("bytes") / sec / 1e9, 1) if sec > 0 else None
+            op_flop = e.pop("flop")
+            e["TFLOPs"] = round(op_flop / sec / 1e12, 2) if op_flop and sec > 0 else None
+            e["ms"] = round(e["ms"], 3)
         pairs = []
         for i in sorted(first.values()):
             y, p1 = bt.postselected(i)
@@ -349,7 +372,8 @@ def hhl_batch(hs, W, count=8192):
                       "first_run_s": round(setup_s, 3), "autotune_s": round(tune_s, 2),
                       "tuned_by_shape": tuned, "error_vs_oracle": result_errors(pairs, dtype),
                       "eager_item_breakdown": {"sum_ms": round(sum(it["ms"] for it in items), 3),
-                                               "by_kind_and_qubits": breakdown}}
+                                               "by_kind_and_qubits": breakdown},
+                      "swept_ops_by_family": dict(sorted(by_family.items(), key=lambda kv: -kv[1]["ms"]))}
         bt.close()
     return out
 

@@ -363,6 +363,17 @@ sv_status svb_last_run_ms(const svb *bt, double *ms);
  * svb_run does; svb_last_run_ms then gives the sum of the items. */
 sv_status svb_run_timed(svb *bt, int cap, int *items, int *kind, int *n,
                         int *count, int *ops, double *ms);
+/* svb_run_timed_ops: as svb_run_timed for the grouped sweeps only, with each
+ * fused op's launch timed on its own (HIP events on the batch's stream), for
+ * a breakdown of the sweeps by kernel family.  For entry i < *count (one per
+ * op of every group, groups in svb_run_timed's item order): item[i] the
+ * group's item index in svb_run_timed, family[i] the sv_kernel_family used,
+ * k[i] the op's targets (UCRY: controls), controlled[i] 1 for a wide gate
+ * with a control qubit, ms[i] device time.  Arrays hold cap entries;
+ * SV_ERR_INVALID (with *count set) if cap is too small.  The outputs it
+ * leaves are not a run's results: call svb_run afterwards. */
+sv_status svb_run_timed_ops(svb *bt, int cap, int *count, int *item, int *family,
+                            int *k, int *controlled, double *ms);
 sv_status svb_size(const svb *bt, int *count);
 sv_status svb_destroy(svb *bt);
 

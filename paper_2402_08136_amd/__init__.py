@@ -140,6 +140,7 @@ _proto("svb_run", _vp)
 _proto("svb_solution", _vp, ctypes.c_int, _dp, ctypes.c_int, ctypes.POINTER(SolutionInfo))
 _proto("svb_last_run_ms", _vp, _dp)
 _proto("svb_run_timed", _vp, ctypes.c_int, _ip, _ip, _ip, _ip, _ip, _dp)
+_proto("svb_run_timed_ops", _vp, ctypes.c_int, _ip, _ip, _ip, _ip, _ip, _dp)
 _proto("svb_postselected", _vp, ctypes.c_int, _dp, ctypes.c_int, _dp)
 _proto("svb_size", _vp, _ip)
 _proto("svb_destroy", _vp)
@@ -518,6 +519,18 @@ class Batch:
                                   _dptr(ms)), "svb_run_timed")
         return [{"kind": "swept" if kind[i] else "batched", "n": int(n[i]), "count": int(count[i]),
                  "ops": int(ops[i]), "ms": float(ms[i])} for i in range(items.value)]
+
+    def run_timed_ops(self, cap: int = 65536):
+        """Each fused op of the grouped sweeps timed on its own: a list of
+        dicts (item, family, k, controlled, ms); run() afterwards for results."""
+        count = ctypes.c_int()
+        item, fam, k, ctl = (np.zeros(cap, dtype=np.int32) for _ in range(4))
+        ms = np.zeros(cap)
+        _check(_lib.svb_run_timed_ops(self.handle, cap, ctypes.byref(count), item.ctypes.data_as(_ip),
+                                      fam.ctypes.data_as(_ip), k.ctypes.data_as(_ip), ctl.ctypes.data_as(_ip),
+                                      _dptr(ms)), "svb_run_timed_ops")
+        return [{"item": int(item[i]), "family": KERNEL_FAMILY[int(fam[i])], "k": int(k[i]),
+                 "controlled": bool(ctl[i]), "ms": float(ms[i])} for i in range(count.value)]
 
     def solution(self, index: int):
         dim = self.dims[index]

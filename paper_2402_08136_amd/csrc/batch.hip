@@ -996,6 +996,63 @@ extern "C" sv_status svb_run_timed(svb *b, int cap, int *items, int *kind, int *
     return SV_OK;
 }
 
+extern "C" sv_status svb_run_timed_ops(svb *b, int cap, int *count, int *item, int *family, int *k,
+                                       int *controlled, double *ms)
+{
+    if (!b || !count || !item || !family || !k || !controlled || !ms || cap < 0)
+        return fail(SV_ERR_INVALID, "svb_run_timed_ops: NULL argument or cap < 0");
+    if (b->insts.empty()) return fail(SV_ERR_INVALID, "svb_run_timed_ops: empty batch");
+    sv_status st;
+    if (!b->uploaded) {
+        if ((st = upload(b)) != SV_OK) {
+            release_device(b);
+            return st;
+        }
+        if ((st = capture(b)) != SV_OK) {
+            release_device(b);
+            return st;
+        }
+    }
+    int total = 0;
+    for (const svb::Swept &sw : b->swept) total += (int)sw.ops.size();
+    *count = total;
+    if (cap < total) return fail(SV_ERR_INVALID, "svb_run_timed_ops: cap below the number of swept ops");
+    std::vector<hipEvent_t> ev(total + 1, nullptr);
+    hipError_t e = hipSuccess;
+    for (auto &x : ev)
+        if (e == hipSuccess) e = hipEventCreate(&x);
+    int at = 0;
+    const int nclass = (int)b->classes.size();
+    for (size_t gi = 0; gi < b->swept.size() && e == hipSuccess; ++gi) {
+        const svb::Swept &sw = b->swept[gi];
+        Group g;
+        swept_group(b, sw, &g);
+        sv_status ls = launch_init_zero_group(g, sw.n, b->dtype, b->stream);
+        for (size_t o = 0; o < sw.ops.size() && ls == SV_OK && e == hipSuccess; ++o, ++at) {
+            e = hipEventRecord(ev[at], b->stream);
+            if (e != hipSuccess) break;
+            const DevOp &op = sw.ops[o];
+            item[at] = nclass + (int)gi;
+            k[at] = op.k;
+            controlled[at] = op.type == OP_WIDE && op.control >= 0;
+            ls = launch_op_group(op, g, sw.n, b->dtype, b->stream, &family[at]);
+            if (ls == SV_OK) e = hipEventRecord(ev[at + 1], b->stream);
+        }
+        if (ls == SV_OK && e == hipSuccess) ls = launch_postselect_group(g, sw.n, sw.ns, b->dtype, b->stream);
+        if (ls != SV_OK && e == hipSuccess) e = hipErrorLaunchFailure;
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    for (int i = 0; i < total && e == hipSuccess; ++i) {
+        float t = 0.f;
+        e = hipEventElapsedTime(&t, ev[i], ev[i + 1]);
+        ms[i] = t;
+    }
+    for (auto &x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (e != hipSuccess) return fail(SV_ERR_HIP, std::string("svb_run_timed_ops: ") + hipGetErrorString(e));
+    return SV_OK;
+}
+
 extern "C" sv_status svb_last_run_ms(const svb *b, double *ms)
 {
     if (!b || !ms) return fail(SV_ERR_INVALID, "svb_last_run_ms: NULL argument");

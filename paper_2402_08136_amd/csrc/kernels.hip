@@ -1010,14 +1010,16 @@ __device__ __forceinline__ void k_wide_mfma_body(typename V2<R>::type *__restric
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
     constexpr uint64_t rows_per_wave = 16 * RT;
+    typedef typename V2<R>::type C;
     R *outr = reinterpret_cast<R *>(psi);
-    const R *inr = reinterpret_cast<const R *>(psi);
-    const R *ur = reinterpret_cast<const R *>(UT);
-    // this lane's real input index k = kk + lk has part s = lk & 1 of
-    // in[k / 2]; its real output column 16 ct + li has part t = li & 1, so
-    // its B entry is part s ^ t of U[j][c], negated when s = 1, t = 0
-    const int s_in = lk & 1, part = s_in ^ (li & 1);
-    const R sgn = (s_in && !(li & 1)) ? R(-1) : R(1);
+    // Real form of the complex product: the output's real column 2j + t is
+    // part t of y_j = sum_c U[j][c] x_c.  A step takes four complex inputs
+    // c0 .. c0+3 (this lane: c = c0 + lk, one 16-byte load per row) in two
+    // products, one over their real parts and one over their imaginary
+    // parts; this lane's B entries for output column 16 ct + li (part
+    // t = li & 1) are, from U[j][c]: Re x_c -> (Re, Im)[t], Im x_c ->
+    // (-Im, Re)[t].
+    const bool odd = li & 1;
     for (uint64_t rb = wave * rows_per_wave; rb < a.ngroups; rb += nwaves * rows_per_wave) {
         uint64_t ga[RT];
         bool oka[RT];
@@ -1033,18 +1035,22 @@ __device__ __forceinline__ void k_wide_mfma_body(typename V2<R>::type *__restric
 #pragma unroll
             for (int ct = 0; ct < CTN; ++ct) acc[rt][ct] = V4{0, 0, 0, 0};
 #pragma unroll 2
-        for (int kk = 0; kk < 2 * D; kk += 4) {
-            const int c = (kk + lk) >> 1;   // complex input column of this lane
+        for (int c0 = 0; c0 < D; c0 += 4) {
+            const int c = c0 + lk;   // complex input column of this lane
             const uint64_t oc = wide_col(a, c);
-            R xv[RT];
+            C xv[RT];
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt) xv[rt] = oka[rt] ? inr[2 * (ga[rt] | oc) + s_in] : R(0);
+            for (int rt = 0; rt < RT; ++rt) xv[rt] = oka[rt] ? psi[ga[rt] | oc] : C{0, 0};
 #pragma unroll
             for (int ct = 0; ct < CTN; ++ct) {
-                const int j = (16 * ct + li) >> 1;
-                const R bv = sgn * ur[2 * ((size_t)c * D + j) + part];   // from U[j][c]
+                const C u = UT[(size_t)c * D + ((16 * ct + li) >> 1)];   // U[j][c]
+                const R b_re = odd ? u.y : u.x;
+                const R b_im = odd ? u.x : -u.y;
 #pragma unroll
-                for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = Mfma<R>::mac(xv[rt], bv, acc[rt][ct]);
+                for (int rt = 0; rt < RT; ++rt) {
+                    acc[rt][ct] = Mfma<R>::mac(xv[rt].x, b_re, acc[rt][ct]);
+                    acc[rt][ct] = Mfma<R>::mac(xv[rt].y, b_im, acc[rt][ct]);
+                }
             }
         }
 #pragma unroll
@@ -1108,7 +1114,10 @@ __device__ __forceinline__ void k_wide_mfma_stage_body(typename V2<R>::type *__r
     const int l = threadIdx.x & 63;
     const int li = l & 15, lk = l >> 4;
     const int ct0 = (threadIdx.x >> 6) * CW;
-    const int s_in = lk & 1, part = s_in ^ (li & 1);   // as in k_wide_mfma_body
+    // this lane's real input index k = kk + lk has part s = lk & 1 of
+    // in[k / 2]; its real output column 16 ct + li has part t = li & 1, so
+    // its B entry is part s ^ t of U[j][c], negated when s = 1, t = 0
+    const int s_in = lk & 1, part = s_in ^ (li & 1);
     const R sgn = (s_in && !(li & 1)) ? R(-1) : R(1);
     const R *ur = reinterpret_cast<const R *>(UT);
     R *outr = reinterpret_cast<R *>(psi);
@@ -1468,13 +1477,25 @@ sv_status launch_dense_t(const DevOp &op, const Group &g, int n, hipStream_t st,
     // gates with targets inside the line
     constexpr int kLineBits = sizeof(R) == 8 ? 3 : 4;
     const int mfma_mode = g_dense_mfma.load(std::memory_order_relaxed);
-    const bool mfma5 = k == 5 && n >= 9 && op.q[2] >= kLineBits;
+    // Batch instances take it for every 4- and 5-qubit gate, whatever the
+    // targets: each member has its own matrix, and the vector kernels, which
+    // read it through the scalar cache row by row, ran at 2.3 TB/s (k = 4,
+    // register form) and 0.9 TB/s (k = 5, LDS regroup) over the groups of an
+    // 8192-solve batch, where the matrix-core form loads it once per wave.
+    // (the choice depends on Group::batch, never on the group's size)
+    const bool batch = g.batch;
+    const bool mfma5 = k == 5 && n >= 9 && (op.q[2] >= kLineBits || batch);
     // (4 qubits: with two targets inside the line; at complex64 also with
     // one, where it beats the pair butterfly, 6.15 against 6.03 TB/s at 33
     // qubits; at complex128 the register and butterfly kernels stay ahead
     // with none or one, 6.29 / 6.22 against 6.22 / 6.16 TB/s)
     const bool line4 = op.q[1] < kLineBits || (sizeof(R) == 4 && op.q[0] < kLineBits);
-    const bool mfma4 = k == 4 && n >= 8 && (line4 || mfma_mode == 2) && op.q[2] >= kLineBits;
+    const bool mfma4 = k == 4 && n >= 8 && (((line4 || mfma_mode == 2) && op.q[2] >= kLineBits) || batch);
+    // Workgroups per member of a batch group: at least 16 (and 4096 over the
+    // group), so that a wave runs several tiles and loads its matrix once for
+    // them (one tile per wave measured 9.4 against 8.9 ms for the 5-qubit
+    // gates of that batch).  No output's arithmetic depends on it.
+    const unsigned batch_cap = batch ? std::max(16u, ((4096u / cnt + 7u) & ~7u)) : 32768u;
     if ((mfma5 || mfma4) && mfma_mode != 0) {
         TileArgs a;
         std::memset(&a, 0, sizeof(a));
@@ -1496,13 +1517,13 @@ sv_status launch_dense_t(const DevOp &op, const Group &g, int n, hipStream_t st,
             a.ntiles >>= 1;
             for (int j = 0; j < k; ++j) a.rpos[j] = op.q[j] - 1;
             for (int s = 0; s < (1 << (k - 2)); ++s) a.reg_off[s] >>= 1;
-            const unsigned grid = grid_for(a.ntiles, 4, 32768);
+            const unsigned grid = grid_for(a.ntiles, 4, batch_cap);
             typedef V2<float>::type CF;
             launch2<CF>(&k_dense_mfma_pair<4>, &k_dense_mfma_pair_g<4>, grid, 256, 0, st, pp, cnt, a);
             HIPCK(hipGetLastError());
             return SV_OK;
         }
-        const unsigned grid = grid_for(a.ntiles, 4, 32768);
+        const unsigned grid = grid_for(a.ntiles, 4, batch_cap);
         if (k == 5)
             launch2(&k_dense_mfma<R, 5>, &k_dense_mfma_g<R, 5>, grid, 256, 0, st, pp, cnt, a);
         else

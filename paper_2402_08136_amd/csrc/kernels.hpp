@@ -51,10 +51,11 @@ struct Group {
     double *partials[kMaxGroup] = {};            // kReducePartials doubles each
     double *out[kMaxGroup] = {};                 // one double each (norm result)
     const unsigned long long *d_members = nullptr;
-    // Members are instances of a batch: wide gates of 8..64 columns always
-    // take the matrix cores, whatever the row count.  Elsewhere the kernel
-    // follows each member's own row count.  The choice never depends on the
-    // group size, so a member's bits are the same alone or grouped.
+    // Members are instances of a batch: wide gates of 8..64 columns and
+    // dense gates of 4 and 5 qubits (on >= 8 / 9 qubits) always take the
+    // matrix cores, whatever the row count or the targets.  Elsewhere the
+    // kernel follows each member's own shape.  The choice never depends on
+    // the group size, so a member's bits are the same alone or grouped.
     bool batch = false;
     // waves a wide-gate launch aims to keep busy over the whole group when
     // it chooses rows per wave (no output's arithmetic depends on it)

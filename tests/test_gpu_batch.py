@@ -192,6 +192,75 @@ def test_tuned_choices_match_oracle(ns, m, dtype, choice):
         hs.svb_set_tune(dtype, ns, m, resident_kib=96)
 
 
+def test_run_timed_ops_covers_every_swept_op():
+    """Per-op timing of the grouped sweeps: one entry per fused op of every
+    group, in item order, on sweep kernel families; the swept results it
+    leaves and the next graph run both match the oracle."""
+    hs = _hs()
+    systems = [W.dc_powerflow(1 << 4, 900 + i) + (8,) for i in range(6)]   # n = 13 at c128: swept
+    systems += [W.dc_powerflow(1 << 2, 910 + i) + (4,) for i in range(3)]  # n = 7: batched kernel
+    refs = _oracle_refs([systems[0], systems[-1]])
+    bt = hs.Batch("c128", 3)
+    for A, b, m in systems:
+        bt.add(hs.circuit_build_hhl(A, b, m, device_evolutions=True))
+    items = bt.run_timed()
+    swept = [i for i, it in enumerate(items) if it["kind"] == "swept"]
+    assert len(swept) == 1 and items[swept[0]]["count"] == 6
+    ops = bt.run_timed_ops()
+    _say(f"run_timed_ops: {len(ops)} ops, {sum(o['ms'] for o in ops):.3f} ms; items {items}")
+    assert len(ops) == items[swept[0]]["ops"]
+    assert {o["item"] for o in ops} == set(swept)
+    assert all(o["ms"] > 0 and o["family"] != "dense_small" for o in ops)
+    assert any(o["family"] == "wide" and o["controlled"] for o in ops)
+    for when in ("after per-op timing", "graph"):
+        for i, ref in ((0, refs[0]), (len(systems) - 1, refs[1])):
+            x_hat, _ = bt.solution(i)
+            y, p1 = bt.postselected(i)
+            check_instance(y, p1, x_hat, ref, "c128", (when, i))
+        bt.run()
+    with pytest.raises(hs.HHLSVError, match="INVALID"):
+        bt.run_timed_ops(cap=1)
+
+
+@pytest.mark.parametrize("ns,m,dtype", [(4, 8, "c128"), (5, 8, "c64")])
+@pytest.mark.parametrize("k", [4, 5])
+def test_batch_dense_gates_on_matrix_cores(ns, m, dtype, k):
+    """Batch groups run every 4- and 5-qubit gate on the matrix cores, also
+    with three targets inside a cache line (e.g. qubits 0..3, or 1..4 at
+    complex64) where a single state takes a vector kernel; against the
+    oracle, and bit for bit the same alone (a group of one) as in a group of
+    four."""
+    hs = _hs()
+    systems = [W.dc_powerflow(1 << ns, 940 + i) + (m,) for i in range(4)]
+    refs = _oracle_refs(systems[:2])
+    circs = [hs.circuit_build_hhl(A, b, mm, device_evolutions=True) for A, b, mm in systems]
+    line_bits = 3 if dtype == "c128" else 4   # a 128-byte line holds 8 / 16 amplitudes
+    low = [q for kind, q, _ in hs.fuse(circs[0], k).gates() if kind == "dense" and len(q) == k and q[2] < line_bits]
+    assert low, "the fused circuit has a gate with three targets inside a line"
+    bt = hs.Batch(dtype, k)
+    for c in circs:
+        bt.add(c)
+    bt.run()
+    ops = bt.run_timed_ops()
+    wide = [o for o in ops if o["family"].startswith("dense") and o["k"] >= 4]
+    _say(f"batch ns={ns} m={m} {dtype} k={k}: {len(ops)} ops, dense k>=4 families "
+         f"{sorted({o['family'] for o in wide})}")
+    assert wide and all(o["family"] == "dense_mfma" for o in wide)
+    bt.run()
+    for i, ref in enumerate(refs):
+        x_hat, _ = bt.solution(i)
+        y, p1 = bt.postselected(i)
+        check_instance(y, p1, x_hat, ref, dtype, ("mfma", k, i))
+    alone = hs.Batch(dtype, k)
+    alone.add(circs[0])
+    alone.run()
+    ya, pa = alone.postselected(0)
+    yg, pg = bt.postselected(0)
+    assert np.array_equal(ya, yg) and pa == pg
+    alone.close()
+    bt.close()
+
+
 def test_batch_errors():
     hs = _hs()
     with pytest.raises(hs.HHLSVError, match="INVALID"):
