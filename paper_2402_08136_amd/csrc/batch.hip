@@ -33,7 +33,7 @@ namespace hhlsv {
 namespace {
 
 constexpr int kThreads = kBatchThreads;
-constexpr int kRedBytes = kThreads * 8;
+static_assert(kBatchScratchBytes >= kThreads * 8, "room for the reduction's partial sums");
 constexpr int kMaxBatchQubits = 24;
 
 
@@ -250,8 +250,9 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BInst *__restrict__ in
 {
     typedef typename V2<R>::type C;
     extern __shared__ unsigned char smem[];
-    double *red = reinterpret_cast<double *>(smem);
-    C *lstate = reinterpret_cast<C *>(smem + kRedBytes);
+    double *red = reinterpret_cast<double *>(smem);   // scratch: partial sums at the end
+    C *mscr = reinterpret_cast<C *>(smem);            // scratch: a dense op's matrix
+    C *lstate = reinterpret_cast<C *>(smem + kBatchScratchBytes);
     for (int w = blockIdx.x; w < count; w += gridDim.x) {
         const BInst in = insts[order[w]];
         C *psi = RESIDENT ? lstate : reinterpret_cast<C *>(in.state);
@@ -263,12 +264,23 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BInst *__restrict__ in
             const C *tab = reinterpret_cast<const C *>(in.tables + op.off);
             switch (op.type) {
             case OP_DENSE:
-                switch (op.k) {
-                case 1: b_dense<C, 1>(psi, in.n, op, tab); break;
-                case 2: b_dense<C, 2>(psi, in.n, op, tab); break;
-                case 3: b_dense<C, 3>(psi, in.n, op, tab); break;
-                case 4: if (KMAX >= 4) b_dense<C, (KMAX >= 4 ? 4 : 1)>(psi, in.n, op, tab); break;
-                default: if (KMAX >= 5) b_dense<C, (KMAX >= 5 ? 5 : 1)>(psi, in.n, op, tab); break;
+                if (op.k <= 4) {
+                    // every thread reads the whole matrix (at most 4 KiB):
+                    // copy it to LDS once, coalesced, rather than stream it
+                    // through the scalar cache for every group; the previous
+                    // op ended with a barrier
+                    static_assert(sizeof(C) << 8 <= (size_t)kBatchScratchBytes, "a 4-qubit matrix fits");
+                    const int cnt = 1 << (2 * op.k);
+                    for (int i = threadIdx.x; i < cnt; i += blockDim.x) mscr[i] = tab[i];
+                    __syncthreads();
+                    switch (op.k) {
+                    case 1: b_dense<C, 1>(psi, in.n, op, mscr); break;
+                    case 2: b_dense<C, 2>(psi, in.n, op, mscr); break;
+                    case 3: b_dense<C, 3>(psi, in.n, op, mscr); break;
+                    default: if (KMAX >= 4) b_dense<C, (KMAX >= 4 ? 4 : 1)>(psi, in.n, op, mscr); break;
+                    }
+                } else if (KMAX >= 5) {
+                    b_dense<C, (KMAX >= 5 ? 5 : 1)>(psi, in.n, op, tab);
                 }
                 break;
             case OP_DIAG: b_diag(psi, in.n, op, tab); break;

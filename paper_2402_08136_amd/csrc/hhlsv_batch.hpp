@@ -36,9 +36,12 @@ constexpr int kBatchThreads = 256;
 constexpr int kBatchLdsLimit = 160 * 1024;
 constexpr size_t kResidentStateMax = 64 * 1024;
 constexpr size_t kResidentStateLimit = 128 * 1024;
+// LDS ahead of the state: the matrix of the current dense op (up to 4 KiB,
+// 4 qubits at complex128), and the final reduction's partial sums
+constexpr int kBatchScratchBytes = 4096;
 inline size_t batch_lds_bytes(int n, sv_dtype d, bool *resident, size_t resident_max = kResidentStateMax)
 {
-    const size_t red = kBatchThreads * 8;
+    const size_t red = kBatchScratchBytes;
     const size_t sb = (d == SV_C128 ? size_t(16) : size_t(8)) << n;
     *resident = sb <= resident_max && sb + red <= (size_t)kBatchLdsLimit;
     return red + (*resident ? sb : 0);

@@ -1041,17 +1041,23 @@ __device__ __forceinline__ void k_wide_mfma_body(typename V2<R>::type *__restric
             C xv[RT];
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) xv[rt] = oka[rt] ? psi[ga[rt] | oc] : C{0, 0};
+            R b_re[CTN], b_im[CTN];
 #pragma unroll
             for (int ct = 0; ct < CTN; ++ct) {
                 const C u = UT[(size_t)c * D + ((16 * ct + li) >> 1)];   // U[j][c]
-                const R b_re = odd ? u.y : u.x;
-                const R b_im = odd ? u.x : -u.y;
-#pragma unroll
-                for (int rt = 0; rt < RT; ++rt) {
-                    acc[rt][ct] = Mfma<R>::mac(xv[rt].x, b_re, acc[rt][ct]);
-                    acc[rt][ct] = Mfma<R>::mac(xv[rt].y, b_im, acc[rt][ct]);
-                }
+                b_re[ct] = odd ? u.y : u.x;
+                b_im[ct] = odd ? u.x : -u.y;
             }
+            // all real-part products, then all imaginary-part ones: RT * CTN
+            // independent accumulations between two into the same tile
+#pragma unroll
+            for (int ct = 0; ct < CTN; ++ct)
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = Mfma<R>::mac(xv[rt].x, b_re[ct], acc[rt][ct]);
+#pragma unroll
+            for (int ct = 0; ct < CTN; ++ct)
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = Mfma<R>::mac(xv[rt].y, b_im[ct], acc[rt][ct]);
         }
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
