@@ -478,7 +478,8 @@ typedef struct {
     int wave_target;   /* waves a grouped wide-gate launch aims to keep busy
                           when it picks rows per wave                          */
     int resident_kib;  /* largest state, in KiB, run with the state in LDS
-                          (64 or 128); larger ones run as grouped sweeps       */
+                          (a power of two up to 128; default 64); larger
+                          ones run as grouped sweeps                          */
     int tuned;         /* 1: chosen by the autotuner, 0: the defaults         */
     double ms;         /* device time of the choice on the tuning batch       */
 } svb_tune;
@@ -489,8 +490,9 @@ typedef struct {
  * created with k_max = 0.  Coordinate descent from the defaults (k 3, groups
  * of 256, wave target 1024, LDS residency up to 64 KiB): k_max = 1..5 first
  * (device times into ms_per_k, 5 entries, may be NULL); then, for a state of
- * 64..128 KiB, residency in LDS; then, for a state that runs as grouped
- * sweeps, groups of 64 and wave targets of 256 and 4096.  A trial's time is
+ * 64..128 KiB, residency in LDS, and for one of 16..64 KiB, the grouped
+ * sweeps instead (at the tuned k and one wider); then, for a state that runs
+ * as grouped sweeps, groups of 64 and wave targets of 256 and 4096.  A trial's time is
  * the sum of its launches run one work item after another (svb_run_timed),
  * the cost the shape adds to a large batch.  k_max and
  * residency change the arithmetic order (the results stay within the parity
@@ -504,7 +506,8 @@ sv_status svb_autotune(sv_dtype dtype, const sv_circuit *sample, int copies,
 sv_status svb_get_tune(sv_dtype dtype, int ns, int m, svb_tune *out);
 /* Record choices for a shape (e.g. a saved tuning table), as the autotuner
  * would; t->tuned and t->ms are ignored.  SV_ERR_INVALID outside k_max 1..5,
- * group_max 1..256, wave_target >= 1, resident_kib 64 or 128. */
+ * group_max 1..256, wave_target >= 1, resident_kib a power of two up to
+ * 128. */
 sv_status svb_set_tune(sv_dtype dtype, int ns, int m, const svb_tune *t);
 
 const char *sv_last_error(void);

@@ -1235,6 +1235,15 @@ extern "C" sv_status svb_autotune_ex(sv_dtype dtype, const sv_circuit *sample, i
         BatchTune t = best;
         t.resident_kib = (int)(kResidentStateLimit >> 10);
         st = consider(t);
+    } else if (sb >= (size_t(16) << 10) && sb <= kResidentStateMax) {
+        // the other way round: a state of 16..64 KiB through the grouped
+        // sweeps (a residency cut just below it), at the tuned k and one wider
+        for (int dk = 0; dk <= 1 && st == SV_OK; ++dk) {
+            BatchTune t = best;
+            t.resident_kib = (int)(sb >> 11);
+            t.k = best.k + dk;
+            if (t.k <= 5) st = consider(t);
+        }
     }
     bool resident = false;
     batch_lds_bytes(sample->c.n, dtype, &resident, (size_t)best.resident_kib << 10);
@@ -1273,10 +1282,10 @@ extern "C" sv_status svb_set_tune(sv_dtype dtype, int ns, int m, const svb_tune 
 {
     if (!t) return fail(SV_ERR_INVALID, "svb_set_tune: NULL argument");
     if (dtype != SV_C128 && dtype != SV_C64) return fail(SV_ERR_INVALID, "svb_set_tune: bad dtype");
-    if (t->k_max < 1 || t->k_max > 5 || t->group_max < 1 || t->group_max > kMaxGroup || t->wave_target < 1 ||
-        (t->resident_kib != 64 && t->resident_kib != 128))
+    const bool pow2 = t->resident_kib >= 1 && t->resident_kib <= 128 && (t->resident_kib & (t->resident_kib - 1)) == 0;
+    if (t->k_max < 1 || t->k_max > 5 || t->group_max < 1 || t->group_max > kMaxGroup || t->wave_target < 1 || !pow2)
         return fail(SV_ERR_INVALID, "svb_set_tune: k_max 1..5, group_max 1..256, wave_target >= 1, "
-                                    "resident_kib 64 or 128");
+                                    "resident_kib a power of two up to 128");
     BatchTune b;
     b.k = t->k_max;
     b.group_max = t->group_max;

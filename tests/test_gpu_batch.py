@@ -151,7 +151,7 @@ def test_autotune_ex_records_every_choice():
     t, ms = hs.svb_autotune_ex("c64", c, copies=24)
     _say(f"autotune_ex ns=5 m=8 c64: {t}, ms per k={np.round(ms, 4).tolist()}")
     assert 1 <= t["k_max"] <= 5 and t["tuned"] == 1 and t["ms"] > 0 and np.all(ms > 0)
-    assert t["resident_kib"] in (64, 128) and 1 <= t["group_max"] <= 256 and t["wave_target"] >= 1
+    assert t["resident_kib"] in (8, 16, 32, 64, 128) and 1 <= t["group_max"] <= 256 and t["wave_target"] >= 1
     assert hs.svb_get_tune("c64", 5, 8) == dict(t, ms=0.0)
 
 
@@ -190,6 +190,32 @@ def test_tuned_choices_match_oracle(ns, m, dtype, choice):
         hs.svb_set_tune(dtype, ns, m)
     with pytest.raises(hs.HHLSVError, match="INVALID"):
         hs.svb_set_tune(dtype, ns, m, resident_kib=96)
+
+
+# (ns, m, dtype): a state of 64 KiB (c128 n = 12, c64 n = 13), in LDS by default
+@pytest.mark.parametrize("ns,m,dtype", [(3, 8, "c128"), (4, 8, "c64")])
+def test_lds_sized_state_on_sweeps_matches_oracle(ns, m, dtype):
+    """The autotuner's other residency choice: a state that fits in LDS run
+    through the grouped sweeps instead (residency cut at 32 KiB)."""
+    hs = _hs()
+    systems = [W.dc_powerflow(1 << ns, 720 + i) + (m,) for i in range(12)]
+    refs = _oracle_refs(systems[:2])
+    try:
+        for kw, kind in ((dict(resident_kib=32), "swept"), ({}, "batched")):
+            hs.svb_set_tune(dtype, ns, m, k_max=4, **kw)
+            bt = hs.Batch(dtype, 0)
+            for A, b, mm in systems:
+                bt.add(hs.circuit_build_hhl(A, b, mm, device_evolutions=True))
+            items = bt.run_timed()
+            assert {it["kind"] for it in items} == {kind}
+            bt.run()
+            for i, ref in enumerate(refs):
+                x_hat, _ = bt.solution(i)
+                y, p1 = bt.postselected(i)
+                check_instance(y, p1, x_hat, ref, dtype, (kind, i))
+            bt.close()
+    finally:
+        hs.svb_set_tune(dtype, ns, m)
 
 
 def test_run_timed_ops_covers_every_swept_op():
