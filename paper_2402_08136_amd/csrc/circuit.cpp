@@ -182,6 +182,7 @@ namespace {
 struct Block {
     std::vector<int> qubits;     // sorted
     std::vector<cd> M;           // dense: 2^k x 2^k over sorted qubits
+    std::vector<cd> dv;          // a merged diagonal block: its 2^k entries (M unused)
     bool diag = true;
     bool open = true;            // false: a gate too wide to fuse, kept as is
     bool alive = true;
@@ -271,6 +272,77 @@ void merge_disjoint(std::vector<Block> &blocks, int n, int k_max)
             }
         }
         for (int q : bj.qubits) last[q] = j;
+    }
+}
+
+// Third pass: diagonal blocks merge with each other past everything they
+// commute with, up to kDiagFuseMax qubits (beyond k_max: a diagonal costs
+// one sweep whatever its width, its table 2^k entries).  The inverse QFT's
+// controlled phases, for instance, come out of the first passes as runs of
+// 5-qubit diagonals on the clock register between its Hadamards.
+constexpr int kDiagFuseMax = 10;
+constexpr int kDiagLookback = 64;
+
+// Whether a diagonal operator on the sorted qubits dq commutes with block b:
+// b is diagonal, or every qubit it shares with dq is one b only reads as a
+// control (a controlled dense gate's control, a uniformly controlled
+// rotation's controls: both are block-diagonal in those qubits' basis).
+bool diag_commutes(const std::vector<int> &dq, const Block &b)
+{
+    if (b.open ? b.diag : gate_is_diagonal(b.orig.kind)) return true;
+    std::vector<int> moved = b.qubits;   // qubits b does not act on diagonally
+    if (!b.open && b.orig.kind == SV_GATE_CDENSE) moved.assign(b.orig.qubits.begin() + 1, b.orig.qubits.end());
+    if (!b.open && b.orig.kind == SV_GATE_UCRY) moved.assign(1, b.orig.qubits[0]);
+    for (int q : moved)
+        if (std::binary_search(dq.begin(), dq.end(), q)) return false;
+    return true;
+}
+
+// The diagonal entries of an open diagonal block (index bit l = qubits[l]).
+std::vector<cd> diag_entries(const Block &b)
+{
+    if (!b.dv.empty()) return b.dv;
+    const size_t D = (size_t)1 << b.qubits.size();
+    std::vector<cd> d(D);
+    for (size_t i = 0; i < D; ++i) d[i] = b.M[i * D + i];
+    return d;
+}
+
+void merge_diagonals(std::vector<Block> &blocks)
+{
+    for (int j = 0; j < (int)blocks.size(); ++j) {
+        Block &bj = blocks[j];
+        if (!bj.alive || !bj.open || !bj.diag) continue;
+        int seen = 0;
+        for (int i = j - 1; i >= 0 && seen < kDiagLookback; --i) {
+            Block &bi = blocks[i];
+            if (!bi.alive) continue;
+            ++seen;
+            if (bi.open && bi.diag) {
+                const std::vector<int> U = unite(bi.qubits, bj.qubits);
+                if ((int)U.size() <= kDiagFuseMax) {
+                    // bj commutes with every block between: apply it right
+                    // after bi, i.e. multiply the two diagonals entry by entry
+                    const std::vector<cd> di = diag_entries(bi), dj = diag_entries(bj);
+                    auto index_in = [&](const std::vector<int> &qs, size_t R) {
+                        size_t r = 0;
+                        for (size_t l = 0; l < qs.size(); ++l) {
+                            const size_t p = std::find(U.begin(), U.end(), qs[l]) - U.begin();
+                            r |= ((R >> p) & 1) << l;
+                        }
+                        return r;
+                    };
+                    std::vector<cd> d((size_t)1 << U.size());
+                    for (size_t R = 0; R < d.size(); ++R) d[R] = dj[index_in(bj.qubits, R)] * di[index_in(bi.qubits, R)];
+                    bi.dv = std::move(d);
+                    bi.M.clear();
+                    bi.qubits = U;
+                    bj.alive = false;
+                    break;
+                }
+            }
+            if (!diag_commutes(bj.qubits, bi)) break;
+        }
     }
 }
 
@@ -473,6 +545,7 @@ extern "C" sv_status fuse(const sv_circuit *in, int k_max, sv_circuit **out)
     }
 
     merge_disjoint(blocks, n, k_max);
+    merge_diagonals(blocks);
 
     auto *oc = new (std::nothrow) sv_circuit;
     if (!oc) return fail(SV_ERR_OOM, "fuse: out of host memory");
@@ -490,9 +563,10 @@ extern "C" sv_status fuse(const sv_circuit *in, int k_max, sv_circuit **out)
         if (b.diag) {
             g.kind = SV_GATE_DIAG;
             g.params.resize(2 * D);
+            const std::vector<cd> d = diag_entries(b);
             for (size_t i = 0; i < D; ++i) {
-                g.params[2 * i] = b.M[i * D + i].real();
-                g.params[2 * i + 1] = b.M[i * D + i].imag();
+                g.params[2 * i] = d[i].real();
+                g.params[2 * i + 1] = d[i].imag();
             }
         } else {
             g.kind = SV_GATE_DENSE;

@@ -160,16 +160,47 @@ def test_fusion_preserves_unitary(n, seed, k):
     c = hs.circuit_from_gates(n, gates)
     f = hs.fuse(c, k)
     assert f.n_gates <= c.n_gates
-    wide_in = sum(len(g.qubits) > k for g in gates)
+    diagonal = ("rz", "p", "cp", "diag")
+    wide_in = sum(len(g.qubits) > k and g.kind not in diagonal for g in gates)
     wide_out = 0
     for kind, qs, ps in f.gates():
         if len(qs) <= k:
             assert kind in ("dense", "diag") and qs == sorted(qs)
+        elif kind in diagonal:
+            assert len(qs) <= 10    # passed through, or diagonals merged past k_max
         else:
             wide_out += 1          # too wide to fuse: passed through unchanged
     assert wide_out == wide_in
     psi = W.random_state(n, seed)
     assert max_abs_diff(np_run(f, psi), np_run(c, psi)) < 1e-13
+
+
+def test_diagonals_merge_past_commuting_gates():
+    """Diagonal blocks merge beyond k_max (up to 10 qubits) past gates they
+    commute with: gates on other qubits and gates that read the shared
+    qubits only as controls; a gate acting on a shared qubit stops them."""
+    n, k = 7, 2
+    U = W.random_unitary(4, np.random.default_rng(5))
+    cd_params = np.stack([U.real, U.imag], -1).ravel()
+    gates = [W.Gate("cp", (2, 3), np.array([0.3])),
+             W.Gate("h", (5,), np.array([])),
+             W.Gate("cdense", (4, 0, 1), cd_params),          # control 4
+             W.Gate("cp", (4, 6), np.array([0.5])),
+             W.Gate("ucry", (0, 5, 6), np.array([0.1, 0.2, 0.3, 0.4])),   # controls 5, 6
+             W.Gate("cp", (5, 6), np.array([0.7])),
+             W.Gate("h", (2,), np.array([])),                 # joins cp(2, 3) into a dense block
+             W.Gate("cp", (2, 4), np.array([1.1]))]
+    c = hs.circuit_from_gates(n, gates)
+    f = hs.fuse(c, k)
+    diags = [qs for kind, qs, _ in f.gates() if kind == "diag"]
+    # cp(5, 6) moves back past the UCRY it only controls and joins cp(4, 6)
+    # (3 qubits, above k_max = 2); cp(2, 4) cannot pass the H on qubit 2
+    assert diags == [[4, 5, 6], [2, 4]]
+    psi = W.random_state(n, 5)
+    assert max_abs_diff(np_run(f, psi), np_run(c, psi)) < 1e-13
+    g = hs.fuse(c, 5)        # wide enough that the first passes merge more
+    psi2 = W.random_state(n, 6)
+    assert max_abs_diff(np_run(g, psi2), np_run(c, psi2)) < 1e-13
 
 
 @pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
