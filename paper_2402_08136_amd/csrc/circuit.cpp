@@ -470,11 +470,45 @@ extern "C" sv_status fuse(const sv_circuit *in, int k_max, sv_circuit **out)
     *out = nullptr;
     if (k_max < 1 || k_max > 5) return fail(SV_ERR_INVALID, "fuse: k_max must be in [1, 5]");
     const int n = in->c.n;
+    // SWAP gates become a relabelling of the qubits instead of a sweep: the
+    // gates after a swap are applied with its two qubits exchanged (an exact
+    // permutation of the amplitudes).  Whatever permutation remains at the
+    // end is undone by swaps, so the fused circuit leaves every amplitude
+    // where the input circuit does; in HHL the inverse QFT's swap layer and
+    // the QFT's cancel, and no swap is left.
+    std::vector<Gate> gates;
+    gates.reserve(in->c.gates.size());
+    {
+        std::vector<int> phys(n);   // logical qubit -> where its data is
+        for (int q = 0; q < n; ++q) phys[q] = q;
+        for (const Gate &g : in->c.gates) {
+            if (g.kind == SV_GATE_SWAP) {
+                std::swap(phys[g.qubits[0]], phys[g.qubits[1]]);
+                continue;
+            }
+            Gate r = g;
+            for (int &q : r.qubits) q = phys[q];
+            gates.push_back(std::move(r));
+        }
+        std::vector<int> logical(n);   // data position -> logical qubit
+        for (int q = 0; q < n; ++q) logical[phys[q]] = q;
+        for (int p = 0; p < n; ++p) {
+            while (logical[p] != p) {
+                // move logical qubit logical[p] home to position logical[p]
+                const int q = logical[p];
+                Gate sw;
+                sw.kind = SV_GATE_SWAP;
+                sw.qubits = {p, q};
+                gates.push_back(sw);
+                std::swap(logical[p], logical[q]);
+            }
+        }
+    }
     std::vector<Block> blocks;
-    blocks.reserve(in->c.gates.size());
+    blocks.reserve(gates.size());
     std::vector<int> last(n, -1);
 
-    for (const Gate &g0 : in->c.gates) {
+    for (const Gate &g0 : gates) {
         const int w = fused_width(g0);
         Gate tmp;
         if (w <= k_max && gate_deferred(g0)) {  // merged on the host: build its matrix here

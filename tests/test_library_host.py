@@ -161,16 +161,19 @@ def test_fusion_preserves_unitary(n, seed, k):
     f = hs.fuse(c, k)
     assert f.n_gates <= c.n_gates
     diagonal = ("rz", "p", "cp", "diag")
-    wide_in = sum(len(g.qubits) > k and g.kind not in diagonal for g in gates)
-    wide_out = 0
+    wide_in = sum(len(g.qubits) > k and g.kind not in diagonal + ("swap",) for g in gates)
+    wide_out = swaps_out = 0
     for kind, qs, ps in f.gates():
         if len(qs) <= k:
             assert kind in ("dense", "diag") and qs == sorted(qs)
         elif kind in diagonal:
             assert len(qs) <= 10    # passed through, or diagonals merged past k_max
+        elif kind == "swap":
+            swaps_out += 1          # what is left of the relabelling, at the end
         else:
-            wide_out += 1          # too wide to fuse: passed through unchanged
+            wide_out += 1          # too wide to fuse: passed through unchanged (qubits relabelled)
     assert wide_out == wide_in
+    assert swaps_out <= min(n - 1, sum(g.kind == "swap" for g in gates))
     psi = W.random_state(n, seed)
     assert max_abs_diff(np_run(f, psi), np_run(c, psi)) < 1e-13
 
@@ -201,6 +204,42 @@ def test_diagonals_merge_past_commuting_gates():
     g = hs.fuse(c, 5)        # wide enough that the first passes merge more
     psi2 = W.random_state(n, 6)
     assert max_abs_diff(np_run(g, psi2), np_run(c, psi2)) < 1e-13
+
+
+def test_swaps_become_relabelling():
+    """SWAP gates cost no sweep: later gates take the exchanged qubits, and
+    the permutation left at the end is undone by as few swaps as it needs
+    (none when the swaps cancel, as the two QFT swap layers of HHL do)."""
+    n = 5
+    rng = np.random.default_rng(9)
+    U = W.random_unitary(4, rng)
+    gates = [W.Gate("h", (0,), np.array([])), W.Gate("swap", (0, 3), np.array([])),
+             W.Gate("dense", (3, 1), np.stack([U.real, U.imag], -1).ravel()),
+             W.Gate("swap", (1, 4), np.array([])), W.Gate("cx", (4, 2), np.array([])),
+             W.Gate("ry", (1,), np.array([0.4]))]
+    c = hs.circuit_from_gates(n, gates)
+    for k in (1, 2, 3):
+        f = hs.fuse(c, k)
+        psi = W.random_state(n, k)
+        assert max_abs_diff(np_run(f, psi), np_run(c, psi)) < 1e-13
+        # the two swaps form a 3-cycle (0 3)(1 4): two restoring swaps at most
+        assert sum(kind == "swap" for kind, _, _ in f.gates()) <= 2
+    # h(0), swap(0, 3), rz(3), swap(3, 0): the rz lands on qubit 0 and joins the h
+    cancel = gates[:2] + [W.Gate("rz", (3,), np.array([0.2])), W.Gate("swap", (3, 0), np.array([]))]
+    cc = hs.circuit_from_gates(n, cancel)
+    f = hs.fuse(cc, 1)
+    assert [(kind, qs) for kind, qs, _ in f.gates()] == [("dense", [0])]
+    psi = W.random_state(n, 4)
+    assert max_abs_diff(np_run(f, psi), np_run(cc, psi)) < 1e-13
+    A, b = W.dc_powerflow(16, 3)
+    hc = hs.circuit_build_hhl(A, b, 6)
+    assert any(kind == "swap" for kind, _, _ in hc.gates())
+    for k in (2, 5):
+        fk = hs.fuse(hc, k)
+        assert all(kind != "swap" for kind, _, _ in fk.gates())
+        psi = np.zeros(1 << hc.n_qubits, dtype=complex)
+        psi[0] = 1
+        assert max_abs_diff(np_run(fk, psi), np_run(hc, psi)) < 1e-12
 
 
 @pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
