@@ -414,8 +414,8 @@ sv_status svb_destroy(svb *bt);
 enum {
     SVS_OPT_PREP_THREADS = 1,  /* host build threads (default min(8, cores/2)) */
     SVS_OPT_K_MAX = 2,         /* fusion width (0: the tuned width for batched
-                                  shapes; for the others 3 below 20 qubits,
-                                  4 from 20; default 0)                       */
+                                  shapes; for the others 3 below 18 qubits,
+                                  5 from 18; default 0)                       */
     SVS_OPT_MAX_BATCH = 3,     /* requests per batched launch (default 256)      */
     SVS_OPT_STREAMS = 4,       /* micro-batches in flight (default 8)            */
     SVS_OPT_QUEUE_LIMIT = 5,   /* queued, not yet admitted requests              */

@@ -65,12 +65,13 @@ __global__ __launch_bounds__(256) void k_gather_outputs(const BInst *__restrict_
 // batched launch with its state in HBM (one workgroup per request), or alone
 // through the whole-GPU sweep kernels.
 enum { kBatchLds = 0, kBatchHbm = 1, kAlone = 2 };
-// Fusion width for kAlone requests when k_max is automatic.  Below 20 qubits
+// Fusion width for kAlone requests when k_max is automatic.  Below 18 qubits
 // a launch has few tiles and the wider gate's arithmetic is not hidden: over
-// a sample of the serving mix, k = 3 took 0.28 ms of kernel time per 10-qubit
-// request against 0.54 ms at k = 4, and stayed ahead up to 19 qubits; from
-// 20 qubits k = 4 is ahead (3.58 against 3.80 ms at 21 qubits).
-inline int alone_k(int n) { return n >= 20 ? 4 : 3; }
+// 315 requests of the serving mix run one at a time, k = 3 took 0.20 ms of
+// kernel time per 10-qubit request against 0.23 at k = 4 and 0.24 at k = 5,
+// and stayed ahead up to 17 qubits; from 18 qubits k = 5 is ahead (0.91
+// against 0.97 ms at 18, 2.08 against 2.21 ms at 21, complex128).
+inline int alone_k(int n) { return n >= 18 ? 5 : 3; }
 
 struct Req {
     uint64_t ticket = 0;
