@@ -80,8 +80,15 @@ typedef enum {
     SV_GATE_UCRY = 11,  /* qubits (t, c_0..c_{r-1}), r <= 20; params: 2^r
                            angles; RY(angle[v]) on t where v = sum_l
                            bit(c_l) 2^l                                   */
-    SV_GATE_DIAG = 12   /* qubits (q_0..q_{k-1}), k <= 12; params: 2^k
+    SV_GATE_DIAG = 12,  /* qubits (q_0..q_{k-1}), k <= 12; params: 2^k
                            complex diagonal entries (2 * 2^k doubles)     */
+    SV_GATE_MUX2 = 13   /* qubits (c_0, c_1, q_0..q_{k-1}), k <= 12;
+                           params: three 2^k x 2^k matrices (as DENSE),
+                           U_1, U_2, U_3, where U_v acts on the targets
+                           where bit(c_0) + 2 bit(c_1) = v; identity
+                           where both are 0.  fuse() makes it from two
+                           controlled dense gates on the same targets
+                           (U_1, U_2 and their product)                   */
 } sv_gate_kind;
 
 typedef struct sv_state sv_state;      /* device state vector + stream   */
@@ -368,8 +375,8 @@ sv_status svb_run_timed(svb *bt, int cap, int *items, int *kind, int *n,
  * a breakdown of the sweeps by kernel family.  For entry i < *count (one per
  * op of every group, groups in svb_run_timed's item order): item[i] the
  * group's item index in svb_run_timed, family[i] the sv_kernel_family used,
- * k[i] the op's targets (UCRY: controls), controlled[i] 1 for a wide gate
- * with a control qubit, ms[i] device time.  Arrays hold cap entries;
+ * k[i] the op's targets (UCRY: controls), controlled[i] the control qubits
+ * of a wide gate (0, 1, or 2 for a MUX2 gate), ms[i] device time.  Arrays hold cap entries;
  * SV_ERR_INVALID (with *count set) if cap is too small.  The outputs it
  * leaves are not a run's results: call svb_run afterwards. */
 sv_status svb_run_timed_ops(svb *bt, int cap, int *count, int *item, int *family,

@@ -30,7 +30,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 C128, C64 = 0, 1
 DTYPES = {"c128": C128, "c64": C64, C128: C128, C64: C64}
 KIND = {"h": 0, "x": 1, "ry": 2, "rz": 3, "p": 4, "u3": 5, "cx": 6, "cp": 7,
-        "swap": 8, "dense": 9, "cdense": 10, "ucry": 11, "diag": 12}
+        "swap": 8, "dense": 9, "cdense": 10, "ucry": 11, "diag": 12, "mux2": 13}
 KIND_NAME = {v: k for k, v in KIND.items()}
 KERNEL_FAMILY = {0: "dense_direct", 1: "dense_lds", 2: "dense_small", 3: "diag",
                  4: "wide", 5: "ucry", 6: "dense_bfly", 7: "dense_mfma"}
@@ -522,7 +522,7 @@ class Batch:
 
     def run_timed_ops(self, cap: int = 65536):
         """Each fused op of the grouped sweeps timed on its own: a list of
-        dicts (item, family, k, controlled, ms); run() afterwards for results."""
+        dicts (item, family, k, controls, ms); run() afterwards for results."""
         count = ctypes.c_int()
         item, fam, k, ctl = (np.zeros(cap, dtype=np.int32) for _ in range(4))
         ms = np.zeros(cap)
@@ -530,7 +530,7 @@ class Batch:
                                       fam.ctypes.data_as(_ip), k.ctypes.data_as(_ip), ctl.ctypes.data_as(_ip),
                                       _dptr(ms)), "svb_run_timed_ops")
         return [{"item": int(item[i]), "family": KERNEL_FAMILY[int(fam[i])], "k": int(k[i]),
-                 "controlled": bool(ctl[i]), "ms": float(ms[i])} for i in range(count.value)]
+                 "controls": int(ctl[i]), "ms": float(ms[i])} for i in range(count.value)]
 
     def solution(self, index: int):
         dim = self.dims[index]

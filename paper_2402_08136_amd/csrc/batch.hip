@@ -156,11 +156,39 @@ __device__ void b_wide(C *psi, int n, const BOp &op, const C *UT)
         return;
     }
     constexpr int RW = 4;
-    const uint32_t ngroups = 1u << (n - k - (op.control >= 0 ? 1 : 0));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int lpr = D < 64 ? D : 64, rps = 64 / lpr;
     const int j0 = lane % lpr, sub = lane / lpr;
     const int CT = D > 64 ? D / 64 : 1;
+    // a MUX2 op (two controls, up to 64 columns): three blocks of rows, for
+    // control values 1..3, each padded to a whole number of wave steps
+    const bool mux = op.control2 >= 0;
+    const uint32_t g0 = 1u << (n - k - (mux ? 2 : op.control >= 0 ? 1 : 0));
+    const uint32_t step_rows = (uint32_t)(RW * rps);
+    const uint32_t g0p = mux && g0 < step_rows ? step_rows : g0;
+    const uint32_t ngroups = mux ? 3 * g0p : g0;
+    auto mux_base = [&](uint32_t g, bool *real) -> uint32_t {
+        const uint32_t v = 1 + g / g0p, r = g % g0p;
+        *real = r < g0 && g < ngroups;
+        const int lo = op.control < op.control2 ? op.control : op.control2;
+        const int hi = op.control < op.control2 ? op.control2 : op.control;
+        uint32_t b = r;
+        bool pl = false, ph = false;
+        for (int j = 0; j < k; ++j) {
+            if (!pl && lo < op.q[j]) {
+                b = insert_zero32(b, lo);
+                pl = true;
+            }
+            if (!ph && hi < op.q[j]) {
+                b = insert_zero32(b, hi);
+                ph = true;
+            }
+            b = insert_zero32(b, op.q[j]);
+        }
+        if (!pl) b = insert_zero32(b, lo);
+        if (!ph) b = insert_zero32(b, hi);
+        return b | ((v & 1u) << op.control) | ((v >> 1) << op.control2);
+    };
     auto off = [&](uint32_t c) -> uint32_t {
         if (op.contiguous) return c << op.q[0];
         uint32_t o = 0;
@@ -180,15 +208,22 @@ __device__ void b_wide(C *psi, int n, const BOp &op, const C *UT)
         if (!placed) b = insert_zero32(b, op.control) | (1u << op.control);
         return b;
     };
-    const uint32_t step = (uint32_t)(RW * rps);
+    const uint32_t step = step_rows;
     for (uint32_t rb = (uint32_t)wave * step; rb < ngroups; rb += (uint32_t)nw * step) {
         uint32_t gb[RW];
         bool ok[RW];
+        // MUX2: the step's rows lie in one block, which selects the matrix
+        const C *Uv = mux ? UT + (size_t)(rb / g0p) * D * D : UT;
 #pragma unroll
         for (int r = 0; r < RW; ++r) {
             const uint32_t g = rb + sub + (uint32_t)rps * r;
-            ok[r] = g < ngroups;
-            gb[r] = ok[r] ? gbase(g) : 0;
+            if (mux) {
+                gb[r] = mux_base(g, &ok[r]);
+                if (!ok[r]) gb[r] = 0;
+            } else {
+                ok[r] = g < ngroups;
+                gb[r] = ok[r] ? gbase(g) : 0;
+            }
         }
         C acc[RW][4];
 #pragma unroll
@@ -200,7 +235,7 @@ __device__ void b_wide(C *psi, int n, const BOp &op, const C *UT)
             const uint32_t oc = off(c);
             C u[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) u[t] = t < CT ? UT[c * D + j0 + 64 * t] : C{0, 0};
+            for (int t = 0; t < 4; ++t) u[t] = t < CT ? Uv[c * D + j0 + 64 * t] : C{0, 0};
 #pragma unroll
             for (int r = 0; r < RW; ++r) {
                 const C x = ok[r] ? psi[gb[r] | oc] : C{0, 0};
@@ -340,7 +375,7 @@ void lower_for_batch(const Circuit &f, sv_dtype dtype, std::vector<BOp> &ops, st
             if (L.deferred != (pass == 1)) continue;
             bytes = (bytes + 255) & ~size_t(255);
             offs[i] = bytes;
-            bytes += (L.deferred ? ((size_t)1 << (2 * L.op.k)) : L.table.size()) * as;
+            bytes += (L.deferred ? deferred_entries(L) : L.table.size()) * as;
         }
     }
     *device_bytes = std::max((bytes + 255) & ~size_t(255), tables.size());
@@ -352,20 +387,15 @@ void lower_for_batch(const Circuit &f, sv_dtype dtype, std::vector<BOp> &ops, st
         op.k = L.op.k;
         op.target = L.op.target;
         op.control = L.op.control;
+        op.control2 = L.op.control2;
         for (int j = 0; j < L.op.k; ++j) op.q[j] = L.op.q[j];
         op.contiguous = 1;
         for (int j = 1; j < L.op.k; ++j)
             if (op.q[j] != op.q[0] + j) op.contiguous = 0;
         const size_t off = offs[li];
         if (L.deferred) {
-            EvoJob jb;
-            std::memset(&jb, 0, sizeof(jb));
-            jb.out_off = off;
-            jb.D = 1 << L.op.k;
-            jb.j = L.evo_j;
-            jb.inv = L.evo_inv ? 1 : 0;
-            jb.t = f.hhl.spec->t;
-            evo.push_back(jb);
+            for (const EvoJob &jb : evolution_jobs(L, f.hhl.spec->t, off, ((size_t)1 << (2 * L.op.k)) * as))
+                evo.push_back(jb);
         } else {
             unsigned char *dst = tables.data() + off;
             const std::vector<cd> &tab = L.table;   // OP_WIDE tables hold U^T
@@ -555,6 +585,7 @@ std::vector<DevOp> swept_ops(const svb *b, const svb::Meta &in)
         for (int j = 0; j < kMaxUcryControls; ++j) d.q[j] = bo.q[j];
         d.target = bo.target;
         d.control = bo.control;
+        d.control2 = bo.control2;
         d.off = bo.off - in.tab_base;
     }
     return ops;
@@ -565,7 +596,8 @@ bool same_ops(const std::vector<DevOp> &x, const std::vector<DevOp> &y)
     if (x.size() != y.size()) return false;
     for (size_t i = 0; i < x.size(); ++i) {
         const DevOp &a = x[i], &c = y[i];
-        if (a.type != c.type || a.k != c.k || a.target != c.target || a.control != c.control || a.off != c.off)
+        if (a.type != c.type || a.k != c.k || a.target != c.target || a.control != c.control ||
+            a.control2 != c.control2 || a.off != c.off)
             return false;
         for (int j = 0; j < a.k; ++j)
             if (a.q[j] != c.q[j]) return false;
@@ -1046,7 +1078,7 @@ extern "C" sv_status svb_run_timed_ops(svb *b, int cap, int *count, int *item, i
             const DevOp &op = sw.ops[o];
             item[at] = nclass + (int)gi;
             k[at] = op.k;
-            controlled[at] = op.type == OP_WIDE && op.control >= 0;
+            controlled[at] = op.type == OP_WIDE ? (op.control >= 0) + (op.control2 >= 0) : 0;
             ls = launch_op_group(op, g, sw.n, b->dtype, b->stream, &family[at]);
             if (ls == SV_OK) e = hipEventRecord(ev[at + 1], b->stream);
         }

@@ -56,7 +56,7 @@ static int gate_width(int kind)
 sv_status validate_gate(int n, int kind, const int *qubits, int nq,
                         const double *params, int nparams)
 {
-    if (kind < SV_GATE_H || kind > SV_GATE_DIAG)
+    if (kind < SV_GATE_H || kind > SV_GATE_MUX2)
         return fail(SV_ERR_INVALID, "circuit_add_gate: unknown gate kind");
     if (nq < 1 || !qubits) return fail(SV_ERR_INVALID, "circuit_add_gate: no qubits");
     if (nparams < 0 || (nparams > 0 && !params))
@@ -85,6 +85,13 @@ sv_status validate_gate(int n, int kind, const int *qubits, int nq,
         const int k = nq - 1;
         if (k < 1 || k > kMaxDenseQubits) return fail(SV_ERR_INVALID, "circuit_add_gate: CDENSE needs 1..12 targets");
         if (nparams != (2L << (2 * k))) return fail(SV_ERR_INVALID, "circuit_add_gate: params must hold the complex matrix");
+        return SV_OK;
+    }
+    if (kind == SV_GATE_MUX2) {
+        const int k = nq - 2;
+        if (k < 1 || k > kMaxDenseQubits) return fail(SV_ERR_INVALID, "circuit_add_gate: MUX2 needs 1..12 targets");
+        if (nparams != 3 * (2L << (2 * k)))
+            return fail(SV_ERR_INVALID, "circuit_add_gate: MUX2 params must hold three complex matrices");
         return SV_OK;
     }
     // UCRY
@@ -135,6 +142,20 @@ std::vector<cd> gate_matrix(const Gate &g)
             M[(2 * r) * D + 2 * r] = 1.0;
             for (size_t c = 0; c < K; ++c)
                 M[(2 * r + 1) * D + (2 * c + 1)] = cd(p[2 * (r * K + c)], p[2 * (r * K + c) + 1]);
+        }
+        return M;
+    }
+    case SV_GATE_MUX2: {  // block-diag(I, U_1, U_2, U_3) over (c0, c1, targets): r = v + 4 r_t
+        const int k = (int)g.qubits.size() - 2;
+        const size_t K = (size_t)1 << k, D = 4 * K;
+        std::vector<cd> M(D * D, 0.0);
+        for (size_t r = 0; r < K; ++r) {
+            M[(4 * r) * D + 4 * r] = 1.0;
+            for (size_t v = 1; v < 4; ++v)
+                for (size_t c = 0; c < K; ++c) {
+                    const size_t at = 2 * ((v - 1) * K * K + r * K + c);
+                    M[(4 * r + v) * D + (4 * c + v)] = cd(p[at], p[at + 1]);
+                }
         }
         return M;
     }
@@ -346,6 +367,76 @@ void merge_diagonals(std::vector<Block> &blocks)
     }
 }
 
+// Last pass: two controlled dense gates in a row on the same targets (the
+// controlled e^{iAt 2^j} of phase estimation) become one MUX2 gate: one
+// sweep instead of two, over three quarters of the state (control values
+// 1..3) instead of two halves.  Up to kMuxMaxTargets targets.
+constexpr int kMuxMaxTargets = 6;
+
+void merge_controlled_pairs(std::vector<Block> &blocks, const HHLParams &h)
+{
+    int prev = -1;   // the previous live block, when it is a candidate
+    for (int j = 0; j < (int)blocks.size(); ++j) {
+        Block &bj = blocks[j];
+        if (!bj.alive) continue;
+        const Gate &b = bj.orig;
+        const int nt = (int)b.qubits.size() - 1;
+        const bool cand = !bj.open && b.kind == SV_GATE_CDENSE && nt >= 2 && nt <= kMuxMaxTargets;
+        if (cand && prev >= 0) {
+            Block &bi = blocks[prev];
+            const Gate &a = bi.orig;
+            const bool same_targets = a.qubits.size() == b.qubits.size() &&
+                                      std::equal(a.qubits.begin() + 1, a.qubits.end(), b.qubits.begin() + 1);
+            const bool both_deferred = gate_deferred(a) && gate_deferred(b) && a.evo_inv == b.evo_inv;
+            const bool neither_deferred = !gate_deferred(a) && !gate_deferred(b);
+            if (same_targets && a.qubits[0] != b.qubits[0] && (both_deferred || neither_deferred)) {
+                Gate m;
+                m.kind = SV_GATE_MUX2;
+                m.qubits = {a.qubits[0], b.qubits[0]};
+                m.qubits.insert(m.qubits.end(), a.qubits.begin() + 1, a.qubits.end());
+                const bool evolutions = a.evo_j >= 0 && b.evo_j >= 0 && a.evo_inv == b.evo_inv && h.spec;
+                if (both_deferred) {
+                    m.evo_j = a.evo_j;
+                    m.evo_j2 = b.evo_j;
+                    m.evo_inv = a.evo_inv;
+                } else if (evolutions) {
+                    // U_3 = e^{iAt (2^ja + 2^jb)} from the eigen-decomposition,
+                    // as the device builds it for the deferred form
+                    m.params = a.params;
+                    m.params.insert(m.params.end(), b.params.begin(), b.params.end());
+                    const std::vector<double> u3 =
+                        evolution_params_pow(*h.spec, std::ldexp(1.0, a.evo_j) + std::ldexp(1.0, b.evo_j), a.evo_inv);
+                    m.params.insert(m.params.end(), u3.begin(), u3.end());
+                    m.evo_j = a.evo_j;
+                    m.evo_j2 = b.evo_j;
+                    m.evo_inv = a.evo_inv;
+                } else {
+                    // U_1 = U_a, U_2 = U_b, U_3 = U_b U_a (a acts first)
+                    const size_t K = (size_t)1 << (a.qubits.size() - 1);
+                    std::vector<cd> ua(K * K), ub(K * K);
+                    for (size_t i = 0; i < K * K; ++i) {
+                        ua[i] = cd(a.params[2 * i], a.params[2 * i + 1]);
+                        ub[i] = cd(b.params[2 * i], b.params[2 * i + 1]);
+                    }
+                    const std::vector<cd> uc = matmul(ub, ua, K);
+                    const std::vector<cd> *mats[3] = {&ua, &ub, &uc};
+                    for (const std::vector<cd> *u : mats)
+                        for (const cd &x : *u) {
+                            m.params.push_back(x.real());
+                            m.params.push_back(x.imag());
+                        }
+                }
+                bi.orig = std::move(m);
+                bi.qubits = unite(bi.qubits, bj.qubits);
+                bj.alive = false;
+                prev = -1;
+                continue;
+            }
+        }
+        prev = cand ? j : -1;
+    }
+}
+
 int fused_width(const Gate &g)
 {
     return (int)g.qubits.size();
@@ -431,7 +522,8 @@ extern "C" sv_status circuit_serialize(const sv_circuit *c, void *buf, size_t *l
     size_t need = 8;
     for (const auto &g : c->c.gates) {
         size_t np = g.params.size();
-        if (gate_deferred(g)) np = (size_t)2 << (2 * (g.qubits.size() - 1));
+        if (gate_deferred(g))
+            np = (size_t)gate_matrices(g) * ((size_t)2 << (2 * (g.qubits.size() - gate_controls(g))));
         need += 12 + 4 * g.qubits.size() + 8 * np;
     }
     if (!buf) {
@@ -580,6 +672,7 @@ extern "C" sv_status fuse(const sv_circuit *in, int k_max, sv_circuit **out)
 
     merge_disjoint(blocks, n, k_max);
     merge_diagonals(blocks);
+    merge_controlled_pairs(blocks, in->c.hhl);
 
     auto *oc = new (std::nothrow) sv_circuit;
     if (!oc) return fail(SV_ERR_OOM, "fuse: out of host memory");

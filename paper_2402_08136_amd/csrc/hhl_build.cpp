@@ -250,8 +250,13 @@ void add_qft(Circuit &c, int q0, int m, bool inverse)
 // b >= a is accumulated (rows of Vt are contiguous: AXPY over b) and mirrored.
 std::vector<double> evolution_params(const Spectral &sp, int j, bool inverse)
 {
+    return evolution_params_pow(sp, std::ldexp(1.0, j), inverse);
+}
+
+std::vector<double> evolution_params_pow(const Spectral &sp, double p, bool inverse)
+{
     const int D = sp.D;
-    const double tj = sp.t * std::ldexp(1.0, j);
+    const double tj = sp.t * p;
     std::vector<double> cs(D), sn(D);
     for (int k = 0; k < D; ++k) {
         const double ph = std::fmod(sp.w[k] * tj, 2.0 * kPi);
@@ -283,6 +288,14 @@ std::vector<double> evolution_params(const Spectral &sp, int j, bool inverse)
 void materialize(Gate &g, const HHLParams &h)
 {
     if (!gate_deferred(g) || !h.spec) return;
+    if (g.kind == SV_GATE_MUX2) {
+        const double p1 = std::ldexp(1.0, g.evo_j), p2 = std::ldexp(1.0, g.evo_j2);
+        for (double p : {p1, p2, p1 + p2}) {
+            const std::vector<double> u = evolution_params_pow(*h.spec, p, g.evo_inv);
+            g.params.insert(g.params.end(), u.begin(), u.end());
+        }
+        return;
+    }
     g.params = evolution_params(*h.spec, g.evo_j, g.evo_inv);
 }
 

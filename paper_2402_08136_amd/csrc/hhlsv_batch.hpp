@@ -15,7 +15,7 @@ struct BOp {
     int control;     // OP_WIDE control, -1 = none
     int contiguous;  // targets (UCRY: controls) are q[0], q[0]+1, ...
     int q[kMaxUcryControls];
-    int pad;
+    int control2;    // OP_WIDE second control (MUX2: tables for control values 1..3), -1 = none
     unsigned long long off;   // byte offset of the op's table in the instance's tables
 };
 

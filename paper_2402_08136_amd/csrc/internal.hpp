@@ -33,9 +33,16 @@ struct Gate {
     // (on the device when applied, on the host by materialize()).
     int evo_j = -1;
     bool evo_inv = false;
+    // MUX2 of two evolution gates: the second control's j (U_1 = e^{iAt 2^j},
+    // U_2 = e^{iAt 2^j2}, U_3 = e^{iAt (2^j + 2^j2)}).
+    int evo_j2 = -1;
 };
 
 inline bool gate_deferred(const Gate &g) { return g.evo_j >= 0 && g.params.empty(); }
+// Matrices a MUX2 gate carries (one for every other gate with a matrix).
+inline int gate_matrices(const Gate &g) { return g.kind == SV_GATE_MUX2 ? 3 : 1; }
+// Targets of a CDENSE (one control) or MUX2 (two controls) gate.
+inline int gate_controls(const Gate &g) { return g.kind == SV_GATE_MUX2 ? 2 : g.kind == SV_GATE_CDENSE ? 1 : 0; }
 
 // Eigen-decomposition of the padded system matrix, A' = V diag(w) V^T, with
 // the eigenvectors as the rows of Vt (Vt[k * D + i] = V[i][k]).
@@ -59,6 +66,8 @@ struct HHLParams {
 // Interleaved complex entries of e^{+-i A' t 2^j} = V diag(e^{+-i phi}) V^T,
 // phi_k = fmod(w_k t 2^j, 2 pi) (FP64, on the host).
 std::vector<double> evolution_params(const Spectral &sp, int j, bool inverse);
+// The same for e^{+-i A' t p} with any real power p (phi_k = fmod(w_k (t p), 2 pi)).
+std::vector<double> evolution_params_pow(const Spectral &sp, double p, bool inverse);
 // Fill a deferred gate's params from the circuit's eigen-decomposition.
 void materialize(Gate &g, const HHLParams &h);
 

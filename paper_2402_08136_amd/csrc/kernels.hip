@@ -642,12 +642,44 @@ __global__ __launch_bounds__(256) void k_wide_g(Members mm, WideArgs a)
 // workgroup barrier.
 // ---------------------------------------------------------------------------
 struct WideGemmArgs {
-    uint64_t ngroups;
+    uint64_t ngroups;   // rows; with control2, three blocks of 2^g0p_log2 rows
     int k;
     int q[kMaxDenseQubits];
     int control;      // -1: none
     int contiguous;   // targets are q[0], q[0]+1, ...
+    int control2;     // -1: none; else a MUX2 op: row block v - 1 takes control
+                      // value v = bit(control) + 2 bit(control2), matrix v - 1
+    int g0p_log2;     // MUX2: rows per block, padded to >= the rows of a wave step
+    uint64_t g0;      // MUX2: real rows per block (the rest are padding)
 };
+
+// Row g of a MUX2 op (a.control2 >= 0): its control value v (1..3, the
+// block it is in), whether it is a real row, and its base index (zeros at
+// the targets, the control bits of v set).
+__device__ __forceinline__ uint64_t mux_row(const WideGemmArgs &a, uint64_t g, int *v, bool *real)
+{
+    *v = 1 + (int)(g >> a.g0p_log2);
+    const uint64_t g0 = g & ((uint64_t(1) << a.g0p_log2) - 1);
+    *real = g0 < a.g0 && g < a.ngroups;
+    const int lo = a.control < a.control2 ? a.control : a.control2;
+    const int hi = a.control < a.control2 ? a.control2 : a.control;
+    uint64_t b = g0;
+    bool pl = false, ph = false;
+    for (int j = 0; j < a.k; ++j) {
+        if (!pl && lo < a.q[j]) {
+            b = insert_zero(b, lo);
+            pl = true;
+        }
+        if (!ph && hi < a.q[j]) {
+            b = insert_zero(b, hi);
+            ph = true;
+        }
+        b = insert_zero(b, a.q[j]);
+    }
+    if (!pl) b = insert_zero(b, lo);
+    if (!ph) b = insert_zero(b, hi);
+    return b | ((uint64_t)(*v & 1) << a.control) | ((uint64_t)(*v >> 1) << a.control2);
+}
 
 template <typename R, int CT, int RW>
 __device__ __forceinline__ void k_wide_gemm_body(typename V2<R>::type *__restrict__ psi,
@@ -686,11 +718,21 @@ __device__ __forceinline__ void k_wide_gemm_body(typename V2<R>::type *__restric
     for (uint64_t rb = wave * rows_per_wave; rb < a.ngroups; rb += nwaves * rows_per_wave) {
         uint64_t gb[RW];
         bool ok[RW];
+        // MUX2: a wave step's rows lie in one block (a block is a whole
+        // number of steps), so they share its matrix; rb < ngroups, so the
+        // block is one of the three
+        const C *__restrict__ Uv = a.control2 >= 0 ? UT + (size_t)(rb >> a.g0p_log2) * D * D : UT;
 #pragma unroll
         for (int r = 0; r < RW; ++r) {
             const uint64_t g = rb + sub + (uint64_t)rps * r;
-            ok[r] = g < a.ngroups;
-            gb[r] = ok[r] ? gbase(g) : 0;
+            if (a.control2 >= 0) {
+                int v;
+                gb[r] = mux_row(a, g, &v, &ok[r]);
+                if (!ok[r]) gb[r] = 0;
+            } else {
+                ok[r] = g < a.ngroups;
+                gb[r] = ok[r] ? gbase(g) : 0;
+            }
         }
         C acc[RW][CT];
 #pragma unroll
@@ -702,7 +744,7 @@ __device__ __forceinline__ void k_wide_gemm_body(typename V2<R>::type *__restric
             const uint64_t oc = off(c);
             C u[CT];
 #pragma unroll
-            for (int t = 0; t < CT; ++t) u[t] = UT[(size_t)c * D + j0 + 64 * t];
+            for (int t = 0; t < CT; ++t) u[t] = Uv[(size_t)c * D + j0 + 64 * t];
 #pragma unroll
             for (int r = 0; r < RW; ++r) {
                 const C x = ok[r] ? psi[gb[r] | oc] : C{0, 0};
@@ -1020,14 +1062,25 @@ __device__ __forceinline__ void k_wide_mfma_body(typename V2<R>::type *__restric
     // t = li & 1) are, from U[j][c]: Re x_c -> (Re, Im)[t], Im x_c ->
     // (-Im, Re)[t].
     const bool odd = li & 1;
+    const bool mux = a.control2 >= 0;
     for (uint64_t rb = wave * rows_per_wave; rb < a.ngroups; rb += nwaves * rows_per_wave) {
         uint64_t ga[RT];
         bool oka[RT];
+        // MUX2: the wave's rows lie in one block (a block is a whole number
+        // of waves' rows), which selects the matrix; rb < ngroups, so the
+        // block is one of the three
+        const C *__restrict__ Uv = mux ? UT + (size_t)(rb >> a.g0p_log2) * D * D : UT;
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
             const uint64_t g = rb + 16 * rt + li;
-            oka[rt] = g < a.ngroups;
-            ga[rt] = oka[rt] ? wide_row(a, g) : 0;
+            if (mux) {
+                int v;
+                ga[rt] = mux_row(a, g, &v, &oka[rt]);
+                if (!oka[rt]) ga[rt] = 0;
+            } else {
+                oka[rt] = g < a.ngroups;
+                ga[rt] = oka[rt] ? wide_row(a, g) : 0;
+            }
         }
         V4 acc[RT][CTN];
 #pragma unroll
@@ -1044,7 +1097,7 @@ __device__ __forceinline__ void k_wide_mfma_body(typename V2<R>::type *__restric
             R b_re[CTN], b_im[CTN];
 #pragma unroll
             for (int ct = 0; ct < CTN; ++ct) {
-                const C u = UT[(size_t)c * D + ((16 * ct + li) >> 1)];   // U[j][c]
+                const C u = Uv[(size_t)c * D + ((16 * ct + li) >> 1)];   // U[j][c]
                 b_re[ct] = odd ? u.y : u.x;
                 b_im[ct] = odd ? u.x : -u.y;
             }
@@ -1064,8 +1117,16 @@ __device__ __forceinline__ void k_wide_mfma_body(typename V2<R>::type *__restric
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const uint64_t g = rb + 16 * rt + Mfma<R>::row(l, v);
-                if (g >= a.ngroups) continue;
-                const uint64_t gb = wide_row(a, g);
+                uint64_t gb;
+                if (mux) {
+                    int cv;
+                    bool real;
+                    gb = mux_row(a, g, &cv, &real);
+                    if (!real) continue;
+                } else {
+                    if (g >= a.ngroups) continue;
+                    gb = wide_row(a, g);
+                }
 #pragma unroll
                 for (int ct = 0; ct < CTN; ++ct) {
                     const int jj = 16 * ct + li;
@@ -1196,7 +1257,8 @@ __global__ __launch_bounds__(64 * kStageWaves) void k_wide_mfma_stage_g(Members 
 
 // ---------------------------------------------------------------------------
 // Evolution tables on the device: U[a][b] = sum_k V[a][k] V[b][k] e^{+-i phi_k}
-// with phi_k = fmod(w_k t 2^j, 2 pi), accumulated in FP64 and stored in the
+// with phi_k = fmod(w_k t p, 2 pi) (p = 2^j, or 2^j + 2^j2 for the product
+// table of a MUX2 gate), accumulated in FP64 and stored in the
 // program dtype.  U is symmetric, so the stored U is also U^T (the OP_WIDE
 // layout).  One job per blockIdx.y.
 // ---------------------------------------------------------------------------
@@ -1209,7 +1271,7 @@ __global__ __launch_bounds__(256) void k_build_evolution(const EvoJob *__restric
     extern __shared__ double ph[];
     const EvoJob jb = jobs[blockIdx.y];
     const int D = jb.D;
-    const double tj = jb.t * (double)(1ull << jb.j);
+    const double tj = jb.tp;
     const double two_pi = 6.28318530717958647692;
     for (int k = threadIdx.x; k < D; k += blockDim.x) {
         const double a = fmod(spec[jb.w_off + k] * tj, two_pi);
@@ -1768,7 +1830,14 @@ sv_status launch_op_t(const DevOp &op, const Group &g, int n, hipStream_t st, in
     }
     case OP_WIDE: {
         *family = SV_KERNEL_WIDE;
-        const uint64_t ngroups = uint64_t(1) << (n - op.k - (op.control >= 0 ? 1 : 0));
+        // a MUX2 op (two controls) runs rows of control values 1..3, each
+        // block with its own matrix; 4..64 columns only (fusion makes no
+        // wider one)
+        const bool mux = op.control2 >= 0;
+        if (mux && (op.k < 2 || op.k > 6 || op.control < 0))
+            return fail(SV_ERR_INVALID, "launch: a two-control wide gate needs 2..6 targets");
+        const uint64_t g0 = uint64_t(1) << (n - op.k - (mux ? 2 : op.control >= 0 ? 1 : 0));
+        const uint64_t ngroups = mux ? 3 * g0 : g0;
         if (op.k >= 2 && op.k <= 9) {
             WideGemmArgs a;
             std::memset(&a, 0, sizeof(a));
@@ -1776,9 +1845,20 @@ sv_status launch_op_t(const DevOp &op, const Group &g, int n, hipStream_t st, in
             a.k = op.k;
             for (int j = 0; j < op.k; ++j) a.q[j] = op.q[j];
             a.control = op.control;
+            a.control2 = mux ? op.control2 : -1;
             a.contiguous = 1;
             for (int j = 1; j < op.k; ++j)
                 if (op.q[j] != op.q[0] + j) a.contiguous = 0;
+            // MUX2: each block padded to a whole number of wave steps (step
+            // rows, a power of two), so that a step never spans two blocks
+            auto set_blocks = [&](uint64_t step) {
+                const uint64_t g0p = std::max(g0, step);
+                int lg = 0;
+                while ((uint64_t(1) << lg) < g0p) ++lg;
+                a.g0 = g0;
+                a.g0p_log2 = lg;
+                a.ngroups = 3 * g0p;
+            };
             const int D = 1 << op.k;
             // matrix-core form for batch instances (launched in groups of up
             // to 64), and for states with rows enough for >= 1024 waves of
@@ -1795,7 +1875,8 @@ sv_status launch_op_t(const DevOp &op, const Group &g, int n, hipStream_t st, in
                 const int rt_max = D == 8 ? 8 : D == 16 ? 8 : D == 32 ? 4 : 2;
                 int rt = rt_max;
                 while (rt > 1 && cnt * waves_of(rt) < (uint64_t)g.wave_target) rt >>= 1;
-                const unsigned grid = grid_for(waves_of(rt), 4, 8192);
+                if (mux) set_blocks(16 * (uint64_t)rt);
+                const unsigned grid = grid_for((a.ngroups + 16 * (uint64_t)rt - 1) / (16 * (uint64_t)rt), 4, 8192);
 #define MFMA_GO(DD, RTV) launch2(&k_wide_mfma<R, DD, RTV>, &k_wide_mfma_g<R, DD, RTV>, grid, 256, 0, st, pp, cnt, a)
 #define MFMA_RT(DD)                            \
     switch (rt) {                              \
@@ -1819,7 +1900,7 @@ sv_status launch_op_t(const DevOp &op, const Group &g, int n, hipStream_t st, in
             // time however many run: 22 us at 128 columns, 59 us at 256; the
             // vector kernel took 26 and 74 us at 2048 rows, 46 and 99 us at
             // 4096)
-            if ((D == 128 || D == 256) && ngroups >= 2048) {
+            if ((D == 128 || D == 256) && ngroups >= 2048 && !mux) {
                 constexpr int RTS = 1;
                 const unsigned grid = grid_for(ngroups, 16 * RTS, 65536);
                 const size_t smem = sizeof(R) * 16 * RTS * (2 * (size_t)D + 2);
@@ -1844,7 +1925,9 @@ sv_status launch_op_t(const DevOp &op, const Group &g, int n, hipStream_t st, in
             auto waves_for = [&](int rw) { return (ngroups + (uint64_t)rw * rps - 1) / ((uint64_t)rw * rps); };
             int rw = 8;
             while (rw > 1 && cnt * waves_for(rw) < (uint64_t)g.wave_target) rw >>= 1;
-            const unsigned grid = grid_for(waves_for(rw), 4, 8192);
+            if (mux) set_blocks((uint64_t)rw * rps);
+            const unsigned grid =
+                grid_for((a.ngroups + (uint64_t)rw * rps - 1) / ((uint64_t)rw * rps), 4, 8192);
 #define WIDE_GO(CT, RWV) launch2(&k_wide_gemm<R, CT, RWV>, &k_wide_gemm_g<R, CT, RWV>, grid, 256, 0, st, pp, cnt, a)
 #define WIDE_RW(CT)                          \
     switch (rw) {                            \
@@ -1948,17 +2031,21 @@ LoweredOp lower_gate_op(const Gate &g0, const HHLParams &h)
     // A controlled gate on two or more targets (the controlled e^{iAt 2^j})
     // is a wide op with a control: only the control = 1 half is read and
     // written, instead of a dense matrix with an identity block.
-    if (gate_deferred(g0) && g0.kind == SV_GATE_CDENSE && (int)g0.qubits.size() >= 3) {
+    if (gate_deferred(g0) && (g0.kind == SV_GATE_CDENSE || g0.kind == SV_GATE_MUX2) &&
+        (int)g0.qubits.size() >= 2 + gate_controls(g0)) {
         // Evolution on the whole system register, built on the device.
-        std::vector<int> tq(g0.qubits.begin() + 1, g0.qubits.end());
+        const int nc = gate_controls(g0);
+        std::vector<int> tq(g0.qubits.begin() + nc, g0.qubits.end());
         std::sort(tq.begin(), tq.end());
         DevOp &op = L.op;
         op.type = OP_WIDE;
         op.k = (int)tq.size();
         for (int l = 0; l < op.k; ++l) op.q[l] = tq[l];
         op.control = g0.qubits[0];
+        op.control2 = nc == 2 ? g0.qubits[1] : -1;
         L.deferred = true;
         L.evo_j = g0.evo_j;
+        L.evo_j2 = nc == 2 ? g0.evo_j2 : -1;
         L.evo_inv = g0.evo_inv;
         // The builder writes U in the order of the sorted targets; the
         // evolution's own target list is the ascending system register.
@@ -2002,6 +2089,23 @@ LoweredOp lower_gate_op(const Gate &g0, const HHLParams &h)
         for (size_t l = 0; l < k; ++l) op.q[l] = sorted[l];
         return L;
     }
+    if (g.kind == SV_GATE_MUX2) {
+        // three wide tables, one per control value 1..3, back to back
+        std::vector<int> tq(g.qubits.begin() + 2, g.qubits.end());
+        const size_t KK = g.params.size() / 6;
+        for (int v = 0; v < 3; ++v) {
+            std::vector<cd> U(KK);
+            for (size_t i = 0; i < KK; ++i) U[i] = cd(g.params[2 * (v * KK + i)], g.params[2 * (v * KK + i) + 1]);
+            const std::vector<cd> t = transpose(to_sorted(U, tq, sorted));
+            L.table.insert(L.table.end(), t.begin(), t.end());
+        }
+        op.type = OP_WIDE;
+        op.k = (int)sorted.size();
+        for (int l = 0; l < op.k; ++l) op.q[l] = sorted[l];
+        op.control = g.qubits[0];
+        op.control2 = g.qubits[1];
+        return L;
+    }
     if (g.kind == SV_GATE_CDENSE && (int)g.qubits.size() >= 3) {
         std::vector<int> tq(g.qubits.begin() + 1, g.qubits.end());
         std::vector<cd> U(g.params.size() / 2);
@@ -2020,6 +2124,32 @@ LoweredOp lower_gate_op(const Gate &g0, const HHLParams &h)
     if (op.type == OP_WIDE) L.table = transpose(L.table);
     op.control = -1;
     return L;
+}
+
+size_t deferred_entries(const LoweredOp &L)
+{
+    return (size_t)(L.op.control2 >= 0 ? 3 : 1) << (2 * L.op.k);
+}
+
+std::vector<EvoJob> evolution_jobs(const LoweredOp &L, double t, unsigned long long out_off, size_t table_bytes)
+{
+    std::vector<double> pows{std::ldexp(1.0, L.evo_j)};
+    if (L.op.control2 >= 0) {
+        const double p2 = std::ldexp(1.0, L.evo_j2);
+        pows.push_back(p2);
+        pows.push_back(pows[0] + p2);
+    }
+    std::vector<EvoJob> out;
+    for (size_t i = 0; i < pows.size(); ++i) {
+        EvoJob jb;
+        std::memset(&jb, 0, sizeof(jb));
+        jb.out_off = out_off + i * table_bytes;
+        jb.D = 1 << L.op.k;
+        jb.inv = L.evo_inv ? 1 : 0;
+        jb.tp = t * pows[i];
+        out.push_back(jb);
+    }
+    return out;
 }
 
 Circuit::~Circuit()
@@ -2060,7 +2190,7 @@ sv_status build_program_image(const Circuit &c, sv_dtype dtype, std::vector<DevO
             if (L.deferred != (pass == 1)) continue;
             bytes = (bytes + 255) & ~size_t(255);
             L.op.off = bytes;
-            bytes += (L.deferred ? ((size_t)1 << (2 * L.op.k)) : L.table.size()) * csz;
+            bytes += (L.deferred ? deferred_entries(L) : L.table.size()) * csz;
         }
     }
     *device_bytes = std::max<size_t>((bytes + 255) & ~size_t(255), image.size());
@@ -2072,17 +2202,12 @@ sv_status build_program_image(const Circuit &c, sv_dtype dtype, std::vector<DevO
         if (L.deferred) {
             if (!c.hhl.spec || c.hhl.spec->D != (1 << L.op.k))
                 return fail(SV_ERR_INVALID, "deferred evolution without a matching eigen-decomposition");
-            EvoJob jb;
-            std::memset(&jb, 0, sizeof(jb));
-            jb.vt_off = 0;
-            jb.w_off = (unsigned long long)c.hhl.spec->D * c.hhl.spec->D;
-            jb.out_off = L.op.off;
-            jb.D = 1 << L.op.k;
-            jb.j = L.evo_j;
-            jb.inv = L.evo_inv ? 1 : 0;
-            jb.t = c.hhl.spec->t;
-            jobs.push_back(jb);
-            *max_D = std::max(*max_D, jb.D);
+            for (EvoJob jb : evolution_jobs(L, c.hhl.spec->t, L.op.off, ((size_t)1 << (2 * L.op.k)) * csz)) {
+                jb.vt_off = 0;
+                jb.w_off = (unsigned long long)c.hhl.spec->D * c.hhl.spec->D;
+                jobs.push_back(jb);
+            }
+            *max_D = std::max(*max_D, 1 << L.op.k);
         } else if (dtype == SV_C128) {
             for (size_t i = 0; i < L.table.size(); ++i) {
                 const double v[2] = {L.table[i].real(), L.table[i].imag()};

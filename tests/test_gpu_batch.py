@@ -237,7 +237,7 @@ def test_run_timed_ops_covers_every_swept_op():
     assert len(ops) == items[swept[0]]["ops"]
     assert {o["item"] for o in ops} == set(swept)
     assert all(o["ms"] > 0 and o["family"] != "dense_small" for o in ops)
-    assert any(o["family"] == "wide" and o["controlled"] for o in ops)
+    assert any(o["family"] == "wide" and o["controls"] >= 1 for o in ops)
     for when in ("after per-op timing", "graph"):
         for i, ref in ((0, refs[0]), (len(systems) - 1, refs[1])):
             x_hat, _ = bt.solution(i)
