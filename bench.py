@@ -350,7 +350,7 @@ def hhl_batch(hs, W, count=8192):
         by_family = {}
         for op in bt.run_timed_ops():
             it = items[op["item"]]
-            touched = it["count"] * 2 ** it["n"] * (1.0 - 0.5 ** op["controls"])
+            touched = it["count"] * 2 ** it["n"] * (1.0 - 0.5 ** op["controls"] if op["controls"] else 1.0)
             fam = op["family"]
             key = f"{fam} k={op['k']}" + {0: "", 1: " controlled", 2: " two controls (MUX2)"}[op["controls"]]
             e = by_family.setdefault(key, {"launches": 0, "ms": 0.0, "bytes": 0.0, "flop": 0.0})
