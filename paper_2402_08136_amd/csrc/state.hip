@@ -22,6 +22,10 @@ struct sv_state {
     hipStream_t own_stream = nullptr;
     hipStream_t stream = nullptr;
     double *scratch = nullptr;   // kReducePartials partials + 1 result
+    // pinned host block for the postselected readout (P1, then the y block
+    // in the state's dtype), allocated at the first readout and grown as needed
+    unsigned char *h_readout = nullptr;
+    size_t h_readout_bytes = 0;
 };
 
 #define HIPCK(x)                                                                   \
@@ -123,6 +127,7 @@ extern "C" sv_status sv_destroy(sv_state *s)
     (void)hipStreamSynchronize(s->stream);
     if (s->owns && s->psi) (void)hipFree(s->psi);
     if (s->scratch) (void)hipFree(s->scratch);
+    if (s->h_readout) (void)hipHostFree(s->h_readout);
     if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
     delete s;
     return SV_OK;
@@ -301,18 +306,32 @@ extern "C" sv_status sv_postselect_solution(sv_state *s, const sv_circuit *hhl, 
     const uint64_t base = uint64_t(1) << (n - 1);
     const size_t D = size_t(1) << h.ns;
     // P(ancilla = 1): device reduction in double; y_s = psi[2^{n-1} + s]
-    // (ancilla 1, clock 0) copied out and widened to double.
-    std::vector<double> buf(2 + 2 * D, 0.0);
-    sv_status st = range_norm2(s, base, uint64_t(1) << n, &buf[0]);
+    // (ancilla 1, clock 0) copied out and widened to double.  Both copies go
+    // into the state's pinned block on its stream, with one wait.
+    const size_t ab = amp_bytes(s->dtype), need = 8 + D * ab;
+    if (s->h_readout_bytes < need) {
+        if (s->h_readout) (void)hipHostFree(s->h_readout);
+        s->h_readout = nullptr;
+        s->h_readout_bytes = 0;
+        HIPCK(hipHostMalloc((void **)&s->h_readout, need));
+        s->h_readout_bytes = need;
+    }
+    sv_status st = launch_norm2_range(s->psi, base, uint64_t(1) << n, s->dtype, s->scratch,
+                                      s->scratch + kReducePartials, s->stream);
     if (st != SV_OK) return st;
+    HIPCK(hipMemcpyAsync(s->h_readout, s->scratch + kReducePartials, 8, hipMemcpyDeviceToHost, s->stream));
+    HIPCK(hipMemcpyAsync(s->h_readout + 8, static_cast<const char *>(s->psi) + base * ab, D * ab,
+                         hipMemcpyDeviceToHost, s->stream));
+    HIPCK(hipStreamSynchronize(s->stream));
+    std::vector<double> buf(2 + 2 * D, 0.0);
+    std::memcpy(&buf[0], s->h_readout, 8);
     if (s->dtype == SV_C128) {
-        st = sv_get_amplitudes(s, base, D, buf.data() + 2);
+        std::memcpy(buf.data() + 2, s->h_readout + 8, D * 16);
     } else {
         std::vector<float> yf(2 * D);
-        st = sv_get_amplitudes(s, base, D, yf.data());
+        std::memcpy(yf.data(), s->h_readout + 8, D * 8);
         for (size_t i = 0; i < 2 * D; ++i) buf[2 + i] = yf[i];
     }
-    if (st != SV_OK) return st;
     return recover_solution(h, buf.data(), x_hat, dim, info);
 }
 
