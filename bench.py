@@ -307,7 +307,8 @@ def hhl_batch(hs, W, count=8192):
     out["controlled_evolution_flop_per_batch"] = flop
     out["controlled_evolution_flop_note"] = (
         "the circuit's 2m controlled e^{iAt2^j} products as written (8 flop per complex multiply-add, "
-        "half the state each); where fusion pairs them into MUX2 gates the device runs 3/4 of that")
+        "half the state each); where fusion merges them into MUX gates the device runs 7/12 (three "
+        "into a MUX3) or 3/4 (two into a MUX2) of that")
     shapes, counts = {}, {}
     for (ns, m, _), c in zip(specs, circs):
         shapes.setdefault((ns, m), c)
@@ -352,7 +353,8 @@ def hhl_batch(hs, W, count=8192):
             it = items[op["item"]]
             touched = it["count"] * 2 ** it["n"] * (1.0 - 0.5 ** op["controls"] if op["controls"] else 1.0)
             fam = op["family"]
-            key = f"{fam} k={op['k']}" + {0: "", 1: " controlled", 2: " two controls (MUX2)"}[op["controls"]]
+            key = f"{fam} k={op['k']}" + {0: "", 1: " controlled", 2: " two controls (MUX2)",
+                                           3: " three controls (MUX3)"}[op["controls"]]
             e = by_family.setdefault(key, {"launches": 0, "ms": 0.0, "bytes": 0.0, "flop": 0.0})
             e["launches"] += 1
             e["ms"] += op["ms"]

@@ -82,13 +82,17 @@ typedef enum {
                            bit(c_l) 2^l                                   */
     SV_GATE_DIAG = 12,  /* qubits (q_0..q_{k-1}), k <= 12; params: 2^k
                            complex diagonal entries (2 * 2^k doubles)     */
-    SV_GATE_MUX2 = 13   /* qubits (c_0, c_1, q_0..q_{k-1}), k <= 12;
+    SV_GATE_MUX2 = 13,  /* qubits (c_0, c_1, q_0..q_{k-1}), k <= 12;
                            params: three 2^k x 2^k matrices (as DENSE),
                            U_1, U_2, U_3, where U_v acts on the targets
                            where bit(c_0) + 2 bit(c_1) = v; identity
                            where both are 0.  fuse() makes it from two
                            controlled dense gates on the same targets
                            (U_1, U_2 and their product)                   */
+    SV_GATE_MUX3 = 14   /* as MUX2 with three controls (c_0, c_1, c_2) and
+                           seven matrices U_1..U_7, v = bit(c_0) +
+                           2 bit(c_1) + 4 bit(c_2); fuse() makes it from
+                           three controlled dense gates                   */
 } sv_gate_kind;
 
 typedef struct sv_state sv_state;      /* device state vector + stream   */

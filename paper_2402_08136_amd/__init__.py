@@ -30,7 +30,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 C128, C64 = 0, 1
 DTYPES = {"c128": C128, "c64": C64, C128: C128, C64: C64}
 KIND = {"h": 0, "x": 1, "ry": 2, "rz": 3, "p": 4, "u3": 5, "cx": 6, "cp": 7,
-        "swap": 8, "dense": 9, "cdense": 10, "ucry": 11, "diag": 12, "mux2": 13}
+        "swap": 8, "dense": 9, "cdense": 10, "ucry": 11, "diag": 12, "mux2": 13,
+        "mux3": 14}
 KIND_NAME = {v: k for k, v in KIND.items()}
 KERNEL_FAMILY = {0: "dense_direct", 1: "dense_lds", 2: "dense_small", 3: "diag",
                  4: "wide", 5: "ucry", 6: "dense_bfly", 7: "dense_mfma"}

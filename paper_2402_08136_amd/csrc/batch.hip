@@ -160,34 +160,37 @@ __device__ void b_wide(C *psi, int n, const BOp &op, const C *UT)
     const int lpr = D < 64 ? D : 64, rps = 64 / lpr;
     const int j0 = lane % lpr, sub = lane / lpr;
     const int CT = D > 64 ? D / 64 : 1;
-    // a MUX2 op (two controls, up to 64 columns): three blocks of rows, for
-    // control values 1..3, each padded to a whole number of wave steps
+    // a MUX op (r = 2 or 3 controls, up to 64 columns): 2^r - 1 blocks of
+    // rows, for control values 1..2^r-1, each padded to a whole number of
+    // wave steps
     const bool mux = op.control2 >= 0;
-    const uint32_t g0 = 1u << (n - k - (mux ? 2 : op.control >= 0 ? 1 : 0));
+    const int nctl = (op.control >= 0) + (op.control2 >= 0) + (op.control3 >= 0);
+    const uint32_t g0 = 1u << (n - k - nctl);
     const uint32_t step_rows = (uint32_t)(RW * rps);
     const uint32_t g0p = mux && g0 < step_rows ? step_rows : g0;
-    const uint32_t ngroups = mux ? 3 * g0p : g0;
+    const uint32_t ngroups = mux ? ((1u << nctl) - 1) * g0p : g0;
+    int cs[3] = {op.control, op.control2, op.control3};   // ascending, for the zero insertion
+    for (int x = 0; x < nctl; ++x)
+        for (int y = x + 1; y < nctl; ++y)
+            if (cs[y] < cs[x]) {
+                const int t = cs[x];
+                cs[x] = cs[y];
+                cs[y] = t;
+            }
     auto mux_base = [&](uint32_t g, bool *real) -> uint32_t {
         const uint32_t v = 1 + g / g0p, r = g % g0p;
         *real = r < g0 && g < ngroups;
-        const int lo = op.control < op.control2 ? op.control : op.control2;
-        const int hi = op.control < op.control2 ? op.control2 : op.control;
         uint32_t b = r;
-        bool pl = false, ph = false;
+        int c = 0;
         for (int j = 0; j < k; ++j) {
-            if (!pl && lo < op.q[j]) {
-                b = insert_zero32(b, lo);
-                pl = true;
-            }
-            if (!ph && hi < op.q[j]) {
-                b = insert_zero32(b, hi);
-                ph = true;
-            }
+            while (c < nctl && cs[c] < op.q[j]) b = insert_zero32(b, cs[c++]);
             b = insert_zero32(b, op.q[j]);
         }
-        if (!pl) b = insert_zero32(b, lo);
-        if (!ph) b = insert_zero32(b, hi);
-        return b | ((v & 1u) << op.control) | ((v >> 1) << op.control2);
+        while (c < nctl) b = insert_zero32(b, cs[c++]);
+        b |= (v & 1u) << op.control;
+        b |= ((v >> 1) & 1u) << op.control2;
+        if (nctl == 3) b |= (v >> 2) << op.control3;
+        return b;
     };
     auto off = [&](uint32_t c) -> uint32_t {
         if (op.contiguous) return c << op.q[0];
@@ -388,6 +391,7 @@ void lower_for_batch(const Circuit &f, sv_dtype dtype, std::vector<BOp> &ops, st
         op.target = L.op.target;
         op.control = L.op.control;
         op.control2 = L.op.control2;
+        op.control3 = L.op.control3;
         for (int j = 0; j < L.op.k; ++j) op.q[j] = L.op.q[j];
         op.contiguous = 1;
         for (int j = 1; j < L.op.k; ++j)
@@ -586,6 +590,7 @@ std::vector<DevOp> swept_ops(const svb *b, const svb::Meta &in)
         d.target = bo.target;
         d.control = bo.control;
         d.control2 = bo.control2;
+        d.control3 = bo.control3;
         d.off = bo.off - in.tab_base;
     }
     return ops;
@@ -597,7 +602,7 @@ bool same_ops(const std::vector<DevOp> &x, const std::vector<DevOp> &y)
     for (size_t i = 0; i < x.size(); ++i) {
         const DevOp &a = x[i], &c = y[i];
         if (a.type != c.type || a.k != c.k || a.target != c.target || a.control != c.control ||
-            a.control2 != c.control2 || a.off != c.off)
+            a.control2 != c.control2 || a.control3 != c.control3 || a.off != c.off)
             return false;
         for (int j = 0; j < a.k; ++j)
             if (a.q[j] != c.q[j]) return false;
@@ -1078,7 +1083,7 @@ extern "C" sv_status svb_run_timed_ops(svb *b, int cap, int *count, int *item, i
             const DevOp &op = sw.ops[o];
             item[at] = nclass + (int)gi;
             k[at] = op.k;
-            controlled[at] = op.type == OP_WIDE ? (op.control >= 0) + (op.control2 >= 0) : 0;
+            controlled[at] = op.type == OP_WIDE ? op_controls(op) : 0;
             ls = launch_op_group(op, g, sw.n, b->dtype, b->stream, &family[at]);
             if (ls == SV_OK) e = hipEventRecord(ev[at + 1], b->stream);
         }

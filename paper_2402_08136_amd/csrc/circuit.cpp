@@ -56,7 +56,7 @@ static int gate_width(int kind)
 sv_status validate_gate(int n, int kind, const int *qubits, int nq,
                         const double *params, int nparams)
 {
-    if (kind < SV_GATE_H || kind > SV_GATE_MUX2)
+    if (kind < SV_GATE_H || kind > SV_GATE_MUX3)
         return fail(SV_ERR_INVALID, "circuit_add_gate: unknown gate kind");
     if (nq < 1 || !qubits) return fail(SV_ERR_INVALID, "circuit_add_gate: no qubits");
     if (nparams < 0 || (nparams > 0 && !params))
@@ -87,11 +87,11 @@ sv_status validate_gate(int n, int kind, const int *qubits, int nq,
         if (nparams != (2L << (2 * k))) return fail(SV_ERR_INVALID, "circuit_add_gate: params must hold the complex matrix");
         return SV_OK;
     }
-    if (kind == SV_GATE_MUX2) {
-        const int k = nq - 2;
-        if (k < 1 || k > kMaxDenseQubits) return fail(SV_ERR_INVALID, "circuit_add_gate: MUX2 needs 1..12 targets");
-        if (nparams != 3 * (2L << (2 * k)))
-            return fail(SV_ERR_INVALID, "circuit_add_gate: MUX2 params must hold three complex matrices");
+    if (kind == SV_GATE_MUX2 || kind == SV_GATE_MUX3) {
+        const int r = kind == SV_GATE_MUX2 ? 2 : 3, k = nq - r;
+        if (k < 1 || k > kMaxDenseQubits) return fail(SV_ERR_INVALID, "circuit_add_gate: MUX needs 1..12 targets");
+        if (nparams != ((1L << r) - 1) * (2L << (2 * k)))
+            return fail(SV_ERR_INVALID, "circuit_add_gate: MUX params must hold 2^r - 1 complex matrices");
         return SV_OK;
     }
     // UCRY
@@ -145,16 +145,18 @@ std::vector<cd> gate_matrix(const Gate &g)
         }
         return M;
     }
-    case SV_GATE_MUX2: {  // block-diag(I, U_1, U_2, U_3) over (c0, c1, targets): r = v + 4 r_t
-        const int k = (int)g.qubits.size() - 2;
-        const size_t K = (size_t)1 << k, D = 4 * K;
+    case SV_GATE_MUX2:
+    case SV_GATE_MUX3: {  // block-diag(I, U_1, ..) over (controls, targets): r = v + V r_t
+        const size_t V = (size_t)1 << gate_controls(g);
+        const int k = (int)g.qubits.size() - gate_controls(g);
+        const size_t K = (size_t)1 << k, D = V * K;
         std::vector<cd> M(D * D, 0.0);
         for (size_t r = 0; r < K; ++r) {
-            M[(4 * r) * D + 4 * r] = 1.0;
-            for (size_t v = 1; v < 4; ++v)
+            M[(V * r) * D + V * r] = 1.0;
+            for (size_t v = 1; v < V; ++v)
                 for (size_t c = 0; c < K; ++c) {
                     const size_t at = 2 * ((v - 1) * K * K + r * K + c);
-                    M[(4 * r + v) * D + (4 * c + v)] = cd(p[at], p[at + 1]);
+                    M[(V * r + v) * D + (V * c + v)] = cd(p[at], p[at + 1]);
                 }
         }
         return M;
@@ -367,74 +369,90 @@ void merge_diagonals(std::vector<Block> &blocks)
     }
 }
 
-// Last pass: two controlled dense gates in a row on the same targets (the
-// controlled e^{iAt 2^j} of phase estimation) become one MUX2 gate: one
-// sweep instead of two, over three quarters of the state (control values
-// 1..3) instead of two halves.  Up to kMuxMaxTargets targets.
+// Last pass: up to three controlled dense gates in a row on the same
+// targets (the controlled e^{iAt 2^j} of phase estimation) become one MUX3
+// or MUX2 gate: one sweep instead of three or two, over the 7/8 or 3/4 of
+// the state where some control is 1 instead of three or two halves.  Up to
+// kMuxMaxTargets targets.
 constexpr int kMuxMaxTargets = 6;
 
-void merge_controlled_pairs(std::vector<Block> &blocks, const HHLParams &h)
+// The MUX gate of the controlled gates gs (applied in that order, same
+// targets, distinct controls, all deferred evolutions or none): control l
+// is gs[l]'s, and U_v is the product of the gates set in v, later gates on
+// the left; for evolutions e^{iAt p_v} from the eigen-decomposition.
+Gate make_mux(const std::vector<const Gate *> &gs, const HHLParams &h)
 {
-    int prev = -1;   // the previous live block, when it is a candidate
+    const int r = (int)gs.size();
+    Gate m;
+    m.kind = r == 2 ? SV_GATE_MUX2 : SV_GATE_MUX3;
+    for (const Gate *g : gs) m.qubits.push_back(g->qubits[0]);
+    m.qubits.insert(m.qubits.end(), gs[0]->qubits.begin() + 1, gs[0]->qubits.end());
+    bool evolutions = h.spec != nullptr;
+    for (const Gate *g : gs) evolutions = evolutions && g->evo_j >= 0 && g->evo_inv == gs[0]->evo_inv;
+    if (evolutions) {
+        m.evo_j = gs[0]->evo_j;
+        m.evo_j2 = gs[1]->evo_j;
+        if (r == 3) m.evo_j3 = gs[2]->evo_j;
+        m.evo_inv = gs[0]->evo_inv;
+        // deferred: the device builds the tables; eager: the same tables on
+        // the host (materialize), so both forms hold the same matrices
+        if (!gate_deferred(*gs[0])) materialize(m, h);
+        return m;
+    }
+    const size_t K = (size_t)1 << (gs[0]->qubits.size() - 1);
+    std::vector<std::vector<cd>> u(r, std::vector<cd>(K * K));
+    for (int l = 0; l < r; ++l)
+        for (size_t i = 0; i < K * K; ++i) u[l][i] = cd(gs[l]->params[2 * i], gs[l]->params[2 * i + 1]);
+    for (int v = 1; v < (1 << r); ++v) {
+        std::vector<cd> P;
+        for (int l = 0; l < r; ++l)
+            if ((v >> l) & 1) P = P.empty() ? u[l] : matmul(u[l], P, K);
+        for (const cd &x : P) {
+            m.params.push_back(x.real());
+            m.params.push_back(x.imag());
+        }
+    }
+    return m;
+}
+
+void merge_controlled_runs(std::vector<Block> &blocks, const HHLParams &h)
+{
+    std::vector<int> run;   // live candidate blocks in a row, mergeable with each other
+    auto flush = [&]() {
+        size_t at = 0;
+        while (run.size() - at >= 2) {
+            const size_t take = std::min<size_t>(3, run.size() - at);
+            std::vector<const Gate *> gs;
+            for (size_t l = 0; l < take; ++l) gs.push_back(&blocks[run[at + l]].orig);
+            Gate m = make_mux(gs, h);
+            Block &b0 = blocks[run[at]];
+            for (size_t l = 1; l < take; ++l) {
+                b0.qubits = unite(b0.qubits, blocks[run[at + l]].qubits);
+                blocks[run[at + l]].alive = false;
+            }
+            b0.orig = std::move(m);
+            at += take;
+        }
+        run.clear();
+    };
     for (int j = 0; j < (int)blocks.size(); ++j) {
         Block &bj = blocks[j];
         if (!bj.alive) continue;
         const Gate &b = bj.orig;
         const int nt = (int)b.qubits.size() - 1;
         const bool cand = !bj.open && b.kind == SV_GATE_CDENSE && nt >= 2 && nt <= kMuxMaxTargets;
-        if (cand && prev >= 0) {
-            Block &bi = blocks[prev];
-            const Gate &a = bi.orig;
-            const bool same_targets = a.qubits.size() == b.qubits.size() &&
-                                      std::equal(a.qubits.begin() + 1, a.qubits.end(), b.qubits.begin() + 1);
-            const bool both_deferred = gate_deferred(a) && gate_deferred(b) && a.evo_inv == b.evo_inv;
-            const bool neither_deferred = !gate_deferred(a) && !gate_deferred(b);
-            if (same_targets && a.qubits[0] != b.qubits[0] && (both_deferred || neither_deferred)) {
-                Gate m;
-                m.kind = SV_GATE_MUX2;
-                m.qubits = {a.qubits[0], b.qubits[0]};
-                m.qubits.insert(m.qubits.end(), a.qubits.begin() + 1, a.qubits.end());
-                const bool evolutions = a.evo_j >= 0 && b.evo_j >= 0 && a.evo_inv == b.evo_inv && h.spec;
-                if (both_deferred) {
-                    m.evo_j = a.evo_j;
-                    m.evo_j2 = b.evo_j;
-                    m.evo_inv = a.evo_inv;
-                } else if (evolutions) {
-                    // U_3 = e^{iAt (2^ja + 2^jb)} from the eigen-decomposition,
-                    // as the device builds it for the deferred form
-                    m.params = a.params;
-                    m.params.insert(m.params.end(), b.params.begin(), b.params.end());
-                    const std::vector<double> u3 =
-                        evolution_params_pow(*h.spec, std::ldexp(1.0, a.evo_j) + std::ldexp(1.0, b.evo_j), a.evo_inv);
-                    m.params.insert(m.params.end(), u3.begin(), u3.end());
-                    m.evo_j = a.evo_j;
-                    m.evo_j2 = b.evo_j;
-                    m.evo_inv = a.evo_inv;
-                } else {
-                    // U_1 = U_a, U_2 = U_b, U_3 = U_b U_a (a acts first)
-                    const size_t K = (size_t)1 << (a.qubits.size() - 1);
-                    std::vector<cd> ua(K * K), ub(K * K);
-                    for (size_t i = 0; i < K * K; ++i) {
-                        ua[i] = cd(a.params[2 * i], a.params[2 * i + 1]);
-                        ub[i] = cd(b.params[2 * i], b.params[2 * i + 1]);
-                    }
-                    const std::vector<cd> uc = matmul(ub, ua, K);
-                    const std::vector<cd> *mats[3] = {&ua, &ub, &uc};
-                    for (const std::vector<cd> *u : mats)
-                        for (const cd &x : *u) {
-                            m.params.push_back(x.real());
-                            m.params.push_back(x.imag());
-                        }
-                }
-                bi.orig = std::move(m);
-                bi.qubits = unite(bi.qubits, bj.qubits);
-                bj.alive = false;
-                prev = -1;
-                continue;
-            }
+        bool joins = cand && !run.empty();
+        if (joins) {
+            const Gate &a = blocks[run[0]].orig;
+            joins = a.qubits.size() == b.qubits.size() &&
+                    std::equal(a.qubits.begin() + 1, a.qubits.end(), b.qubits.begin() + 1) &&
+                    gate_deferred(a) == gate_deferred(b) && a.evo_inv == b.evo_inv;
+            for (int ri : run) joins = joins && blocks[ri].orig.qubits[0] != b.qubits[0];
         }
-        prev = cand ? j : -1;
+        if (!joins) flush();
+        if (cand) run.push_back(j);
     }
+    flush();
 }
 
 int fused_width(const Gate &g)
@@ -672,7 +690,7 @@ extern "C" sv_status fuse(const sv_circuit *in, int k_max, sv_circuit **out)
 
     merge_disjoint(blocks, n, k_max);
     merge_diagonals(blocks);
-    merge_controlled_pairs(blocks, in->c.hhl);
+    merge_controlled_runs(blocks, in->c.hhl);
 
     auto *oc = new (std::nothrow) sv_circuit;
     if (!oc) return fail(SV_ERR_OOM, "fuse: out of host memory");

@@ -288,9 +288,12 @@ std::vector<double> evolution_params_pow(const Spectral &sp, double p, bool inve
 void materialize(Gate &g, const HHLParams &h)
 {
     if (!gate_deferred(g) || !h.spec) return;
-    if (g.kind == SV_GATE_MUX2) {
-        const double p1 = std::ldexp(1.0, g.evo_j), p2 = std::ldexp(1.0, g.evo_j2);
-        for (double p : {p1, p2, p1 + p2}) {
+    if (g.kind == SV_GATE_MUX2 || g.kind == SV_GATE_MUX3) {
+        const std::vector<int> js = gate_evo_js(g);
+        for (int v = 1; v < (1 << (int)js.size()); ++v) {
+            double p = 0.0;   // sum of 2^j over the controls set in v, lowest first
+            for (size_t l = 0; l < js.size(); ++l)
+                if ((v >> l) & 1) p += std::ldexp(1.0, js[l]);
             const std::vector<double> u = evolution_params_pow(*h.spec, p, g.evo_inv);
             g.params.insert(g.params.end(), u.begin(), u.end());
         }

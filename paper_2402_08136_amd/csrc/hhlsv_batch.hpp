@@ -15,7 +15,9 @@ struct BOp {
     int control;     // OP_WIDE control, -1 = none
     int contiguous;  // targets (UCRY: controls) are q[0], q[0]+1, ...
     int q[kMaxUcryControls];
-    int control2;    // OP_WIDE second control (MUX2: tables for control values 1..3), -1 = none
+    int control2;    // OP_WIDE second and third controls (a MUX: tables for
+    int control3;    // control values 1..2^r-1), -1 = none
+    int pad2;
     unsigned long long off;   // byte offset of the op's table in the instance's tables
 };
 

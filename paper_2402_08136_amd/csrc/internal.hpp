@@ -33,16 +33,30 @@ struct Gate {
     // (on the device when applied, on the host by materialize()).
     int evo_j = -1;
     bool evo_inv = false;
-    // MUX2 of two evolution gates: the second control's j (U_1 = e^{iAt 2^j},
-    // U_2 = e^{iAt 2^j2}, U_3 = e^{iAt (2^j + 2^j2)}).
-    int evo_j2 = -1;
+    // MUX2 / MUX3 of evolution gates: the other controls' j (U_v =
+    // e^{iAt p_v}, p_v the sum of 2^j over the controls set in v).
+    int evo_j2 = -1, evo_j3 = -1;
 };
 
 inline bool gate_deferred(const Gate &g) { return g.evo_j >= 0 && g.params.empty(); }
-// Matrices a MUX2 gate carries (one for every other gate with a matrix).
-inline int gate_matrices(const Gate &g) { return g.kind == SV_GATE_MUX2 ? 3 : 1; }
-// Targets of a CDENSE (one control) or MUX2 (two controls) gate.
-inline int gate_controls(const Gate &g) { return g.kind == SV_GATE_MUX2 ? 2 : g.kind == SV_GATE_CDENSE ? 1 : 0; }
+// Control qubits of a CDENSE (1), MUX2 (2) or MUX3 (3) gate, 0 otherwise.
+inline int gate_controls(const Gate &g)
+{
+    return g.kind == SV_GATE_MUX3 ? 3 : g.kind == SV_GATE_MUX2 ? 2 : g.kind == SV_GATE_CDENSE ? 1 : 0;
+}
+// Matrices a gate carries: 2^r - 1 for a MUX of r controls, else one.
+inline int gate_matrices(const Gate &g)
+{
+    return g.kind == SV_GATE_MUX2 || g.kind == SV_GATE_MUX3 ? (1 << gate_controls(g)) - 1 : 1;
+}
+// The j of each control of a deferred evolution gate, in control order.
+inline std::vector<int> gate_evo_js(const Gate &g)
+{
+    std::vector<int> js{g.evo_j};
+    if (gate_controls(g) >= 2) js.push_back(g.evo_j2);
+    if (gate_controls(g) >= 3) js.push_back(g.evo_j3);
+    return js;
+}
 
 // Eigen-decomposition of the padded system matrix, A' = V diag(w) V^T, with
 // the eigenvectors as the rows of Vt (Vt[k * D + i] = V[i][k]).

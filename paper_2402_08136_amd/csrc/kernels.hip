@@ -642,43 +642,39 @@ __global__ __launch_bounds__(256) void k_wide_g(Members mm, WideArgs a)
 // workgroup barrier.
 // ---------------------------------------------------------------------------
 struct WideGemmArgs {
-    uint64_t ngroups;   // rows; with control2, three blocks of 2^g0p_log2 rows
+    uint64_t ngroups;   // rows; a MUX op: 2^r - 1 blocks of 2^g0p_log2 rows
     int k;
     int q[kMaxDenseQubits];
     int control;      // -1: none
     int contiguous;   // targets are q[0], q[0]+1, ...
-    int control2;     // -1: none; else a MUX2 op: row block v - 1 takes control
-                      // value v = bit(control) + 2 bit(control2), matrix v - 1
-    int g0p_log2;     // MUX2: rows per block, padded to >= the rows of a wave step
-    uint64_t g0;      // MUX2: real rows per block (the rest are padding)
+    int control2;     // -1: none; else a MUX op of r = 2 or 3 controls
+    int control3;     // (control, control2[, control3]): row block v - 1 takes
+                      // control value v (bit l = control l), matrix v - 1
+    int ctl_sorted[3];  // MUX: the r control qubits in ascending order
+    int nctl;           // MUX: r
+    int g0p_log2;     // MUX: rows per block, padded to >= the rows of a wave step
+    uint64_t g0;      // MUX: real rows per block (the rest are padding)
 };
 
-// Row g of a MUX2 op (a.control2 >= 0): its control value v (1..3, the
+// Row g of a MUX op (a.control2 >= 0): its control value v (1..2^r-1, the
 // block it is in), whether it is a real row, and its base index (zeros at
-// the targets, the control bits of v set).
+// the targets and controls, the control bits of v set).
 __device__ __forceinline__ uint64_t mux_row(const WideGemmArgs &a, uint64_t g, int *v, bool *real)
 {
     *v = 1 + (int)(g >> a.g0p_log2);
     const uint64_t g0 = g & ((uint64_t(1) << a.g0p_log2) - 1);
     *real = g0 < a.g0 && g < a.ngroups;
-    const int lo = a.control < a.control2 ? a.control : a.control2;
-    const int hi = a.control < a.control2 ? a.control2 : a.control;
     uint64_t b = g0;
-    bool pl = false, ph = false;
+    int c = 0;   // controls placed so far (ascending)
     for (int j = 0; j < a.k; ++j) {
-        if (!pl && lo < a.q[j]) {
-            b = insert_zero(b, lo);
-            pl = true;
-        }
-        if (!ph && hi < a.q[j]) {
-            b = insert_zero(b, hi);
-            ph = true;
-        }
+        while (c < a.nctl && a.ctl_sorted[c] < a.q[j]) b = insert_zero(b, a.ctl_sorted[c++]);
         b = insert_zero(b, a.q[j]);
     }
-    if (!pl) b = insert_zero(b, lo);
-    if (!ph) b = insert_zero(b, hi);
-    return b | ((uint64_t)(*v & 1) << a.control) | ((uint64_t)(*v >> 1) << a.control2);
+    while (c < a.nctl) b = insert_zero(b, a.ctl_sorted[c++]);
+    b |= (uint64_t)(*v & 1) << a.control;
+    b |= (uint64_t)((*v >> 1) & 1) << a.control2;
+    if (a.nctl == 3) b |= (uint64_t)(*v >> 2) << a.control3;
+    return b;
 }
 
 template <typename R, int CT, int RW>
@@ -1830,14 +1826,16 @@ sv_status launch_op_t(const DevOp &op, const Group &g, int n, hipStream_t st, in
     }
     case OP_WIDE: {
         *family = SV_KERNEL_WIDE;
-        // a MUX2 op (two controls) runs rows of control values 1..3, each
-        // block with its own matrix; 4..64 columns only (fusion makes no
-        // wider one)
+        // a MUX op (r = 2 or 3 controls) runs rows of control values
+        // 1..2^r-1, each block with its own matrix; 4..64 columns only
+        // (fusion makes no wider one)
         const bool mux = op.control2 >= 0;
+        const int nctl = op_controls(op);
         if (mux && (op.k < 2 || op.k > 6 || op.control < 0))
-            return fail(SV_ERR_INVALID, "launch: a two-control wide gate needs 2..6 targets");
-        const uint64_t g0 = uint64_t(1) << (n - op.k - (mux ? 2 : op.control >= 0 ? 1 : 0));
-        const uint64_t ngroups = mux ? 3 * g0 : g0;
+            return fail(SV_ERR_INVALID, "launch: a multi-control wide gate needs 2..6 targets");
+        const uint64_t nblocks = mux ? (uint64_t(1) << nctl) - 1 : 1;
+        const uint64_t g0 = uint64_t(1) << (n - op.k - nctl);
+        const uint64_t ngroups = nblocks * g0;
         if (op.k >= 2 && op.k <= 9) {
             WideGemmArgs a;
             std::memset(&a, 0, sizeof(a));
@@ -1846,10 +1844,17 @@ sv_status launch_op_t(const DevOp &op, const Group &g, int n, hipStream_t st, in
             for (int j = 0; j < op.k; ++j) a.q[j] = op.q[j];
             a.control = op.control;
             a.control2 = mux ? op.control2 : -1;
+            a.control3 = mux ? op.control3 : -1;
+            if (mux) {
+                a.nctl = nctl;
+                const int cs[3] = {op.control, op.control2, op.control3};
+                for (int l = 0; l < nctl; ++l) a.ctl_sorted[l] = cs[l];
+                std::sort(a.ctl_sorted, a.ctl_sorted + nctl);
+            }
             a.contiguous = 1;
             for (int j = 1; j < op.k; ++j)
                 if (op.q[j] != op.q[0] + j) a.contiguous = 0;
-            // MUX2: each block padded to a whole number of wave steps (step
+            // MUX: each block padded to a whole number of wave steps (step
             // rows, a power of two), so that a step never spans two blocks
             auto set_blocks = [&](uint64_t step) {
                 const uint64_t g0p = std::max(g0, step);
@@ -1857,7 +1862,7 @@ sv_status launch_op_t(const DevOp &op, const Group &g, int n, hipStream_t st, in
                 while ((uint64_t(1) << lg) < g0p) ++lg;
                 a.g0 = g0;
                 a.g0p_log2 = lg;
-                a.ngroups = 3 * g0p;
+                a.ngroups = nblocks * g0p;
             };
             const int D = 1 << op.k;
             // matrix-core form for batch instances (launched in groups of up
@@ -2031,21 +2036,22 @@ LoweredOp lower_gate_op(const Gate &g0, const HHLParams &h)
     // A controlled gate on two or more targets (the controlled e^{iAt 2^j})
     // is a wide op with a control: only the control = 1 half is read and
     // written, instead of a dense matrix with an identity block.
-    if (gate_deferred(g0) && (g0.kind == SV_GATE_CDENSE || g0.kind == SV_GATE_MUX2) &&
-        (int)g0.qubits.size() >= 2 + gate_controls(g0)) {
+    const int nc0 = gate_controls(g0);
+    if (gate_deferred(g0) && nc0 >= 1 && (int)g0.qubits.size() >= 2 + nc0) {
         // Evolution on the whole system register, built on the device.
-        const int nc = gate_controls(g0);
-        std::vector<int> tq(g0.qubits.begin() + nc, g0.qubits.end());
+        std::vector<int> tq(g0.qubits.begin() + nc0, g0.qubits.end());
         std::sort(tq.begin(), tq.end());
         DevOp &op = L.op;
         op.type = OP_WIDE;
         op.k = (int)tq.size();
         for (int l = 0; l < op.k; ++l) op.q[l] = tq[l];
         op.control = g0.qubits[0];
-        op.control2 = nc == 2 ? g0.qubits[1] : -1;
+        op.control2 = nc0 >= 2 ? g0.qubits[1] : -1;
+        op.control3 = nc0 >= 3 ? g0.qubits[2] : -1;
         L.deferred = true;
         L.evo_j = g0.evo_j;
-        L.evo_j2 = nc == 2 ? g0.evo_j2 : -1;
+        L.evo_j2 = nc0 >= 2 ? g0.evo_j2 : -1;
+        L.evo_j3 = nc0 >= 3 ? g0.evo_j3 : -1;
         L.evo_inv = g0.evo_inv;
         // The builder writes U in the order of the sorted targets; the
         // evolution's own target list is the ascending system register.
@@ -2089,11 +2095,12 @@ LoweredOp lower_gate_op(const Gate &g0, const HHLParams &h)
         for (size_t l = 0; l < k; ++l) op.q[l] = sorted[l];
         return L;
     }
-    if (g.kind == SV_GATE_MUX2) {
-        // three wide tables, one per control value 1..3, back to back
-        std::vector<int> tq(g.qubits.begin() + 2, g.qubits.end());
-        const size_t KK = g.params.size() / 6;
-        for (int v = 0; v < 3; ++v) {
+    if (g.kind == SV_GATE_MUX2 || g.kind == SV_GATE_MUX3) {
+        // 2^r - 1 wide tables, one per control value, back to back
+        const int nc = gate_controls(g), nm = gate_matrices(g);
+        std::vector<int> tq(g.qubits.begin() + nc, g.qubits.end());
+        const size_t KK = g.params.size() / (2 * (size_t)nm);
+        for (int v = 0; v < nm; ++v) {
             std::vector<cd> U(KK);
             for (size_t i = 0; i < KK; ++i) U[i] = cd(g.params[2 * (v * KK + i)], g.params[2 * (v * KK + i) + 1]);
             const std::vector<cd> t = transpose(to_sorted(U, tq, sorted));
@@ -2104,6 +2111,7 @@ LoweredOp lower_gate_op(const Gate &g0, const HHLParams &h)
         for (int l = 0; l < op.k; ++l) op.q[l] = sorted[l];
         op.control = g.qubits[0];
         op.control2 = g.qubits[1];
+        op.control3 = nc == 3 ? g.qubits[2] : -1;
         return L;
     }
     if (g.kind == SV_GATE_CDENSE && (int)g.qubits.size() >= 3) {
@@ -2128,16 +2136,24 @@ LoweredOp lower_gate_op(const Gate &g0, const HHLParams &h)
 
 size_t deferred_entries(const LoweredOp &L)
 {
-    return (size_t)(L.op.control2 >= 0 ? 3 : 1) << (2 * L.op.k);
+    const int nc = op_controls(L.op);
+    return (size_t)(L.op.control2 >= 0 ? (1 << nc) - 1 : 1) << (2 * L.op.k);
 }
 
 std::vector<EvoJob> evolution_jobs(const LoweredOp &L, double t, unsigned long long out_off, size_t table_bytes)
 {
-    std::vector<double> pows{std::ldexp(1.0, L.evo_j)};
-    if (L.op.control2 >= 0) {
-        const double p2 = std::ldexp(1.0, L.evo_j2);
-        pows.push_back(p2);
-        pows.push_back(pows[0] + p2);
+    // the power of each table: 2^j, or for a MUX the sum of 2^j over the
+    // controls set in v = 1..2^r-1 (lowest first, as the host sums it)
+    std::vector<int> js{L.evo_j};
+    if (L.op.control2 >= 0) js.push_back(L.evo_j2);
+    if (L.op.control3 >= 0) js.push_back(L.evo_j3);
+    std::vector<double> pows;
+    if (js.size() == 1) pows.push_back(std::ldexp(1.0, L.evo_j));
+    for (int v = 1; js.size() > 1 && v < (1 << (int)js.size()); ++v) {
+        double p = 0.0;
+        for (size_t l = 0; l < js.size(); ++l)
+            if ((v >> l) & 1) p += std::ldexp(1.0, js[l]);
+        pows.push_back(p);
     }
     std::vector<EvoJob> out;
     for (size_t i = 0; i < pows.size(); ++i) {

@@ -87,8 +87,8 @@ struct DevOp {
     int q[kMaxUcryControls] = {0};   // sorted targets / UCRY control list
     int target = -1;         // UCRY target
     int control = -1;        // OP_WIDE control qubit, -1 = none
-    int control2 = -1;       // OP_WIDE second control (a MUX2 gate: three
-                             // matrices, for control values 1, 2, 3), -1 = none
+    int control2 = -1;       // OP_WIDE second and third controls (a MUX gate:
+    int control3 = -1;       // 2^r - 1 matrices, for control values 1..2^r-1), -1 = none
     size_t off = 0;          // byte offset of the op's table in the buffer
 };
 
@@ -124,7 +124,7 @@ struct LoweredOp {
     bool deferred = false;
     int evo_j = -1;
     bool evo_inv = false;
-    int evo_j2 = -1;   // MUX2: the second evolution's j (three tables)
+    int evo_j2 = -1, evo_j3 = -1;   // MUX: the other evolutions' j (2^r - 1 tables)
 };
 LoweredOp lower_gate_op(const Gate &g, const HHLParams &h);
 
@@ -140,7 +140,12 @@ struct EvoJob {
 // The tables of a deferred evolution op (one, or three for a MUX2 gate):
 // job i builds e^{+-i A' t p_i} at out_off + i * table_bytes.
 std::vector<EvoJob> evolution_jobs(const LoweredOp &L, double t, unsigned long long out_off, size_t table_bytes);
-// Table entries a deferred op's region holds (4^k, or 3 * 4^k for MUX2).
+// Controls of an op (0..3) and the table entries a deferred op's region
+// holds (4^k, or (2^r - 1) 4^k for a MUX of r controls).
+inline int op_controls(const DevOp &op)
+{
+    return (op.control >= 0) + (op.control2 >= 0) + (op.control3 >= 0);
+}
 size_t deferred_entries(const LoweredOp &L);
 sv_status launch_build_evolutions(const EvoJob *d_jobs, int njobs, int max_D, const double *d_spec,
                                   void *d_tables, sv_dtype dtype, hipStream_t st);

@@ -483,7 +483,8 @@ uint64_t op_signature(int n, const std::vector<DevOp> &ops)
     mix(ops.size());
     for (const DevOp &op : ops) {
         mix((uint64_t)op.type | ((uint64_t)op.k << 8) | ((uint64_t)(op.target + 1) << 16) |
-            ((uint64_t)(op.control + 1) << 32) | ((uint64_t)(op.control2 + 1) << 48));
+            ((uint64_t)(op.control + 1) << 32) | ((uint64_t)(op.control2 + 1) << 44) |
+            ((uint64_t)(op.control3 + 1) << 54));
         for (int j = 0; j < op.k; ++j) mix((uint64_t)op.q[j]);
         mix(op.off);
     }
@@ -496,7 +497,7 @@ bool same_ops(const std::vector<DevOp> &a, const std::vector<DevOp> &b)
     for (size_t i = 0; i < a.size(); ++i) {
         const DevOp &x = a[i], &y = b[i];
         if (x.type != y.type || x.k != y.k || x.target != y.target || x.control != y.control ||
-            x.control2 != y.control2 || x.off != y.off)
+            x.control2 != y.control2 || x.control3 != y.control3 || x.off != y.off)
             return false;
         for (int j = 0; j < x.k; ++j)
             if (x.q[j] != y.q[j]) return false;

@@ -403,21 +403,22 @@ def test_wide_gate_matrix_cores(k, control, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("r", [2, 3])
 @pytest.mark.parametrize("k,n", [(2, 9), (3, 12), (6, 14), (3, 20), (6, 21), (5, 22)])
-def test_two_controlled_gates_as_mux2(k, n, dtype):
-    """Two controlled dense gates in a row on the same k targets, fused into
-    one MUX2 op (three matrices by control value), against the oracle's two
+def test_controlled_gates_as_mux(k, n, r, dtype):
+    """r controlled dense gates in a row on the same k targets, fused into
+    one MUX op (2^r - 1 matrices by control value), against the oracle's r
     gates: the vector GEMM on small states, the matrix cores from 16384 rows
-    (3 * 2^(n-k-2)); scattered targets and controls, a single state."""
-    rng = np.random.default_rng(300 + 10 * k + n)
-    qs = rng.choice(n, size=k + 2, replace=False).tolist()
-    Ua, Ub = W.random_unitary(1 << k, rng), W.random_unitary(1 << k, rng)
-    gates = [W.Gate("cdense", (qs[0],) + tuple(qs[2:]), np.ascontiguousarray(Ua).view(np.float64).ravel()),
-             W.Gate("cdense", (qs[1],) + tuple(qs[2:]), np.ascontiguousarray(Ub).view(np.float64).ravel())]
+    ((2^r - 1) 2^(n-k-r)); scattered targets and controls, a single state."""
+    rng = np.random.default_rng(300 + 10 * k + n + 1000 * r)
+    qs = rng.choice(n, size=k + r, replace=False).tolist()
+    gates = [W.Gate("cdense", (qs[l],) + tuple(qs[r:]),
+                    np.ascontiguousarray(W.random_unitary(1 << k, rng)).view(np.float64).ravel())
+             for l in range(r)]
     hs = _hs()
     fused = hs.fuse(hs.circuit_from_gates(n, gates), 1)
-    assert [kind for kind, _, _ in fused.gates()] == ["mux2"]
-    _say(f"mux2 n={n} k={k} qubits={qs} rows={3 << (n - k - 2)} dtype={dtype}")
+    assert [kind for kind, _, _ in fused.gates()] == [f"mux{r}"]
+    _say(f"mux{r} n={n} k={k} qubits={qs} rows={((1 << r) - 1) << (n - k - r)} dtype={dtype}")
     psi0 = W.random_state(n, 11 * k + n)
     want = oracle.apply_circuit(psi0, n, gates)
     got = run_gpu(n, gates, psi0, dtype, k=1)

@@ -45,15 +45,15 @@ def _np_apply_gate(psi, n, kind, qs, ps):
         return apply_tensor(psi, n, qs[1:], cmat(ps, len(qs) - 1), control=qs[0])
     if kind == "ucry":
         return apply_ucry_tensor(psi, n, qs[0], qs[1:], ps)
-    if kind == "mux2":
-        # block-diag(I, U_1, U_2, U_3) over (c0, c1, targets): index v + 4 r
-        k = len(qs) - 2
-        K = 1 << k
-        us = np.asarray(ps).view(np.complex128).reshape(3, K, K)
-        M = np.zeros((4 * K, 4 * K), dtype=complex)
-        M[0::4, 0::4] = np.eye(K)
-        for v in range(1, 4):
-            M[v::4, v::4] = us[v - 1]
+    if kind in ("mux2", "mux3"):
+        # block-diag(I, U_1, ..) over (controls, targets): index v + V r
+        r = 2 if kind == "mux2" else 3
+        V, K = 1 << r, 1 << (len(qs) - r)
+        us = np.asarray(ps).view(np.complex128).reshape(V - 1, K, K)
+        M = np.zeros((V * K, V * K), dtype=complex)
+        M[0::V, 0::V] = np.eye(K)
+        for v in range(1, V):
+            M[v::V, v::V] = us[v - 1]
         return apply_tensor(psi, n, qs, M)
     return apply_tensor(psi, n, qs, oracle.gate_matrix(kind, ps))
 
@@ -183,7 +183,7 @@ def test_fusion_preserves_unitary(n, seed, k):
         else:
             # too wide to fuse: passed through unchanged (qubits relabelled),
             # or two controlled gates on the same targets as one MUX2
-            wide_out += 2 if kind == "mux2" else 1
+            wide_out += {"mux2": 2, "mux3": 3}.get(kind, 1)
     assert wide_out == wide_in
     assert swaps_out <= min(n - 1, sum(g.kind == "swap" for g in gates))
     psi = W.random_state(n, seed)
@@ -255,22 +255,25 @@ def test_swaps_become_relabelling():
 
 
 @pytest.mark.parametrize("device_evolutions", [False, True])
-def test_controlled_evolution_pairs_become_mux2(device_evolutions):
-    """Consecutive controlled evolutions on the system register merge in
-    pairs into MUX2 gates (U_a, U_b and U_b U_a = e^{iAt(2^a + 2^b)} by
-    control value): m of them instead of 2m controlled gates, same state."""
-    ns, m = 4, 6
+@pytest.mark.parametrize("m", [6, 7, 8])
+def test_controlled_evolutions_become_mux_gates(device_evolutions, m):
+    """Runs of controlled evolutions on the system register merge in threes
+    into MUX3 gates (a pair left over into a MUX2, a single one stays):
+    U_v is the product of the evolutions set in v, e^{iAt sum 2^j}."""
+    ns = 4
     A, b = W.dc_powerflow(1 << ns, 8)
     c = hs.circuit_build_hhl(A, b, m, device_evolutions=device_evolutions)
     ref = hs.circuit_build_hhl(A, b, m)
     f = hs.fuse(c, 3)          # 5-qubit controlled gates stay whole at k_max = 3
     kinds = [kind for kind, _, _ in f.gates()]
-    assert kinds.count("mux2") == m and "cdense" not in kinds
-    muxes = [(qs, ps) for kind, qs, ps in f.gates() if kind == "mux2"]
-    qs, ps = muxes[0]
-    assert qs[2:] == list(range(ns)) and qs[0] != qs[1]
-    us = np.asarray(ps).view(np.complex128).reshape(3, 1 << ns, 1 << ns)
-    assert np.allclose(us[2], us[1] @ us[0], atol=1e-12)
+    # two runs of m (phase estimation and its inverse)
+    assert kinds.count("mux3") == 2 * (m // 3)
+    assert kinds.count("mux2") == 2 * (m % 3 == 2) and kinds.count("cdense") == 2 * (m % 3 == 1)
+    qs, ps = next((qs, ps) for kind, qs, ps in f.gates() if kind == "mux3")
+    assert qs[3:] == list(range(ns)) and len(set(qs[:3])) == 3
+    us = np.asarray(ps).view(np.complex128).reshape(7, 1 << ns, 1 << ns)
+    assert np.allclose(us[2], us[1] @ us[0], atol=1e-12)                # v = 3
+    assert np.allclose(us[6], us[3] @ us[1] @ us[0], atol=1e-12)        # v = 7
     psi = np.zeros(1 << c.n_qubits, dtype=complex)
     psi[0] = 1
     assert max_abs_diff(np_run(f, psi), np_run(ref, psi)) < 1e-12
@@ -280,7 +283,7 @@ def test_controlled_evolution_pairs_become_mux2(device_evolutions):
     gates = [W.Gate("cdense", (2, 0, 1), up), W.Gate("h", (0,), np.array([])),
              W.Gate("cdense", (3, 0, 1), up), W.Gate("cdense", (4, 1, 0), up)]
     g = hs.fuse(hs.circuit_from_gates(5, gates), 2)
-    assert [kind for kind, _, _ in g.gates()].count("mux2") == 0
+    assert not any(kind.startswith("mux") for kind, _, _ in g.gates())
 
 
 @pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
