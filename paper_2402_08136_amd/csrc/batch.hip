@@ -783,16 +783,36 @@ sv_status capture(svb *b)
     HIPCK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipEventRecord(b->ev[0], b->stream);
     for (int i = 0; i < nside && e == hipSuccess; ++i) e = hipStreamWaitEvent(b->side[i], b->ev[0], 0);
-    for (size_t c = 0; c < b->classes.size() && e == hipSuccess; ++c) {
-        const BatchClass &cl = b->classes[c];
-        if (launch_batch_class(b->d_insts, b->d_order + cl.first, cl.count, cl.n, cl.kmax, true, b->dtype,
-                               b->side[c % nside]) != SV_OK)
-            e = hipErrorLaunchFailure;
-    }
-    // swept groups, spread over the side streams after the classes
-    for (size_t gi = 0; gi < b->swept.size() && e == hipSuccess; ++gi) {
-        const svb::Swept &sw = b->swept[gi];
-        const hipStream_t st = b->side[(b->classes.size() + gi) % nside];
+    // work items (size classes of the batched kernel, groups of the sweeps)
+    // largest first, each on the side stream with the least work so far;
+    // work ~ instances * amplitudes * ops (a class: 40 ops per instance)
+    struct Item {
+        double work;
+        bool swept;
+        size_t idx;
+    };
+    std::vector<Item> items;
+    for (size_t c = 0; c < b->classes.size(); ++c)
+        items.push_back({(double)b->classes[c].count * std::ldexp(40.0, b->classes[c].n), false, c});
+    for (size_t gi = 0; gi < b->swept.size(); ++gi)
+        items.push_back({(double)b->swept[gi].members.size() * std::ldexp((double)b->swept[gi].ops.size(),
+                                                                          b->swept[gi].n),
+                         true, gi});
+    std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) { return x.work > y.work; });
+    std::vector<double> load(nside, 0.0);
+    for (const Item &it : items) {
+        if (e != hipSuccess) break;
+        const int si = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[si] += it.work;
+        const hipStream_t st = b->side[si];
+        if (!it.swept) {
+            const BatchClass &cl = b->classes[it.idx];
+            if (launch_batch_class(b->d_insts, b->d_order + cl.first, cl.count, cl.n, cl.kmax, true, b->dtype,
+                                   st) != SV_OK)
+                e = hipErrorLaunchFailure;
+            continue;
+        }
+        const svb::Swept &sw = b->swept[it.idx];
         Group g;
         swept_group(b, sw, &g);
         sv_status ls = launch_init_zero_group(g, sw.n, b->dtype, st);
