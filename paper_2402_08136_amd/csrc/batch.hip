@@ -215,7 +215,7 @@ __device__ void b_wide(C *psi, int n, const BOp &op, const C *UT)
     for (uint32_t rb = (uint32_t)wave * step; rb < ngroups; rb += (uint32_t)nw * step) {
         uint32_t gb[RW];
         bool ok[RW];
-        // MUX2: the step's rows lie in one block, which selects the matrix
+        // MUX: the step's rows lie in one block, which selects the matrix
         const C *Uv = mux ? UT + (size_t)(rb / g0p) * D * D : UT;
 #pragma unroll
         for (int r = 0; r < RW; ++r) {

@@ -714,9 +714,9 @@ __device__ __forceinline__ void k_wide_gemm_body(typename V2<R>::type *__restric
     for (uint64_t rb = wave * rows_per_wave; rb < a.ngroups; rb += nwaves * rows_per_wave) {
         uint64_t gb[RW];
         bool ok[RW];
-        // MUX2: a wave step's rows lie in one block (a block is a whole
+        // MUX: a wave step's rows lie in one block (a block is a whole
         // number of steps), so they share its matrix; rb < ngroups, so the
-        // block is one of the three
+        // block is one of the 2^r - 1
         const C *__restrict__ Uv = a.control2 >= 0 ? UT + (size_t)(rb >> a.g0p_log2) * D * D : UT;
 #pragma unroll
         for (int r = 0; r < RW; ++r) {
@@ -1062,9 +1062,9 @@ __device__ __forceinline__ void k_wide_mfma_body(typename V2<R>::type *__restric
     for (uint64_t rb = wave * rows_per_wave; rb < a.ngroups; rb += nwaves * rows_per_wave) {
         uint64_t ga[RT];
         bool oka[RT];
-        // MUX2: the wave's rows lie in one block (a block is a whole number
+        // MUX: the wave's rows lie in one block (a block is a whole number
         // of waves' rows), which selects the matrix; rb < ngroups, so the
-        // block is one of the three
+        // block is one of the 2^r - 1
         const C *__restrict__ Uv = mux ? UT + (size_t)(rb >> a.g0p_log2) * D * D : UT;
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
@@ -1253,8 +1253,8 @@ __global__ __launch_bounds__(64 * kStageWaves) void k_wide_mfma_stage_g(Members 
 
 // ---------------------------------------------------------------------------
 // Evolution tables on the device: U[a][b] = sum_k V[a][k] V[b][k] e^{+-i phi_k}
-// with phi_k = fmod(w_k t p, 2 pi) (p = 2^j, or 2^j + 2^j2 for the product
-// table of a MUX2 gate), accumulated in FP64 and stored in the
+// with phi_k = fmod(w_k t p, 2 pi) (p = 2^j, or for the tables of a MUX gate
+// the sum of 2^j over the controls set), accumulated in FP64 and stored in the
 // program dtype.  U is symmetric, so the stored U is also U^T (the OP_WIDE
 // layout).  One job per blockIdx.y.
 // ---------------------------------------------------------------------------

@@ -137,7 +137,7 @@ struct EvoJob {
     int D, inv;
     double tp;                   // t times the power p of e^{+-i A' t p}
 };
-// The tables of a deferred evolution op (one, or three for a MUX2 gate):
+// The tables of a deferred evolution op (one, or 2^r - 1 for a MUX gate):
 // job i builds e^{+-i A' t p_i} at out_off + i * table_bytes.
 std::vector<EvoJob> evolution_jobs(const LoweredOp &L, double t, unsigned long long out_off, size_t table_bytes);
 // Controls of an op (0..3) and the table entries a deferred op's region
