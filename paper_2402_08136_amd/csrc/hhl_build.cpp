@@ -22,7 +22,14 @@ constexpr double kPi = 3.14159265358979323846;
 // backwards (Q = H_0 (H_1 (... H_{N-3}))), so each reflector touches only the
 // trailing block; the result is returned transposed, Zt = Q^T (rows are the
 // columns of Q), ready for the row rotations of the QR sweeps.
-__attribute__((target_clones("arch=haswell", "default")))
+//
+// This and the QR sweeps below are built twice, with AVX2 and for the
+// baseline ISA, and the loader picks the AVX2 copy where the CPU has it.
+// AVX2 alone brings no fused multiply-add, so both copies round every
+// operation alike and give the same bits.  (A clone for a whole CPU
+// generation, such as arch=haswell, also asks for RDRND, which virtual
+// machines may hide; then the baseline copy would always run.)
+__attribute__((target_clones("avx2", "default")))
 void tridiagonalise(std::vector<double> &A, int N, std::vector<double> &d, std::vector<double> &e,
                     std::vector<double> &Zt)
 {
@@ -104,7 +111,7 @@ void tridiagonalise(std::vector<double> &A, int N, std::vector<double> &d, std::
 // (Golub & Van Loan, Alg. 8.3.2): each step chases a bulge down the active
 // block with Givens rotations G(p, p+1) = [[c, s], [-s, c]], T <- G T G^T,
 // applied to d / e in O(1) and to the rows p, p+1 of Z^T in O(N).
-__attribute__((target_clones("arch=haswell", "default")))
+__attribute__((target_clones("avx2", "default")))
 bool tridiagonal_qr(std::vector<double> &d, std::vector<double> &e, std::vector<double> &Zt, int N)
 {
     const double eps = 2.220446049250313e-16;
