@@ -367,16 +367,21 @@ void merge_diagonals(std::vector<Block> &blocks)
                     // bj commutes with every block between: apply it right
                     // after bi, i.e. multiply the two diagonals entry by entry
                     const std::vector<cd> di = diag_entries(bi), dj = diag_entries(bj);
-                    auto index_in = [&](const std::vector<int> &qs, size_t R) {
+                    // position in U of each qubit of a block, found once
+                    auto positions = [&](const std::vector<int> &qs) {
+                        std::vector<int> pos(qs.size());
+                        for (size_t l = 0; l < qs.size(); ++l)
+                            pos[l] = (int)(std::find(U.begin(), U.end(), qs[l]) - U.begin());
+                        return pos;
+                    };
+                    const std::vector<int> pi = positions(bi.qubits), pj = positions(bj.qubits);
+                    auto index_in = [](const std::vector<int> &pos, size_t R) {
                         size_t r = 0;
-                        for (size_t l = 0; l < qs.size(); ++l) {
-                            const size_t p = std::find(U.begin(), U.end(), qs[l]) - U.begin();
-                            r |= ((R >> p) & 1) << l;
-                        }
+                        for (size_t l = 0; l < pos.size(); ++l) r |= ((R >> pos[l]) & 1) << l;
                         return r;
                     };
                     std::vector<cd> d((size_t)1 << U.size());
-                    for (size_t R = 0; R < d.size(); ++R) d[R] = dj[index_in(bj.qubits, R)] * di[index_in(bi.qubits, R)];
+                    for (size_t R = 0; R < d.size(); ++R) d[R] = dj[index_in(pj, R)] * di[index_in(pi, R)];
                     bi.dv = std::move(d);
                     bi.M.clear();
                     bi.qubits = U;
